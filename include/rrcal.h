@@ -1,0 +1,224 @@
+/*
+ * rrcal -- calibrated O(N log N) FFT-correlator for a redundant array on a
+ * regular square grid, on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Gorthi, Parsons & Dillon (2020), "Calibration schemes with
+ * O(N log N) scaling for large-N radio interferometers built on a regular
+ * grid".  Fig. 1(b) of the paper: channelised antenna voltages feed both an
+ * FFT-correlator (gain application, spatial FFT, |.|^2 integrated over time,
+ * giving the redundantly averaged visibilities V^unique of eq. modelvis) and
+ * a calibrator (a reduced X-engine over a subset of redundant groups giving
+ * V^reduced, then redundant-baseline calibration, eq. redcal / eq. redchi,
+ * whose gains are applied to the voltages).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Grid:   n x n antennas, unit spacing; antenna i sits at (x, y) =
+ *         (i mod n, i div n).  N = n*n.
+ * Types:  a baseline-type is an integer displacement d = (dx, dy) with
+ *         |dx|, |dy| < n in the canonical half-plane (dy > 0, or dy == 0 and
+ *         dx > 0).  Its redundant group is every pair (i, j) with
+ *         r_i - r_j = d (the orientation of eq. redcal: d_alpha = r_0 - r_1
+ *         for V_01); there are N_d = (n - |dx|)(n - |dy|) of them.
+ *         `types_xy` arrays hold K such types as 2*K int32 (dx0, dy0, dx1, ...).
+ * Pairs:  V^reduced lists the pairs of the selected types type-major, in the
+ *         order the types were given; within a type by the raster index of
+ *         i.  Pair b of type (dx, dy): with w = n - |dx|, i = (yi, xi) with
+ *         yi = b / w + dy, xi = b % w + max(dx, 0), and j = i - (dy*n + dx).
+ * Lags:   V^unique holds every canonical lag (2 n (n - 1) of them) in the
+ *         order dy ascending, then dx ascending (dy = 0 starts at dx = 1).
+ * Units:  one (array, channel) integration.  A plan covers U units of the
+ *         same grid; every per-unit array has the unit as its slowest index.
+ * Complex numbers are interleaved (re, im); complex64 = two float32.
+ *
+ * Memory: every pointer argument named `d_*` is device memory owned by the
+ * caller (the Python binding allocates it with PyTorch).  The library never
+ * allocates device memory; scratch space is the caller's `d_work` buffer of
+ * rrc_workspace_size() bytes.  A plan owns host memory only.
+ *
+ * Streams: `stream` is a hipStream_t passed as void* (NULL = the null
+ * stream).  Device work is enqueued asynchronously; outputs are valid once
+ * the stream reaches that point.  A plan (and its workspace) may be used by
+ * one stream at a time.
+ *
+ * Errors: every int-returning call returns RRC_OK (0) or a negative code
+ * (rrc_strerror() names it).  Invalid arguments are detected on the host
+ * before anything is enqueued.  Numerical outcomes of the solve (not
+ * converged, non-finite data) never fail a call: they are reported per unit
+ * in the `status` output.
+ */
+#ifndef RRCAL_H
+#define RRCAL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ------------------------------------------------------- */
+#define RRC_OK        0
+#define RRC_EINVAL   -1   /* bad argument (NULL pointer, size, type, mode)   */
+#define RRC_EDEGEN   -2   /* selection has more than the four degeneracies  */
+#define RRC_EDEVICE  -3   /* a HIP runtime call failed                       */
+#define RRC_ENOTIMPL -4   /* combination not supported by this build         */
+#define RRC_ERANGE   -5   /* size beyond a documented limit                  */
+
+/* ---- voltage formats ---------------------------------------------------- */
+#define RRC_C64 0   /* complex64 samples, 8 bytes                            */
+#define RRC_CI4 1   /* 4-bit complex, 1 byte = (re << 4) | (im & 0xF), two's
+                       complement nibbles with values in [-7, 7]             */
+
+/* ---- solver options ----------------------------------------------------- */
+#define RRC_INIT_FIRSTCAL 0  /* start from logcal amplitudes + chained phases */
+#define RRC_INIT_GAINS    1  /* start from the caller's gains                 */
+#define RRC_DEGEN_REFANT  0  /* sum ln|g| = 0; antennas (0,0),(1,0),(0,1) real */
+#define RRC_DEGEN_MATCH   1  /* match mean ln|g| and the phase plane of g_ref */
+
+/* per-unit solve status */
+#define RRC_UNIT_CONVERGED 0
+#define RRC_UNIT_MAXITER   1
+#define RRC_UNIT_NONFINITE 2
+
+/* Limits of this build. */
+#define RRC_MAX_TYPES 32     /* K, selected baseline-types                    */
+#define RRC_MAX_GRID  64     /* n; the padded FFT size is M = max(16, 2^ceil(log2 2n)) */
+
+typedef struct rrc_plan rrc_plan;
+
+typedef struct {
+    int32_t init_mode;   /* RRC_INIT_*                                            */
+    int32_t degen_mode;  /* RRC_DEGEN_*                                           */
+    int32_t max_gn;      /* Gauss-Newton steps with an FP32 residual (>= 1)       */
+    int32_t fp64_steps;  /* further steps with the residual in FP64 (>= 0)        */
+    int32_t max_cg;      /* CG iterations per normal-equation solve (>= 1)        */
+    float   cg_tol;      /* CG stops at ||r|| <= cg_tol ||b||                     */
+    float   tol32;       /* FP32 stage stops once the rms log-step is below this  */
+} rrc_solver_opts;
+
+typedef struct {
+    int32_t n;            /* grid side                                   */
+    int32_t n_ant;        /* N = n*n                                     */
+    int32_t fft_size;     /* M, padded spatial FFT size                  */
+    int32_t n_lags;       /* 2 n (n - 1), length of V^unique per unit    */
+    int32_t n_types;      /* K                                           */
+    int32_t n_pairs;      /* P, length of V^reduced per unit             */
+    int32_t dof;          /* P - N - K + 2 (eq. dof)                     */
+    int32_t n_units;      /* U                                           */
+    int32_t n_time;       /* T, samples per integration                  */
+    int32_t dtype;        /* RRC_C64 or RRC_CI4                          */
+    uint64_t workspace_bytes;
+} rrc_plan_info;
+
+/* Default solver options (FIRSTCAL, REFANT, 12 FP32 steps, 2 FP64 steps,
+ * 400 CG iterations, cg_tol 1e-2, tol32 1e-6). */
+void rrc_default_opts(rrc_solver_opts* opts);
+
+/* Subset redundant-calibration selection (Sec. 5.1, Sec. 5.4
+ * eq. subredcal_frac_bls, Sec. 6.1): whole redundant groups in ascending
+ * baseline length (ties: dy, then dx), the prefix whose pair count is
+ * closest to p N log_b N (ties to the shorter prefix), extended until the
+ * degeneracy criterion of Sec. 5.2 holds.  Host only, pure.
+ * Writes K types to `types_xy` (room for `cap` types) and K, P to the outputs.
+ * log_base <= 1 selects the natural logarithm.  RRC_ERANGE if cap < K. */
+int rrc_select_subset(int32_t n, double p, double log_base, int32_t* types_xy,
+                      int32_t cap, int32_t* k_out, int32_t* n_pairs_out);
+
+/* Null-space dimension of the linearised calibration system for a
+ * selection (Sec. 5.2): amplitude part (ln|g|, ln|V|) and phase part
+ * (arg g, arg V).  A valid selection has 1 + 3 = 4.  Host only, pure. */
+int rrc_degeneracy_count(int32_t n, const int32_t* types_xy, int32_t k,
+                         int32_t* n_null_amp, int32_t* n_null_phase);
+
+/* Create a plan for U units of an n x n grid with T samples each.  The
+ * selection must satisfy the degeneracy criterion (else RRC_EDEGEN) and,
+ * for RRC_INIT_FIRSTCAL, contain the types (1,0) and (0,1).  opts may be
+ * NULL (defaults).  n in [2, RRC_MAX_GRID], K in [1, RRC_MAX_TYPES]. */
+int rrc_plan_create(rrc_plan** out, int32_t n, const int32_t* types_xy, int32_t k,
+                    int32_t n_units, int32_t n_time, int32_t dtype,
+                    const rrc_solver_opts* opts);
+void rrc_plan_destroy(rrc_plan* plan);
+int rrc_plan_get_info(const rrc_plan* plan, rrc_plan_info* info);
+int rrc_workspace_size(const rrc_plan* plan, size_t* bytes);
+
+/* (a1)-(a3) FFT-correlator (Fig. 1(b) yellow box; Sec. 2 eq. modelvis).
+ * d_volt:   [U][T][N] voltages (complex64, or 1 byte each for RRC_CI4).
+ * d_gains:  [U][N] complex64 gains g; the voltages are divided by them.
+ * d_vunique:[U][n_lags] complex64, V(d) = C(d) / (N_d T) with C the
+ *           time-integrated autocorrelation of the calibrated voltage grid
+ *           (the convolution theorem, Sec. 1), equal to eq. modelvis.
+ * d_vauto:  [U] float32, C(0) / (N T).  */
+int rrc_fftcorr(rrc_plan* plan, void* stream, const void* d_volt, const void* d_gains,
+                void* d_vunique, float* d_vauto, void* d_work);
+
+/* (a4) Reduced X-engine (Fig. 1(b) blue box): for every selected pair,
+ * V_ij = (1/T) sum_t v_i(t) conj(v_j(t)) on the raw voltages.
+ * d_vred: [U][P] complex64 for RRC_C64; for RRC_CI4 [U][P][2] int32 exact
+ * raw sums (no 1/T). */
+int rrc_xengine(rrc_plan* plan, void* stream, const void* d_volt, void* d_vred, void* d_work);
+
+/* (a5) Reduced redundant calibration (eq. redcal, eq. redchi, eq. dof):
+ * minimise chi^2 = sum_b |V_b - g_i conj(g_j) V_alpha|^2 over the gains and
+ * the K model visibilities, then fix the four degeneracies (Sec. 5.2).
+ * d_vred:      [U][P] as written by rrc_xengine for this plan's dtype.
+ * d_gains_in:  [U][N] complex64 start gains (RRC_INIT_GAINS) or NULL.
+ * d_gains_ref: [U][N] complex64 reference gains (RRC_DEGEN_MATCH) or NULL.
+ * d_gains_out: [U][N] complex64; d_vmodel: [U][K] complex64 (in the units
+ *              of d_vred); d_chisq [U] float32 (computed in FP64);
+ *              d_niter [U] int32 Gauss-Newton steps; d_status [U] int32. */
+int rrc_solve(rrc_plan* plan, void* stream, const void* d_vred, const void* d_gains_in,
+              const void* d_gains_ref, void* d_gains_out, void* d_vmodel, float* d_chisq,
+              int32_t* d_niter, int32_t* d_status, void* d_work);
+
+/* (a5) chi^2 only: d_chisq[u] = sum_b |V_b - g_i conj(g_j) V_alpha|^2 for
+ * complex64 d_g [U][N], d_vm [U][K], d_vred [U][P] (complex64, any dtype
+ * plan; int sums must be converted by the caller).  FP32 products, FP64 sum. */
+int rrc_chisq_fwd(rrc_plan* plan, void* stream, const void* d_g, const void* d_vm,
+                  const void* d_vred, float* d_chisq);
+
+/* (a6) Adjoint of chi^2 (from eq. redchi): the gradient in PyTorch's complex
+ * convention, 2 d chi^2 / d conj(z), for z = g ([U][N]) and z = V ([U][K]):
+ *   2 dchi2/dconj(g_i) = -2 [ sum_{(i,j)} r_b g_j conj(V_a) + sum_{(k,i)} conj(r_b) g_k V_b' ]
+ *   2 dchi2/dconj(V_a) = -2 sum_{b in a} r_b conj(g_i) g_j
+ * with r_b = V_b - g_i conj(g_j) V_alpha, and the diagonal of J^H J:
+ *   diag_g_i = sum_{(i,j)} |g_j V_a|^2 + sum_{(k,i)} |g_k V_b'|^2,
+ *   diag_v_a = sum_{b in a} |g_i g_j|^2.
+ * Outputs complex64 d_grad_g [U][N], d_grad_v [U][K], float32 d_diag_g
+ * [U][N], d_diag_v [U][K]; any output pointer may be NULL to skip it. */
+int rrc_chisq_adj(rrc_plan* plan, void* stream, const void* d_g, const void* d_vm,
+                  const void* d_vred, void* d_grad_g, void* d_grad_v, float* d_diag_g,
+                  float* d_diag_v);
+
+/* The whole hot path for one integration of U units.
+ * mode RRC_RUN_PIPELINED: the FFT-correlator applies d_gains_in (the
+ *   previous integration's solution, Fig. 1 real-time loop) while the
+ *   X-engine and the solve run on the same voltages; the solved gains are
+ *   for the next integration.
+ * mode RRC_RUN_SELFCAL: X-engine, solve, then the FFT-correlator applies the
+ *   just-solved gains (reads the voltages twice).
+ * Outputs as in the calls above; d_gains_in may be NULL in SELFCAL mode. */
+#define RRC_RUN_PIPELINED 1
+#define RRC_RUN_SELFCAL   2
+typedef struct {
+    const void* d_volt;
+    const void* d_gains_in;
+    const void* d_gains_ref;
+    void*    d_vunique;
+    float*   d_vauto;
+    void*    d_vred;
+    void*    d_gains_out;
+    void*    d_vmodel;
+    float*   d_chisq;
+    int32_t* d_niter;
+    int32_t* d_status;
+    void*    d_work;
+} rrc_io;
+int rrc_run(rrc_plan* plan, void* stream, int32_t mode, const rrc_io* io);
+
+const char* rrc_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RRCAL_H */

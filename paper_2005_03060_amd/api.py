@@ -1,0 +1,234 @@
+"""Python surface over the C-ABI: argument marshalling only.
+
+Every step of the path runs in the HIP kernels of librrcal.so; PyTorch
+provides device memory (all buffers, including the workspace) and the
+current stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Dict, Optional, Sequence, Tuple
+
+import torch
+
+from . import _lib as L
+
+
+def _stream() -> C.c_void_p:
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _types_array(types: Sequence[Tuple[int, int]]):
+    flat = [int(v) for d in types for v in d]
+    return (C.c_int32 * max(1, len(flat)))(*flat)
+
+
+def select_subset(n: int, p: float = 1.0, log_base: float = 0.0):
+    """Subset selection rule (host only): returns (types, n_pairs)."""
+    lib = L.load_library()
+    buf = (C.c_int32 * (2 * L.RRC_MAX_TYPES))()
+    k, npairs = C.c_int32(), C.c_int32()
+    L.check(lib.rrc_select_subset(n, p, log_base, buf, L.RRC_MAX_TYPES, C.byref(k), C.byref(npairs)),
+            "rrc_select_subset")
+    return [(buf[2 * t], buf[2 * t + 1]) for t in range(k.value)], npairs.value
+
+
+def degeneracy_count(n: int, types: Sequence[Tuple[int, int]]):
+    """(amplitude, phase) null-space dimensions of a selection (host only)."""
+    lib = L.load_library()
+    na, nph = C.c_int32(), C.c_int32()
+    L.check(lib.rrc_degeneracy_count(n, _types_array(types), len(types), C.byref(na), C.byref(nph)),
+            "rrc_degeneracy_count")
+    return na.value, nph.value
+
+
+def default_opts() -> Dict[str, float]:
+    lib = L.load_library()
+    o = L.SolverOpts()
+    lib.rrc_default_opts(C.byref(o))
+    return {f: getattr(o, f) for f, _ in L.SolverOpts._fields_}
+
+
+class Plan:
+    """A plan for U units (channels) of an n x n grid with T samples each."""
+
+    def __init__(self, n: int, types: Sequence[Tuple[int, int]], n_units: int, n_time: int,
+                 dtype: str = "c64", **opts):
+        self._lib = L.load_library()
+        self.n = n
+        self.types = [tuple(int(v) for v in t) for t in types]
+        self.dtype = {"c64": L.RRC_C64, "ci4": L.RRC_CI4}[dtype]
+        o = L.SolverOpts()
+        self._lib.rrc_default_opts(C.byref(o))
+        names = {"init_mode": {"firstcal": L.RRC_INIT_FIRSTCAL, "gains": L.RRC_INIT_GAINS},
+                 "degen_mode": {"refant": L.RRC_DEGEN_REFANT, "match": L.RRC_DEGEN_MATCH}}
+        for key, val in opts.items():
+            if key in names and isinstance(val, str):
+                val = names[key][val]
+            setattr(o, key, val)
+        self.opts = o
+        h = C.c_void_p()
+        L.check(self._lib.rrc_plan_create(C.byref(h), n, _types_array(self.types), len(self.types),
+                                          n_units, n_time, self.dtype, C.byref(o)), "rrc_plan_create")
+        self._h = h
+        info = L.PlanInfo()
+        L.check(self._lib.rrc_plan_get_info(h, C.byref(info)), "rrc_plan_get_info")
+        self.info = {f: getattr(info, f) for f, _ in L.PlanInfo._fields_}
+        self.n_ant = info.n_ant
+        self.n_pairs = info.n_pairs
+        self.n_lags = info.n_lags
+        self.n_units = n_units
+        self.n_time = n_time
+        self.dof = info.dof
+        self._ws: Optional[torch.Tensor] = None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._lib.rrc_plan_destroy(h)
+            self._h = None
+
+    # ------------------------------------------------------------ helpers
+    def workspace(self, device="cuda") -> torch.Tensor:
+        nb = int(self.info["workspace_bytes"])
+        if self._ws is None or self._ws.device != torch.device(device) or self._ws.numel() < nb:
+            self._ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=device)
+        return self._ws
+
+    def _check_volt(self, volt: torch.Tensor):
+        shape = (self.n_units, self.n_time, self.n_ant)
+        want = torch.complex64 if self.dtype == L.RRC_C64 else torch.uint8
+        if tuple(volt.shape) != shape or volt.dtype != want or not volt.is_cuda or not volt.is_contiguous():
+            raise ValueError(f"volt must be a contiguous {want} CUDA tensor of shape {shape}, "
+                             f"got {volt.dtype} {tuple(volt.shape)} on {volt.device}")
+
+    def _check_c64(self, t: Optional[torch.Tensor], shape, name):
+        if t is None:
+            return
+        if tuple(t.shape) != tuple(shape) or t.dtype != torch.complex64 or not t.is_cuda or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous complex64 CUDA tensor of shape {tuple(shape)}")
+
+    def vred_like(self, device) -> torch.Tensor:
+        if self.dtype == L.RRC_CI4:
+            return torch.empty((self.n_units, self.n_pairs, 2), dtype=torch.int32, device=device)
+        return torch.empty((self.n_units, self.n_pairs), dtype=torch.complex64, device=device)
+
+    # -------------------------------------------------------------- calls
+    def fftcorr(self, volt: torch.Tensor, gains: torch.Tensor):
+        """(a1)-(a3): returns (V^unique [U, n_lags] complex64, V_auto [U] float32)."""
+        self._check_volt(volt)
+        self._check_c64(gains, (self.n_units, self.n_ant), "gains")
+        vu = torch.empty((self.n_units, self.n_lags), dtype=torch.complex64, device=volt.device)
+        va = torch.empty((self.n_units,), dtype=torch.float32, device=volt.device)
+        L.check(self._lib.rrc_fftcorr(self._h, _stream(), _ptr(volt), _ptr(gains), _ptr(vu), _ptr(va),
+                                      _ptr(self.workspace(volt.device))), "rrc_fftcorr")
+        return vu, va
+
+    def xengine(self, volt: torch.Tensor) -> torch.Tensor:
+        """(a4): V^reduced [U, P] complex64, or [U, P, 2] int32 raw sums for 4-bit data."""
+        self._check_volt(volt)
+        vr = self.vred_like(volt.device)
+        L.check(self._lib.rrc_xengine(self._h, _stream(), _ptr(volt), _ptr(vr),
+                                      _ptr(self.workspace(volt.device))), "rrc_xengine")
+        return vr
+
+    def solve(self, vred: torch.Tensor, gains_in: Optional[torch.Tensor] = None,
+              gains_ref: Optional[torch.Tensor] = None) -> Dict[str, torch.Tensor]:
+        """(a5): gains [U, N], vmodel [U, K], chisq [U], niter [U], status [U]."""
+        dev = vred.device
+        want = self.vred_like(dev)
+        if tuple(vred.shape) != tuple(want.shape) or vred.dtype != want.dtype or not vred.is_contiguous():
+            raise ValueError(f"vred must be contiguous {want.dtype} of shape {tuple(want.shape)}")
+        self._check_c64(gains_in, (self.n_units, self.n_ant), "gains_in")
+        self._check_c64(gains_ref, (self.n_units, self.n_ant), "gains_ref")
+        out = dict(gains=torch.empty((self.n_units, self.n_ant), dtype=torch.complex64, device=dev),
+                   vmodel=torch.empty((self.n_units, len(self.types)), dtype=torch.complex64, device=dev),
+                   chisq=torch.empty((self.n_units,), dtype=torch.float32, device=dev),
+                   niter=torch.empty((self.n_units,), dtype=torch.int32, device=dev),
+                   status=torch.empty((self.n_units,), dtype=torch.int32, device=dev))
+        L.check(self._lib.rrc_solve(self._h, _stream(), _ptr(vred), _ptr(gains_in), _ptr(gains_ref),
+                                    _ptr(out["gains"]), _ptr(out["vmodel"]), _ptr(out["chisq"]),
+                                    _ptr(out["niter"]), _ptr(out["status"]), _ptr(self.workspace(dev))),
+                "rrc_solve")
+        return out
+
+    def chisq_fwd(self, g, vm, vred) -> torch.Tensor:
+        self._check_c64(g, (self.n_units, self.n_ant), "g")
+        self._check_c64(vm, (self.n_units, len(self.types)), "vm")
+        self._check_c64(vred, (self.n_units, self.n_pairs), "vred")
+        out = torch.empty((self.n_units,), dtype=torch.float32, device=g.device)
+        L.check(self._lib.rrc_chisq_fwd(self._h, _stream(), _ptr(g), _ptr(vm), _ptr(vred), _ptr(out)),
+                "rrc_chisq_fwd")
+        return out
+
+    def chisq_adj(self, g, vm, vred):
+        """(a6): (2 dchi2/dconj(g), 2 dchi2/dconj(V), diag_g, diag_v)."""
+        self._check_c64(g, (self.n_units, self.n_ant), "g")
+        self._check_c64(vm, (self.n_units, len(self.types)), "vm")
+        self._check_c64(vred, (self.n_units, self.n_pairs), "vred")
+        gg = torch.empty_like(g)
+        gv = torch.empty_like(vm)
+        dg = torch.empty(g.shape, dtype=torch.float32, device=g.device)
+        dv = torch.empty(vm.shape, dtype=torch.float32, device=g.device)
+        L.check(self._lib.rrc_chisq_adj(self._h, _stream(), _ptr(g), _ptr(vm), _ptr(vred), _ptr(gg),
+                                        _ptr(gv), _ptr(dg), _ptr(dv)), "rrc_chisq_adj")
+        return gg, gv, dg, dv
+
+    def run(self, volt: torch.Tensor, gains_in: Optional[torch.Tensor] = None,
+            gains_ref: Optional[torch.Tensor] = None, mode: str = "pipelined",
+            out: Optional[Dict[str, torch.Tensor]] = None) -> Dict[str, torch.Tensor]:
+        """The whole hot path (rrc_run); `out` may supply preallocated outputs."""
+        self._check_volt(volt)
+        self._check_c64(gains_in, (self.n_units, self.n_ant), "gains_in")
+        self._check_c64(gains_ref, (self.n_units, self.n_ant), "gains_ref")
+        dev = volt.device
+        if out is None:
+            out = self.alloc_outputs(dev)
+        io = L.RunIO(_ptr(volt), _ptr(gains_in), _ptr(gains_ref), _ptr(out["vunique"]), _ptr(out["vauto"]),
+                     _ptr(out["vred"]), _ptr(out["gains"]), _ptr(out["vmodel"]), _ptr(out["chisq"]),
+                     _ptr(out["niter"]), _ptr(out["status"]), _ptr(self.workspace(dev)))
+        m = {"pipelined": L.RRC_RUN_PIPELINED, "selfcal": L.RRC_RUN_SELFCAL}[mode]
+        L.check(self._lib.rrc_run(self._h, _stream(), m, C.byref(io)), "rrc_run")
+        return out
+
+    def alloc_outputs(self, device) -> Dict[str, torch.Tensor]:
+        U = self.n_units
+        return dict(vunique=torch.empty((U, self.n_lags), dtype=torch.complex64, device=device),
+                    vauto=torch.empty((U,), dtype=torch.float32, device=device),
+                    vred=self.vred_like(device),
+                    gains=torch.empty((U, self.n_ant), dtype=torch.complex64, device=device),
+                    vmodel=torch.empty((U, len(self.types)), dtype=torch.complex64, device=device),
+                    chisq=torch.empty((U,), dtype=torch.float32, device=device),
+                    niter=torch.empty((U,), dtype=torch.int32, device=device),
+                    status=torch.empty((U,), dtype=torch.int32, device=device))
+
+
+class ChiSq(torch.autograd.Function):
+    """chi^2 per unit with the hand-written adjoint as its backward.
+
+    backward returns grad_out * 2 dchi2/dconj(z), PyTorch's convention for
+    the gradient of a real function of complex inputs.
+    """
+
+    @staticmethod
+    def forward(ctx, g, vm, vred, plan):
+        ctx.plan = plan
+        ctx.save_for_backward(g, vm, vred)
+        return plan.chisq_fwd(g.detach().contiguous(), vm.detach().contiguous(), vred.detach().contiguous())
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        g, vm, vred = ctx.saved_tensors
+        gg, gv, _, _ = ctx.plan.chisq_adj(g.detach().contiguous(), vm.detach().contiguous(),
+                                          vred.detach().contiguous())
+        go = grad_out.to(torch.float32)
+        return gg * go[:, None], gv * go[:, None], None, None
+
+
+def chisq(g: torch.Tensor, vm: torch.Tensor, vred: torch.Tensor, plan: Plan) -> torch.Tensor:
+    """Differentiable chi^2 (per unit) of eq. redchi with uniform noise."""
+    return ChiSq.apply(g, vm, vred, plan)

@@ -1,0 +1,454 @@
+// The C-ABI of include/rrcal.h: plans, the subset selection rule, the
+// degeneracy count, argument checking and kernel dispatch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/rrcal.h"
+#include "rrc_launch.h"
+
+using rrc::Sel;
+
+struct rrc_plan {
+    Sel sel;
+    int M;
+    int nlag;
+    int U, T, dtype;
+    rrc_solver_opts opts;
+    // FFT-correlator
+    int fft_tchunk, fft_nchunk;
+    // X-engine
+    int x_tchunk, x_nchunk, x_ppt, x_npblk, x_xs;
+    // solver
+    bool solve_lds;
+    size_t solve_lds_bytes, slab_bytes;
+    // workspace layout
+    size_t off_fft, off_x, off_slab, ws_bytes;
+};
+
+namespace {
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+struct Type {
+    int dx, dy;
+};
+
+// Canonical types of an n x n grid sorted by (|d|^2, dy, dx).
+std::vector<Type> sorted_types(int n) {
+    std::vector<Type> t;
+    for (int dy = 0; dy < n; ++dy)
+        for (int dx = -(n - 1); dx < n; ++dx)
+            if (dy > 0 || dx > 0) t.push_back({dx, dy});
+    std::sort(t.begin(), t.end(), [](const Type& a, const Type& b) {
+        const int la = a.dx * a.dx + a.dy * a.dy, lb = b.dx * b.dx + b.dy * b.dy;
+        if (la != lb) return la < lb;
+        if (a.dy != b.dy) return a.dy < b.dy;
+        return a.dx < b.dx;
+    });
+    return t;
+}
+
+int group_size(int n, int dx, int dy) { return (n - std::abs(dx)) * (n - std::abs(dy)); }
+
+bool valid_type(int n, int dx, int dy) {
+    if (std::abs(dx) >= n || dy < 0 || dy >= n) return false;
+    return dy > 0 || dx > 0;
+}
+
+// Null-space dimension of the normal matrix of a system whose rows are
+// e_i + s e_j + e_{N+t} (s = +1 amplitude, -1 phase) over all selected
+// pairs.  The matrix is assembled in skyline (profile) storage with the
+// antennas in raster order and the K type unknowns last, and factored as
+// L D L^T without pivoting; a positive semi-definite matrix meets a zero
+// pivot exactly on each null direction, counted against a relative
+// tolerance.
+int normal_nullity(int n, const std::vector<Type>& sel, int sign) {
+    const int N = n * n, K = (int)sel.size(), V = N + K;
+    int bw = 0;
+    for (const Type& t : sel) bw = std::max(bw, t.dy * n + std::abs(t.dx));
+    std::vector<int> first(V);
+    for (int r = 0; r < V; ++r) first[r] = r < N ? std::max(0, r - bw) : 0;
+    std::vector<size_t> start(V + 1, 0);
+    for (int r = 0; r < V; ++r) start[r + 1] = start[r] + (size_t)(r - first[r] + 1);
+    std::vector<double> A(start[V], 0.0);
+    auto at = [&](int r, int c) -> double& {      // c <= r, c >= first[r]
+        return A[start[r] + (size_t)(c - first[r])];
+    };
+    for (int t = 0; t < K; ++t) {
+        const int dx = sel[t].dx, dy = sel[t].dy;
+        for (int y = 0; y < n; ++y)
+            for (int x = 0; x < n; ++x) {
+                const int jx = x - dx, jy = y - dy;
+                if (jx < 0 || jx >= n || jy < 0 || jy >= n) continue;
+                const int i = y * n + x, j = jy * n + jx;
+                const int idx[3] = {i, j, N + t};
+                const double cf[3] = {1.0, (double)sign, 1.0};
+                for (int p = 0; p < 3; ++p)
+                    for (int q = 0; q <= p; ++q) {
+                        int r = idx[p], c = idx[q];
+                        if (c > r) std::swap(r, c);
+                        at(r, c) += cf[p] * cf[q];
+                    }
+            }
+    }
+    // the loop above adds the off-diagonal once per unordered (p, q); the
+    // diagonal terms (p == q) once as well -- which is A^T A exactly.
+    std::vector<double> D(V, 0.0), diag0(V);
+    for (int r = 0; r < V; ++r) diag0[r] = at(r, r);
+    int null = 0;
+    for (int r = 0; r < V; ++r) {
+        const int fr = first[r];
+        for (int c = fr; c < r; ++c) {
+            const int lo = std::max(fr, first[c]);
+            double s = at(r, c);
+            for (int k = lo; k < c; ++k) s -= at(r, k) * D[k] * at(c, k);
+            at(r, c) = (D[c] != 0.0) ? s / D[c] : 0.0;
+        }
+        double d = at(r, r);
+        for (int k = fr; k < r; ++k) d -= at(r, k) * at(r, k) * D[k];
+        if (d <= 1e-9 * std::max(1.0, diag0[r])) {
+            ++null;
+            d = 0.0;
+        }
+        D[r] = d;
+        at(r, r) = 1.0;
+    }
+    return null;
+}
+
+int build_sel(int n, const int32_t* types_xy, int k, Sel& s) {
+    if (n < 2 || n > RRC_MAX_GRID || k < 1 || k > RRC_MAX_TYPES || !types_xy) return RRC_EINVAL;
+    std::memset(&s, 0, sizeof(s));
+    s.n = n;
+    s.N = n * n;
+    s.K = k;
+    int off = 0;
+    for (int t = 0; t < k; ++t) {
+        const int dx = types_xy[2 * t], dy = types_xy[2 * t + 1];
+        if (!valid_type(n, dx, dy)) return RRC_EINVAL;
+        for (int u = 0; u < t; ++u)
+            if (s.dx[u] == dx && s.dy[u] == dy) return RRC_EINVAL;
+        s.dx[t] = dx;
+        s.dy[t] = dy;
+        s.off[t] = off;
+        off += group_size(n, dx, dy);
+    }
+    s.off[k] = off;
+    s.P = off;
+    return RRC_OK;
+}
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+int ceil_div(long a, long b) { return (int)((a + b - 1) / b); }
+
+}  // namespace
+
+extern "C" {
+
+void rrc_default_opts(rrc_solver_opts* o) {
+    if (!o) return;
+    o->init_mode = RRC_INIT_FIRSTCAL;
+    o->degen_mode = RRC_DEGEN_REFANT;
+    o->max_gn = 12;
+    o->fp64_steps = 2;
+    o->max_cg = 400;
+    o->cg_tol = 1e-2f;
+    o->tol32 = 1e-6f;
+}
+
+const char* rrc_strerror(int code) {
+    switch (code) {
+        case RRC_OK: return "ok";
+        case RRC_EINVAL: return "invalid argument";
+        case RRC_EDEGEN: return "selection has more than the four redundant-calibration degeneracies";
+        case RRC_EDEVICE: return "HIP runtime error";
+        case RRC_ENOTIMPL: return "not implemented";
+        case RRC_ERANGE: return "size beyond a limit";
+        default: return "unknown error";
+    }
+}
+
+int rrc_degeneracy_count(int32_t n, const int32_t* types_xy, int32_t k, int32_t* n_null_amp,
+                         int32_t* n_null_phase) {
+    Sel s;
+    const int rc = build_sel(n, types_xy, k, s);
+    if (rc != RRC_OK) return rc;
+    if (!n_null_amp || !n_null_phase) return RRC_EINVAL;
+    std::vector<Type> sel(k);
+    for (int t = 0; t < k; ++t) sel[t] = {s.dx[t], s.dy[t]};
+    *n_null_amp = normal_nullity(n, sel, +1);
+    *n_null_phase = normal_nullity(n, sel, -1);
+    return RRC_OK;
+}
+
+int rrc_select_subset(int32_t n, double p, double log_base, int32_t* types_xy, int32_t cap,
+                      int32_t* k_out, int32_t* n_pairs_out) {
+    if (n < 2 || n > RRC_MAX_GRID || !(p > 0.0) || !types_xy || !k_out || !n_pairs_out)
+        return RRC_EINVAL;
+    const std::vector<Type> all = sorted_types(n);
+    const double N = (double)n * n;
+    const double lg = (log_base > 1.0) ? std::log(N) / std::log(log_base) : std::log(N);
+    const double budget = p * N * lg;
+    long cum = 0;
+    int best = 1;
+    double best_d = 1e300;
+    for (size_t t = 0; t < all.size(); ++t) {
+        cum += group_size(n, all[t].dx, all[t].dy);
+        const double d = std::fabs((double)cum - budget);
+        if (d < best_d) {
+            best_d = d;
+            best = (int)t + 1;
+        }
+    }
+    int k = best;
+    std::vector<int32_t> xy;
+    while (true) {
+        xy.clear();
+        for (int t = 0; t < k; ++t) {
+            xy.push_back(all[t].dx);
+            xy.push_back(all[t].dy);
+        }
+        if (k > RRC_MAX_TYPES) return RRC_ERANGE;
+        int32_t na = 0, np = 0;
+        const int rc = rrc_degeneracy_count(n, xy.data(), k, &na, &np);
+        if (rc != RRC_OK) return rc;
+        if (na + np == 4) break;
+        if (k >= (int)all.size()) return RRC_EDEGEN;
+        ++k;
+    }
+    if (k > cap) return RRC_ERANGE;
+    long pairs = 0;
+    for (int t = 0; t < k; ++t) {
+        types_xy[2 * t] = all[t].dx;
+        types_xy[2 * t + 1] = all[t].dy;
+        pairs += group_size(n, all[t].dx, all[t].dy);
+    }
+    *k_out = k;
+    *n_pairs_out = (int32_t)pairs;
+    return RRC_OK;
+}
+
+int rrc_plan_create(rrc_plan** out, int32_t n, const int32_t* types_xy, int32_t k,
+                    int32_t n_units, int32_t n_time, int32_t dtype, const rrc_solver_opts* opts) {
+    if (!out) return RRC_EINVAL;
+    *out = nullptr;
+    Sel s;
+    int rc = build_sel(n, types_xy, k, s);
+    if (rc != RRC_OK) return rc;
+    if (n_units < 1 || n_time < 1 || (dtype != RRC_C64 && dtype != RRC_CI4)) return RRC_EINVAL;
+    if (dtype == RRC_CI4 && (long)n_time * 98L > 2147483647L) return RRC_ERANGE;
+    rrc_solver_opts o;
+    rrc_default_opts(&o);
+    if (opts) o = *opts;
+    if (o.max_gn < 1 || o.fp64_steps < 0 || o.max_cg < 1 || !(o.cg_tol > 0.f) ||
+        (o.init_mode != RRC_INIT_FIRSTCAL && o.init_mode != RRC_INIT_GAINS) ||
+        (o.degen_mode != RRC_DEGEN_REFANT && o.degen_mode != RRC_DEGEN_MATCH))
+        return RRC_EINVAL;
+    bool has10 = false, has01 = false;
+    for (int t = 0; t < k; ++t) {
+        has10 |= (s.dx[t] == 1 && s.dy[t] == 0);
+        has01 |= (s.dx[t] == 0 && s.dy[t] == 1);
+    }
+    if (o.init_mode == RRC_INIT_FIRSTCAL && !(has10 && has01)) return RRC_EINVAL;
+    int32_t na = 0, np = 0;
+    rc = rrc_degeneracy_count(n, types_xy, k, &na, &np);
+    if (rc != RRC_OK) return rc;
+    if (na + np != 4) return RRC_EDEGEN;
+
+    rrc_plan* p = new (std::nothrow) rrc_plan();
+    if (!p) return RRC_ERANGE;
+    p->sel = s;
+    int M = 16;                      // smallest transform the kernels instantiate
+    while (M < 2 * n) M *= 2;
+    p->M = M;
+    p->nlag = 2 * n * (n - 1);
+    p->U = n_units;
+    p->T = n_time;
+    p->dtype = dtype;
+    p->opts = o;
+
+    // FFT-correlator: aim for >= 2048 workgroups, each doing >= 4 steps
+    const int S = rrc::fft_samples_per_step_for(M);
+    int nch = std::max(1, std::min(ceil_div(2048, n_units), n_time / (4 * S)));
+    int tch = ceil_div(ceil_div(n_time, nch), S) * S;
+    p->fft_tchunk = tch;
+    p->fft_nchunk = ceil_div(n_time, tch);
+
+    // X-engine
+    p->x_ppt = s.P <= 1024 ? 4 : (s.P <= 2048 ? 8 : 16);
+    p->x_npblk = ceil_div(s.P, 256 * p->x_ppt);
+    const int bytes_per = dtype == RRC_CI4 ? 1 : 8;
+    p->x_xs = std::max(1, 32768 / (s.N * bytes_per));
+    const long wg = (long)n_units * p->x_npblk;
+    int xn = std::max(1, std::min(ceil_div(2048, wg), n_time / (4 * p->x_xs)));
+    int xt = ceil_div(ceil_div(n_time, xn), p->x_xs) * p->x_xs;
+    p->x_tchunk = xt;
+    p->x_nchunk = ceil_div(n_time, xt);
+
+    // solver
+    const size_t hot = rrc::solve_hot_bytes(s);
+    p->solve_lds = hot <= 150 * 1024;
+    p->solve_lds_bytes = rrc::solve_lds_bytes(s, p->solve_lds);
+    p->slab_bytes = align256(rrc::solve_slab_bytes(s, p->solve_lds));
+
+    size_t off = 0;
+    p->off_fft = off;
+    off = align256(off + (size_t)n_units * p->fft_nchunk * M * M * sizeof(float));
+    p->off_x = off;
+    off = align256(off + (size_t)n_units * p->x_nchunk * s.P * 8);
+    p->off_slab = off;
+    off = align256(off + (size_t)n_units * p->slab_bytes);
+    p->ws_bytes = off;
+    *out = p;
+    return RRC_OK;
+}
+
+void rrc_plan_destroy(rrc_plan* p) { delete p; }
+
+int rrc_plan_get_info(const rrc_plan* p, rrc_plan_info* info) {
+    if (!p || !info) return RRC_EINVAL;
+    info->n = p->sel.n;
+    info->n_ant = p->sel.N;
+    info->fft_size = p->M;
+    info->n_lags = p->nlag;
+    info->n_types = p->sel.K;
+    info->n_pairs = p->sel.P;
+    info->dof = p->sel.P - p->sel.N - p->sel.K + 2;
+    info->n_units = p->U;
+    info->n_time = p->T;
+    info->dtype = p->dtype;
+    info->workspace_bytes = p->ws_bytes;
+    return RRC_OK;
+}
+
+int rrc_workspace_size(const rrc_plan* p, size_t* bytes) {
+    if (!p || !bytes) return RRC_EINVAL;
+    *bytes = p->ws_bytes;
+    return RRC_OK;
+}
+
+int rrc_fftcorr(rrc_plan* p, void* stream, const void* d_volt, const void* d_gains, void* d_vunique,
+                float* d_vauto, void* d_work) {
+    if (!p || !d_volt || !d_gains || !d_vunique || !d_vauto || !d_work) return RRC_EINVAL;
+    rrc::FftLaunch L;
+    L.M = p->M;
+    L.n = p->sel.n;
+    L.T = p->T;
+    L.n_units = p->U;
+    L.tchunk = p->fft_tchunk;
+    L.nchunk = p->fft_nchunk;
+    L.ci4 = p->dtype == RRC_CI4;
+    L.volt = d_volt;
+    L.gains = reinterpret_cast<const float2*>(d_gains);
+    L.ppart = reinterpret_cast<float*>(static_cast<char*>(d_work) + p->off_fft);
+    L.vunique = reinterpret_cast<float2*>(d_vunique);
+    L.vauto = d_vauto;
+    return rrc::launch_fftcorr(L, as_stream(stream)) == hipSuccess ? RRC_OK : RRC_EDEVICE;
+}
+
+int rrc_xengine(rrc_plan* p, void* stream, const void* d_volt, void* d_vred, void* d_work) {
+    if (!p || !d_volt || !d_vred || !d_work) return RRC_EINVAL;
+    rrc::XengLaunch L;
+    L.sel = p->sel;
+    L.T = p->T;
+    L.n_units = p->U;
+    L.tchunk = p->x_tchunk;
+    L.nchunk = p->x_nchunk;
+    L.ppt = p->x_ppt;
+    L.npblk = p->x_npblk;
+    L.xs = p->x_xs;
+    L.ci4 = p->dtype == RRC_CI4;
+    L.volt = d_volt;
+    L.vpart = static_cast<char*>(d_work) + p->off_x;
+    L.vred = d_vred;
+    return rrc::launch_xengine(L, as_stream(stream)) == hipSuccess ? RRC_OK : RRC_EDEVICE;
+}
+
+int rrc_solve(rrc_plan* p, void* stream, const void* d_vred, const void* d_gains_in,
+              const void* d_gains_ref, void* d_gains_out, void* d_vmodel, float* d_chisq,
+              int32_t* d_niter, int32_t* d_status, void* d_work) {
+    if (!p || !d_vred || !d_gains_out || !d_vmodel || !d_chisq || !d_niter || !d_status || !d_work)
+        return RRC_EINVAL;
+    if (p->opts.init_mode == RRC_INIT_GAINS && !d_gains_in) return RRC_EINVAL;
+    if (p->opts.degen_mode == RRC_DEGEN_MATCH && !d_gains_ref) return RRC_EINVAL;
+    rrc::SolveLaunch L;
+    L.sel = p->sel;
+    L.n_units = p->U;
+    L.ci4 = p->dtype == RRC_CI4;
+    L.lds = p->solve_lds;
+    L.lds_bytes = p->solve_lds_bytes;
+    L.slab_bytes = p->slab_bytes;
+    L.o = {p->opts.init_mode, p->opts.degen_mode, p->opts.max_gn, p->opts.fp64_steps,
+           p->opts.max_cg, p->opts.cg_tol, p->opts.tol32};
+    L.vred = d_vred;
+    L.gains_in = reinterpret_cast<const float2*>(d_gains_in);
+    L.gains_ref = reinterpret_cast<const float2*>(d_gains_ref);
+    L.gains_out = reinterpret_cast<float2*>(d_gains_out);
+    L.vmodel = reinterpret_cast<float2*>(d_vmodel);
+    L.chisq = d_chisq;
+    L.niter = d_niter;
+    L.status = d_status;
+    L.slab = static_cast<char*>(d_work) + p->off_slab;
+    return rrc::launch_solve(L, as_stream(stream)) == hipSuccess ? RRC_OK : RRC_EDEVICE;
+}
+
+static int chisq_common(rrc_plan* p, void* stream, const void* d_g, const void* d_vm,
+                        const void* d_vred, float* d_chisq, void* d_grad_g, void* d_grad_v,
+                        float* d_diag_g, float* d_diag_v, bool adj) {
+    if (!p || !d_g || !d_vm || !d_vred) return RRC_EINVAL;
+    if (!adj && !d_chisq) return RRC_EINVAL;
+    rrc::ChisqLaunch L;
+    L.sel = p->sel;
+    L.n_units = p->U;
+    L.g = reinterpret_cast<const float2*>(d_g);
+    L.vm = reinterpret_cast<const float2*>(d_vm);
+    L.vred = reinterpret_cast<const float2*>(d_vred);
+    L.chisq = d_chisq;
+    L.grad_g = reinterpret_cast<float2*>(d_grad_g);
+    L.grad_v = reinterpret_cast<float2*>(d_grad_v);
+    L.diag_g = d_diag_g;
+    L.diag_v = d_diag_v;
+    return rrc::launch_chisq(L, as_stream(stream), adj) == hipSuccess ? RRC_OK : RRC_EDEVICE;
+}
+
+int rrc_chisq_fwd(rrc_plan* p, void* stream, const void* d_g, const void* d_vm, const void* d_vred,
+                  float* d_chisq) {
+    return chisq_common(p, stream, d_g, d_vm, d_vred, d_chisq, nullptr, nullptr, nullptr, nullptr,
+                        false);
+}
+
+int rrc_chisq_adj(rrc_plan* p, void* stream, const void* d_g, const void* d_vm, const void* d_vred,
+                  void* d_grad_g, void* d_grad_v, float* d_diag_g, float* d_diag_v) {
+    return chisq_common(p, stream, d_g, d_vm, d_vred, nullptr, d_grad_g, d_grad_v, d_diag_g,
+                        d_diag_v, true);
+}
+
+int rrc_run(rrc_plan* p, void* stream, int32_t mode, const rrc_io* io) {
+    if (!p || !io) return RRC_EINVAL;
+    if (mode != RRC_RUN_PIPELINED && mode != RRC_RUN_SELFCAL) return RRC_EINVAL;
+    if (mode == RRC_RUN_PIPELINED && !io->d_gains_in) return RRC_EINVAL;
+    int rc = rrc_xengine(p, stream, io->d_volt, io->d_vred, io->d_work);
+    if (rc != RRC_OK) return rc;
+    if (mode == RRC_RUN_PIPELINED) {
+        rc = rrc_fftcorr(p, stream, io->d_volt, io->d_gains_in, io->d_vunique, io->d_vauto,
+                         io->d_work);
+        if (rc != RRC_OK) return rc;
+    }
+    rc = rrc_solve(p, stream, io->d_vred, io->d_gains_in, io->d_gains_ref, io->d_gains_out,
+                   io->d_vmodel, io->d_chisq, io->d_niter, io->d_status, io->d_work);
+    if (rc != RRC_OK) return rc;
+    if (mode == RRC_RUN_SELFCAL) {
+        rc = rrc_fftcorr(p, stream, io->d_volt, io->d_gains_out, io->d_vunique, io->d_vauto,
+                         io->d_work);
+    }
+    return rc;
+}
+
+}  // extern "C"

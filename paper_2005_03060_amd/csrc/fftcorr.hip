@@ -1,0 +1,259 @@
+// (a1)-(a3) FFT-correlator: gain application, zero-padded 2-D spatial FFT
+// per sample, |E|^2 integrated over time, inverse transform and redundant
+// normalisation (Fig. 1(b) yellow box; eq. modelvis; convolution theorem of
+// Sec. 1).
+//
+// Pass 1 (k_fftcorr): one workgroup owns one unit and one chunk of samples.
+// It processes S samples per step.  Row stage: thread (s, y, h) loads row y
+// of sample s (n voltages) straight from HBM, divides by the gains, and
+// computes the h-th half of that row's M-point transform: because only the
+// first n <= M/2 inputs are non-zero, E(2m) is the M/2-point FFT of x_k and
+// E(2m+1) the M/2-point FFT of x_k w_M^k, so each half is independent.  The
+// halves go to an LDS row buffer.  Column stage: thread (u, h') takes column
+// u of two samples and does the same half-split transform over y, squaring
+// and accumulating |E|^2 in registers across the whole chunk.  Partial power
+// grids are reduced in LDS and written once per workgroup.
+//
+// Pass 2 (k_fftfin): one workgroup per unit sums the partial grids in a
+// fixed order and evaluates C(d) = (1/M^2) sum_u P(u) e^{+2 pi i u.d/M} only
+// at the 2n-1 x n lags it needs (separable direct DFT, x then y), then
+// V(d) = C(d) / (N_d T).
+#include "rrc_device.h"
+#include "rrc_launch.h"
+
+namespace rrc {
+
+template <int M> struct FftCfg;
+template <> struct FftCfg<16>  { static constexpr int S = 16; };
+template <> struct FftCfg<32>  { static constexpr int S = 8; };
+template <> struct FftCfg<64>  { static constexpr int S = 4; };
+template <> struct FftCfg<128> { static constexpr int S = 1; };
+
+constexpr int kFftThreads = 256;
+
+template <int M>
+constexpr int fft_samples_per_step() { return FftCfg<M>::S; }
+
+// Loads voltage (y, k) of sample row `vrow` as a complex float.
+template <bool CI4>
+__device__ __forceinline__ float2 load_volt(const void* base, size_t idx);
+
+template <>
+__device__ __forceinline__ float2 load_volt<false>(const void* base, size_t idx) {
+    return reinterpret_cast<const float2*>(base)[idx];
+}
+template <>
+__device__ __forceinline__ float2 load_volt<true>(const void* base, size_t idx) {
+    const int b = reinterpret_cast<const uint8_t*>(base)[idx];
+    const int re = (b << 24) >> 28;            // sign-extended high nibble
+    const int im = (b << 28) >> 28;            // sign-extended low nibble
+    return make_float2((float)re, (float)im);
+}
+
+template <int M, bool CI4>
+__global__ __launch_bounds__(kFftThreads) void k_fftcorr(const void* __restrict__ volt,
+                                                         const float2* __restrict__ gains,
+                                                         float* __restrict__ ppart, int n, int T,
+                                                         int tchunk, int nchunk) {
+    constexpr int H = M / 2;
+    constexpr int S = FftCfg<M>::S;
+    constexpr int NT = kFftThreads;
+    constexpr int RS = M + 1;                     // padded LDS row stride (complex)
+    constexpr int CPT = 2 * M * S / NT;           // column tasks per thread (1 or 2)
+    constexpr int G = S / CPT;                    // threads sharing one column half
+    static_assert(CPT == 1 || CPT == 2, "column tasks per thread");
+    static_assert(M * M <= 2 * S * H * RS, "power grid must fit in the row buffer");
+
+    __shared__ float2 rbuf[S * H * RS];
+    __shared__ float2 hinv[H * (H + 1)];
+
+    const int tid = threadIdx.x;
+    const int unit = blockIdx.y;
+    const int chunk = blockIdx.x;
+    const int N = n * n;
+    const int tb = chunk * tchunk;
+    const int te = min(T, tb + tchunk);
+
+    for (int a = tid; a < N; a += NT) {
+        const float2 g = gains[(size_t)unit * N + a];
+        const float d = 1.0f / cabs2(g);
+        hinv[(a / n) * (H + 1) + (a % n)] = make_float2(g.x * d, -g.y * d);   // 1/g
+    }
+
+    float acc[H];
+#pragma unroll
+    for (int r = 0; r < H; ++r) acc[r] = 0.0f;
+
+    const int rh = tid & 1;
+    const int ry = (tid >> 1) % n;
+    const int rs = (tid >> 1) / n;
+    const bool row_active = rs < S;
+    const int ch = tid & 1;
+    const int cu = (tid >> 1) % M;
+    const int cs0 = (tid >> 1) / M;
+
+    __syncthreads();
+
+    for (int t0 = tb; t0 < te; t0 += S) {
+        if (row_active) {
+            float2 x[H];
+            const int t = t0 + rs;
+            const bool live = t < te;
+            const size_t rowbase = ((size_t)unit * T + (live ? t : tb)) * N + (size_t)ry * n;
+            const float2* hrow = hinv + ry * (H + 1);
+#pragma unroll
+            for (int k = 0; k < H; ++k) {
+                if (k < n && live) {
+                    x[k] = cmul(load_volt<CI4>(volt, rowbase + k), hrow[k]);
+                } else {
+                    x[k] = make_float2(0.0f, 0.0f);
+                }
+            }
+            if (rh) {
+#pragma unroll
+                for (int k = 0; k < H; ++k) x[k] = twmul<M>(x[k], k);
+            }
+            fft_dif<H>(x);
+            float2* out = rbuf + (rs * H + ry) * RS;
+#pragma unroll
+            for (int r = 0; r < H; ++r) out[2 * bitrev<H>(r) + rh] = x[r];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) {
+            const int s = cs0 + c * G;
+            float2 x[H];
+#pragma unroll
+            for (int k = 0; k < H; ++k) {
+                x[k] = (k < n) ? rbuf[(s * H + k) * RS + cu] : make_float2(0.0f, 0.0f);
+            }
+            if (ch) {
+#pragma unroll
+                for (int k = 0; k < H; ++k) x[k] = twmul<M>(x[k], k);
+            }
+            fft_dif<H>(x);
+#pragma unroll
+            for (int r = 0; r < H; ++r) acc[r] += cabs2(x[r]);
+        }
+        __syncthreads();
+    }
+
+    // Reduce the G partial grids that share a column half, in a fixed order.
+    float* pl = reinterpret_cast<float*>(rbuf);
+    for (int q = tid; q < M * M; q += NT) pl[q] = 0.0f;
+    __syncthreads();
+    for (int gidx = 0; gidx < G; ++gidx) {
+        if (cs0 == gidx) {
+#pragma unroll
+            for (int r = 0; r < H; ++r) pl[(2 * bitrev<H>(r) + ch) * M + cu] += acc[r];
+        }
+        __syncthreads();
+    }
+    float* dst = ppart + ((size_t)unit * nchunk + chunk) * (M * M);
+    for (int q = tid; q < M * M; q += NT) dst[q] = pl[q];
+}
+
+// Lag index of a canonical d in the V^unique layout.
+__device__ __forceinline__ int lag_index(int n, int dx, int dy) {
+    return dy == 0 ? dx - 1 : (n - 1) + (dy - 1) * (2 * n - 1) + (dx + n - 1);
+}
+
+constexpr int kFinThreads = 256;
+constexpr int kFinDxBlock = 32;
+
+template <int M>
+__global__ __launch_bounds__(kFinThreads) void k_fftfin(const float* __restrict__ ppart, int nchunk,
+                                                        int n, int T, float2* __restrict__ vunique,
+                                                        float* __restrict__ vauto) {
+    constexpr int NT = kFinThreads;
+    constexpr int DB = kFinDxBlock;
+    __shared__ float pw[M * M];
+    __shared__ float2 twp[M];              // e^{+2 pi i k / M}
+    __shared__ float2 abuf[M * DB];
+
+    const int tid = threadIdx.x;
+    const int unit = blockIdx.x;
+    const int N = n * n;
+    const int nlag = 2 * n * (n - 1);
+    const float* src = ppart + (size_t)unit * nchunk * (M * M);
+    for (int q = tid; q < M * M; q += NT) {
+        float s = 0.0f;
+        for (int c = 0; c < nchunk; ++c) s += src[(size_t)c * (M * M) + q];
+        pw[q] = s;
+    }
+    for (int k = tid; k < M; k += NT) twp[k] = make_float2(Tw<M>::t.re[k], -Tw<M>::t.im[k]);
+    __syncthreads();
+
+    const float norm = 1.0f / ((float)M * (float)M * (float)T);
+    for (int dx0 = -(n - 1); dx0 <= n - 1; dx0 += DB) {
+        // stage x: A(u_y, dx) = sum_{u_x} P(u_y, u_x) e^{+2 pi i u_x dx / M}
+        for (int q = tid; q < M * DB; q += NT) {
+            const int uy = q / DB, di = q % DB;
+            const int dx = dx0 + di;
+            float2 a = make_float2(0.0f, 0.0f);
+            if (dx <= n - 1) {
+                const float* prow = pw + uy * M;
+                for (int ux = 0; ux < M; ++ux) {
+                    const float2 w = twp[(ux * dx) & (M - 1)];
+                    a.x += prow[ux] * w.x;
+                    a.y += prow[ux] * w.y;
+                }
+            }
+            abuf[q] = a;
+        }
+        __syncthreads();
+        // stage y: C(dx, dy) = sum_{u_y} A(u_y, dx) e^{+2 pi i u_y dy / M}
+        for (int q = tid; q < n * DB; q += NT) {
+            const int dy = q / DB, di = q % DB;
+            const int dx = dx0 + di;
+            if (dx > n - 1 || (dy == 0 && dx < 0)) continue;
+            float2 c = make_float2(0.0f, 0.0f);
+            for (int uy = 0; uy < M; ++uy) {
+                c = cadd(c, cmul(abuf[uy * DB + di], twp[(uy * dy) & (M - 1)]));
+            }
+            if (dx == 0 && dy == 0) {
+                vauto[unit] = c.x * norm / (float)N;
+            } else {
+                const int adx = dx < 0 ? -dx : dx;
+                const float nd = (float)((n - adx) * (n - dy));
+                vunique[(size_t)unit * nlag + lag_index(n, dx, dy)] =
+                    make_float2(c.x * norm / nd, c.y * norm / nd);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <int M, bool CI4>
+static hipError_t launch_fft_m(const FftLaunch& L, hipStream_t st) {
+    dim3 grid1(L.nchunk, L.n_units);
+    hipLaunchKernelGGL((k_fftcorr<M, CI4>), grid1, dim3(kFftThreads), 0, st, L.volt, L.gains,
+                       L.ppart, L.n, L.T, L.tchunk, L.nchunk);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_fftfin<M>), dim3(L.n_units), dim3(kFinThreads), 0, st, L.ppart, L.nchunk,
+                       L.n, L.T, L.vunique, L.vauto);
+    return hipGetLastError();
+}
+
+int fft_samples_per_step_for(int M) {
+    switch (M) {
+        case 16: return fft_samples_per_step<16>();
+        case 32: return fft_samples_per_step<32>();
+        case 64: return fft_samples_per_step<64>();
+        case 128: return fft_samples_per_step<128>();
+        default: return 0;
+    }
+}
+
+hipError_t launch_fftcorr(const FftLaunch& L, hipStream_t st) {
+    switch (L.M) {
+        case 16: return L.ci4 ? launch_fft_m<16, true>(L, st) : launch_fft_m<16, false>(L, st);
+        case 32: return L.ci4 ? launch_fft_m<32, true>(L, st) : launch_fft_m<32, false>(L, st);
+        case 64: return L.ci4 ? launch_fft_m<64, true>(L, st) : launch_fft_m<64, false>(L, st);
+        case 128: return L.ci4 ? launch_fft_m<128, true>(L, st) : launch_fft_m<128, false>(L, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace rrc

@@ -1,0 +1,190 @@
+// Device-side helpers shared by the HIP kernels: complex arithmetic,
+// compile-time twiddles, an in-register radix-2 FFT, and the implicit
+// geometry of a square grid with a list of selected baseline-types.
+#pragma once
+
+#ifdef RRC_HOST_EMU
+#include "rrc_emu.h"   // CPU build of the kernels' bodies, for host-side tests
+#else
+#include <hip/hip_runtime.h>
+#endif
+#include <stdint.h>
+
+#define RRC_HD __host__ __device__ __forceinline__
+
+namespace rrc {
+
+constexpr int kMaxTypes = 32;
+
+// ------------------------------------------------------------------ complex
+
+RRC_HD float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+RRC_HD float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+RRC_HD float2 cmul(float2 a, float2 b) { return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+// a * conj(b)
+RRC_HD float2 cmulc(float2 a, float2 b) { return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y); }
+RRC_HD float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+RRC_HD float cabs2(float2 a) { return a.x * a.x + a.y * a.y; }
+
+RRC_HD double2 dadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+RRC_HD double2 dsub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+RRC_HD double2 dmul(double2 a, double2 b) { return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+RRC_HD double2 dmulc(double2 a, double2 b) { return make_double2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y); }
+RRC_HD double2 dconj(double2 a) { return make_double2(a.x, -a.y); }
+RRC_HD double dabs2(double2 a) { return a.x * a.x + a.y * a.y; }
+RRC_HD double2 to_d(float2 a) { return make_double2(a.x, a.y); }
+RRC_HD float2 to_f(double2 a) { return make_float2((float)a.x, (float)a.y); }
+
+// ------------------------------------------------- compile-time twiddles
+//
+// e^{-2 pi i k / L} evaluated in double at compile time.  The angle is
+// reduced to an octant, so multiples of pi/4 come out exact (0, +-1,
+// +-sqrt(1/2)) and the remaining values are Taylor series on [0, pi/4].
+
+constexpr double kPi = 3.14159265358979323846;
+
+constexpr double cx_sin(double x) {
+    double x2 = x * x, term = x, sum = x;
+    for (int i = 1; i < 14; ++i) { term *= -x2 / ((2.0 * i) * (2.0 * i + 1.0)); sum += term; }
+    return sum;
+}
+constexpr double cx_cos(double x) {
+    double x2 = x * x, term = 1.0, sum = 1.0;
+    for (int i = 1; i < 14; ++i) { term *= -x2 / ((2.0 * i - 1.0) * (2.0 * i)); sum += term; }
+    return sum;
+}
+
+struct cd { double re, im; };
+
+// (cos t, sin t) for t = 2 pi k / L, k in [0, L)
+constexpr cd cx_cis(int k, int L) {
+    k %= L;
+    if (k < 0) k += L;
+    const long q = 8L * k;
+    const int o = (int)(q / L);
+    const long rem = q - (long)o * L;
+    const double psi = (kPi / 4.0) * ((double)rem / (double)L);
+    const double phi = (kPi / 4.0) * ((double)(L - rem) / (double)L);
+    const double cp = cx_cos(psi), sp = cx_sin(psi);
+    const double cf = cx_cos(phi), sf = cx_sin(phi);
+    switch (o) {
+        case 0: return cd{cp, sp};
+        case 1: return cd{sf, cf};
+        case 2: return cd{-sp, cp};
+        case 3: return cd{-cf, sf};
+        case 4: return cd{-cp, -sp};
+        case 5: return cd{-sf, -cf};
+        case 6: return cd{sp, -cp};
+        default: return cd{cf, -sf};
+    }
+}
+
+template <int L>
+struct TwTable {
+    float re[L];
+    float im[L];   // e^{-2 pi i k / L} = re + i im
+    constexpr TwTable() : re(), im() {
+        for (int k = 0; k < L; ++k) {
+            cd c = cx_cis(k, L);
+            re[k] = (float)c.re;
+            im[k] = (float)(-c.im);
+        }
+    }
+};
+
+template <int L>
+struct Tw {
+    static constexpr TwTable<L> t{};
+};
+
+// d * e^{-2 pi i k / L}; k is a compile-time constant after unrolling, so
+// the trivial factors reduce to swaps and sign flips.
+template <int L>
+RRC_HD float2 twmul(float2 d, int k) {
+    if (k == 0) return d;
+    if (4 * k == L) return make_float2(d.y, -d.x);
+    if (2 * k == L) return make_float2(-d.x, -d.y);
+    if (4 * k == 3 * L) return make_float2(-d.y, d.x);
+    constexpr float s = 0.70710678118654752440f;
+    if (8 * k == L) return make_float2((d.x + d.y) * s, (d.y - d.x) * s);
+    if (8 * k == 3 * L) return make_float2((d.y - d.x) * s, -(d.x + d.y) * s);
+    const float c = Tw<L>::t.re[k], sn = Tw<L>::t.im[k];
+    return make_float2(d.x * c - d.y * sn, d.x * sn + d.y * c);
+}
+
+// In-register radix-2 decimation-in-frequency FFT of length L:
+// X[f] = sum_k x[k] e^{-2 pi i f k / L}, natural-order input, output
+// element r holds frequency bitrev(r).
+template <int L>
+RRC_HD void fft_dif(float2 (&a)[L]) {
+#pragma unroll
+    for (int h = L / 2; h >= 1; h >>= 1) {
+#pragma unroll
+        for (int b = 0; b < L; b += 2 * h) {
+#pragma unroll
+            for (int j = 0; j < h; ++j) {
+                const float2 u = a[b + j], v = a[b + j + h];
+                a[b + j] = cadd(u, v);
+                a[b + j + h] = twmul<L>(csub(u, v), j * (L / (2 * h)));
+            }
+        }
+    }
+}
+
+template <int L>
+constexpr int bitrev(int r) {
+    int out = 0;
+    for (int m = 1, k = L >> 1; m < L; m <<= 1, k >>= 1)
+        if (r & m) out |= k;
+    return out;
+}
+
+constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v >> 1); }
+
+// ------------------------------------------------------------- geometry
+
+// The selected baseline-types of a plan, passed to kernels by value.
+struct Sel {
+    int n;                  // grid side
+    int N;                  // n*n
+    int K;                  // selected types
+    int P;                  // pairs
+    int dx[kMaxTypes];
+    int dy[kMaxTypes];
+    int off[kMaxTypes + 1]; // pair offset of each type, off[K] = P
+};
+
+// pair b of type t -> (i, j) with r_i - r_j = d_t
+RRC_HD void pair_ij(const Sel& s, int t, int b_local, int& i, int& j) {
+    const int dx = s.dx[t], dy = s.dy[t];
+    const int w = s.n - (dx < 0 ? -dx : dx);
+    const int yi = b_local / w + dy;
+    const int xi = b_local % w + (dx > 0 ? dx : 0);
+    i = yi * s.n + xi;
+    j = i - (dy * s.n + dx);
+}
+
+// Global pair index of the pair (a, a - d_t) with antenna a = (ax, ay)
+// first, or -1 if either antenna lies outside the grid.
+RRC_HD int pair_as_first(const Sel& s, int t, int ax, int ay) {
+    const int dx = s.dx[t], dy = s.dy[t];
+    const int jx = ax - dx, jy = ay - dy;
+    if (ax < 0 || ax >= s.n || ay < 0 || ay >= s.n) return -1;
+    if (jx < 0 || jx >= s.n || jy < 0 || jy >= s.n) return -1;
+    const int w = s.n - (dx < 0 ? -dx : dx);
+    return s.off[t] + (ay - dy) * w + (ax - (dx > 0 ? dx : 0));
+}
+
+// Global pair index of the pair (a + d_t, a) with antenna a second, or -1.
+RRC_HD int pair_as_second(const Sel& s, int t, int ax, int ay) {
+    return pair_as_first(s, t, ax + s.dx[t], ay + s.dy[t]);
+}
+
+// type of global pair b (linear scan; K is small)
+RRC_HD int type_of(const Sel& s, int b) {
+    int t = 0;
+    while (t + 1 < s.K && b >= s.off[t + 1]) ++t;
+    return t;
+}
+
+}  // namespace rrc

@@ -1,0 +1,84 @@
+// Host-side launch descriptors shared between the C-ABI layer and the
+// kernel translation units.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "rrc_device.h"
+
+namespace rrc {
+
+struct FftLaunch {
+    int M, n, T, n_units;
+    int tchunk, nchunk;
+    bool ci4;
+    const void* volt;
+    const float2* gains;
+    float* ppart;          // workspace: [U][nchunk][M][M]
+    float2* vunique;
+    float* vauto;
+};
+
+struct XengLaunch {
+    Sel sel;
+    int T, n_units;
+    int tchunk, nchunk;    // time chunks per unit
+    int ppt;               // pairs per thread (template selector)
+    int npblk;             // pair blocks per unit
+    int xs;                // samples staged in LDS per step
+    bool ci4;
+    const void* volt;
+    void* vpart;           // workspace: [U][nchunk][P] float2 or int2
+    void* vred;            // output: [U][P] float2 (scaled by 1/T) or int2
+};
+
+struct SolveOpts {
+    int init_mode, degen_mode, max_gn, fp64_steps, max_cg;
+    float cg_tol, tol32;
+};
+
+struct SolveLaunch {
+    Sel sel;
+    int n_units;
+    bool ci4;
+    bool lds;              // hot arrays in LDS
+    size_t lds_bytes;      // dynamic LDS per workgroup
+    size_t slab_bytes;     // per-unit global scratch
+    SolveOpts o;
+    const void* vred;
+    const float2* gains_in;
+    const float2* gains_ref;
+    float2* gains_out;
+    float2* vmodel;
+    float* chisq;
+    int* niter;
+    int* status;
+    char* slab;            // workspace: [U][slab_bytes]
+};
+
+struct ChisqLaunch {
+    Sel sel;
+    int n_units;
+    const float2* g;
+    const float2* vm;
+    const float2* vred;
+    float* chisq;
+    float2* grad_g;
+    float2* grad_v;
+    float* diag_g;
+    float* diag_v;
+};
+
+#ifndef RRC_HOST_EMU
+int fft_samples_per_step_for(int M);
+hipError_t launch_fftcorr(const FftLaunch& L, hipStream_t st);
+hipError_t launch_xengine(const XengLaunch& L, hipStream_t st);
+size_t solve_hot_bytes(const Sel& s);
+size_t solve_slab_bytes(const Sel& s, bool lds);
+size_t solve_lds_bytes(const Sel& s, bool lds);
+hipError_t launch_solve(const SolveLaunch& L, hipStream_t st);
+hipError_t launch_chisq(const ChisqLaunch& L, hipStream_t st, bool adjoint);
+#endif
+
+}  // namespace rrc

@@ -1,0 +1,65 @@
+"""Shared helpers of the GPU parity tests: seeded inputs, oracle references
+and the tolerances they are held to."""
+import numpy as np
+
+from oracle import correlator as OC
+from oracle import geometry as OG
+from oracle import redcal as OR
+from synthdata import WORKLOADS, Workload, pack_ci4, quantise_ci4, unit_gains, unit_voltages
+
+# V^unique: relative L2 over the lag vector of a unit, same gains on both
+# sides (the correlator's FP32 error alone).
+TOL_VUNIQUE = 1e-5
+# Gains after the same degeneracy convention, oracle solving the GPU's own
+# V^reduced in FP64.
+TOL_GAINS = 1e-6
+# FP32 X-engine: |dV_b| relative to the unit's mean voltage power.  T
+# products of |v|^2 ~ 1 summed in FP32 in runs of at most a few hundred
+# samples: a random-walk rounding error of ~sqrt(T) * 6e-8 < 4e-6 for
+# T <= 4096; 2e-5 leaves margin for the worst case.
+TOL_XENG = 2e-5
+
+
+def make_units(n, n_units, n_time, wid=90, snr=10.0, drift=False, array=0):
+    """complex64 voltages [U, T, N] and complex128 gains [U, N] (seeded)."""
+    m = 16
+    while m < 2 * n:
+        m *= 2
+    g = unit_gains(wid, array, n, n_units, drift)
+    v = np.empty((n_units, n_time, n * n), dtype=np.complex64)
+    for c in range(n_units):
+        v[c] = unit_voltages(wid, array, c, n, m, n_time, snr, g[c]).astype(np.complex64)
+    return v, g
+
+
+def make_ci4_units(n, n_units, n_time, wid=91):
+    v, g = make_units(n, n_units, n_time, wid=wid)
+    out = np.empty(v.shape, dtype=np.uint8)
+    re_all = np.empty(v.shape, dtype=np.int8)
+    im_all = np.empty(v.shape, dtype=np.int8)
+    for c in range(n_units):
+        re, im = quantise_ci4(v[c].astype(np.complex128))
+        re_all[c], im_all[c] = re, im
+        out[c] = pack_ci4(re, im)
+    return out, re_all, im_all, g
+
+
+def oracle_vunique(v_unit, gains, n):
+    pos = OG.square_positions(n)
+    vf = OC.fx_correlate(v_unit.astype(np.complex128))
+    lags = OC.canonical_lags(n)
+    return OC.redundant_average(vf, gains, pos, lags), OC.calibrated_auto(vf, gains)
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def pairs_of(n, types):
+    return OG.group_pairs(OG.square_positions(n), types)
+
+
+def oracle_solve(vred64, n, types, fix="refant", g_ref=None, init=None):
+    pos = OG.square_positions(n)
+    pairs, tix = OG.group_pairs(pos, types)
+    return OR.calibrate(vred64, pos, types, pairs, tix, fix=fix, g_ref=g_ref, init=init)

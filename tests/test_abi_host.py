@@ -1,0 +1,112 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+include/rrcal.h declares, and its host-only calls agree with the oracle."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2005_03060_amd as rrc
+from paper_2005_03060_amd import _lib
+from oracle import geometry as G
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "rrcal.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(rrc_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = rrc.load_library()
+    names = _declared()
+    assert len(names) >= 14
+    for name in names:
+        assert hasattr(lib, name), name
+    assert sorted(_lib.EXPORTS) == names
+
+
+def test_strerror_and_defaults():
+    lib = rrc.load_library()
+    assert lib.rrc_strerror(0) == b"ok"
+    assert b"degeneracies" in lib.rrc_strerror(-2)
+    o = rrc.default_opts()
+    assert o["max_gn"] >= 1 and o["fp64_steps"] >= 1 and o["init_mode"] == 0
+
+
+@pytest.mark.parametrize("n", [4, 8, 12, 16, 24, 32])
+def test_selection_matches_oracle(n):
+    types, npairs = rrc.select_subset(n)
+    ref = G.select_subset_square(n)
+    assert types == [tuple(t) for t in ref]
+    pairs, _ = G.group_pairs(G.square_positions(n), ref)
+    assert npairs == len(pairs)
+
+
+@pytest.mark.parametrize("base", [2.0, 10.0])
+def test_selection_other_log_bases(base):
+    for n in [8, 16]:
+        types, _ = rrc.select_subset(n, 1.0, base)
+        assert types == [tuple(t) for t in G.select_subset_square(n, 1.0, base)]
+
+
+def test_degeneracy_count_matches_oracle():
+    rng = np.random.default_rng(0)
+    for trial in range(25):
+        n = int(rng.integers(3, 8))
+        allt, _ = G.square_types(n)
+        k = int(rng.integers(1, min(8, len(allt)) + 1))
+        sel = [allt[i] for i in sorted(rng.choice(len(allt), k, replace=False))]
+        assert rrc.degeneracy_count(n, sel) == G.nullity(G.square_positions(n), sel), (n, sel)
+
+
+def test_plan_errors():
+    with pytest.raises(rrc.RRCError) as e:
+        rrc.Plan(6, [(1, 0), (0, 1)], 1, 16)            # bipartite: 5 degeneracies
+    assert e.value.code == _lib.RRC_EDEGEN
+    with pytest.raises(rrc.RRCError) as e:
+        rrc.Plan(6, [(1, 0), (7, 0)], 1, 16)            # |dx| >= n
+    assert e.value.code == _lib.RRC_EINVAL
+    with pytest.raises(rrc.RRCError) as e:
+        rrc.Plan(6, [(1, 0), (1, 0), (0, 1)], 1, 16)    # duplicate type
+    assert e.value.code == _lib.RRC_EINVAL
+    with pytest.raises(rrc.RRCError) as e:
+        rrc.Plan(6, [(-1, 0), (0, 1), (1, 1)], 1, 16)   # not canonical
+    assert e.value.code == _lib.RRC_EINVAL
+    with pytest.raises(rrc.RRCError) as e:               # firstcal needs (1,0) and (0,1)
+        rrc.Plan(6, [(1, 1), (-1, 1), (2, 0), (0, 2), (1, 0)], 1, 16)
+    assert e.value.code == _lib.RRC_EINVAL
+    p = rrc.Plan(6, [(1, 1), (-1, 1), (2, 0), (0, 2), (1, 0)], 1, 16, init_mode="gains")
+    assert p.n_pairs == 25 + 25 + 24 + 24 + 30
+    with pytest.raises(rrc.RRCError):
+        rrc.Plan(65, [(1, 0)], 1, 16)
+    with pytest.raises(rrc.RRCError):
+        rrc.Plan(8, [(1, 0), (0, 1), (1, 1)], 0, 16)
+
+
+def test_plan_info_sizes():
+    for n, t in [(8, 256), (16, 1024), (32, 2048), (64, 4096)]:
+        types, npairs = rrc.select_subset(n)
+        p = rrc.Plan(n, types, 4, t, dtype="ci4" if n == 64 else "c64")
+        assert p.info["n_ant"] == n * n and p.info["n_lags"] == 2 * n * (n - 1)
+        assert p.info["n_pairs"] == npairs
+        assert p.info["dof"] == npairs - n * n - len(types) + 2
+        assert p.info["fft_size"] == max(16, 1 << (2 * n - 1).bit_length())
+        assert p.info["workspace_bytes"] > 0
+
+
+def test_raw_abi_rejects_null_pointers():
+    lib = rrc.load_library()
+    types, _ = rrc.select_subset(8)
+    plan = rrc.Plan(8, types, 1, 64)
+    h = plan._h
+    assert lib.rrc_fftcorr(h, None, None, None, None, None, None) == _lib.RRC_EINVAL
+    assert lib.rrc_xengine(h, None, None, None, None) == _lib.RRC_EINVAL
+    assert lib.rrc_solve(h, None, None, None, None, None, None, None, None, None, None) == _lib.RRC_EINVAL
+    assert lib.rrc_run(h, None, 1, None) == _lib.RRC_EINVAL
+    assert lib.rrc_plan_get_info(None, None) == _lib.RRC_EINVAL
+    sz = ctypes.c_size_t()
+    assert lib.rrc_workspace_size(h, ctypes.byref(sz)) == 0 and sz.value == plan.info["workspace_bytes"]

@@ -1,0 +1,225 @@
+"""Parity of the HIP path (through the C-ABI) with the FP64 CPU oracle."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import correlator as OC
+from oracle import geometry as OG
+from oracle import redcal as OR
+from tests.gpu_util import (TOL_GAINS, TOL_VUNIQUE, TOL_XENG, make_ci4_units, make_units,
+                            oracle_solve, oracle_vunique, pairs_of, rel_l2)
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+def _plan(rrc, n, U, T, dtype="c64", types=None, **kw):
+    if types is None:
+        types, _ = rrc.select_subset(n)
+    return rrc.Plan(n, types, U, T, dtype=dtype, **kw), types
+
+
+# ------------------------------------------------------------------ (a1)-(a3)
+
+@pytest.mark.parametrize("n,U,T", [(8, 1, 256), (16, 6, 1024), (3, 2, 37), (5, 3, 250),
+                                   (12, 2, 333), (24, 2, 200), (32, 2, 512)])
+def test_fftcorr_matches_oracle(rrc, n, U, T):
+    v, g = make_units(n, U, T)
+    plan, _ = _plan(rrc, n, U, T)
+    g64 = g.astype(np.complex64)
+    vu, va = plan.fftcorr(torch.from_numpy(v).to(DEV), torch.from_numpy(g64).to(DEV))
+    vu, va = vu.cpu().numpy(), va.cpu().numpy()
+    for u in range(U):
+        ref, aref = oracle_vunique(v[u], g64[u].astype(np.complex128), n)
+        err = rel_l2(vu[u], ref)
+        print(f"n={n} T={T} unit {u}: V^unique rel L2 {err:.2e}, auto {abs(va[u] - aref) / aref:.2e}")
+        assert err <= TOL_VUNIQUE
+        assert abs(va[u] - aref) <= 1e-5 * aref
+
+
+def test_fftcorr_single_mode_closed_form(rrc):
+    # one sky mode, no noise, unit gains: V(d) = <|s|^2> exp(-2 pi i k0.d / M)
+    n, T, m = 16, 64, 32
+    rng = np.random.default_rng(5)
+    s = (rng.standard_normal(T) + 1j * rng.standard_normal(T))
+    k0 = np.array([3, 7])
+    pos = OG.square_positions(n)
+    v = (s[:, None] * np.exp(-2j * np.pi * (pos @ k0) / m)[None, :]).astype(np.complex64)[None]
+    plan, _ = _plan(rrc, n, 1, T)
+    vu, _ = plan.fftcorr(torch.from_numpy(v).to(DEV), torch.ones((1, n * n), dtype=torch.complex64, device=DEV))
+    p = np.mean(np.abs(v[0, :, 0]) ** 2)
+    ref = np.array([p * np.exp(-2j * np.pi * (k0 @ np.array(d)) / m) for d in OC.canonical_lags(n)])
+    assert rel_l2(vu.cpu().numpy()[0], ref) <= TOL_VUNIQUE
+
+
+# ----------------------------------------------------------------------- (a4)
+
+@pytest.mark.parametrize("n,U,T", [(8, 1, 256), (16, 4, 1024), (5, 2, 97), (32, 2, 2048)])
+def test_xengine_float_matches_oracle(rrc, n, U, T):
+    v, _ = make_units(n, U, T)
+    plan, types = _plan(rrc, n, U, T)
+    vr = plan.xengine(torch.from_numpy(v).to(DEV)).cpu().numpy()
+    pairs, _ = pairs_of(n, types)
+    for u in range(U):
+        ref = OC.xengine(OC.fx_correlate(v[u].astype(np.complex128)), pairs)
+        scale = np.mean(np.abs(v[u].astype(np.complex128)) ** 2)
+        err = np.max(np.abs(vr[u] - ref)) / scale
+        print(f"n={n} T={T} unit {u}: X-engine max err / power {err:.2e}")
+        assert err <= TOL_XENG
+
+
+@pytest.mark.parametrize("n,U,T", [(8, 2, 300), (16, 2, 1024), (64, 2, 4096)])
+def test_xengine_ci4_bit_exact(rrc, n, U, T):
+    b, re, im, _ = make_ci4_units(n, U, T)
+    plan, types = _plan(rrc, n, U, T, dtype="ci4")
+    vr = plan.xengine(torch.from_numpy(b).to(DEV)).cpu().numpy().astype(np.int64)
+    pairs, _ = pairs_of(n, types)
+    for u in range(U):
+        ref = OC.xengine_int(re[u], im[u], pairs)
+        assert np.array_equal(vr[u], ref), f"unit {u}: {np.sum(vr[u] != ref)} mismatches"
+
+
+# ----------------------------------------------------------------------- (a5)
+
+@pytest.mark.parametrize("n,U,T,snr", [(8, 1, 256, 10.0), (16, 4, 1024, 10.0), (32, 2, 2048, 5.0)])
+def test_solve_matches_oracle(rrc, n, U, T, snr):
+    v, _ = make_units(n, U, T, snr=snr)
+    plan, types = _plan(rrc, n, U, T)
+    vr_d = plan.xengine(torch.from_numpy(v).to(DEV))
+    out = plan.solve(vr_d)
+    vr = vr_d.cpu().numpy()
+    for u in range(U):
+        ref = oracle_solve(vr[u].astype(np.complex128), n, types)
+        g = out["gains"][u].cpu().numpy().astype(np.complex128)
+        gerr = np.max(np.abs(g - ref["g"]) / np.abs(ref["g"]))
+        cerr = abs(float(out["chisq"][u]) - ref["chisq"]) / ref["chisq"]
+        verr = np.max(np.abs(out["vmodel"][u].cpu().numpy() - ref["vm"]) / np.abs(ref["vm"]))
+        print(f"n={n} unit {u}: gains {gerr:.2e} vmodel {verr:.2e} chi2 {cerr:.2e} "
+              f"niter {int(out['niter'][u])} status {int(out['status'][u])}")
+        assert int(out["status"][u]) == 0
+        assert gerr <= TOL_GAINS
+        assert verr <= 1e-5
+        assert cerr <= 1e-5
+
+
+def test_solve_ci4_matches_oracle(rrc):
+    n, U, T = 16, 2, 1024
+    b, re, im, _ = make_ci4_units(n, U, T)
+    plan, types = _plan(rrc, n, U, T, dtype="ci4")
+    vr_d = plan.xengine(torch.from_numpy(b).to(DEV))
+    out = plan.solve(vr_d)
+    vr = vr_d.cpu().numpy().astype(np.float64)
+    for u in range(U):
+        ref = oracle_solve(vr[u, :, 0] + 1j * vr[u, :, 1], n, types)
+        g = out["gains"][u].cpu().numpy().astype(np.complex128)
+        assert np.max(np.abs(g - ref["g"]) / np.abs(ref["g"])) <= TOL_GAINS
+
+
+def test_solve_from_gains_and_match_mode(rrc):
+    n, U, T = 16, 2, 1024
+    v, gtrue = make_units(n, U, T)
+    types, _ = rrc.select_subset(n)
+    plan = rrc.Plan(n, types, U, T, init_mode="gains", degen_mode="match")
+    vr_d = plan.xengine(torch.from_numpy(v).to(DEV))
+    gin = torch.from_numpy(gtrue.astype(np.complex64)).to(DEV)
+    out = plan.solve(vr_d, gains_in=gin, gains_ref=gin)
+    vr = vr_d.cpu().numpy().astype(np.complex128)
+    for u in range(U):
+        gref = gtrue[u].astype(np.complex64).astype(np.complex128)
+        # matching phases is only well posed near the reference: start both there
+        pairs, tix = pairs_of(n, types)
+        ref = oracle_solve(vr[u], n, types, fix="match", g_ref=gref,
+                           init=(gref, OR.group_mean(vr[u], gref, pairs, tix, len(types))))
+        g = out["gains"][u].cpu().numpy().astype(np.complex128)
+        assert np.max(np.abs(g - ref["g"]) / np.abs(ref["g"])) <= TOL_GAINS
+        assert int(out["status"][u]) == 0
+
+
+def test_solve_nonfinite_unit_is_flagged(rrc):
+    n, U, T = 8, 2, 128
+    v, _ = make_units(n, U, T)
+    v[1, 5, 7] = np.nan
+    plan, _ = _plan(rrc, n, U, T)
+    out = plan.run(torch.from_numpy(v).to(DEV), mode="selfcal")
+    st = out["status"].cpu().numpy()
+    assert st[0] == 0 and st[1] == 2
+
+
+# ----------------------------------------------------------------------- (a6)
+
+def test_chisq_and_adjoint_match_oracle(rrc):
+    n, U, T = 16, 3, 512
+    v, gtrue = make_units(n, U, T)
+    plan, types = _plan(rrc, n, U, T)
+    pairs, tix = pairs_of(n, types)
+    vr_d = plan.xengine(torch.from_numpy(v).to(DEV))
+    rng = np.random.default_rng(3)
+    g = (gtrue * (1 + 0.03 * (rng.standard_normal(gtrue.shape) + 1j * rng.standard_normal(gtrue.shape)))).astype(np.complex64)
+    vm = np.stack([OR.group_mean(vr_d[u].cpu().numpy().astype(np.complex128), gtrue[u], pairs, tix, len(types))
+                   for u in range(U)]).astype(np.complex64)
+    gd, vmd = torch.from_numpy(g).to(DEV), torch.from_numpy(vm).to(DEV)
+    c = plan.chisq_fwd(gd, vmd, vr_d).cpu().numpy()
+    gg, gv, dg, dv = [x.cpu().numpy() for x in plan.chisq_adj(gd, vmd, vr_d)]
+    vr = vr_d.cpu().numpy()
+    for u in range(U):
+        g64, v64, r64 = g[u].astype(np.complex128), vm[u].astype(np.complex128), vr[u].astype(np.complex128)
+        cref = OR.chisq(r64, g64, v64, pairs, tix)
+        assert abs(c[u] - cref) <= 1e-5 * cref
+        rg, rv = OR.wirtinger_grad(r64, g64, v64, pairs, tix)
+        hg, hv = OR.jhj_diag(g64, v64, pairs, tix)
+        sc = np.max(np.abs(2 * rg))
+        assert np.max(np.abs(gg[u] - 2 * rg)) <= 1e-5 * sc
+        assert np.max(np.abs(gv[u] - 2 * rv)) <= 1e-5 * np.max(np.abs(2 * rv))
+        assert np.max(np.abs(dg[u] - hg) / hg) <= 1e-5
+        assert np.max(np.abs(dv[u] - hv) / hv) <= 1e-5
+
+
+def test_chisq_autograd_function(rrc):
+    n, U, T = 8, 2, 256
+    v, gtrue = make_units(n, U, T)
+    plan, types = _plan(rrc, n, U, T)
+    vr_d = plan.xengine(torch.from_numpy(v).to(DEV))
+    g = torch.from_numpy(gtrue.astype(np.complex64)).to(DEV).requires_grad_(True)
+    vm = torch.full((U, len(types)), 0.3 + 0.1j, dtype=torch.complex64, device=DEV).requires_grad_(True)
+    w = torch.tensor([0.7, 1.3], device=DEV)
+    loss = (rrc.chisq(g, vm, vr_d, plan) * w).sum()
+    loss.backward()
+    gg, gv, _, _ = plan.chisq_adj(g.detach(), vm.detach(), vr_d)
+    assert torch.allclose(g.grad, gg * w[:, None], rtol=1e-6, atol=0)
+    assert torch.allclose(vm.grad, gv * w[:, None], rtol=1e-6, atol=0)
+
+
+# ---------------------------------------------------------------- whole path
+
+def test_run_modes_consistent(rrc):
+    n, U, T = 16, 3, 1024
+    v, gtrue = make_units(n, U, T)
+    plan, types = _plan(rrc, n, U, T)
+    vd = torch.from_numpy(v).to(DEV)
+    gin = torch.from_numpy(gtrue.astype(np.complex64)).to(DEV)
+    a = plan.run(vd, gains_in=gin, mode="pipelined")
+    vu_a, _ = plan.fftcorr(vd, gin)
+    assert torch.equal(a["vunique"], vu_a)
+    b = plan.run(vd, mode="selfcal")
+    vu_b, _ = plan.fftcorr(vd, b["gains"].contiguous())
+    assert torch.equal(b["vunique"], vu_b)
+    assert torch.equal(a["gains"], b["gains"])
+    # end to end against the oracle: gains from the GPU V^reduced, V^unique with the GPU gains
+    for u in range(U):
+        ref = oracle_solve(b["vred"][u].cpu().numpy().astype(np.complex128), n, types)
+        g = b["gains"][u].cpu().numpy().astype(np.complex128)
+        assert np.max(np.abs(g - ref["g"]) / np.abs(ref["g"])) <= TOL_GAINS
+        vref, _ = oracle_vunique(v[u], g, n)
+        assert rel_l2(b["vunique"][u].cpu().numpy(), vref) <= TOL_VUNIQUE
+
+
+def test_repeat_is_bitwise_deterministic(rrc):
+    n, U, T = 16, 4, 512
+    v, _ = make_units(n, U, T)
+    plan, _ = _plan(rrc, n, U, T)
+    vd = torch.from_numpy(v).to(DEV)
+    a = plan.run(vd, mode="selfcal")
+    b = plan.run(vd, mode="selfcal", out=plan.alloc_outputs(DEV))
+    for k in ("vunique", "vred", "gains", "vmodel", "chisq"):
+        assert torch.equal(a[k], b[k]), k
