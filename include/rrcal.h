@@ -34,7 +34,8 @@
  * Memory: every pointer argument named `d_*` is device memory owned by the
  * caller (the Python binding allocates it with PyTorch).  The library never
  * allocates device memory; scratch space is the caller's `d_work` buffer of
- * rrc_workspace_size() bytes.  A plan owns host memory only.
+ * rrc_workspace_size() bytes (no initial contents needed).  A plan owns
+ * host memory only.
  *
  * Streams: `stream` is a hipStream_t passed as void* (NULL = the null
  * stream).  Device work is enqueued asynchronously; outputs are valid once
@@ -194,7 +195,10 @@ int rrc_chisq_adj(rrc_plan* plan, void* stream, const void* d_g, const void* d_v
  * mode RRC_RUN_PIPELINED: the FFT-correlator applies d_gains_in (the
  *   previous integration's solution, Fig. 1 real-time loop) while the
  *   X-engine and the solve run on the same voltages; the solved gains are
- *   for the next integration.
+ *   for the next integration.  The FFT-correlator is forked onto a stream
+ *   the plan owns (created on first use on the current device, default
+ *   priority) and joined back into `stream` with events, so all outputs
+ *   are ordered on `stream` as usual.
  * mode RRC_RUN_SELFCAL: X-engine, solve, then the FFT-correlator applies the
  *   just-solved gains (reads the voltages twice).
  * Outputs as in the calls above; d_gains_in may be NULL in SELFCAL mode. */

@@ -29,6 +29,10 @@ struct rrc_plan {
     size_t solve_lds_bytes, slab_bytes;
     // workspace layout
     size_t off_fft, off_x, off_slab, ws_bytes;
+    // fork/join of the pipelined run (created on first use, default priority)
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    int aux_device = -1;
 };
 
 namespace {
@@ -310,7 +314,33 @@ int rrc_plan_create(rrc_plan** out, int32_t n, const int32_t* types_xy, int32_t 
     return RRC_OK;
 }
 
-void rrc_plan_destroy(rrc_plan* p) { delete p; }
+static void release_aux(rrc_plan* p) {
+    if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
+    if (p->ev_join) (void)hipEventDestroy(p->ev_join);
+    if (p->aux) (void)hipStreamDestroy(p->aux);
+    p->aux = nullptr;
+    p->ev_fork = p->ev_join = nullptr;
+    p->aux_device = -1;
+}
+
+// The auxiliary stream and events live on the device that is current.
+static bool ensure_aux(rrc_plan* p) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return false;
+    if (p->aux && p->aux_device == dev) return true;
+    release_aux(p);
+    if (hipStreamCreateWithFlags(&p->aux, hipStreamNonBlocking) != hipSuccess) return false;
+    if (hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming) != hipSuccess) return false;
+    if (hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming) != hipSuccess) return false;
+    p->aux_device = dev;
+    return true;
+}
+
+void rrc_plan_destroy(rrc_plan* p) {
+    if (!p) return;
+    release_aux(p);
+    delete p;
+}
 
 int rrc_plan_get_info(const rrc_plan* p, rrc_plan_info* info) {
     if (!p || !info) return RRC_EINVAL;
@@ -434,19 +464,32 @@ int rrc_run(rrc_plan* p, void* stream, int32_t mode, const rrc_io* io) {
     if (!p || !io) return RRC_EINVAL;
     if (mode != RRC_RUN_PIPELINED && mode != RRC_RUN_SELFCAL) return RRC_EINVAL;
     if (mode == RRC_RUN_PIPELINED && !io->d_gains_in) return RRC_EINVAL;
-    int rc = rrc_xengine(p, stream, io->d_volt, io->d_vred, io->d_work);
-    if (rc != RRC_OK) return rc;
+    if (!io->d_volt || !io->d_vunique || !io->d_vauto || !io->d_vred || !io->d_gains_out ||
+        !io->d_vmodel || !io->d_chisq || !io->d_niter || !io->d_status || !io->d_work)
+        return RRC_EINVAL;
+    hipStream_t st = as_stream(stream);
+    int rc;
     if (mode == RRC_RUN_PIPELINED) {
-        rc = rrc_fftcorr(p, stream, io->d_volt, io->d_gains_in, io->d_vunique, io->d_vauto,
+        // The FFT-correlator needs only the previous gains: it runs on the
+        // auxiliary stream while the X-engine and the solve run on `stream`.
+        if (!ensure_aux(p)) return RRC_EDEVICE;
+        if (hipEventRecord(p->ev_fork, st) != hipSuccess) return RRC_EDEVICE;
+        if (hipStreamWaitEvent(p->aux, p->ev_fork, 0) != hipSuccess) return RRC_EDEVICE;
+        rc = rrc_fftcorr(p, p->aux, io->d_volt, io->d_gains_in, io->d_vunique, io->d_vauto,
                          io->d_work);
         if (rc != RRC_OK) return rc;
+        if (hipEventRecord(p->ev_join, p->aux) != hipSuccess) return RRC_EDEVICE;
     }
+    rc = rrc_xengine(p, stream, io->d_volt, io->d_vred, io->d_work);
+    if (rc != RRC_OK) return rc;
     rc = rrc_solve(p, stream, io->d_vred, io->d_gains_in, io->d_gains_ref, io->d_gains_out,
                    io->d_vmodel, io->d_chisq, io->d_niter, io->d_status, io->d_work);
     if (rc != RRC_OK) return rc;
     if (mode == RRC_RUN_SELFCAL) {
         rc = rrc_fftcorr(p, stream, io->d_volt, io->d_gains_out, io->d_vunique, io->d_vauto,
                          io->d_work);
+    } else if (hipStreamWaitEvent(st, p->ev_join, 0) != hipSuccess) {
+        return RRC_EDEVICE;
     }
     return rc;
 }

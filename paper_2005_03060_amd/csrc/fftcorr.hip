@@ -14,10 +14,13 @@
 // and accumulating |E|^2 in registers across the whole chunk.  Partial power
 // grids are reduced in LDS and written once per workgroup.
 //
-// Pass 2 (k_fftfin): one workgroup per unit sums the partial grids in a
-// fixed order and evaluates C(d) = (1/M^2) sum_u P(u) e^{+2 pi i u.d/M} only
-// at the 2n-1 x n lags it needs (separable direct DFT, x then y), then
-// V(d) = C(d) / (N_d T).
+// Finish (a second kernel, one workgroup per unit): sum the unit's partial
+// grids in a fixed order and transform back,
+// C(d) = (1/M^2) sum_u P(u) e^{+2 pi i u.d/M}, then V(d) = C(d) / (N_d T).
+// For M <= 64 with register FFTs (k_fftfin_fft); for M = 128 by a separable
+// direct DFT at the 2n-1 x n lags it needs (k_fftfin).  A kernel boundary
+// rather than a "last workgroup" handshake: the XCDs' L2 caches are not
+// coherent, so a device-scope fence in every workgroup costs far more.
 #include "rrc_device.h"
 #include "rrc_launch.h"
 
@@ -48,6 +51,85 @@ __device__ __forceinline__ float2 load_volt<true>(const void* base, size_t idx) 
     const int re = (b << 24) >> 28;            // sign-extended high nibble
     const int im = (b << 28) >> 28;            // sign-extended low nibble
     return make_float2((float)re, (float)im);
+}
+
+// Lag index of a canonical d in the V^unique layout.
+__device__ __forceinline__ int lag_index(int n, int dx, int dy) {
+    return dy == 0 ? dx - 1 : (n - 1) + (dy - 1) * (2 * n - 1) + (dx + n - 1);
+}
+
+// Inverse transform of one unit's integrated power grid and redundant
+// normalisation, by one workgroup, for M <= 64: C = conj(FFT2(P)) / M^2
+// (P is real).  Only M/2-point FFTs are used, so the registers needed match
+// the main loop.  Rows: P is real, so its M-point transform comes from one
+// M/2-point FFT of z_k = P_{2k} + i P_{2k+1} (X_f = A_f + w^f B_f,
+// X_{f+M/2} = A_f - w^f B_f with A, B the transforms of the even and odd
+// samples, recovered from Z_f and conj(Z_{M/2-f})).  Columns: only
+// dx in (-n, n) and dy in [0, n) are needed; two threads per column
+// transform the even and odd rows, and X_dy = E_dy + w^dy O_dy.
+// `lds` must hold M (M+1) + M^2 complex values.
+template <int M>
+__device__ __forceinline__ void inverse_to_lags(float2* lds, const float* __restrict__ src, int nchunk,
+                                                int n, int T, float2* __restrict__ vunique,
+                                                float* __restrict__ vauto, int unit) {
+    constexpr int H = M / 2, RS = M + 1, NT = kFftThreads;
+    float2* A = lds;                                       // [M][RS] row transforms
+    float* psum = reinterpret_cast<float*>(lds + M * RS);  // [M][RS] integrated power
+    float2* eo = lds + M * RS;                             // [2][M][H], reuses psum's space
+    const int tid = threadIdx.x;
+    for (int q = tid; q < M * M; q += NT) {
+        float acc2 = 0.0f;
+        for (int c = 0; c < nchunk; ++c) acc2 += src[(size_t)c * (M * M) + q];
+        psum[(q / M) * RS + (q % M)] = acc2;
+    }
+    __syncthreads();
+    if (tid < M) {
+        float2 z[H];
+#pragma unroll
+        for (int k = 0; k < H; ++k) z[k] = make_float2(psum[tid * RS + 2 * k], psum[tid * RS + 2 * k + 1]);
+        fft_dif<H>(z);
+#pragma unroll
+        for (int f = 0; f < H; ++f) {
+            const float2 zf = z[bitrev<H>(f)];
+            const float2 zc = cconj(z[bitrev<H>((H - f) & (H - 1))]);
+            const float2 ev = make_float2(0.5f * (zf.x + zc.x), 0.5f * (zf.y + zc.y));
+            const float2 od = make_float2(0.5f * (zf.y - zc.y), -0.5f * (zf.x - zc.x));
+            const float2 wod = twmul<M>(od, f);
+            A[tid * RS + f] = cadd(ev, wod);
+            A[tid * RS + f + H] = csub(ev, wod);
+        }
+    }
+    __syncthreads();
+    {
+        const int f = tid >> 1, h = tid & 1;
+        const int dx = f < H ? f : f - M;
+        if (tid < 2 * M && dx > -n && dx < n) {
+            float2 x[H];
+#pragma unroll
+            for (int k = 0; k < H; ++k) x[k] = A[(2 * k + h) * RS + f];
+            fft_dif<H>(x);
+#pragma unroll
+            for (int r = 0; r < H; ++r) eo[(h * M + f) * H + bitrev<H>(r)] = x[r];
+        }
+    }
+    __syncthreads();
+    const int N = n * n;
+    const int nlag = 2 * n * (n - 1);
+    const float norm = 1.0f / ((float)M * (float)M * (float)T);
+    for (int q = tid; q < M * n; q += NT) {
+        const int f = q / n, dy = q % n;
+        const int dx = f < H ? f : f - M;
+        if (dx <= -n || dx >= n || (dy == 0 && dx < 0)) continue;
+        const float2 xv = cadd(eo[f * H + dy], twmul<M>(eo[(M + f) * H + dy], dy));
+        const float2 c = make_float2(xv.x * norm, -xv.y * norm);
+        if (dx == 0 && dy == 0) {
+            vauto[unit] = c.x / (float)N;
+        } else {
+            const int adx = dx < 0 ? -dx : dx;
+            const float nd = (float)((n - adx) * (n - dy));
+            vunique[(size_t)unit * nlag + lag_index(n, dx, dy)] = make_float2(c.x / nd, c.y / nd);
+        }
+    }
 }
 
 template <int M, bool CI4>
@@ -153,11 +235,6 @@ __global__ __launch_bounds__(kFftThreads) void k_fftcorr(const void* __restrict_
     for (int q = tid; q < M * M; q += NT) dst[q] = pl[q];
 }
 
-// Lag index of a canonical d in the V^unique layout.
-__device__ __forceinline__ int lag_index(int n, int dx, int dy) {
-    return dy == 0 ? dx - 1 : (n - 1) + (dy - 1) * (2 * n - 1) + (dx + n - 1);
-}
-
 constexpr int kFinThreads = 256;
 constexpr int kFinDxBlock = 32;
 
@@ -224,6 +301,17 @@ __global__ __launch_bounds__(kFinThreads) void k_fftfin(const float* __restrict_
     }
 }
 
+// Finish for M <= 64: one workgroup per unit, register FFTs (see
+// inverse_to_lags).
+template <int M>
+__global__ __launch_bounds__(kFftThreads) void k_fftfin_fft(const float* __restrict__ ppart, int nchunk,
+                                                            int n, int T, float2* __restrict__ vunique,
+                                                            float* __restrict__ vauto) {
+    __shared__ float2 lds[M * (M + 1) + M * M];
+    const int unit = blockIdx.x;
+    inverse_to_lags<M>(lds, ppart + (size_t)unit * nchunk * (M * M), nchunk, n, T, vunique, vauto, unit);
+}
+
 template <int M, bool CI4>
 static hipError_t launch_fft_m(const FftLaunch& L, hipStream_t st) {
     dim3 grid1(L.nchunk, L.n_units);
@@ -231,8 +319,13 @@ static hipError_t launch_fft_m(const FftLaunch& L, hipStream_t st) {
                        L.ppart, L.n, L.T, L.tchunk, L.nchunk);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_fftfin<M>), dim3(L.n_units), dim3(kFinThreads), 0, st, L.ppart, L.nchunk,
-                       L.n, L.T, L.vunique, L.vauto);
+    if constexpr (M <= 64) {
+        hipLaunchKernelGGL((k_fftfin_fft<M>), dim3(L.n_units), dim3(kFftThreads), 0, st, L.ppart,
+                           L.nchunk, L.n, L.T, L.vunique, L.vauto);
+    } else {
+        hipLaunchKernelGGL((k_fftfin<M>), dim3(L.n_units), dim3(kFinThreads), 0, st, L.ppart,
+                           L.nchunk, L.n, L.T, L.vunique, L.vauto);
+    }
     return hipGetLastError();
 }
 

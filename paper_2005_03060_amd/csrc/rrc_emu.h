@@ -1,11 +1,13 @@
 // Host shims that let the workgroup bodies of the kernels compile as plain
 // C++ (RRC_HOST_EMU).  Every work-item of a workgroup runs as a cooperative
-// fiber in one OS thread; __syncthreads() switches to the next fiber, so a
-// barrier completes once every fiber has reached it.  __shfl_xor goes
-// through a shared exchange buffer between two barriers.  A fiber that
-// finishes while others still wait at a barrier is reported as a
-// non-uniform barrier.  Used only by the CPU test-suite to exercise kernel
-// logic without a GPU; the library itself never includes this file.
+// fiber in one OS thread; __syncthreads() completes once every fiber has
+// reached it, and the wave-level exchange behind __shfl_xor once the 64
+// fibers of the wave have.  Barriers reached by only some fibers are
+// reported as non-uniform.  The order in which the fibers run between two
+// barriers is selectable (forward, reverse or a seeded shuffle per
+// interval): results that depend on it reveal a data race.  Used only by the
+// CPU test-suite to exercise kernel logic without a GPU; the library itself
+// never includes this file.
 #pragma once
 
 #include <ucontext.h>
@@ -13,7 +15,9 @@
 #include <cmath>
 #include <cstddef>
 #include <cstdint>
+#include <algorithm>
 #include <functional>
+#include <random>
 #include <vector>
 
 #define __host__
@@ -36,14 +40,18 @@ struct Dim {
     unsigned x;
 };
 
+enum State { RUN = 0, AT_BLOCK = 1, AT_WAVE = 2, DONE = 3 };
+
 struct Group {
     int nthreads = 0;
     std::vector<ucontext_t> ctx;
     std::vector<std::vector<char>> stacks;
-    std::vector<char> done;
+    std::vector<int> state;
     ucontext_t sched;
     double xbuf[1024];
     bool bad_barrier = false;
+    int order = 0;            // 0 forward, 1 reverse, 2 shuffled per interval
+    unsigned seed = 1;
 };
 
 inline Group& group() {
@@ -61,17 +69,25 @@ inline std::function<void()>& body() {
 
 inline void fiber_entry() {
     body()();
-    group().done[cur().x] = 1;
+    group().state[cur().x] = DONE;
 }
 
-// Runs f() as `nthreads` work-items of one workgroup.  Returns false if the
-// barriers were not reached uniformly.
+inline void wait_as(int st) {
+    Group& g = group();
+    g.state[cur().x] = st;
+    swapcontext(&g.ctx[cur().x], &g.sched);
+}
+
+// Runs f() as `nthreads` work-items of one workgroup (waves of 64).
+// Work-items run until they reach a barrier; a wave barrier releases when
+// all 64 work-items of the wave wait at one, a workgroup barrier when all
+// work-items do.  Returns false if the barriers were not reached uniformly.
 inline bool run_group(int nthreads, const std::function<void()>& f) {
     Group& g = group();
     g.nthreads = nthreads;
     g.ctx.assign(nthreads, ucontext_t{});
     g.stacks.assign(nthreads, std::vector<char>(256 * 1024));
-    g.done.assign(nthreads, 0);
+    g.state.assign(nthreads, RUN);
     g.bad_barrier = false;
     body() = f;
     for (int t = 0; t < nthreads; ++t) {
@@ -81,43 +97,66 @@ inline bool run_group(int nthreads, const std::function<void()>& f) {
         g.ctx[t].uc_link = &g.sched;
         makecontext(&g.ctx[t], fiber_entry, 0);
     }
+    std::vector<int> perm(nthreads);
+    for (int t = 0; t < nthreads; ++t) perm[t] = t;
+    std::mt19937 rng(g.seed);
+    if (g.order == 1) std::reverse(perm.begin(), perm.end());
+    const int nwaves = (nthreads + 63) / 64;
     while (true) {
-        int finished = 0;
-        for (int t = 0; t < nthreads; ++t) {
-            if (g.done[t]) {
-                ++finished;
-                continue;
-            }
+        if (g.order == 2) std::shuffle(perm.begin(), perm.end(), rng);
+        for (int q = 0; q < nthreads; ++q) {
+            const int t = perm[q];
+            if (g.state[t] != RUN) continue;
             cur().x = (unsigned)t;
             swapcontext(&g.sched, &g.ctx[t]);
-            if (g.done[t]) ++finished;
         }
-        if (finished == nthreads) break;
-        if (finished > 0) {            // some returned while others wait at a barrier
-            g.bad_barrier = true;
-            break;
+        // every work-item now waits at a barrier or is done
+        bool released = false;
+        for (int w = 0; w < nwaves; ++w) {
+            int at_wave = 0, done = 0, cnt = 0;
+            for (int t = w * 64; t < std::min(nthreads, w * 64 + 64); ++t, ++cnt) {
+                at_wave += g.state[t] == AT_WAVE;
+                done += g.state[t] == DONE;
+            }
+            if (at_wave == cnt) {
+                for (int t = w * 64; t < w * 64 + cnt; ++t) g.state[t] = RUN;
+                released = true;
+            } else if (at_wave > 0 && done > 0) {
+                g.bad_barrier = true;
+                return false;
+            }
         }
+        if (released) continue;
+        int at_block = 0, done = 0;
+        for (int t = 0; t < nthreads; ++t) {
+            at_block += g.state[t] == AT_BLOCK;
+            done += g.state[t] == DONE;
+        }
+        if (done == nthreads) return true;
+        if (at_block == nthreads) {
+            for (int t = 0; t < nthreads; ++t) g.state[t] = RUN;
+            continue;
+        }
+        g.bad_barrier = true;      // mixed: some at a barrier the others never reach
+        return false;
     }
-    return !g.bad_barrier;
 }
 
 }  // namespace rrc_emu
 
 #define threadIdx (rrc_emu::cur())
 
-inline void __syncthreads() {
-    rrc_emu::Group& g = rrc_emu::group();
-    swapcontext(&g.ctx[rrc_emu::cur().x], &g.sched);
-}
+inline void __syncthreads() { rrc_emu::wait_as(rrc_emu::AT_BLOCK); }
 
-// All work-items of the group call this together (uniform control flow).
+// Cross-lane exchange within a wave: all 64 work-items of the wave call it
+// together.
 template <typename T>
 inline T __shfl_xor(T v, int o, int /*width*/) {
     rrc_emu::Group& g = rrc_emu::group();
     const unsigned t = rrc_emu::cur().x;
     g.xbuf[t] = (double)v;
-    __syncthreads();
+    rrc_emu::wait_as(rrc_emu::AT_WAVE);
     const T r = (T)g.xbuf[rrc_emu::cur().x ^ (unsigned)o];
-    __syncthreads();
+    rrc_emu::wait_as(rrc_emu::AT_WAVE);
     return r;
 }

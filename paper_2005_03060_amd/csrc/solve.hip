@@ -81,6 +81,7 @@ size_t solve_slab_bytes(const Sel& s, bool lds) {
 size_t solve_lds_bytes(const Sel& s, bool lds) { return lds ? hot_layout(s).bytes : 0; }
 
 struct Mem {
+    const Sel* ls;          // the selection copied to LDS, for type-indexed lookups
     float *w, *sa, *sp, *d;
     float *xa, *ra, *za, *pa, *qa;
     float *xp, *rp, *zp, *pp, *qp;
@@ -92,53 +93,77 @@ struct Mem {
 
 // ------------------------------------------------------------ reductions
 
-__device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
 struct Shared {
-    float redf[kSWaves * 3 * kMaxTypes];
-    double tq[kSWaves * 2 * kMaxTypes];
-    double redd[kSWaves * 12];
+    Sel sel;                                // copy of the selection (runtime type indices)
+    float bf[2 * kSWaves * 4];              // block_sum slots (two phases)
+    double bd[2 * kSWaves * 12];
     double bcast[8];
 };
 
-// Sums NV values over the workgroup; every thread gets the totals.
-// Fixed order (waves 0..W-1), so the result is deterministic.
-template <int NV, typename T>
-__device__ __forceinline__ void block_sum(T (&v)[NV], T* red) {
+// Sums NV values over the workgroup; every thread gets the totals, in a
+// fixed order (deterministic).  The slots alternate between two phases, so
+// one barrier suffices: a slot is rewritten only two calls later, after a
+// barrier every reader of the previous use has passed.
+struct Reducer {
+    Shared* sh;
+    int pf = 0, pd = 0;
+};
+
+template <int NV>
+__device__ __forceinline__ void block_sum(float (&v)[NV], Reducer& R) {
+    static_assert(NV <= 4, "float slots");
+    float* slot = R.sh->bf + R.pf * (kSWaves * 4);
+    R.pf ^= 1;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-    for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
+    for (int i = 0; i < NV; ++i) v[i] = wave_allsum(v[i]);
     if (lane == 0) {
 #pragma unroll
-        for (int i = 0; i < NV; ++i) red[wave * NV + i] = v[i];
+        for (int i = 0; i < NV; ++i) slot[wave * 4 + i] = v[i];
     }
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
-        T s = 0;
-        for (int w = 0; w < kSWaves; ++w) s += red[w * NV + i];
+        float s = 0.f;
+        for (int w = 0; w < kSWaves; ++w) s += slot[w * 4 + i];
         v[i] = s;
     }
+}
+
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], Reducer& R) {
+    static_assert(NV <= 12, "double slots");
+    double* slot = R.sh->bd + R.pd * (kSWaves * 12);
+    R.pd ^= 1;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[i] = wave_allsum(v[i]);
+    if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) slot[wave * 12 + i] = v[i];
+    }
     __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        double s = 0.0;
+        for (int w = 0; w < kSWaves; ++w) s += slot[w * 12 + i];
+        v[i] = s;
+    }
 }
 
 // --------------------------------------------------------- pair visitors
 //
-// Every pair is visited once, from its first antenna: thread-owned
-// antennas a = tid + k*NT, types t.  b = global pair index, j = partner.
+// Work-item tid owns antennas a = tid + k*NT (k < APT) and, for the type
+// unknowns, type row t = 4*lane + wave (lane = tid % 64, wave = tid / 64)
+// when that is < K.  Every pair is visited once from its first antenna.
+// The selection is read from its LDS copy.  Type rows are summed by waves over each type's
+// contiguous pair range (wave w takes types w, w+4, ...), and the owner lane
+// of a type row is in the wave that sums it.
 
 template <int APT>
 struct Own {
     int a[APT], x[APT], y[APT];
+    int trow;   // owned type row, or -1
 };
 
 template <int APT>
@@ -150,6 +175,8 @@ __device__ __forceinline__ Own<APT> own_antennas(const Sel& s) {
         o.x[k] = o.a[k] % s.n;
         o.y[k] = o.a[k] / s.n;
     }
+    const int t = (threadIdx.x & 63) * kSWaves + (threadIdx.x >> 6);
+    o.trow = t < s.K ? t : -1;
     return o;
 }
 
@@ -169,21 +196,29 @@ __device__ __forceinline__ double2 load_vred_d(const void* v, bool ci4, size_t i
     return make_double2(f.x, f.y);
 }
 
-// Antenna gather: sum over the 2K pairs touching antenna (x, y) of
-// f(first-array value) and g(second-array value), signs +/- per system.
+// Antenna rows: out_a = sum over the pairs touching a of A_b (both ends),
+// B_b (first end) - B_b (second end), and C_b (both ends, if C).
 template <int APT>
-__device__ __forceinline__ void gather3(const Sel& s, const Own<APT>& o, const float* A, const float* B,
-                                        const float* C, float* outA, float* outB, float* outC,
-                                        float sgnB2) {
+__device__ __forceinline__ void gather_rows(const Sel& s, const Own<APT>& o, const float* A,
+                                            const float* B, const float* C, float* outA,
+                                            float* outB, float* outC) {
 #pragma unroll
     for (int k = 0; k < APT; ++k) {
         if (o.a[k] >= s.N) continue;
         float ya = 0.f, yb = 0.f, yc = 0.f;
         for (int t = 0; t < s.K; ++t) {
             const int b1 = pair_as_first(s, t, o.x[k], o.y[k]);
-            if (b1 >= 0) { ya += A[b1]; yb += B[b1]; if (C) yc += C[b1]; }
             const int b2 = pair_as_second(s, t, o.x[k], o.y[k]);
-            if (b2 >= 0) { ya += A[b2]; yb += sgnB2 * B[b2]; if (C) yc += C[b2]; }
+            if (b1 >= 0) {
+                ya += A[b1];
+                yb += B[b1];
+                if (C) yc += C[b1];
+            }
+            if (b2 >= 0) {
+                ya += A[b2];
+                yb -= B[b2];
+                if (C) yc += C[b2];
+            }
         }
         outA[o.a[k]] = ya;
         outB[o.a[k]] = yb;
@@ -191,37 +226,41 @@ __device__ __forceinline__ void gather3(const Sel& s, const Own<APT>& o, const f
     }
 }
 
-// Writes the per-type sums of up to three per-pair quantities that were
-// accumulated per thread (in `part`) into dst rows N+t.
-__device__ __forceinline__ void type_sums_store(float* red, int t, float v0, float v1, float v2) {
-    v0 = wave_sum(v0);
-    v1 = wave_sum(v1);
-    v2 = wave_sum(v2);
-    if ((threadIdx.x & 63) == 0) {
-        const int w = threadIdx.x >> 6;
-        red[(w * kMaxTypes + t) * 3 + 0] = v0;
-        red[(w * kMaxTypes + t) * 3 + 1] = v1;
-        red[(w * kMaxTypes + t) * 3 + 2] = v2;
+// Type rows: out[N + t] = sum over the pairs of type t of A_b (and B_b, C_b).
+template <int APT>
+__device__ __forceinline__ void type_rows(const Sel& s, const float* A, const float* B, const float* C,
+                                          float* outA, float* outB, float* outC) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int t = wave; t < s.K; t += kSWaves) {
+        float ya = 0.f, yb = 0.f, yc = 0.f;
+        for (int b = s.off[t] + lane; b < s.off[t + 1]; b += 64) {
+            ya += A[b];
+            yb += B[b];
+            if (C) yc += C[b];
+        }
+        ya = wave_allsum(ya);
+        yb = wave_allsum(yb);
+        if (C) yc = wave_allsum(yc);
+        if (lane == t / kSWaves) {
+            outA[s.N + t] = ya;
+            outB[s.N + t] = yb;
+            if (outC) outC[s.N + t] = yc;
+        }
     }
-}
-__device__ __forceinline__ float type_sum_read(const float* red, int t, int c) {
-    float s = 0.f;
-    for (int w = 0; w < kSWaves; ++w) s += red[(w * kMaxTypes + t) * 3 + c];
-    return s;
 }
 
 // ------------------------------------------------- matrix-free operators
 //
 // Amplitude system: rows b: a_i + a_j + c_t, weight w_b.
 // Phase system:     rows b: p_i - p_j + c_t, weight w_b.
-// H x = sum_b w_b row_b (row_b . x).  Computes qa = Ha pa, qp = Hp pp.
+// H x = sum_b w_b row_b (row_b . x).  Computes qa = Ha pa, qp = Hp pp;
+// each result element is written by its owner.
 template <int APT>
-__device__ void apply_H(const Sel& s, const Own<APT>& o, const Mem& m, Shared& sh) {
+__device__ __forceinline__ void apply_H(const Sel& s, const Own<APT>& o, const Mem& m) {
     const int N = s.N;
     for (int t = 0; t < s.K; ++t) {
         const int dxy = s.dy[t] * s.n + s.dx[t];
         const float cta = m.pa[N + t], ctp = m.pp[N + t];
-        float suma = 0.f, sump = 0.f;
 #pragma unroll
         for (int k = 0; k < APT; ++k) {
             if (o.a[k] >= N) continue;
@@ -229,48 +268,35 @@ __device__ void apply_H(const Sel& s, const Own<APT>& o, const Mem& m, Shared& s
             if (b < 0) continue;
             const int i = o.a[k], j = i - dxy;
             const float wb = m.w[b];
-            const float va = wb * (m.pa[i] + m.pa[j] + cta);
-            const float vp = wb * (m.pp[i] - m.pp[j] + ctp);
-            m.sa[b] = va;
-            m.sp[b] = vp;
-            suma += va;
-            sump += vp;
+            m.sa[b] = wb * (m.pa[i] + m.pa[j] + cta);
+            m.sp[b] = wb * (m.pp[i] - m.pp[j] + ctp);
         }
-        type_sums_store(sh.redf, t, suma, sump, 0.f);
     }
     __syncthreads();
-    gather3<APT>(s, o, m.sa, m.sp, nullptr, m.qa, m.qp, nullptr, -1.0f);
-    if ((int)threadIdx.x < s.K) {
-        const int t = threadIdx.x;
-        m.qa[N + t] = type_sum_read(sh.redf, t, 0);
-        m.qp[N + t] = type_sum_read(sh.redf, t, 1);
-    }
-    __syncthreads();
+    gather_rows<APT>(s, o, m.sa, m.sp, nullptr, m.qa, m.qp, nullptr);
+    type_rows<APT>(*m.ls, m.sa, m.sp, nullptr, m.qa, m.qp, nullptr);
 }
 
 // Jacobi-preconditioned CG on both systems at once, from x = 0 with the
-// right-hand sides already in ra / rp and the diagonal in d.  Returns the
-// number of iterations, or -1 if a right-hand side is not finite.
+// right-hand sides already in ra / rp and the diagonal in d (inverted in
+// place).  Returns the number of iterations, or -1 if a right-hand side is
+// not finite.
 template <int APT>
-__device__ int pcg2(const Sel& s, const Own<APT>& o, const Mem& m, Shared& sh, int max_cg,
-                    float tol) {
-    const int N = s.N, V = s.N + s.K;
-    const bool mine_t = (int)threadIdx.x < s.K;
-    const int t_own = N + threadIdx.x;
+__device__ int pcg2(const Sel& s, const Own<APT>& o, const Mem& m, Reducer& R, int max_cg, float tol) {
+    const int N = s.N;
     auto each = [&](auto&& f) {
 #pragma unroll
         for (int k = 0; k < APT; ++k)
             if (o.a[k] < N) f(o.a[k]);
-        if (mine_t) f(t_own);
+        if (o.trow >= 0) f(N + o.trow);
     };
     float v4[4] = {0.f, 0.f, 0.f, 0.f};
     each([&](int e) {
         const float di = m.d[e] > 0.f ? 1.0f / m.d[e] : 0.f;
+        m.d[e] = di;                      // the diagonal is kept inverted from here on
         m.xa[e] = 0.f;
         m.xp[e] = 0.f;
         const float za = m.ra[e] * di, zp = m.rp[e] * di;
-        m.za[e] = za;
-        m.zp[e] = zp;
         m.pa[e] = za;
         m.pp[e] = zp;
         v4[0] += m.ra[e] * za;
@@ -278,26 +304,36 @@ __device__ int pcg2(const Sel& s, const Own<APT>& o, const Mem& m, Shared& sh, i
         v4[2] += m.ra[e] * m.ra[e];
         v4[3] += m.rp[e] * m.rp[e];
     });
-    block_sum<4>(v4, sh.redf);
+    block_sum<4>(v4, R);
     if (!(v4[2] == v4[2]) || !(v4[3] == v4[3]) || isinf(v4[2]) || isinf(v4[3])) return -1;
     float rza = v4[0], rzp = v4[1];
     const float stopa = tol * tol * v4[2], stopp = tol * tol * v4[3];
     bool done_a = !(v4[2] > 0.f), done_p = !(v4[3] > 0.f);
-    (void)V;
     int it = 0;
     for (; it < max_cg && !(done_a && done_p); ++it) {
-        apply_H<APT>(s, o, m, sh);
+        apply_H<APT>(s, o, m);
         float v2[2] = {0.f, 0.f};
         each([&](int e) {
             v2[0] += m.pa[e] * m.qa[e];
             v2[1] += m.pp[e] * m.qp[e];
         });
-        block_sum<2>(v2, sh.redf);
+        block_sum<2>(v2, R);
         const float ala = (!done_a && v2[0] > 0.f) ? rza / v2[0] : 0.f;
         const float alp = (!done_p && v2[1] > 0.f) ? rzp / v2[1] : 0.f;
         float w4[4] = {0.f, 0.f, 0.f, 0.f};
-        each([&](int e) {
-            const float di = m.d[e] > 0.f ? 1.0f / m.d[e] : 0.f;
+        float za_own[APT + 1], zp_own[APT + 1];
+#pragma unroll
+        for (int k = 0; k <= APT; ++k) {
+            za_own[k] = zp_own[k] = 0.f;
+            int e;
+            if (k < APT) {
+                e = o.a[k];
+                if (e >= N) continue;
+            } else {
+                if (o.trow < 0) continue;
+                e = N + o.trow;
+            }
+            const float di = m.d[e];
             m.xa[e] += ala * m.pa[e];
             m.xp[e] += alp * m.pp[e];
             const float ra = m.ra[e] - ala * m.qa[e];
@@ -305,22 +341,31 @@ __device__ int pcg2(const Sel& s, const Own<APT>& o, const Mem& m, Shared& sh, i
             m.ra[e] = ra;
             m.rp[e] = rp;
             const float za = ra * di, zp = rp * di;
-            m.za[e] = za;
-            m.zp[e] = zp;
+            za_own[k] = za;
+            zp_own[k] = zp;
             w4[0] += ra * za;
             w4[1] += rp * zp;
             w4[2] += ra * ra;
             w4[3] += rp * rp;
-        });
-        block_sum<4>(w4, sh.redf);
+        }
+        block_sum<4>(w4, R);
         const float ba = (rza > 0.f) ? w4[0] / rza : 0.f;
         const float bp = (rzp > 0.f) ? w4[1] / rzp : 0.f;
         if (!done_a) rza = w4[0];
         if (!done_p) rzp = w4[1];
-        each([&](int e) {
-            if (!done_a) m.pa[e] = m.za[e] + ba * m.pa[e];
-            if (!done_p) m.pp[e] = m.zp[e] + bp * m.pp[e];
-        });
+#pragma unroll
+        for (int k = 0; k <= APT; ++k) {
+            int e;
+            if (k < APT) {
+                e = o.a[k];
+                if (e >= N) continue;
+            } else {
+                if (o.trow < 0) continue;
+                e = N + o.trow;
+            }
+            if (!done_a) m.pa[e] = za_own[k] + ba * m.pa[e];
+            if (!done_p) m.pp[e] = zp_own[k] + bp * m.pp[e];
+        }
         done_a = done_a || !(w4[2] > stopa);
         done_p = done_p || !(w4[3] > stopp);
         __syncthreads();
@@ -332,41 +377,30 @@ __device__ int pcg2(const Sel& s, const Own<APT>& o, const Mem& m, Shared& sh, i
 
 // Residual pass, FP32: for every pair m_b, w_b = |m_b|^2 and
 // q_b = r_b conj(m_b); then the right-hand sides (ra, rp = J^H r split into
-// real and imaginary parts) and the diagonal d by antenna gather.
+// real and imaginary parts) and the diagonal d.
 template <int APT>
-__device__ void residual_pass32(const Sel& s, const Own<APT>& o, const Mem& m, Shared& sh,
-                                const void* vred, bool ci4, size_t vbase) {
+__device__ void residual_pass32(const Sel& s, const Own<APT>& o, const Mem& m, const void* vred,
+                                bool ci4, size_t vbase) {
     const int N = s.N;
     for (int t = 0; t < s.K; ++t) {
         const int dxy = s.dy[t] * s.n + s.dx[t];
-        float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+        const float2 vt = m.vm[t];
 #pragma unroll
         for (int k = 0; k < APT; ++k) {
             if (o.a[k] >= N) continue;
             const int b = pair_as_first(s, t, o.x[k], o.y[k]);
             if (b < 0) continue;
             const int i = o.a[k], j = i - dxy;
-            const float2 mm = cmul(cmulc(m.g[i], m.g[j]), m.vm[t]);
+            const float2 mm = cmul(cmulc(m.g[i], m.g[j]), vt);
             const float2 q = cmulc(csub(load_vred(vred, ci4, vbase + b), mm), mm);
-            const float wb = cabs2(mm);
             m.sa[b] = q.x;
             m.sp[b] = q.y;
-            m.w[b] = wb;
-            s0 += q.x;
-            s1 += q.y;
-            s2 += wb;
+            m.w[b] = cabs2(mm);
         }
-        type_sums_store(sh.redf, t, s0, s1, s2);
     }
     __syncthreads();
-    gather3<APT>(s, o, m.sa, m.sp, m.w, m.ra, m.rp, m.d, -1.0f);
-    if ((int)threadIdx.x < s.K) {
-        const int t = threadIdx.x;
-        m.ra[N + t] = type_sum_read(sh.redf, t, 0);
-        m.rp[N + t] = type_sum_read(sh.redf, t, 1);
-        m.d[N + t] = type_sum_read(sh.redf, t, 2);
-    }
-    __syncthreads();
+    gather_rows<APT>(s, o, m.sa, m.sp, m.w, m.ra, m.rp, m.d);
+    type_rows<APT>(*m.ls, m.sa, m.sp, m.w, m.ra, m.rp, m.d);
 }
 
 // q_b = r_b conj(m_b) in FP64 for the pair (i, j) of type t.
@@ -379,38 +413,25 @@ __device__ __forceinline__ double2 q_hi(const Mem& m, const void* vred, bool ci4
 
 // Residual pass, FP64: near the optimum J^H r is a sum of per-pair terms
 // of the size of the noise that cancel to a tiny total, so it is summed in
-// FP64, per antenna, recomputing each pair's residual at both ends.  The
-// FP32 normal equations then get the right-hand side scaled to unit norm;
-// the scale is returned (multiply the solution by it).
+// FP64: per antenna over its pairs, and per type by the summing wave, each
+// pair's residual recomputed where it is needed.  The FP32 normal
+// equations then get the right-hand side scaled to unit norm; the scale is
+// returned (multiply the solution by it).
 template <int APT>
-__device__ double residual_pass64(const Sel& s, const Own<APT>& o, const Mem& m, Shared& sh,
+__device__ double residual_pass64(const Sel& s, const Own<APT>& o, const Mem& m, Reducer& R,
                                   const void* vred, bool ci4, size_t vbase) {
     const int N = s.N;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int t = 0; t < s.K; ++t) {
         const int dxy = s.dy[t] * s.n + s.dx[t];
-        double q0 = 0.0, q1 = 0.0;
-        float s2 = 0.f;
 #pragma unroll
         for (int k = 0; k < APT; ++k) {
             if (o.a[k] >= N) continue;
             const int b = pair_as_first(s, t, o.x[k], o.y[k]);
             if (b < 0) continue;
-            const int i = o.a[k], j = i - dxy;
-            double wb;
-            const double2 q = q_hi(m, vred, ci4, vbase, b, i, j, t, wb);
-            m.w[b] = (float)wb;
-            q0 += q.x;
-            q1 += q.y;
-            s2 += (float)wb;
-        }
-        q0 = wave_sum(q0);
-        q1 = wave_sum(q1);
-        s2 = wave_sum(s2);
-        if ((threadIdx.x & 63) == 0) {
-            const int w = threadIdx.x >> 6;
-            sh.tq[(w * kMaxTypes + t) * 2 + 0] = q0;
-            sh.tq[(w * kMaxTypes + t) * 2 + 1] = q1;
-            sh.redf[(w * kMaxTypes + t) * 3 + 2] = s2;
+            const int i = o.a[k];
+            const double2 mm = dmul(dmulc(m.gd[i], m.gd[i - dxy]), m.vmd[t]);
+            m.w[b] = (float)dabs2(mm);
         }
     }
     __syncthreads();
@@ -426,16 +447,15 @@ __device__ double residual_pass64(const Sel& s, const Own<APT>& o, const Mem& m,
         for (int t = 0; t < s.K; ++t) {
             const int dxy = s.dy[t] * s.n + s.dx[t];
             const int b1 = pair_as_first(s, t, o.x[k], o.y[k]);
+            const int b2 = pair_as_second(s, t, o.x[k], o.y[k]);
+            double wb;
             if (b1 >= 0) {
-                double wb;
                 const double2 q = q_hi(m, vred, ci4, vbase, b1, a, a - dxy, t, wb);
                 ya += q.x;
                 yp += q.y;
                 dd += m.w[b1];
             }
-            const int b2 = pair_as_second(s, t, o.x[k], o.y[k]);
             if (b2 >= 0) {
-                double wb;
                 const double2 q = q_hi(m, vred, ci4, vbase, b2, a + dxy, a, t, wb);
                 ya += q.x;
                 yp -= q.y;
@@ -448,21 +468,30 @@ __device__ double residual_pass64(const Sel& s, const Own<APT>& o, const Mem& m,
         nrm[0] += ya * ya + yp * yp;
     }
     ra_loc[APT] = rp_loc[APT] = 0.0;
-    if ((int)threadIdx.x < s.K) {
-        const int t = threadIdx.x;
-        double a0 = 0.0, a1 = 0.0;
-        float dsum = 0.f;
-        for (int w = 0; w < kSWaves; ++w) {
-            a0 += sh.tq[(w * kMaxTypes + t) * 2 + 0];
-            a1 += sh.tq[(w * kMaxTypes + t) * 2 + 1];
-            dsum += sh.redf[(w * kMaxTypes + t) * 3 + 2];
+    const Sel& ls = *m.ls;
+    for (int t = wave; t < ls.K; t += kSWaves) {
+        double ya = 0.0, yp = 0.0;
+        float dd = 0.f;
+        for (int b = ls.off[t] + lane; b < ls.off[t + 1]; b += 64) {
+            int i, j;
+            pair_ij(ls, t, b - ls.off[t], i, j);
+            double wb;
+            const double2 q = q_hi(m, vred, ci4, vbase, b, i, j, t, wb);
+            ya += q.x;
+            yp += q.y;
+            dd += m.w[b];
         }
-        ra_loc[APT] = a0;
-        rp_loc[APT] = a1;
-        m.d[N + t] = dsum;
-        nrm[0] += a0 * a0 + a1 * a1;
+        ya = wave_allsum(ya);
+        yp = wave_allsum(yp);
+        dd = wave_allsum(dd);
+        if (lane == t / kSWaves) {
+            ra_loc[APT] = ya;
+            rp_loc[APT] = yp;
+            m.d[N + t] = dd;
+            nrm[0] += ya * ya + yp * yp;
+        }
     }
-    block_sum<1>(nrm, sh.redd);
+    block_sum<1>(nrm, R);
     const double scale = nrm[0] > 0.0 ? sqrt(nrm[0]) : 1.0;
     const double inv = 1.0 / scale;
 #pragma unroll
@@ -471,80 +500,65 @@ __device__ double residual_pass64(const Sel& s, const Own<APT>& o, const Mem& m,
         m.ra[o.a[k]] = (float)(ra_loc[k] * inv);
         m.rp[o.a[k]] = (float)(rp_loc[k] * inv);
     }
-    if ((int)threadIdx.x < s.K) {
-        m.ra[N + threadIdx.x] = (float)(ra_loc[APT] * inv);
-        m.rp[N + threadIdx.x] = (float)(rp_loc[APT] * inv);
+    if (o.trow >= 0) {
+        m.ra[N + o.trow] = (float)(ra_loc[APT] * inv);
+        m.rp[N + o.trow] = (float)(rp_loc[APT] * inv);
     }
-    __syncthreads();
     return scale;
 }
 
-// V_t = mean over the group of V_b / (g_i conj(g_j)) (FP32 parameters).
+// V_t = mean over the group of V_b / (g_i conj(g_j)) (FP32 parameters),
+// summed by the waves; visible to all after the closing barrier.
 template <int APT>
-__device__ void group_mean(const Sel& s, const Own<APT>& o, const Mem& m, Shared& sh,
-                           const void* vred, bool ci4, size_t vbase) {
-    const int N = s.N;
-    for (int t = 0; t < s.K; ++t) {
-        const int dxy = s.dy[t] * s.n + s.dx[t];
+__device__ void group_mean(const Mem& m, const void* vred, bool ci4, size_t vbase) {
+    const Sel& s = *m.ls;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int t = wave; t < s.K; t += kSWaves) {
         float sr = 0.f, si = 0.f;
-#pragma unroll
-        for (int k = 0; k < APT; ++k) {
-            if (o.a[k] >= N) continue;
-            const int b = pair_as_first(s, t, o.x[k], o.y[k]);
-            if (b < 0) continue;
-            const int i = o.a[k], j = i - dxy;
+        for (int b = s.off[t] + lane; b < s.off[t + 1]; b += 64) {
+            int i, j;
+            pair_ij(s, t, b - s.off[t], i, j);
             const float2 gg = cmulc(m.g[i], m.g[j]);
             const float2 q = cmulc(load_vred(vred, ci4, vbase + b), gg);
             const float inv = 1.0f / cabs2(gg);
             sr += q.x * inv;
             si += q.y * inv;
         }
-        type_sums_store(sh.redf, t, sr, si, 0.f);
-    }
-    __syncthreads();
-    if ((int)threadIdx.x < s.K) {
-        const int t = threadIdx.x;
-        const float cnt = (float)(s.off[t + 1] - s.off[t]);
-        m.vm[t] = make_float2(type_sum_read(sh.redf, t, 0) / cnt, type_sum_read(sh.redf, t, 1) / cnt);
+        sr = wave_allsum(sr);
+        si = wave_allsum(si);
+        if (lane == 0) {
+            const float cnt = (float)(s.off[t + 1] - s.off[t]);
+            m.vm[t] = make_float2(sr / cnt, si / cnt);
+        }
     }
     __syncthreads();
 }
 
 // Logcal amplitudes and chained phases (see the file comment).
 template <int APT>
-__device__ void firstcal(const Sel& s, const Own<APT>& o, const Mem& m, Shared& sh, const void* vred,
+__device__ void firstcal(const Sel& s, const Own<APT>& o, const Mem& m, Reducer& R, const void* vred,
                          bool ci4, size_t vbase, int t10, int t01, int max_cg) {
     const int N = s.N, n = s.n;
     // amplitude: unweighted least squares on ln|V_b|
     for (int t = 0; t < s.K; ++t) {
-        float s0 = 0.f, s2 = 0.f;
 #pragma unroll
         for (int k = 0; k < APT; ++k) {
             if (o.a[k] >= N) continue;
             const int b = pair_as_first(s, t, o.x[k], o.y[k]);
             if (b < 0) continue;
-            const float lv = 0.5f * logf(fmaxf(cabs2(load_vred(vred, ci4, vbase + b)), 1e-30f));
-            m.sa[b] = lv;
+            m.sa[b] = 0.5f * logf(fmaxf(cabs2(load_vred(vred, ci4, vbase + b)), 1e-30f));
             m.sp[b] = 0.f;
             m.w[b] = 1.0f;
-            s0 += lv;
-            s2 += 1.0f;
         }
-        type_sums_store(sh.redf, t, s0, 0.f, s2);
     }
     __syncthreads();
-    gather3<APT>(s, o, m.sa, m.sp, m.w, m.ra, m.rp, m.d, -1.0f);
-    if ((int)threadIdx.x < s.K) {
-        const int t = threadIdx.x;
-        m.ra[N + t] = type_sum_read(sh.redf, t, 0);
-        m.rp[N + t] = 0.f;
-        m.d[N + t] = type_sum_read(sh.redf, t, 2);
-    }
-    __syncthreads();
-    pcg2<APT>(s, o, m, sh, max_cg, 1e-5f);
+    gather_rows<APT>(s, o, m.sa, m.sp, m.w, m.ra, m.rp, m.d);
+    type_rows<APT>(*m.ls, m.sa, m.sp, m.w, m.ra, m.rp, m.d);
+    pcg2<APT>(s, o, m, R, max_cg, 1e-3f);
     // phase increments along the chains, in qp[] (scratch)
-    const float2 v10 = load_vred(vred, ci4, vbase + s.off[t10]);
-    const float2 v01 = load_vred(vred, ci4, vbase + s.off[t01]);
+    const int off10 = m.ls->off[t10], off01 = m.ls->off[t01];
+    const float2 v10 = load_vred(vred, ci4, vbase + off10);
+    const float2 v01 = load_vred(vred, ci4, vbase + off01);
     const float psi10 = atan2f(v10.y, v10.x), psi01 = atan2f(v01.y, v01.x);
     const float2 r10 = make_float2(cosf(psi10), -sinf(psi10));
     const float2 r01 = make_float2(cosf(psi01), -sinf(psi01));
@@ -554,10 +568,10 @@ __device__ void firstcal(const Sel& s, const Own<APT>& o, const Mem& m, Shared& 
         const int x = o.x[k], y = o.y[k];
         float inc = 0.f;
         if (y == 0 && x >= 1) {
-            const float2 v = cmul(load_vred(vred, ci4, vbase + s.off[t10] + (x - 1)), r10);
+            const float2 v = cmul(load_vred(vred, ci4, vbase + off10 + (x - 1)), r10);
             inc = atan2f(v.y, v.x);
         } else if (y >= 1) {
-            const float2 v = cmul(load_vred(vred, ci4, vbase + s.off[t01] + (y - 1) * n + x), r01);
+            const float2 v = cmul(load_vred(vred, ci4, vbase + off01 + (y - 1) * n + x), r01);
             inc = atan2f(v.y, v.x);
         }
         m.qp[o.a[k]] = inc;
@@ -589,7 +603,19 @@ __device__ void firstcal(const Sel& s, const Own<APT>& o, const Mem& m, Shared& 
 // The whole solve of one unit by one workgroup.
 template <int APT, bool LDS>
 __device__ void solve_unit(const SolveLaunch& L, Shared& sh, unsigned char* ssm, int unit) {
-    const Sel& s = L.sel;
+    // The selection is read from an LDS copy: indexing the by-value kernel
+    // argument with a type index would make the compiler copy the argument
+    // to private memory.
+    if (threadIdx.x == 0) {
+        const int* src = reinterpret_cast<const int*>(&L.sel);
+        int* dst = reinterpret_cast<int*>(&sh.sel);
+#pragma unroll
+        for (int i = 0; i < (int)(sizeof(Sel) / sizeof(int)); ++i) dst[i] = src[i];
+    }
+    __syncthreads();
+    const Sel& ls = sh.sel;
+    const Sel& s = ls;
+    Reducer R{&sh};
     const int N = s.N, K = s.K;
     const size_t vbase = (size_t)unit * s.P;
     char* slab = L.slab + (size_t)unit * L.slab_bytes;
@@ -597,6 +623,7 @@ __device__ void solve_unit(const SolveLaunch& L, Shared& sh, unsigned char* ssm,
     const HotLayout H = hot_layout(s);
     const ColdLayout C = cold_layout(s, LDS ? 0 : H.bytes);
     Mem m;
+    m.ls = &ls;
     m.w = reinterpret_cast<float*>(hot + H.w);
     m.sa = reinterpret_cast<float*>(hot + H.sa);
     m.sp = reinterpret_cast<float*>(hot + H.sp);
@@ -628,12 +655,12 @@ __device__ void solve_unit(const SolveLaunch& L, Shared& sh, unsigned char* ssm,
     } else {
         int t10 = -1, t01 = -1;
         for (int t = 0; t < K; ++t) {
-            if (s.dx[t] == 1 && s.dy[t] == 0) t10 = t;
-            if (s.dx[t] == 0 && s.dy[t] == 1) t01 = t;
+            if (ls.dx[t] == 1 && ls.dy[t] == 0) t10 = t;
+            if (ls.dx[t] == 0 && ls.dy[t] == 1) t01 = t;
         }
-        firstcal<APT>(s, o, m, sh, L.vred, L.ci4, vbase, t10, t01, op.max_cg);
+        firstcal<APT>(s, o, m, R, L.vred, L.ci4, vbase, t10, t01, op.max_cg);
     }
-    group_mean<APT>(s, o, m, sh, L.vred, L.ci4, vbase);
+    group_mean<APT>(m, L.vred, L.ci4, vbase);
 
     // ---- Gauss-Newton
     int status = 0;
@@ -645,11 +672,11 @@ __device__ void solve_unit(const SolveLaunch& L, Shared& sh, unsigned char* ssm,
         double xscale = 1.0;
         if (hi) {
             if (hi_left <= 0) break;
-            xscale = residual_pass64<APT>(s, o, m, sh, L.vred, L.ci4, vbase);
+            xscale = residual_pass64<APT>(s, o, m, R, L.vred, L.ci4, vbase);
         } else {
-            residual_pass32<APT>(s, o, m, sh, L.vred, L.ci4, vbase);
+            residual_pass32<APT>(s, o, m, L.vred, L.ci4, vbase);
         }
-        if (pcg2<APT>(s, o, m, sh, op.max_cg, op.cg_tol) < 0) {   // non-finite data
+        if (pcg2<APT>(s, o, m, R, op.max_cg, op.cg_tol) < 0) {   // non-finite data
             status = 2;
             break;
         }
@@ -662,8 +689,8 @@ __device__ void solve_unit(const SolveLaunch& L, Shared& sh, unsigned char* ssm,
                 e = o.a[k];
                 if (e >= N) continue;
             } else {
-                if ((int)threadIdx.x >= K) continue;
-                e = N + threadIdx.x;
+                if (o.trow < 0) continue;
+                e = N + o.trow;
             }
             const float xa = m.xa[e], xp = m.xp[e];
             if (hi) {
@@ -690,7 +717,7 @@ __device__ void solve_unit(const SolveLaunch& L, Shared& sh, unsigned char* ssm,
                 else m.vm[e - N] = cmul(m.vm[e - N], f);
             }
         }
-        block_sum<1>(e2, sh.redf);
+        block_sum<1>(e2, R);
         ++steps;
         const float rms = sqrtf(e2[0] / (float)(N + K));
         if (!(rms == rms) || isinf(rms)) {
@@ -741,7 +768,7 @@ __device__ void solve_unit(const SolveLaunch& L, Shared& sh, unsigned char* ssm,
             v9[7] += x * y;
             v9[8] += y * y;
         }
-        block_sum<9>(v9, sh.redd);
+        block_sum<9>(v9, R);
         if (threadIdx.x == 0) {
             // [N  Sx  Sy ; Sx Sxx Sxy ; Sy Sxy Syy] c = [S, Sx, Sy] by Cramer's rule
             const double a00 = N, a01 = v9[4], a02 = v9[5], a11 = v9[6], a12 = v9[7], a22 = v9[8];
@@ -764,7 +791,7 @@ __device__ void solve_unit(const SolveLaunch& L, Shared& sh, unsigned char* ssm,
 #pragma unroll
         for (int k = 0; k < APT; ++k)
             if (o.a[k] < N) v1[0] += 0.5 * log(dabs2(m.gd[o.a[k]]));
-        block_sum<1>(v1, sh.redd);
+        block_sum<1>(v1, R);
         if (threadIdx.x == 0) {
             const double2 g0 = m.gd[0], g1 = m.gd[1], gn = m.gd[s.n];
             const double2 qx = dmulc(g1, g0), qy = dmulc(gn, g0);
@@ -788,7 +815,7 @@ __device__ void solve_unit(const SolveLaunch& L, Shared& sh, unsigned char* ssm,
         if ((int)threadIdx.x < K) {
             const int t = threadIdx.x;
             double sn, cs;
-            sincos(kx * s.dx[t] + ky * s.dy[t], &sn, &cs);
+            sincos(kx * ls.dx[t] + ky * ls.dy[t], &sn, &cs);
             const double2 v = m.vmd[t];
             const double l2 = lam * lam;
             m.vmd[t] = make_double2((v.x * cs - v.y * sn) * l2, (v.x * sn + v.y * cs) * l2);
@@ -810,7 +837,7 @@ __device__ void solve_unit(const SolveLaunch& L, Shared& sh, unsigned char* ssm,
             c1[0] += dabs2(dsub(load_vred_d(L.vred, L.ci4, vbase + b), mm));
         }
     }
-    block_sum<1>(c1, sh.redd);
+    block_sum<1>(c1, R);
 #pragma unroll
     for (int k = 0; k < APT; ++k)
         if (o.a[k] < N) L.gains_out[(size_t)unit * N + o.a[k]] = to_f(m.gd[o.a[k]]);
@@ -831,26 +858,29 @@ __global__ __launch_bounds__(kSThreads) void k_solve(SolveLaunch L) {
     solve_unit<APT, LDS>(L, sh, ssm, blockIdx.x);
 }
 
-template <int APT>
+template <int APT, bool LDS_OK>
 static hipError_t launch_solve_apt(const SolveLaunch& L, hipStream_t st) {
-    if (L.lds) {
-        auto kern = k_solve<APT, true>;
-        hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.lds_bytes);
-        hipLaunchKernelGGL(kern, dim3(L.n_units), dim3(kSThreads), L.lds_bytes, st, L);
+    if constexpr (LDS_OK) {
+        if (L.lds) {
+            auto kern = k_solve<APT, true>;
+            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.lds_bytes);
+            hipLaunchKernelGGL(kern, dim3(L.n_units), dim3(kSThreads), L.lds_bytes, st, L);
+            return hipGetLastError();
+        }
     } else {
-        hipLaunchKernelGGL((k_solve<APT, false>), dim3(L.n_units), dim3(kSThreads), 0, st, L);
+        if (L.lds) return hipErrorInvalidValue;
     }
+    hipLaunchKernelGGL((k_solve<APT, false>), dim3(L.n_units), dim3(kSThreads), 0, st, L);
     return hipGetLastError();
 }
 
 hipError_t launch_solve(const SolveLaunch& L, hipStream_t st) {
     const int apt = (L.sel.N + kSThreads - 1) / kSThreads;
-    if (apt <= 1) return launch_solve_apt<1>(L, st);
-    if (apt <= 2) return launch_solve_apt<2>(L, st);
-    if (apt <= 4) return launch_solve_apt<4>(L, st);
-    if (apt <= 8) return launch_solve_apt<8>(L, st);
-    if (apt <= 16) return launch_solve_apt<16>(L, st);
+    if (apt <= 1) return launch_solve_apt<1, true>(L, st);
+    if (apt <= 2) return launch_solve_apt<2, true>(L, st);
+    if (apt <= 4) return launch_solve_apt<4, true>(L, st);
+    if (apt <= 16) return launch_solve_apt<16, false>(L, st);
     return hipErrorInvalidValue;
 }
 
@@ -863,14 +893,21 @@ hipError_t launch_solve(const SolveLaunch& L, hipStream_t st) {
 template <int APT, bool ADJ>
 __global__ __launch_bounds__(kSThreads) void k_chisq(ChisqLaunch L) {
     __shared__ Shared sh;
-    __shared__ float tsum[4 * kMaxTypes];
-    const Sel& s = L.sel;
+    if (threadIdx.x == 0) {
+        const int* src = reinterpret_cast<const int*>(&L.sel);
+        int* dst = reinterpret_cast<int*>(&sh.sel);
+#pragma unroll
+        for (int i = 0; i < (int)(sizeof(Sel) / sizeof(int)); ++i) dst[i] = src[i];
+    }
+    __syncthreads();
+    const Sel& s = sh.sel;
     const int unit = blockIdx.x;
     const int N = s.N, K = s.K;
     const float2* g = L.g + (size_t)unit * N;
     const float2* vm = L.vm + (size_t)unit * K;
     const float2* vr = L.vred + (size_t)unit * s.P;
     const Own<APT> o = own_antennas<APT>(s);
+    Reducer R{&sh};
     if constexpr (!ADJ) {
         double c1[1] = {0.0};
         for (int t = 0; t < K; ++t) {
@@ -885,7 +922,7 @@ __global__ __launch_bounds__(kSThreads) void k_chisq(ChisqLaunch L) {
                 c1[0] += (double)cabs2(r);
             }
         }
-        block_sum<1>(c1, sh.redd);
+        block_sum<1>(c1, R);
         if (threadIdx.x == 0) L.chisq[unit] = (float)c1[0];
     } else {
         // antenna rows
@@ -917,16 +954,13 @@ __global__ __launch_bounds__(kSThreads) void k_chisq(ChisqLaunch L) {
             if (L.grad_g) L.grad_g[(size_t)unit * N + a] = make_float2(2.f * gr.x, 2.f * gr.y);
             if (L.diag_g) L.diag_g[(size_t)unit * N + a] = dg;
         }
-        // type rows
-        for (int t = 0; t < K; ++t) {
-            const int dxy = s.dy[t] * s.n + s.dx[t];
+        // type rows, summed by the waves over each type's pairs
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        for (int t = wave; t < K; t += kSWaves) {
             float sr = 0.f, si = 0.f, sd = 0.f;
-#pragma unroll
-            for (int k = 0; k < APT; ++k) {
-                if (o.a[k] >= N) continue;
-                const int b = pair_as_first(s, t, o.x[k], o.y[k]);
-                if (b < 0) continue;
-                const int i = o.a[k], j = i - dxy;
+            for (int b = s.off[t] + lane; b < s.off[t + 1]; b += 64) {
+                int i, j;
+                pair_ij(s, t, b - s.off[t], i, j);
                 const float2 gg = cmulc(g[j], g[i]);                // conj(g_i) g_j
                 const float2 r = csub(vr[b], cmul(cmulc(g[i], g[j]), vm[t]));
                 const float2 q = cmul(r, gg);
@@ -934,16 +968,14 @@ __global__ __launch_bounds__(kSThreads) void k_chisq(ChisqLaunch L) {
                 si -= q.y;
                 sd += cabs2(gg);
             }
-            type_sums_store(sh.redf, t, sr, si, sd);
+            sr = wave_allsum(sr);
+            si = wave_allsum(si);
+            sd = wave_allsum(sd);
+            if (lane == 0) {
+                if (L.grad_v) L.grad_v[(size_t)unit * K + t] = make_float2(2.f * sr, 2.f * si);
+                if (L.diag_v) L.diag_v[(size_t)unit * K + t] = sd;
+            }
         }
-        __syncthreads();
-        if ((int)threadIdx.x < K) {
-            const int t = threadIdx.x;
-            const float gr = type_sum_read(sh.redf, t, 0), gi = type_sum_read(sh.redf, t, 1);
-            if (L.grad_v) L.grad_v[(size_t)unit * K + t] = make_float2(2.f * gr, 2.f * gi);
-            if (L.diag_v) L.diag_v[(size_t)unit * K + t] = type_sum_read(sh.redf, t, 2);
-        }
-        (void)tsum;
     }
 }
 

@@ -19,7 +19,9 @@ static bool run_unit(const SolveLaunch& L, bool lds, unsigned char* ldsbuf, int 
 extern "C" int rrc_emu_solve(int n, const int* types_xy, int K, int U, int ci4, const void* vred,
                              const void* gains_in, const void* gains_ref, const int* iopts,
                              const float* fopts, void* gains_out, void* vmodel, float* chisq,
-                             int* niter, int* status, int use_lds) {
+                             int* niter, int* status, int use_lds, int order) {
+    rrc_emu::group().order = order;
+    rrc_emu::group().seed = 12345u;
     Sel s{};
     s.n = n;
     s.N = n * n;

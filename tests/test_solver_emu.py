@@ -41,7 +41,7 @@ def emu():
 
 
 def emu_solve(lib, vred, n, types, init=0, degen=0, gin=None, gref=None, lds=1, max_gn=12, fp64=2,
-              max_cg=400, cg_tol=1e-2, tol32=1e-6):
+              max_cg=400, cg_tol=1e-2, tol32=1e-6, order=0):
     U = vred.shape[0]
     N, K = n * n, len(types)
     txy = (C.c_int * (2 * K))(*[v for t in types for v in t])
@@ -59,7 +59,7 @@ def emu_solve(lib, vred, n, types, init=0, degen=0, gin=None, gref=None, lds=1, 
 
     rc = lib.rrc_emu_solve(n, txy, K, U, 0, p(vr), p(gin), p(gref), io, fo, p(go), p(vm),
                            ch.ctypes.data_as(C.POINTER(C.c_float)), ni.ctypes.data_as(C.POINTER(C.c_int)),
-                           st.ctypes.data_as(C.POINTER(C.c_int)), lds)
+                           st.ctypes.data_as(C.POINTER(C.c_int)), lds, order)
     assert rc == 0, "non-uniform barrier" if rc == -2 else rc
     return go, vm, ch, ni, st
 
@@ -107,3 +107,13 @@ def test_emulated_solver_maxiter_status(emu):
     vr, _, pos, types, pairs, tix = _vred(6, 64)
     _, _, _, ni, st = emu_solve(emu, vr, 6, types, max_gn=1, fp64=0)
     assert st[0] == 1 and ni[0] == 1
+
+
+@pytest.mark.parametrize("lds", [1, 0])
+def test_emulated_solver_has_no_data_race(emu, lds):
+    # the result must not depend on the order work-items run between barriers
+    vr, _, pos, types, pairs, tix = _vred(8, 256)
+    outs = [emu_solve(emu, vr, 8, types, lds=lds, order=o) for o in (0, 1, 2)]
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            assert np.array_equal(a, b)
