@@ -83,7 +83,7 @@ extern "C" {
 #define RRC_UNIT_NONFINITE 2
 
 /* Limits of this build. */
-#define RRC_MAX_TYPES 32     /* K, selected baseline-types                    */
+#define RRC_MAX_TYPES 16     /* K, selected baseline-types                    */
 #define RRC_MAX_GRID  64     /* n; the padded FFT size is M = max(16, 2^ceil(log2 2n)) */
 
 typedef struct rrc_plan rrc_plan;

@@ -26,7 +26,7 @@ RRC_DEGEN_REFANT = 0
 RRC_DEGEN_MATCH = 1
 RRC_RUN_PIPELINED = 1
 RRC_RUN_SELFCAL = 2
-RRC_MAX_TYPES = 32
+RRC_MAX_TYPES = 16
 RRC_MAX_GRID = 64
 
 EXPORTS = ("rrc_default_opts", "rrc_select_subset", "rrc_degeneracy_count", "rrc_plan_create",

@@ -14,7 +14,7 @@
 
 namespace rrc {
 
-constexpr int kMaxTypes = 32;
+constexpr int kMaxTypes = 16;
 
 // ------------------------------------------------------------------ complex
 
@@ -154,6 +154,8 @@ inline T wave_allsum(T v) {
     for (int o = 1; o <= 32; o <<= 1) v += __shfl_xor(v, o, 64);
     return v;
 }
+template <typename T>
+inline T wave_sum_last(T v) { return wave_allsum(v); }
 #else
 template <int CTRL>
 __device__ __forceinline__ int dpp_i(int v) {
@@ -189,6 +191,33 @@ __device__ __forceinline__ double wave_allsum(double v) {
     v += dpp_d<0x124>(v);
     v += dpp_d<0x128>(v);
     return (lane_d(v, 0) + lane_d(v, 16)) + (lane_d(v, 32) + lane_d(v, 48));
+}
+
+// Sum over the 64 lanes, complete in lane 63 only (other lanes hold
+// partial sums), kept in vector registers.  After the row sums, the
+// row_bcast:15 step adds row 0 into row 1 and row 2 into row 3 (the other
+// rows add zero), and row_bcast:31 adds rows 0+1 into rows 2 and 3.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int dpp_rows_i(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, ROWS, 0xF, false);
+}
+__device__ __forceinline__ float wave_sum_last(float v) {
+    v += dpp_f<0xB1>(v);
+    v += dpp_f<0x4E>(v);
+    v += dpp_f<0x124>(v);
+    v += dpp_f<0x128>(v);
+    v += __int_as_float(dpp_rows_i<0x142, 0xA>(__float_as_int(v)));   // row_bcast:15
+    v += __int_as_float(dpp_rows_i<0x143, 0xC>(__float_as_int(v)));   // row_bcast:31
+    return v;
+}
+__device__ __forceinline__ double wave_sum_last(double v) {
+    v += dpp_d<0xB1>(v);
+    v += dpp_d<0x4E>(v);
+    v += dpp_d<0x124>(v);
+    v += dpp_d<0x128>(v);
+    v += __hiloint2double(dpp_rows_i<0x142, 0xA>(__double2hiint(v)), dpp_rows_i<0x142, 0xA>(__double2loint(v)));
+    v += __hiloint2double(dpp_rows_i<0x143, 0xC>(__double2hiint(v)), dpp_rows_i<0x143, 0xC>(__double2loint(v)));
+    return v;
 }
 #endif
 

@@ -15,6 +15,7 @@
 #include <cmath>
 #include <cstddef>
 #include <cstdint>
+#include <cstring>
 #include <algorithm>
 #include <functional>
 #include <random>
@@ -28,11 +29,15 @@
 struct float2 { float x, y; };
 struct double2 { double x, y; };
 struct int2 { int x, y; };
+struct float4 { float x, y, z, w; };
 inline float2 make_float2(float a, float b) { return float2{a, b}; }
 inline double2 make_double2(double a, double b) { return double2{a, b}; }
 inline int2 make_int2(int a, int b) { return int2{a, b}; }
 
 using std::isinf;
+
+inline float __int_as_float(int v) { float f; std::memcpy(&f, &v, 4); return f; }
+inline int __float_as_int(float f) { int v; std::memcpy(&v, &f, 4); return v; }
 
 namespace rrc_emu {
 

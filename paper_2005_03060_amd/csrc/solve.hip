@@ -9,25 +9,40 @@
 // multiplicative form: perturbing g_i -> g_i e^{eta_i} and
 // V_alpha -> V_alpha e^{zeta_alpha} linearises the relative residual as
 //     r_b / m_b  ~  eta_i + conj(eta_j) + zeta_alpha,   m_b = g_i conj(g_j) V_alpha,
-// with weight |m_b|^2.  Its real part involves only log-amplitudes
-// (a_i + a_j + c_alpha) and its imaginary part only phases
-// (phi_i - phi_j + psi_alpha) -- the two real systems of eq. logcal, here
-// with the current weights -- so each step solves two decoupled, sparse,
-// positive semi-definite normal equations.  Their right-hand sides are the
-// adjoint J^H r (the same sums as the chi^2 gradient of rrc_chisq_adj) and
-// their diagonal is diag(J^H J); they are solved together by
-// Jacobi-preconditioned conjugate gradients, matrix-free over the pairs.
+// with weight w_b = |m_b|^2 = |g_i|^2 |g_j|^2 |V_alpha|^2.  Its real part
+// involves only log-amplitudes (a_i + a_j + c_alpha) and its imaginary part
+// only phases (phi_i - phi_j + psi_alpha) -- the two real systems of
+// eq. logcal, here with the current weights -- so each step solves two
+// decoupled, sparse, positive semi-definite normal equations.  Their
+// right-hand sides are the adjoint J^H r (the sums of rrc_chisq_adj) and
+// their diagonal is diag(J^H J); both are solved together by
+// Jacobi-preconditioned conjugate gradients, matrix-free.
 //
-// Precision: the first steps take the residual in FP32 from FP32
-// parameters; once the rms log-step is below tol32 the parameters are
-// promoted to FP64 and `fp64_steps` more steps take the residual in FP64
-// (the normal equations stay FP32: iterative refinement).  The four
-// degeneracies (Sec. 5.2) are fixed in FP64 and chi^2 is summed in FP64.
+// Layout.  Work-item a owns antenna row a (and a + NT, ... when the grid
+// has more antennas than the workgroup has work-items); work-item t < K
+// also owns type row t.  A work-item keeps the CG state of its rows in
+// registers.  The only vector other work-items read is the search
+// direction, kept in LDS as one 16-byte record per row
+// {p_amp, p_phase, |g|^2 (|V|^2 for a type row), -}: the matrix-vector
+// product of an antenna row needs one LDS read per incident pair (at most
+// 2K) and no per-pair storage, so the whole state of a unit (directions,
+// gains and unique visibilities) fits in LDS for any grid up to 64 x 64.  Type-row
+// sums (over a type's pairs) and CG's dot products are block reductions in
+// a fixed order, so results are deterministic.
+//
+// Precision: parameters, residuals and the right-hand side are FP64; the
+// right-hand side is handed to the FP32 normal equations scaled to unit
+// norm, so each step is one step of iterative refinement (near the optimum
+// J^H r is a sum of terms the size of the noise that cancel to a tiny
+// total, which FP32 could not resolve).  Steps continue until the rms
+// log-step is below tol32 (at most max_gn), then `fp64_steps` more.  The
+// four degeneracies (Sec. 5.2) are fixed in FP64 and chi^2 is summed in
+// FP64.
 //
 // Start (the paper does not say how its solver was started): either the
-// caller's gains, or logcal amplitudes (real part of eq. logcal) with
-// phases chained along the (1,0) and (0,1) groups.  V_alpha then starts at
-// the group mean of V_b / (g_i conj(g_j)).
+// caller's gains, or logcal amplitudes (real part of eq. logcal, unit
+// weights) with phases chained along the (1,0) and (0,1) groups.  V_alpha
+// then starts at the group mean of V_b / (g_i conj(g_j)).
 #include "rrc_device.h"
 #include "rrc_launch.h"
 
@@ -35,149 +50,120 @@
 
 namespace rrc {
 
-constexpr int kSThreads = 256;
-constexpr int kSWaves = kSThreads / 64;
+constexpr int kChunk = 8;                     // types per FP64 type-sum reduction
+constexpr int kRedF = 2 * kMaxTypes + 4;      // floats per block reduction (max)
+constexpr int kRedD = 3 * kChunk;             // doubles per block reduction (max)
 
 __host__ __device__ inline size_t align16(size_t v) { return (v + 15) & ~(size_t)15; }
 
-// Per-unit arrays.  "Hot" arrays are touched every CG iteration; they live
-// in LDS when they fit, otherwise in the global slab.  "Cold" arrays are
-// touched once per Gauss-Newton step and always live in the global slab.
-struct HotLayout {
-    size_t w, sa, sp, d, xa, ra, za, pa, qa, xp, rp, zp, pp, qp, bytes;
+// Dynamic LDS of one unit's solve.
+// Parameters are held in FP64 throughout; in the FP32 phase they carry
+// FP32 values (exactly) and are read and updated in FP32.
+struct SolveLayout {
+    size_t rec, gd, vmd, bytes;
 };
-struct ColdLayout {
-    size_t g, vm, gd, vmd, bytes;
-};
-
-__host__ __device__ inline HotLayout hot_layout(const Sel& s) {
-    HotLayout L{};
-    const size_t P = s.P, V = (size_t)s.N + s.K;
+__host__ __device__ inline SolveLayout solve_layout(const Sel& s) {
+    SolveLayout L{};
     size_t o = 0;
-    L.w = o;  o = align16(o + 4 * P);
-    L.sa = o; o = align16(o + 4 * P);
-    L.sp = o; o = align16(o + 4 * P);
-    size_t* vecs[] = {&L.d, &L.xa, &L.ra, &L.za, &L.pa, &L.qa, &L.xp, &L.rp, &L.zp, &L.pp, &L.qp};
-    for (size_t* v : vecs) { *v = o; o = align16(o + 4 * V); }
+    L.rec = o; o = align16(o + 16 * ((size_t)s.N + s.K));
+    L.gd = o;  o = align16(o + 16 * (size_t)s.N);
+    L.vmd = o; o = align16(o + 16 * (size_t)s.K);
     L.bytes = o;
     return L;
 }
-__host__ __device__ inline ColdLayout cold_layout(const Sel& s, size_t base) {
-    ColdLayout L{};
-    size_t o = base;
-    L.g = o;   o = align16(o + 8 * (size_t)s.N);
-    L.vm = o;  o = align16(o + 8 * (size_t)s.K);
-    L.gd = o;  o = align16(o + 16 * (size_t)s.N);
-    L.vmd = o; o = align16(o + 16 * (size_t)s.K);
-    L.bytes = o - base;
-    return L;
-}
 
-size_t solve_hot_bytes(const Sel& s) { return hot_layout(s).bytes; }
-size_t solve_slab_bytes(const Sel& s, bool lds) {
-    const size_t hot = lds ? 0 : hot_layout(s).bytes;
-    return align16(hot + cold_layout(s, hot).bytes);
-}
-size_t solve_lds_bytes(const Sel& s, bool lds) { return lds ? hot_layout(s).bytes : 0; }
+size_t solve_hot_bytes(const Sel& s) { return solve_layout(s).bytes; }
+size_t solve_slab_bytes(const Sel&, bool) { return 0; }
+size_t solve_lds_bytes(const Sel& s, bool) { return solve_layout(s).bytes; }
 
-struct Mem {
-    const Sel* ls;          // the selection copied to LDS, for type-indexed lookups
-    float *w, *sa, *sp, *d;
-    float *xa, *ra, *za, *pa, *qa;
-    float *xp, *rp, *zp, *pp, *qp;
-    float2* g;
-    float2* vm;
-    double2* gd;
-    double2* vmd;
+// Workgroup shape: one antenna per work-item up to 1024 antennas, then
+// 2 or 4 per work-item.
+inline int solve_threads_for(int N) { return N <= 256 ? 256 : (N <= 512 ? 512 : 1024); }
+
+// Per-type constants of the selection, in LDS: the raster offset d_t of
+// the type and the pair indices as affine functions of an antenna's
+// (x, y): pair (a, a - d_t) is c1 + y w + x, pair (a + d_t, a) is
+// c2 + y w + x (a pair type's group is stored row-major over the rows of
+// its first antenna, w = n - |dx| pairs per row).
+struct TypeInfo {
+    int dxy, w, c1, c2;
+    int dx, dy, off, cnt;
 };
 
-// ------------------------------------------------------------ reductions
-
+template <int NW>
 struct Shared {
-    Sel sel;                                // copy of the selection (runtime type indices)
-    float bf[2 * kSWaves * 4];              // block_sum slots (two phases)
-    double bd[2 * kSWaves * 12];
+    Sel sel;                               // copy of the selection
+    TypeInfo ty[kMaxTypes];
+    float redf[2 * NW * kRedF];            // block reduction slots (two phases)
+    double redd[2 * NW * kRedD];
+    float totf[2 * kRedF];
+    double totd[2 * kRedD];
     double bcast[8];
 };
 
-// Sums NV values over the workgroup; every thread gets the totals, in a
-// fixed order (deterministic).  The slots alternate between two phases, so
-// one barrier suffices: a slot is rewritten only two calls later, after a
-// barrier every reader of the previous use has passed.
+// ------------------------------------------------------------ reductions
+//
+// block_sum adds NV values over the workgroup and returns the totals to
+// every work-item, in a fixed order.  Slots alternate between two phases,
+// so a slot is rewritten only two calls later, after a barrier that every
+// reader of its previous use has passed.  With many waves the per-wave
+// partials are first added by NV work-items (one more barrier), so each
+// work-item reads NV values instead of NW * NV.
 struct Reducer {
-    Shared* sh;
+    float* sf;
+    double* sd;
+    float* tf;
+    double* td;
     int pf = 0, pd = 0;
 };
 
-template <int NV>
+template <int NW, int NV, int STRIDE, typename T>
+__device__ __forceinline__ void block_sum_impl(T (&v)[NV], T* slots, T* tots, int& ph) {
+    T* slot = slots + ph * (NW * STRIDE);
+    T* tot = tots + ph * STRIDE;
+    ph ^= 1;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[i] = wave_sum_last(v[i]);
+    if (lane == 63) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) slot[wave * STRIDE + i] = v[i];
+    }
+    __syncthreads();
+    if constexpr (NW * NV <= 64) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            T acc = 0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) acc += slot[w * STRIDE + i];
+            v[i] = acc;
+        }
+    } else {
+        if ((int)threadIdx.x < NV) {
+            T acc = 0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) acc += slot[w * STRIDE + threadIdx.x];
+            tot[threadIdx.x] = acc;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < NV; ++i) v[i] = tot[i];
+    }
+}
+template <int NW, int NV>
 __device__ __forceinline__ void block_sum(float (&v)[NV], Reducer& R) {
-    static_assert(NV <= 4, "float slots");
-    float* slot = R.sh->bf + R.pf * (kSWaves * 4);
-    R.pf ^= 1;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int i = 0; i < NV; ++i) v[i] = wave_allsum(v[i]);
-    if (lane == 0) {
-#pragma unroll
-        for (int i = 0; i < NV; ++i) slot[wave * 4 + i] = v[i];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < NV; ++i) {
-        float s = 0.f;
-        for (int w = 0; w < kSWaves; ++w) s += slot[w * 4 + i];
-        v[i] = s;
-    }
+    static_assert(NV <= kRedF, "float reduction size");
+    block_sum_impl<NW, NV, kRedF, float>(v, R.sf, R.tf, R.pf);
 }
-
-template <int NV>
+template <int NW, int NV>
 __device__ __forceinline__ void block_sum(double (&v)[NV], Reducer& R) {
-    static_assert(NV <= 12, "double slots");
-    double* slot = R.sh->bd + R.pd * (kSWaves * 12);
-    R.pd ^= 1;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int i = 0; i < NV; ++i) v[i] = wave_allsum(v[i]);
-    if (lane == 0) {
-#pragma unroll
-        for (int i = 0; i < NV; ++i) slot[wave * 12 + i] = v[i];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < NV; ++i) {
-        double s = 0.0;
-        for (int w = 0; w < kSWaves; ++w) s += slot[w * 12 + i];
-        v[i] = s;
-    }
+    static_assert(NV <= kRedD, "double reduction size");
+    block_sum_impl<NW, NV, kRedD, double>(v, R.sd, R.td, R.pd);
 }
 
-// --------------------------------------------------------- pair visitors
-//
-// Work-item tid owns antennas a = tid + k*NT (k < APT) and, for the type
-// unknowns, type row t = 4*lane + wave (lane = tid % 64, wave = tid / 64)
-// when that is < K.  Every pair is visited once from its first antenna.
-// The selection is read from its LDS copy.  Type rows are summed by waves over each type's
-// contiguous pair range (wave w takes types w, w+4, ...), and the owner lane
-// of a type row is in the wave that sums it.
-
-template <int APT>
-struct Own {
-    int a[APT], x[APT], y[APT];
-    int trow;   // owned type row, or -1
-};
-
-template <int APT>
-__device__ __forceinline__ Own<APT> own_antennas(const Sel& s) {
-    Own<APT> o;
-#pragma unroll
-    for (int k = 0; k < APT; ++k) {
-        o.a[k] = threadIdx.x + k * kSThreads;
-        o.x[k] = o.a[k] % s.n;
-        o.y[k] = o.a[k] / s.n;
-    }
-    const int t = (threadIdx.x & 63) * kSWaves + (threadIdx.x >> 6);
-    o.trow = t < s.K ? t : -1;
-    return o;
+template <int NW>
+__device__ __forceinline__ Reducer make_reducer(Shared<NW>& sh) {
+    return Reducer{sh.redf, sh.redd, sh.totf, sh.totd};
 }
 
 __device__ __forceinline__ float2 load_vred(const void* v, bool ci4, size_t idx) {
@@ -196,530 +182,526 @@ __device__ __forceinline__ double2 load_vred_d(const void* v, bool ci4, size_t i
     return make_double2(f.x, f.y);
 }
 
-// Antenna rows: out_a = sum over the pairs touching a of A_b (both ends),
-// B_b (first end) - B_b (second end), and C_b (both ends, if C).
-template <int APT>
-__device__ __forceinline__ void gather_rows(const Sel& s, const Own<APT>& o, const float* A,
-                                            const float* B, const float* C, float* outA,
-                                            float* outB, float* outC) {
+// The selection is read from an LDS copy: indexing the by-value kernel
+// argument with a run-time type index would make the compiler copy the
+// argument to private memory.  Thread 0 copies it with compile-time offsets.
+__device__ __forceinline__ void copy_sel(const Sel& src, Sel& dst) {
+    if (threadIdx.x == 0) {
+        const int* a = reinterpret_cast<const int*>(&src);
+        int* b = reinterpret_cast<int*>(&dst);
 #pragma unroll
-    for (int k = 0; k < APT; ++k) {
-        if (o.a[k] >= s.N) continue;
-        float ya = 0.f, yb = 0.f, yc = 0.f;
-        for (int t = 0; t < s.K; ++t) {
-            const int b1 = pair_as_first(s, t, o.x[k], o.y[k]);
-            const int b2 = pair_as_second(s, t, o.x[k], o.y[k]);
-            if (b1 >= 0) {
-                ya += A[b1];
-                yb += B[b1];
-                if (C) yc += C[b1];
-            }
-            if (b2 >= 0) {
-                ya += A[b2];
-                yb -= B[b2];
-                if (C) yc += C[b2];
-            }
-        }
-        outA[o.a[k]] = ya;
-        outB[o.a[k]] = yb;
-        if (outC) outC[o.a[k]] = yc;
+        for (int i = 0; i < (int)(sizeof(Sel) / sizeof(int)); ++i) b[i] = a[i];
     }
+    __syncthreads();
 }
 
-// Type rows: out[N + t] = sum over the pairs of type t of A_b (and B_b, C_b).
-template <int APT>
-__device__ __forceinline__ void type_rows(const Sel& s, const float* A, const float* B, const float* C,
-                                          float* outA, float* outB, float* outC) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int t = wave; t < s.K; t += kSWaves) {
-        float ya = 0.f, yb = 0.f, yc = 0.f;
-        for (int b = s.off[t] + lane; b < s.off[t + 1]; b += 64) {
-            ya += A[b];
-            yb += B[b];
-            if (C) yc += C[b];
-        }
-        ya = wave_allsum(ya);
-        yb = wave_allsum(yb);
-        if (C) yc = wave_allsum(yc);
-        if (lane == t / kSWaves) {
-            outA[s.N + t] = ya;
-            outB[s.N + t] = yb;
-            if (outC) outC[s.N + t] = yc;
-        }
-    }
-}
-
-// ------------------------------------------------- matrix-free operators
+// ------------------------------------------------------------- the solver
 //
-// Amplitude system: rows b: a_i + a_j + c_t, weight w_b.
-// Phase system:     rows b: p_i - p_j + c_t, weight w_b.
-// H x = sum_b w_b row_b (row_b . x).  Computes qa = Ha pa, qp = Hp pp;
-// each result element is written by its owner.
-template <int APT>
-__device__ __forceinline__ void apply_H(const Sel& s, const Own<APT>& o, const Mem& m) {
-    const int N = s.N;
-    for (int t = 0; t < s.K; ++t) {
-        const int dxy = s.dy[t] * s.n + s.dx[t];
-        const float cta = m.pa[N + t], ctp = m.pp[N + t];
+// Type indices are compile-time constants everywhere (loops over the types
+// are unrolled to KMAX), so the selection is read straight from the kernel
+// argument into scalar registers.
+
+template <int NT, int APT, int KMAX>
+struct Solver {
+    static constexpr int NW = NT / 64;
+    static constexpr int R1 = APT + 1;     // own rows: APT antennas + one type row
+    const Sel& s;
+    const TypeInfo* ty;
+    Reducer R;
+    int N, K, n, tid;
+    float4* rec;       // [N + K] {p_amp, p_phase, |g|^2 or |V|^2, scratch}
+    double2* gd;       // [N] gains
+    double2* vmd;      // [K] unique visibilities
+    const void* vred;
+    bool ci4;
+    size_t vbase;
+    // own antenna rows
+    int a[APT], ax_[APT], ay_[APT];
+    bool live[APT];
+    unsigned m1[APT], m2[APT];   // bit t: pair (a, a - d_t) / (a + d_t, a) exists
+    float gw[APT];               // own |g|^2 as published in the records
+    bool own_t;
+    // CG state of the own rows (index APT: the owned type row)
+    float xa[R1], xp[R1], ra[R1], rp[R1], di[R1], pa[R1], pp[R1];
+
+    __device__ Solver(const Sel& sel, const TypeInfo* tyi, Reducer red, unsigned char* lds, const void* vr,
+                      bool c4, size_t vb)
+        : s(sel), ty(tyi), R(red), vred(vr), ci4(c4), vbase(vb) {
+        N = s.N;
+        K = s.K;
+        n = s.n;
+        tid = threadIdx.x;
+        const SolveLayout Ly = solve_layout(s);
+        rec = reinterpret_cast<float4*>(lds + Ly.rec);
+        gd = reinterpret_cast<double2*>(lds + Ly.gd);
+        vmd = reinterpret_cast<double2*>(lds + Ly.vmd);
+        own_t = tid < K;
+        if (own_t) rec[N + tid].w = __int_as_float(ty[tid].dxy);
 #pragma unroll
         for (int k = 0; k < APT; ++k) {
-            if (o.a[k] >= N) continue;
-            const int b = pair_as_first(s, t, o.x[k], o.y[k]);
-            if (b < 0) continue;
-            const int i = o.a[k], j = i - dxy;
-            const float wb = m.w[b];
-            m.sa[b] = wb * (m.pa[i] + m.pa[j] + cta);
-            m.sp[b] = wb * (m.pp[i] - m.pp[j] + ctp);
+            a[k] = tid + k * NT;
+            live[k] = a[k] < N;
+            m1[k] = m2[k] = 0u;
+            gw[k] = 0.f;
+            ax_[k] = a[k] % n;
+            ay_[k] = a[k] / n;
+#pragma unroll
+            for (int t = 0; t < KMAX; ++t) {
+                if (t >= K || !live[k]) continue;
+                const int dx = ty[t].dx, dy = ty[t].dy;
+                const int jx = ax_[k] - dx, jy = ay_[k] - dy, ix = ax_[k] + dx, iy = ay_[k] + dy;
+                if (jx >= 0 && jx < n && jy >= 0 && jy < n) m1[k] |= 1u << t;
+                if (ix >= 0 && ix < n && iy >= 0 && iy < n) m2[k] |= 1u << t;
+            }
         }
     }
-    __syncthreads();
-    gather_rows<APT>(s, o, m.sa, m.sp, nullptr, m.qa, m.qp, nullptr);
-    type_rows<APT>(*m.ls, m.sa, m.sp, nullptr, m.qa, m.qp, nullptr);
-}
 
-// Jacobi-preconditioned CG on both systems at once, from x = 0 with the
-// right-hand sides already in ra / rp and the diagonal in d (inverted in
-// place).  Returns the number of iterations, or -1 if a right-hand side is
-// not finite.
-template <int APT>
-__device__ int pcg2(const Sel& s, const Own<APT>& o, const Mem& m, Reducer& R, int max_cg, float tol) {
-    const int N = s.N;
-    auto each = [&](auto&& f) {
+    __device__ bool mine(int k) const { return k < APT ? live[k] : own_t; }
+    __device__ int dxy(int t) const { return ty[t].dxy; }
+    // pair (a, a - d_t) / (a + d_t, a) of own antenna k
+    __device__ int b1(int t, int k) const { return ty[t].c1 + ay_[k] * ty[t].w + ax_[k]; }
+    __device__ int b2(int t, int k) const { return ty[t].c2 + ay_[k] * ty[t].w + ax_[k]; }
+    __device__ int ax(int k) const { return ax_[k]; }
+    __device__ int ay(int k) const { return ay_[k]; }
+
+    // ---- residual pass: the right-hand sides ra, rp (J^H r split into its
+    // amplitude and phase parts, scaled to unit norm; the scale is
+    // returned), the inverse diagonal di of J^H J, and the weights of the
+    // records.  FP64 throughout.  Each work-item recomputes the residuals
+    // of its antennas' pairs; type rows are block sums over the pairs (each
+    // pair counted at its first antenna), kChunk types at a time.
+    __device__ double residuals() {
+        double rA[R1], rP[R1];
+        float dd[R1];
 #pragma unroll
-        for (int k = 0; k < APT; ++k)
-            if (o.a[k] < N) f(o.a[k]);
-        if (o.trow >= 0) f(N + o.trow);
-    };
-    float v4[4] = {0.f, 0.f, 0.f, 0.f};
-    each([&](int e) {
-        const float di = m.d[e] > 0.f ? 1.0f / m.d[e] : 0.f;
-        m.d[e] = di;                      // the diagonal is kept inverted from here on
-        m.xa[e] = 0.f;
-        m.xp[e] = 0.f;
-        const float za = m.ra[e] * di, zp = m.rp[e] * di;
-        m.pa[e] = za;
-        m.pp[e] = zp;
-        v4[0] += m.ra[e] * za;
-        v4[1] += m.rp[e] * zp;
-        v4[2] += m.ra[e] * m.ra[e];
-        v4[3] += m.rp[e] * m.rp[e];
-    });
-    block_sum<4>(v4, R);
-    if (!(v4[2] == v4[2]) || !(v4[3] == v4[3]) || isinf(v4[2]) || isinf(v4[3])) return -1;
-    float rza = v4[0], rzp = v4[1];
-    const float stopa = tol * tol * v4[2], stopp = tol * tol * v4[3];
-    bool done_a = !(v4[2] > 0.f), done_p = !(v4[3] > 0.f);
-    int it = 0;
-    for (; it < max_cg && !(done_a && done_p); ++it) {
-        apply_H<APT>(s, o, m);
-        float v2[2] = {0.f, 0.f};
-        each([&](int e) {
-            v2[0] += m.pa[e] * m.qa[e];
-            v2[1] += m.pp[e] * m.qp[e];
-        });
-        block_sum<2>(v2, R);
-        const float ala = (!done_a && v2[0] > 0.f) ? rza / v2[0] : 0.f;
-        const float alp = (!done_p && v2[1] > 0.f) ? rzp / v2[1] : 0.f;
-        float w4[4] = {0.f, 0.f, 0.f, 0.f};
-        float za_own[APT + 1], zp_own[APT + 1];
-#pragma unroll
-        for (int k = 0; k <= APT; ++k) {
-            za_own[k] = zp_own[k] = 0.f;
-            int e;
-            if (k < APT) {
-                e = o.a[k];
-                if (e >= N) continue;
-            } else {
-                if (o.trow < 0) continue;
-                e = N + o.trow;
-            }
-            const float di = m.d[e];
-            m.xa[e] += ala * m.pa[e];
-            m.xp[e] += alp * m.pp[e];
-            const float ra = m.ra[e] - ala * m.qa[e];
-            const float rp = m.rp[e] - alp * m.qp[e];
-            m.ra[e] = ra;
-            m.rp[e] = rp;
-            const float za = ra * di, zp = rp * di;
-            za_own[k] = za;
-            zp_own[k] = zp;
-            w4[0] += ra * za;
-            w4[1] += rp * zp;
-            w4[2] += ra * ra;
-            w4[3] += rp * rp;
+        for (int k = 0; k < R1; ++k) {
+            rA[k] = rP[k] = 0.0;
+            dd[k] = 0.f;
         }
-        block_sum<4>(w4, R);
-        const float ba = (rza > 0.f) ? w4[0] / rza : 0.f;
-        const float bp = (rzp > 0.f) ? w4[1] / rzp : 0.f;
-        if (!done_a) rza = w4[0];
-        if (!done_p) rzp = w4[1];
 #pragma unroll
-        for (int k = 0; k <= APT; ++k) {
-            int e;
-            if (k < APT) {
-                e = o.a[k];
-                if (e >= N) continue;
-            } else {
-                if (o.trow < 0) continue;
-                e = N + o.trow;
+        for (int c0 = 0; c0 < KMAX; c0 += kChunk) {
+            if (c0 >= K) break;
+            double tq[3 * kChunk];
+#pragma unroll
+            for (int i = 0; i < 3 * kChunk; ++i) tq[i] = 0.0;
+#pragma unroll
+            for (int tt = 0; tt < kChunk; ++tt) {
+                const int t = c0 + tt;
+                if (t >= K) break;
+                const double2 vt = vmd[t];
+#pragma unroll
+                for (int k = 0; k < APT; ++k) {
+                    if (!live[k]) continue;
+                    // e = 0: pair (a, a - d_t); e = 1: pair (a + d_t, a)
+#pragma unroll 1
+                    for (int e = 0; e < 2; ++e) {
+                        if (!(((e ? m2[k] : m1[k]) >> t) & 1u)) continue;
+                        const int i = e ? a[k] + dxy(t) : a[k];
+                        const int b = e ? b2(t, k) : b1(t, k);
+                        const double2 mm = dmul(dmulc(gd[i], gd[i - dxy(t)]), vt);
+                        const double2 q = dmulc(dsub(load_vred_d(vred, ci4, vbase + b), mm), mm);
+                        const double wb = dabs2(mm);
+                        rA[k] += q.x;
+                        rP[k] += e ? -q.y : q.y;
+                        dd[k] += (float)wb;
+                        if (!e) {
+                            tq[tt] += q.x;
+                            tq[kChunk + tt] += q.y;
+                            tq[2 * kChunk + tt] += wb;
+                        }
+                    }
+                }
             }
-            if (!done_a) m.pa[e] = za_own[k] + ba * m.pa[e];
-            if (!done_p) m.pp[e] = zp_own[k] + bp * m.pp[e];
+            block_sum<NW, 3 * kChunk>(tq, R);
+#pragma unroll
+            for (int tt = 0; tt < kChunk; ++tt) {
+                if (own_t && tid == c0 + tt) {
+                    rA[APT] = tq[tt];
+                    rP[APT] = tq[kChunk + tt];
+                    dd[APT] = (float)tq[2 * kChunk + tt];
+                }
+            }
         }
-        done_a = done_a || !(w4[2] > stopa);
-        done_p = done_p || !(w4[3] > stopp);
+        double nrm[1] = {0.0};
+#pragma unroll
+        for (int k = 0; k < R1; ++k)
+            if (mine(k)) nrm[0] += rA[k] * rA[k] + rP[k] * rP[k];
+        block_sum<NW, 1>(nrm, R);
+        const double scale = nrm[0] > 0.0 ? sqrt(nrm[0]) : 1.0;
+        const double inv = 1.0 / scale;
+#pragma unroll
+        for (int k = 0; k < R1; ++k) {
+            ra[k] = mine(k) ? (float)(rA[k] * inv) : 0.f;
+            rp[k] = mine(k) ? (float)(rP[k] * inv) : 0.f;
+            di[k] = dd[k] > 0.f ? 1.0f / dd[k] : 0.f;
+        }
+        return scale;
+    }
+
+    // |g|^2 of the own antennas and |V_t|^2 of the own type row into the
+    // records, for the neighbours' matrix-vector products (published by the
+    // barrier of the first reduction of the following CG solve).
+    __device__ void publish_weights(bool unit) {
+#pragma unroll
+        for (int k = 0; k < APT; ++k) {
+            if (!live[k]) continue;
+            gw[k] = unit ? 1.f : (float)dabs2(gd[a[k]]);
+            rec[a[k]].z = gw[k];
+        }
+        if (own_t) rec[N + tid].z = unit ? 1.f : (float)dabs2(vmd[tid]);
+    }
+
+    // q = H p on the own rows of both systems, p read from the records.
+    // The type rows' q are block sums of their pairs' terms (each pair
+    // counted at its first antenna); the same reduction carries p.Hp of the
+    // antenna rows, and every work-item adds the type rows' part of p.Hp
+    // from the totals.
+    __device__ void matvec(float (&qa)[R1], float (&qp)[R1], float& pqa, float& pqp) {
+        float cs[2 * KMAX + 2];
+#pragma unroll
+        for (int i = 0; i < 2 * KMAX + 2; ++i) cs[i] = 0.f;
+#pragma unroll
+        for (int k = 0; k < R1; ++k) qa[k] = qp[k] = 0.f;
+#pragma unroll
+        for (int t = 0; t < KMAX; ++t) {
+            if (t >= K) break;
+            const float4 rt = rec[N + t];         // .w: d_t
+            const int dt = __float_as_int(rt.w);
+#pragma unroll
+            for (int k = 0; k < APT; ++k) {
+                if (!live[k]) continue;
+                if ((m1[k] >> t) & 1u) {          // pair (a, j), j = a - d_t
+                    const float4 rj = rec[a[k] - dt];
+                    const float w = gw[k] * rj.z * rt.z;
+                    const float eA = w * (pa[k] + rj.x + rt.x);
+                    const float eP = w * (pp[k] - rj.y + rt.y);
+                    qa[k] += eA;
+                    qp[k] += eP;
+                    cs[t] += eA;
+                    cs[KMAX + t] += eP;
+                }
+                if ((m2[k] >> t) & 1u) {          // pair (i, a), i = a + d_t
+                    const float4 ri = rec[a[k] + dt];
+                    const float w = gw[k] * ri.z * rt.z;
+                    qa[k] += w * (ri.x + pa[k] + rt.x);
+                    qp[k] -= w * (ri.y - pp[k] + rt.y);
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < APT; ++k) {
+            cs[2 * KMAX] += pa[k] * qa[k];
+            cs[2 * KMAX + 1] += pp[k] * qp[k];
+        }
+        block_sum<NW, 2 * KMAX + 2>(cs, R);
+        pqa = cs[2 * KMAX];
+        pqp = cs[2 * KMAX + 1];
+#pragma unroll
+        for (int t = 0; t < KMAX; ++t) {
+            if (t >= K) break;
+            const float4 rt = rec[N + t];       // p is unchanged until write_p
+            pqa += rt.x * cs[t];
+            pqp += rt.y * cs[KMAX + t];
+            if (own_t && t == tid) {
+                qa[APT] = cs[t];
+                qp[APT] = cs[KMAX + t];
+            }
+        }
+    }
+
+    __device__ void write_p() {
+#pragma unroll
+        for (int k = 0; k < APT; ++k) {
+            if (!live[k]) continue;
+            rec[a[k]].x = pa[k];
+            rec[a[k]].y = pp[k];
+        }
+        if (own_t) {
+            rec[N + tid].x = pa[APT];
+            rec[N + tid].y = pp[APT];
+        }
+    }
+
+    // Jacobi-preconditioned CG on both systems from x = 0, right-hand sides
+    // in ra / rp, inverse diagonal in di, weights in the records.  Each
+    // system stops when its residual norm has fallen by `tol`.  Returns the
+    // iterations, or -1 if a right-hand side is not finite.
+    __device__ int pcg(int max_cg, float tol) {
+        float v4[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int k = 0; k < R1; ++k) {
+            xa[k] = xp[k] = 0.f;
+            pa[k] = ra[k] * di[k];
+            pp[k] = rp[k] * di[k];
+            v4[0] += ra[k] * pa[k];
+            v4[1] += rp[k] * pp[k];
+            v4[2] += ra[k] * ra[k];
+            v4[3] += rp[k] * rp[k];
+        }
+        write_p();
+        block_sum<NW, 4>(v4, R);       // its barrier also publishes p
+        if (!(v4[2] == v4[2]) || !(v4[3] == v4[3]) || isinf(v4[2]) || isinf(v4[3])) return -1;
+        float rza = v4[0], rzp = v4[1];
+        const float stopa = tol * tol * v4[2], stopp = tol * tol * v4[3];
+        bool done_a = !(v4[2] > 0.f), done_p = !(v4[3] > 0.f);
+        int it = 0;
+        for (; it < max_cg && !(done_a && done_p); ++it) {
+            float qa[R1], qp[R1], pqa, pqp;
+            matvec(qa, qp, pqa, pqp);
+            const float ala = (!done_a && pqa > 0.f) ? rza / pqa : 0.f;
+            const float alp = (!done_p && pqp > 0.f) ? rzp / pqp : 0.f;
+            float w4[4] = {0.f, 0.f, 0.f, 0.f};
+            float za[R1], zp[R1];
+#pragma unroll
+            for (int k = 0; k < R1; ++k) {
+                xa[k] += ala * pa[k];
+                xp[k] += alp * pp[k];
+                ra[k] -= ala * qa[k];
+                rp[k] -= alp * qp[k];
+                za[k] = ra[k] * di[k];
+                zp[k] = rp[k] * di[k];
+                w4[0] += ra[k] * za[k];
+                w4[1] += rp[k] * zp[k];
+                w4[2] += ra[k] * ra[k];
+                w4[3] += rp[k] * rp[k];
+            }
+            block_sum<NW, 4>(w4, R);
+            const float ba = (rza > 0.f) ? w4[0] / rza : 0.f;
+            const float bp = (rzp > 0.f) ? w4[1] / rzp : 0.f;
+            if (!done_a) rza = w4[0];
+            if (!done_p) rzp = w4[1];
+#pragma unroll
+            for (int k = 0; k < R1; ++k) {
+                if (!done_a) pa[k] = za[k] + ba * pa[k];
+                if (!done_p) pp[k] = zp[k] + bp * pp[k];
+            }
+            done_a = done_a || !(w4[2] > stopa);
+            done_p = done_p || !(w4[3] > stopp);
+            write_p();
+            __syncthreads();
+        }
+        return it;
+    }
+
+    // V_t = mean over the group of V_b / (g_i conj(g_j)), in FP32.
+    __device__ void group_mean() {
+        float sv[2 * KMAX];
+#pragma unroll
+        for (int i = 0; i < 2 * KMAX; ++i) sv[i] = 0.f;
+#pragma unroll
+        for (int t = 0; t < KMAX; ++t) {
+            if (t >= K) break;
+#pragma unroll
+            for (int k = 0; k < APT; ++k) {
+                if (!live[k] || !((m1[k] >> t) & 1u)) continue;
+                const int b = b1(t, k);
+                const float2 gg = cmulc(to_f(gd[a[k]]), to_f(gd[a[k] - dxy(t)]));
+                const float2 q = cmulc(load_vred(vred, ci4, vbase + b), gg);
+                const float inv = 1.0f / cabs2(gg);
+                sv[t] += q.x * inv;
+                sv[KMAX + t] += q.y * inv;
+            }
+        }
+        block_sum<NW, 2 * KMAX>(sv, R);
+#pragma unroll
+        for (int t = 0; t < KMAX; ++t) {
+            if (t >= K || !own_t || t != tid) continue;
+            const float cnt = (float)ty[t].cnt;
+            vmd[t] = to_d(make_float2(sv[t] / cnt, sv[KMAX + t] / cnt));
+        }
         __syncthreads();
     }
-    return it;
-}
 
-// ------------------------------------------------------------ GN pieces
-
-// Residual pass, FP32: for every pair m_b, w_b = |m_b|^2 and
-// q_b = r_b conj(m_b); then the right-hand sides (ra, rp = J^H r split into
-// real and imaginary parts) and the diagonal d.
-template <int APT>
-__device__ void residual_pass32(const Sel& s, const Own<APT>& o, const Mem& m, const void* vred,
-                                bool ci4, size_t vbase) {
-    const int N = s.N;
-    for (int t = 0; t < s.K; ++t) {
-        const int dxy = s.dy[t] * s.n + s.dx[t];
-        const float2 vt = m.vm[t];
+    // Start, part 1: the logcal amplitude system (unit weights, right-hand
+    // side sum of ln|V_b|) in ra / di, phase system empty.
+    __device__ void firstcal_rhs() {
+        float tq[2 * KMAX];
 #pragma unroll
-        for (int k = 0; k < APT; ++k) {
-            if (o.a[k] >= N) continue;
-            const int b = pair_as_first(s, t, o.x[k], o.y[k]);
-            if (b < 0) continue;
-            const int i = o.a[k], j = i - dxy;
-            const float2 mm = cmul(cmulc(m.g[i], m.g[j]), vt);
-            const float2 q = cmulc(csub(load_vred(vred, ci4, vbase + b), mm), mm);
-            m.sa[b] = q.x;
-            m.sp[b] = q.y;
-            m.w[b] = cabs2(mm);
-        }
-    }
-    __syncthreads();
-    gather_rows<APT>(s, o, m.sa, m.sp, m.w, m.ra, m.rp, m.d);
-    type_rows<APT>(*m.ls, m.sa, m.sp, m.w, m.ra, m.rp, m.d);
-}
-
-// q_b = r_b conj(m_b) in FP64 for the pair (i, j) of type t.
-__device__ __forceinline__ double2 q_hi(const Mem& m, const void* vred, bool ci4, size_t vb, int b,
-                                        int i, int j, int t, double& wb) {
-    const double2 mm = dmul(dmulc(m.gd[i], m.gd[j]), m.vmd[t]);
-    wb = dabs2(mm);
-    return dmulc(dsub(load_vred_d(vred, ci4, vb + b), mm), mm);
-}
-
-// Residual pass, FP64: near the optimum J^H r is a sum of per-pair terms
-// of the size of the noise that cancel to a tiny total, so it is summed in
-// FP64: per antenna over its pairs, and per type by the summing wave, each
-// pair's residual recomputed where it is needed.  The FP32 normal
-// equations then get the right-hand side scaled to unit norm; the scale is
-// returned (multiply the solution by it).
-template <int APT>
-__device__ double residual_pass64(const Sel& s, const Own<APT>& o, const Mem& m, Reducer& R,
-                                  const void* vred, bool ci4, size_t vbase) {
-    const int N = s.N;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int t = 0; t < s.K; ++t) {
-        const int dxy = s.dy[t] * s.n + s.dx[t];
+        for (int i = 0; i < 2 * KMAX; ++i) tq[i] = 0.f;
+        float rA[R1], dd[R1];
 #pragma unroll
-        for (int k = 0; k < APT; ++k) {
-            if (o.a[k] >= N) continue;
-            const int b = pair_as_first(s, t, o.x[k], o.y[k]);
-            if (b < 0) continue;
-            const int i = o.a[k];
-            const double2 mm = dmul(dmulc(m.gd[i], m.gd[i - dxy]), m.vmd[t]);
-            m.w[b] = (float)dabs2(mm);
-        }
-    }
-    __syncthreads();
-    double ra_loc[APT + 1], rp_loc[APT + 1];
-    double nrm[1] = {0.0};
+        for (int k = 0; k < R1; ++k) rA[k] = dd[k] = 0.f;
 #pragma unroll
-    for (int k = 0; k < APT; ++k) {
-        ra_loc[k] = rp_loc[k] = 0.0;
-        if (o.a[k] >= N) continue;
-        const int a = o.a[k];
-        double ya = 0.0, yp = 0.0;
-        float dd = 0.f;
-        for (int t = 0; t < s.K; ++t) {
-            const int dxy = s.dy[t] * s.n + s.dx[t];
-            const int b1 = pair_as_first(s, t, o.x[k], o.y[k]);
-            const int b2 = pair_as_second(s, t, o.x[k], o.y[k]);
-            double wb;
-            if (b1 >= 0) {
-                const double2 q = q_hi(m, vred, ci4, vbase, b1, a, a - dxy, t, wb);
-                ya += q.x;
-                yp += q.y;
-                dd += m.w[b1];
-            }
-            if (b2 >= 0) {
-                const double2 q = q_hi(m, vred, ci4, vbase, b2, a + dxy, a, t, wb);
-                ya += q.x;
-                yp -= q.y;
-                dd += m.w[b2];
+        for (int t = 0; t < KMAX; ++t) {
+            if (t >= K) break;
+#pragma unroll
+            for (int k = 0; k < APT; ++k) {
+                if (!live[k]) continue;
+                if ((m1[k] >> t) & 1u) {
+                    const int b = b1(t, k);
+                    const float lv = 0.5f * logf(fmaxf(cabs2(load_vred(vred, ci4, vbase + b)), 1e-30f));
+                    rA[k] += lv;
+                    dd[k] += 1.f;
+                    tq[t] += lv;
+                    tq[KMAX + t] += 1.f;
+                }
+                if ((m2[k] >> t) & 1u) {
+                    const int b = b2(t, k);
+                    rA[k] += 0.5f * logf(fmaxf(cabs2(load_vred(vred, ci4, vbase + b)), 1e-30f));
+                    dd[k] += 1.f;
+                }
             }
         }
-        ra_loc[k] = ya;
-        rp_loc[k] = yp;
-        m.d[a] = dd;
-        nrm[0] += ya * ya + yp * yp;
-    }
-    ra_loc[APT] = rp_loc[APT] = 0.0;
-    const Sel& ls = *m.ls;
-    for (int t = wave; t < ls.K; t += kSWaves) {
-        double ya = 0.0, yp = 0.0;
-        float dd = 0.f;
-        for (int b = ls.off[t] + lane; b < ls.off[t + 1]; b += 64) {
-            int i, j;
-            pair_ij(ls, t, b - ls.off[t], i, j);
-            double wb;
-            const double2 q = q_hi(m, vred, ci4, vbase, b, i, j, t, wb);
-            ya += q.x;
-            yp += q.y;
-            dd += m.w[b];
-        }
-        ya = wave_allsum(ya);
-        yp = wave_allsum(yp);
-        dd = wave_allsum(dd);
-        if (lane == t / kSWaves) {
-            ra_loc[APT] = ya;
-            rp_loc[APT] = yp;
-            m.d[N + t] = dd;
-            nrm[0] += ya * ya + yp * yp;
-        }
-    }
-    block_sum<1>(nrm, R);
-    const double scale = nrm[0] > 0.0 ? sqrt(nrm[0]) : 1.0;
-    const double inv = 1.0 / scale;
+        block_sum<NW, 2 * KMAX>(tq, R);
 #pragma unroll
-    for (int k = 0; k < APT; ++k) {
-        if (o.a[k] >= N) continue;
-        m.ra[o.a[k]] = (float)(ra_loc[k] * inv);
-        m.rp[o.a[k]] = (float)(rp_loc[k] * inv);
-    }
-    if (o.trow >= 0) {
-        m.ra[N + o.trow] = (float)(ra_loc[APT] * inv);
-        m.rp[N + o.trow] = (float)(rp_loc[APT] * inv);
-    }
-    return scale;
-}
-
-// V_t = mean over the group of V_b / (g_i conj(g_j)) (FP32 parameters),
-// summed by the waves; visible to all after the closing barrier.
-template <int APT>
-__device__ void group_mean(const Mem& m, const void* vred, bool ci4, size_t vbase) {
-    const Sel& s = *m.ls;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int t = wave; t < s.K; t += kSWaves) {
-        float sr = 0.f, si = 0.f;
-        for (int b = s.off[t] + lane; b < s.off[t + 1]; b += 64) {
-            int i, j;
-            pair_ij(s, t, b - s.off[t], i, j);
-            const float2 gg = cmulc(m.g[i], m.g[j]);
-            const float2 q = cmulc(load_vred(vred, ci4, vbase + b), gg);
-            const float inv = 1.0f / cabs2(gg);
-            sr += q.x * inv;
-            si += q.y * inv;
+        for (int t = 0; t < KMAX; ++t) {
+            if (t >= K || !own_t || t != tid) continue;
+            rA[APT] = tq[t];
+            dd[APT] = tq[KMAX + t];
         }
-        sr = wave_allsum(sr);
-        si = wave_allsum(si);
-        if (lane == 0) {
-            const float cnt = (float)(s.off[t + 1] - s.off[t]);
-            m.vm[t] = make_float2(sr / cnt, si / cnt);
+#pragma unroll
+        for (int k = 0; k < R1; ++k) {
+            ra[k] = mine(k) ? rA[k] : 0.f;
+            rp[k] = 0.f;
+            di[k] = dd[k] > 0.f ? 1.0f / dd[k] : 0.f;
         }
+        publish_weights(true);
     }
-    __syncthreads();
-}
 
-// Logcal amplitudes and chained phases (see the file comment).
-template <int APT>
-__device__ void firstcal(const Sel& s, const Own<APT>& o, const Mem& m, Reducer& R, const void* vred,
-                         bool ci4, size_t vbase, int t10, int t01, int max_cg) {
-    const int N = s.N, n = s.n;
-    // amplitude: unweighted least squares on ln|V_b|
-    for (int t = 0; t < s.K; ++t) {
+    // Start, part 2: amplitudes from the solved system, phases chained from
+    // antenna (0,0) along the (1,0) group in the first row and the (0,1)
+    // group up each column (each link's phase taken relative to the first
+    // visibility of its group), into gd.
+    __device__ void firstcal_finish() {
+        int off10 = 0, off01 = 0;
+#pragma unroll
+        for (int t = 0; t < KMAX; ++t) {
+            if (t >= K) break;
+            if (ty[t].dx == 1 && ty[t].dy == 0) off10 = ty[t].off;
+            if (ty[t].dx == 0 && ty[t].dy == 1) off01 = ty[t].off;
+        }
+        const float2 v10 = load_vred(vred, ci4, vbase + off10);
+        const float2 v01 = load_vred(vred, ci4, vbase + off01);
+        const float psi10 = atan2f(v10.y, v10.x), psi01 = atan2f(v01.y, v01.x);
+        const float2 r10 = make_float2(cosf(psi10), -sinf(psi10));
+        const float2 r01 = make_float2(cosf(psi01), -sinf(psi01));
 #pragma unroll
         for (int k = 0; k < APT; ++k) {
-            if (o.a[k] >= N) continue;
-            const int b = pair_as_first(s, t, o.x[k], o.y[k]);
-            if (b < 0) continue;
-            m.sa[b] = 0.5f * logf(fmaxf(cabs2(load_vred(vred, ci4, vbase + b)), 1e-30f));
-            m.sp[b] = 0.f;
-            m.w[b] = 1.0f;
+            if (!live[k]) continue;
+            const int x = ax(k), y = ay(k);
+            float inc = 0.f;
+            if (y == 0 && x >= 1) {           // pair ((x,0), (x-1,0))
+                const float2 v = cmul(load_vred(vred, ci4, vbase + off10 + (x - 1)), r10);
+                inc = atan2f(v.y, v.x);
+            } else if (y >= 1) {              // pair ((x,y), (x,y-1))
+                const float2 v = cmul(load_vred(vred, ci4, vbase + off01 + (y - 1) * n + x), r01);
+                inc = atan2f(v.y, v.x);
+            }
+            rec[a[k]].w = inc;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            rec[0].w = 0.f;
+            for (int x = 1; x < n; ++x) rec[x].w += rec[x - 1].w;
+        }
+        __syncthreads();
+        if (tid < n) {
+            for (int y = 1; y < n; ++y) rec[y * n + tid].w += rec[(y - 1) * n + tid].w;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < APT; ++k) {
+            if (!live[k]) continue;
+            const float amp = expf(xa[k]);
+            float sn, cs;
+            sincosf(rec[a[k]].w, &sn, &cs);
+            gd[a[k]] = to_d(make_float2(amp * cs, amp * sn));
+        }
+        __syncthreads();
+    }
+
+    // g <- g e^{eta}, V <- V e^{zeta} with (eta, zeta) = xscale * x, in
+    // FP64.  The factor is formed as 1 + (small part), the small parts
+    // (expm1 of the log-amplitude step, cos - 1 and sin of the phase step)
+    // in FP32 to full relative precision, so the update keeps FP64 accuracy
+    // however small the step.  Returns the rms step; the reduction's barrier
+    // publishes g and V.
+    __device__ float update(double xscale) {
+        float e2[1] = {0.f};
+#pragma unroll
+        for (int k = 0; k < R1; ++k) {
+            if (!mine(k)) continue;
+            const float ea = (float)(xa[k] * xscale), ep = (float)(xp[k] * xscale);
+            e2[0] += ea * ea + ep * ep;
+            const float sh = sinf(0.5f * ep);
+            const double da = (double)expm1f(ea);
+            const double dc = -2.0 * (double)(sh * sh);      // cos(ep) - 1
+            const double sp = (double)sinf(ep);
+            const double fr = (1.0 + da) * (1.0 + dc), fi = (1.0 + da) * sp;
+            const double2 f = make_double2(fr, fi);
+            if (k < APT) gd[a[k]] = dmul(gd[a[k]], f);
+            else vmd[tid] = dmul(vmd[tid], f);
+        }
+        block_sum<NW, 1>(e2, R);
+        return sqrtf(e2[0] / (float)(N + K));
+    }
+};
+
+// The whole solve of one unit by one workgroup of NT work-items.
+template <int NT, int APT, int KMAX>
+__device__ void solve_unit(const SolveLaunch& L, Shared<NT / 64>& sh, unsigned char* lds, int unit) {
+    constexpr int NW = NT / 64;
+    const Sel& s = L.sel;
+    const SolveOpts op = L.o;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int t = 0; t < KMAX; ++t) {
+            if (t >= s.K) break;
+            const int dx = s.dx[t], dy = s.dy[t], w = s.n - (dx < 0 ? -dx : dx);
+            TypeInfo& T = sh.ty[t];
+            T.dxy = dy * s.n + dx;
+            T.w = w;
+            T.c1 = s.off[t] - dy * w - (dx > 0 ? dx : 0);
+            T.c2 = s.off[t] + (dx < 0 ? dx : 0);
+            T.dx = dx;
+            T.dy = dy;
+            T.off = s.off[t];
+            T.cnt = s.off[t + 1] - s.off[t];
         }
     }
     __syncthreads();
-    gather_rows<APT>(s, o, m.sa, m.sp, m.w, m.ra, m.rp, m.d);
-    type_rows<APT>(*m.ls, m.sa, m.sp, m.w, m.ra, m.rp, m.d);
-    pcg2<APT>(s, o, m, R, max_cg, 1e-3f);
-    // phase increments along the chains, in qp[] (scratch)
-    const int off10 = m.ls->off[t10], off01 = m.ls->off[t01];
-    const float2 v10 = load_vred(vred, ci4, vbase + off10);
-    const float2 v01 = load_vred(vred, ci4, vbase + off01);
-    const float psi10 = atan2f(v10.y, v10.x), psi01 = atan2f(v01.y, v01.x);
-    const float2 r10 = make_float2(cosf(psi10), -sinf(psi10));
-    const float2 r01 = make_float2(cosf(psi01), -sinf(psi01));
-#pragma unroll
-    for (int k = 0; k < APT; ++k) {
-        if (o.a[k] >= N) continue;
-        const int x = o.x[k], y = o.y[k];
-        float inc = 0.f;
-        if (y == 0 && x >= 1) {
-            const float2 v = cmul(load_vred(vred, ci4, vbase + off10 + (x - 1)), r10);
-            inc = atan2f(v.y, v.x);
-        } else if (y >= 1) {
-            const float2 v = cmul(load_vred(vred, ci4, vbase + off01 + (y - 1) * n + x), r01);
-            inc = atan2f(v.y, v.x);
-        }
-        m.qp[o.a[k]] = inc;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        m.qp[0] = 0.f;
-        for (int x = 1; x < n; ++x) m.qp[x] += m.qp[x - 1];
-    }
-    __syncthreads();
-    if ((int)threadIdx.x < n) {
-        const int x = threadIdx.x;
-        for (int y = 1; y < n; ++y) m.qp[y * n + x] += m.qp[(y - 1) * n + x];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < APT; ++k) {
-        if (o.a[k] >= N) continue;
-        const float amp = expf(m.xa[o.a[k]]);
-        float sn, cs;
-        sincosf(m.qp[o.a[k]], &sn, &cs);
-        m.g[o.a[k]] = make_float2(amp * cs, amp * sn);
-    }
-    __syncthreads();
-}
+    Solver<NT, APT, KMAX> S(s, sh.ty, make_reducer(sh), lds, L.vred, L.ci4, (size_t)unit * s.P);
+    Reducer& R = S.R;
+    const int N = S.N, K = S.K, tid = S.tid;
 
-// ------------------------------------------------------------- the kernel
-
-// The whole solve of one unit by one workgroup.
-template <int APT, bool LDS>
-__device__ void solve_unit(const SolveLaunch& L, Shared& sh, unsigned char* ssm, int unit) {
-    // The selection is read from an LDS copy: indexing the by-value kernel
-    // argument with a type index would make the compiler copy the argument
-    // to private memory.
-    if (threadIdx.x == 0) {
-        const int* src = reinterpret_cast<const int*>(&L.sel);
-        int* dst = reinterpret_cast<int*>(&sh.sel);
-#pragma unroll
-        for (int i = 0; i < (int)(sizeof(Sel) / sizeof(int)); ++i) dst[i] = src[i];
-    }
-    __syncthreads();
-    const Sel& ls = sh.sel;
-    const Sel& s = ls;
-    Reducer R{&sh};
-    const int N = s.N, K = s.K;
-    const size_t vbase = (size_t)unit * s.P;
-    char* slab = L.slab + (size_t)unit * L.slab_bytes;
-    char* hot = LDS ? reinterpret_cast<char*>(ssm) : slab;
-    const HotLayout H = hot_layout(s);
-    const ColdLayout C = cold_layout(s, LDS ? 0 : H.bytes);
-    Mem m;
-    m.ls = &ls;
-    m.w = reinterpret_cast<float*>(hot + H.w);
-    m.sa = reinterpret_cast<float*>(hot + H.sa);
-    m.sp = reinterpret_cast<float*>(hot + H.sp);
-    m.d = reinterpret_cast<float*>(hot + H.d);
-    m.xa = reinterpret_cast<float*>(hot + H.xa);
-    m.ra = reinterpret_cast<float*>(hot + H.ra);
-    m.za = reinterpret_cast<float*>(hot + H.za);
-    m.pa = reinterpret_cast<float*>(hot + H.pa);
-    m.qa = reinterpret_cast<float*>(hot + H.qa);
-    m.xp = reinterpret_cast<float*>(hot + H.xp);
-    m.rp = reinterpret_cast<float*>(hot + H.rp);
-    m.zp = reinterpret_cast<float*>(hot + H.zp);
-    m.pp = reinterpret_cast<float*>(hot + H.pp);
-    m.qp = reinterpret_cast<float*>(hot + H.qp);
-    m.g = reinterpret_cast<float2*>(slab + C.g);
-    m.vm = reinterpret_cast<float2*>(slab + C.vm);
-    m.gd = reinterpret_cast<double2*>(slab + C.gd);
-    m.vmd = reinterpret_cast<double2*>(slab + C.vmd);
-
-    const Own<APT> o = own_antennas<APT>(s);
-    const SolveOpts& op = L.o;
-
-    // ---- start
-    if (op.init_mode == 1 && L.gains_in) {
+    // ---- start: caller's gains, or the logcal solve (the first CG solve
+    // of the loop below)
+    bool start = !(op.init_mode == 1 && L.gains_in);
+    if (!start) {
 #pragma unroll
         for (int k = 0; k < APT; ++k)
-            if (o.a[k] < N) m.g[o.a[k]] = L.gains_in[(size_t)unit * N + o.a[k]];
+            if (S.live[k]) S.gd[S.a[k]] = to_d(L.gains_in[(size_t)unit * N + S.a[k]]);
         __syncthreads();
-    } else {
-        int t10 = -1, t01 = -1;
-        for (int t = 0; t < K; ++t) {
-            if (ls.dx[t] == 1 && ls.dy[t] == 0) t10 = t;
-            if (ls.dx[t] == 0 && ls.dy[t] == 1) t01 = t;
-        }
-        firstcal<APT>(s, o, m, R, L.vred, L.ci4, vbase, t10, t01, op.max_cg);
+        S.group_mean();
     }
-    group_mean<APT>(m, L.vred, L.ci4, vbase);
 
-    // ---- Gauss-Newton
-    int status = 0;
-    int steps = 0;
+    // ---- Gauss-Newton: FP32 steps while the rms step is above tol32 (at
+    // most max_gn), then fp64_steps more
+    int status = 0, steps = 0, n32 = 0;
     bool hi = false;
     int hi_left = op.fp64_steps;
-    int n32 = 0;
     while (true) {
         double xscale = 1.0;
-        if (hi) {
-            if (hi_left <= 0) break;
-            xscale = residual_pass64<APT>(s, o, m, R, L.vred, L.ci4, vbase);
+        if (start) {
+            S.firstcal_rhs();
         } else {
-            residual_pass32<APT>(s, o, m, L.vred, L.ci4, vbase);
+            if (hi && hi_left <= 0) break;
+            xscale = S.residuals();
+            S.publish_weights(false);
         }
-        if (pcg2<APT>(s, o, m, R, op.max_cg, op.cg_tol) < 0) {   // non-finite data
+        const int it = S.pcg(op.max_cg, start ? 1e-3f : op.cg_tol);
+        if (start) {
+            S.firstcal_finish();
+            S.group_mean();
+            start = false;
+            continue;
+        }
+        if (it < 0) {           // non-finite data
             status = 2;
             break;
         }
-        // update g <- g e^{eta}, V <- V e^{zeta}
-        float e2[1] = {0.f};
-#pragma unroll
-        for (int k = 0; k <= APT; ++k) {
-            int e;
-            if (k < APT) {
-                e = o.a[k];
-                if (e >= N) continue;
-            } else {
-                if (o.trow < 0) continue;
-                e = N + o.trow;
-            }
-            const float xa = m.xa[e], xp = m.xp[e];
-            if (hi) {
-                const double xad = xa * xscale, xpd = xp * xscale;
-                e2[0] += (float)(xad * xad + xpd * xpd);
-                double sn, cs;
-                sincos(xpd, &sn, &cs);
-                const double amp = exp(xad);
-                const double2 f = make_double2(amp * cs, amp * sn);
-                if (e < N) {
-                    m.gd[e] = dmul(m.gd[e], f);
-                    m.g[e] = to_f(m.gd[e]);
-                } else {
-                    m.vmd[e - N] = dmul(m.vmd[e - N], f);
-                    m.vm[e - N] = to_f(m.vmd[e - N]);
-                }
-            } else {
-                e2[0] += xa * xa + xp * xp;
-                float sn, cs;
-                sincosf(xp, &sn, &cs);
-                const float amp = expf(xa);
-                const float2 f = make_float2(amp * cs, amp * sn);
-                if (e < N) m.g[e] = cmul(m.g[e], f);
-                else m.vm[e - N] = cmul(m.vm[e - N], f);
-            }
-        }
-        block_sum<1>(e2, R);
+        const float rms = S.update(xscale);
         ++steps;
-        const float rms = sqrtf(e2[0] / (float)(N + K));
         if (!(rms == rms) || isinf(rms)) {
             status = 2;
             break;
@@ -731,34 +713,23 @@ __device__ void solve_unit(const SolveLaunch& L, Shared& sh, unsigned char* ssm,
             if (rms < op.tol32 || n32 >= op.max_gn) {
                 if (!(rms < op.tol32)) status = 1;
                 hi = true;
-#pragma unroll
-                for (int k = 0; k < APT; ++k)
-                    if (o.a[k] < N) m.gd[o.a[k]] = to_d(m.g[o.a[k]]);
-                if ((int)threadIdx.x < K) m.vmd[threadIdx.x] = to_d(m.vm[threadIdx.x]);
-                __syncthreads();
             }
         }
-    }
-    if (!hi) {
-#pragma unroll
-        for (int k = 0; k < APT; ++k)
-            if (o.a[k] < N) m.gd[o.a[k]] = to_d(m.g[o.a[k]]);
-        if ((int)threadIdx.x < K) m.vmd[threadIdx.x] = to_d(m.vm[threadIdx.x]);
-        __syncthreads();
     }
 
     // ---- degeneracies (FP64)
     if (op.degen_mode == 1 && L.gains_ref) {
+        // match the mean log-amplitude and a phase plane to the reference
         double v9[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
         for (int k = 0; k < APT; ++k) {
-            if (o.a[k] >= N) continue;
-            const double2 g = m.gd[o.a[k]];
-            const double2 gr = to_d(L.gains_ref[(size_t)unit * N + o.a[k]]);
-            const double2 q = dmulc(g, gr);
+            if (!S.live[k]) continue;
+            const double2 gg = S.gd[S.a[k]];
+            const double2 gr = to_d(L.gains_ref[(size_t)unit * N + S.a[k]]);
+            const double2 q = dmulc(gg, gr);
             const double ph = atan2(q.y, q.x);
-            const double x = o.x[k], y = o.y[k];
-            v9[0] += 0.5 * log(dabs2(g)) - 0.5 * log(dabs2(gr));
+            const double x = S.ax(k), y = S.ay(k);
+            v9[0] += 0.5 * log(dabs2(gg)) - 0.5 * log(dabs2(gr));
             v9[1] += ph;
             v9[2] += ph * x;
             v9[3] += ph * y;
@@ -768,8 +739,8 @@ __device__ void solve_unit(const SolveLaunch& L, Shared& sh, unsigned char* ssm,
             v9[7] += x * y;
             v9[8] += y * y;
         }
-        block_sum<9>(v9, R);
-        if (threadIdx.x == 0) {
+        block_sum<NW, 9>(v9, R);
+        if (tid == 0) {
             // [N  Sx  Sy ; Sx Sxx Sxy ; Sy Sxy Syy] c = [S, Sx, Sy] by Cramer's rule
             const double a00 = N, a01 = v9[4], a02 = v9[5], a11 = v9[6], a12 = v9[7], a22 = v9[8];
             const double det = a00 * (a11 * a22 - a12 * a12) - a01 * (a01 * a22 - a12 * a02) +
@@ -787,13 +758,14 @@ __device__ void solve_unit(const SolveLaunch& L, Shared& sh, unsigned char* ssm,
             sh.bcast[3] = c2;
         }
     } else {
+        // sum ln|g| = 0; antennas (0,0), (1,0) and (0,1) real
         double v1[1] = {0.0};
 #pragma unroll
         for (int k = 0; k < APT; ++k)
-            if (o.a[k] < N) v1[0] += 0.5 * log(dabs2(m.gd[o.a[k]]));
-        block_sum<1>(v1, R);
-        if (threadIdx.x == 0) {
-            const double2 g0 = m.gd[0], g1 = m.gd[1], gn = m.gd[s.n];
+            if (S.live[k]) v1[0] += 0.5 * log(dabs2(S.gd[S.a[k]]));
+        block_sum<NW, 1>(v1, R);
+        if (tid == 0) {
+            const double2 g0 = S.gd[0], g1 = S.gd[1], gn = S.gd[s.n];
             const double2 qx = dmulc(g1, g0), qy = dmulc(gn, g0);
             sh.bcast[0] = exp(v1[0] / N);
             sh.bcast[1] = atan2(g0.y, g0.x);
@@ -806,43 +778,43 @@ __device__ void solve_unit(const SolveLaunch& L, Shared& sh, unsigned char* ssm,
         const double lam = sh.bcast[0], c0 = sh.bcast[1], kx = sh.bcast[2], ky = sh.bcast[3];
 #pragma unroll
         for (int k = 0; k < APT; ++k) {
-            if (o.a[k] >= N) continue;
+            if (!S.live[k]) continue;
             double sn, cs;
-            sincos(-(c0 + kx * o.x[k] + ky * o.y[k]), &sn, &cs);
-            const double2 g = m.gd[o.a[k]];
-            m.gd[o.a[k]] = make_double2((g.x * cs - g.y * sn) / lam, (g.x * sn + g.y * cs) / lam);
+            sincos(-(c0 + kx * S.ax(k) + ky * S.ay(k)), &sn, &cs);
+            const double2 gg = S.gd[S.a[k]];
+            S.gd[S.a[k]] = make_double2((gg.x * cs - gg.y * sn) / lam, (gg.x * sn + gg.y * cs) / lam);
         }
-        if ((int)threadIdx.x < K) {
-            const int t = threadIdx.x;
+#pragma unroll
+        for (int t = 0; t < KMAX; ++t) {
+            if (t >= K || !S.own_t || t != tid) continue;
             double sn, cs;
-            sincos(kx * ls.dx[t] + ky * ls.dy[t], &sn, &cs);
-            const double2 v = m.vmd[t];
+            sincos(kx * sh.ty[t].dx + ky * sh.ty[t].dy, &sn, &cs);
+            const double2 v = S.vmd[t];
             const double l2 = lam * lam;
-            m.vmd[t] = make_double2((v.x * cs - v.y * sn) * l2, (v.x * sn + v.y * cs) * l2);
+            S.vmd[t] = make_double2((v.x * cs - v.y * sn) * l2, (v.x * sn + v.y * cs) * l2);
         }
     }
     __syncthreads();
 
     // ---- chi^2 (FP64) and outputs
     double c1[1] = {0.0};
-    for (int t = 0; t < K; ++t) {
-        const int dxy = s.dy[t] * s.n + s.dx[t];
+#pragma unroll
+    for (int t = 0; t < KMAX; ++t) {
+        if (t >= K) break;
 #pragma unroll
         for (int k = 0; k < APT; ++k) {
-            if (o.a[k] >= N) continue;
-            const int b = pair_as_first(s, t, o.x[k], o.y[k]);
-            if (b < 0) continue;
-            const int i = o.a[k], j = i - dxy;
-            const double2 mm = dmul(dmulc(m.gd[i], m.gd[j]), m.vmd[t]);
-            c1[0] += dabs2(dsub(load_vred_d(L.vred, L.ci4, vbase + b), mm));
+            if (!S.live[k] || !((S.m1[k] >> t) & 1u)) continue;
+            const int b = S.b1(t, k);
+            const double2 mm = dmul(dmulc(S.gd[S.a[k]], S.gd[S.a[k] - S.dxy(t)]), S.vmd[t]);
+            c1[0] += dabs2(dsub(load_vred_d(L.vred, L.ci4, S.vbase + b), mm));
         }
     }
-    block_sum<1>(c1, R);
+    block_sum<NW, 1>(c1, R);
 #pragma unroll
     for (int k = 0; k < APT; ++k)
-        if (o.a[k] < N) L.gains_out[(size_t)unit * N + o.a[k]] = to_f(m.gd[o.a[k]]);
-    if ((int)threadIdx.x < K) L.vmodel[(size_t)unit * K + threadIdx.x] = to_f(m.vmd[threadIdx.x]);
-    if (threadIdx.x == 0) {
+        if (S.live[k]) L.gains_out[(size_t)unit * N + S.a[k]] = to_f(S.gd[S.a[k]]);
+    if (S.own_t) L.vmodel[(size_t)unit * K + tid] = to_f(S.vmd[tid]);
+    if (tid == 0) {
         const bool fin = c1[0] == c1[0] && !isinf(c1[0]);
         L.chisq[unit] = (float)c1[0];
         L.niter[unit] = steps;
@@ -851,98 +823,96 @@ __device__ void solve_unit(const SolveLaunch& L, Shared& sh, unsigned char* ssm,
 }
 
 #ifndef RRC_HOST_EMU
-template <int APT, bool LDS>
-__global__ __launch_bounds__(kSThreads) void k_solve(SolveLaunch L) {
+template <int NT, int APT, int KMAX>
+__global__ __launch_bounds__(NT) void k_solve(SolveLaunch L) {
     extern __shared__ __align__(16) unsigned char ssm[];
-    __shared__ Shared sh;
-    solve_unit<APT, LDS>(L, sh, ssm, blockIdx.x);
+    __shared__ Shared<NT / 64> sh;
+    solve_unit<NT, APT, KMAX>(L, sh, ssm, blockIdx.x);
 }
 
-template <int APT, bool LDS_OK>
-static hipError_t launch_solve_apt(const SolveLaunch& L, hipStream_t st) {
-    if constexpr (LDS_OK) {
-        if (L.lds) {
-            auto kern = k_solve<APT, true>;
-            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.lds_bytes);
-            hipLaunchKernelGGL(kern, dim3(L.n_units), dim3(kSThreads), L.lds_bytes, st, L);
-            return hipGetLastError();
-        }
-    } else {
-        if (L.lds) return hipErrorInvalidValue;
-    }
-    hipLaunchKernelGGL((k_solve<APT, false>), dim3(L.n_units), dim3(kSThreads), 0, st, L);
+template <int NT, int APT, int KMAX>
+static hipError_t launch_solve_k(const SolveLaunch& L, hipStream_t st) {
+    auto kern = k_solve<NT, APT, KMAX>;
+    if (hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)L.lds_bytes) != hipSuccess)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(kern, dim3(L.n_units), dim3(NT), L.lds_bytes, st, L);
     return hipGetLastError();
 }
 
+template <int NT, int APT>
+static hipError_t launch_solve_shape(const SolveLaunch& L, hipStream_t st) {
+    if (L.sel.K <= 8) return launch_solve_k<NT, APT, 8>(L, st);
+    return launch_solve_k<NT, APT, kMaxTypes>(L, st);
+}
+
 hipError_t launch_solve(const SolveLaunch& L, hipStream_t st) {
-    const int apt = (L.sel.N + kSThreads - 1) / kSThreads;
-    if (apt <= 1) return launch_solve_apt<1, true>(L, st);
-    if (apt <= 2) return launch_solve_apt<2, true>(L, st);
-    if (apt <= 4) return launch_solve_apt<4, true>(L, st);
-    if (apt <= 16) return launch_solve_apt<16, false>(L, st);
+    const int N = L.sel.N;
+    if (L.sel.K < 1 || L.sel.K > kMaxTypes || L.sel.K > solve_threads_for(N)) return hipErrorInvalidValue;
+    if (N <= 256) return launch_solve_shape<256, 1>(L, st);
+    if (N <= 512) return launch_solve_shape<512, 1>(L, st);
+    if (N <= 1024) return launch_solve_shape<1024, 1>(L, st);
+    if (N <= 2048) return launch_solve_shape<1024, 2>(L, st);
+    if (N <= 4096) return launch_solve_shape<1024, 4>(L, st);
     return hipErrorInvalidValue;
 }
 
 // --------------------------------------------------- chi^2 and its adjoint
 //
-// One workgroup per unit.  Forward: sum_b |r_b|^2 in FP64 over FP32
-// products.  Adjoint (a6): antenna-centric gathers over the 2K incident
-// pairs, r_b recomputed on the fly; type sums by wave reductions.
+// One workgroup of 256 work-items per unit.  Forward: sum_b |r_b|^2 in
+// FP64 over FP32 products.  Adjoint (a6): antenna-centric gathers over the
+// (at most 2K) incident pairs with r_b recomputed on the fly; type rows
+// summed by one wave per type over the type's pairs.
+
+constexpr int kCThreads = 256;
 
 template <int APT, bool ADJ>
-__global__ __launch_bounds__(kSThreads) void k_chisq(ChisqLaunch L) {
-    __shared__ Shared sh;
-    if (threadIdx.x == 0) {
-        const int* src = reinterpret_cast<const int*>(&L.sel);
-        int* dst = reinterpret_cast<int*>(&sh.sel);
-#pragma unroll
-        for (int i = 0; i < (int)(sizeof(Sel) / sizeof(int)); ++i) dst[i] = src[i];
-    }
-    __syncthreads();
+__global__ __launch_bounds__(kCThreads) void k_chisq(ChisqLaunch L) {
+    __shared__ Shared<kCThreads / 64> sh;
+    copy_sel(L.sel, sh.sel);
     const Sel& s = sh.sel;
     const int unit = blockIdx.x;
-    const int N = s.N, K = s.K;
+    const int N = s.N, K = s.K, n = s.n;
     const float2* g = L.g + (size_t)unit * N;
     const float2* vm = L.vm + (size_t)unit * K;
     const float2* vr = L.vred + (size_t)unit * s.P;
-    const Own<APT> o = own_antennas<APT>(s);
-    Reducer R{&sh};
+    Reducer R = make_reducer(sh);
     if constexpr (!ADJ) {
         double c1[1] = {0.0};
         for (int t = 0; t < K; ++t) {
-            const int dxy = s.dy[t] * s.n + s.dx[t];
+            const int dxy = s.dy[t] * n + s.dx[t];
 #pragma unroll
             for (int k = 0; k < APT; ++k) {
-                if (o.a[k] >= N) continue;
-                const int b = pair_as_first(s, t, o.x[k], o.y[k]);
+                const int a = threadIdx.x + k * kCThreads;
+                if (a >= N) continue;
+                const int b = pair_as_first(s, t, a % n, a / n);
                 if (b < 0) continue;
-                const int i = o.a[k], j = i - dxy;
-                const float2 r = csub(vr[b], cmul(cmulc(g[i], g[j]), vm[t]));
+                const float2 r = csub(vr[b], cmul(cmulc(g[a], g[a - dxy]), vm[t]));
                 c1[0] += (double)cabs2(r);
             }
         }
-        block_sum<1>(c1, R);
+        block_sum<kCThreads / 64, 1>(c1, R);
         if (threadIdx.x == 0) L.chisq[unit] = (float)c1[0];
     } else {
         // antenna rows
 #pragma unroll
         for (int k = 0; k < APT; ++k) {
-            if (o.a[k] >= N) continue;
-            const int a = o.a[k];
+            const int a = threadIdx.x + k * kCThreads;
+            if (a >= N) continue;
+            const int x = a % n, y = a / n;
             float2 gr = make_float2(0.f, 0.f);
             float dg = 0.f;
             for (int t = 0; t < K; ++t) {
-                const int dxy = s.dy[t] * s.n + s.dx[t];
-                const int b1 = pair_as_first(s, t, o.x[k], o.y[k]);
+                const int dxy = s.dy[t] * n + s.dx[t];
+                const int b1 = pair_as_first(s, t, x, y);
                 if (b1 >= 0) {   // pair (a, j): - r_b g_j conj(V_t)
                     const int j = a - dxy;
-                    const float2 c = cmulc(g[j], vm[t]);            // g_j conj(V_t)
+                    const float2 c = cmulc(g[j], vm[t]);
                     const float2 r = csub(vr[b1], cmul(cmulc(g[a], g[j]), vm[t]));
                     gr = csub(gr, cmul(r, c));
                     dg += cabs2(c);
                 }
-                const int b2 = pair_as_second(s, t, o.x[k], o.y[k]);
+                const int b2 = pair_as_second(s, t, x, y);
                 if (b2 >= 0) {   // pair (i, a): - conj(r_b) g_i V_t
                     const int i = a + dxy;
                     const float2 c = cmul(g[i], vm[t]);
@@ -954,9 +924,9 @@ __global__ __launch_bounds__(kSThreads) void k_chisq(ChisqLaunch L) {
             if (L.grad_g) L.grad_g[(size_t)unit * N + a] = make_float2(2.f * gr.x, 2.f * gr.y);
             if (L.diag_g) L.diag_g[(size_t)unit * N + a] = dg;
         }
-        // type rows, summed by the waves over each type's pairs
+        // type rows
         const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-        for (int t = wave; t < K; t += kSWaves) {
+        for (int t = wave; t < K; t += kCThreads / 64) {
             float sr = 0.f, si = 0.f, sd = 0.f;
             for (int b = s.off[t] + lane; b < s.off[t + 1]; b += 64) {
                 int i, j;
@@ -981,21 +951,18 @@ __global__ __launch_bounds__(kSThreads) void k_chisq(ChisqLaunch L) {
 
 template <int APT>
 static hipError_t launch_chisq_apt(const ChisqLaunch& L, hipStream_t st, bool adj) {
-    if (adj) hipLaunchKernelGGL((k_chisq<APT, true>), dim3(L.n_units), dim3(kSThreads), 0, st, L);
-    else hipLaunchKernelGGL((k_chisq<APT, false>), dim3(L.n_units), dim3(kSThreads), 0, st, L);
+    if (adj) hipLaunchKernelGGL((k_chisq<APT, true>), dim3(L.n_units), dim3(kCThreads), 0, st, L);
+    else hipLaunchKernelGGL((k_chisq<APT, false>), dim3(L.n_units), dim3(kCThreads), 0, st, L);
     return hipGetLastError();
 }
 
 hipError_t launch_chisq(const ChisqLaunch& L, hipStream_t st, bool adjoint) {
-    const int apt = (L.sel.N + kSThreads - 1) / kSThreads;
+    const int apt = (L.sel.N + kCThreads - 1) / kCThreads;
     if (apt <= 1) return launch_chisq_apt<1>(L, st, adjoint);
-    if (apt <= 2) return launch_chisq_apt<2>(L, st, adjoint);
     if (apt <= 4) return launch_chisq_apt<4>(L, st, adjoint);
-    if (apt <= 8) return launch_chisq_apt<8>(L, st, adjoint);
     if (apt <= 16) return launch_chisq_apt<16>(L, st, adjoint);
     return hipErrorInvalidValue;
 }
-
 #endif  // RRC_HOST_EMU
 
 }  // namespace rrc

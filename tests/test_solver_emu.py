@@ -40,7 +40,7 @@ def emu():
     return C.CDLL(out)
 
 
-def emu_solve(lib, vred, n, types, init=0, degen=0, gin=None, gref=None, lds=1, max_gn=12, fp64=2,
+def emu_solve(lib, vred, n, types, init=0, degen=0, gin=None, gref=None, threads=0, max_gn=12, fp64=2,
               max_cg=400, cg_tol=1e-2, tol32=1e-6, order=0):
     U = vred.shape[0]
     N, K = n * n, len(types)
@@ -59,7 +59,7 @@ def emu_solve(lib, vred, n, types, init=0, degen=0, gin=None, gref=None, lds=1, 
 
     rc = lib.rrc_emu_solve(n, txy, K, U, 0, p(vr), p(gin), p(gref), io, fo, p(go), p(vm),
                            ch.ctypes.data_as(C.POINTER(C.c_float)), ni.ctypes.data_as(C.POINTER(C.c_int)),
-                           st.ctypes.data_as(C.POINTER(C.c_int)), lds, order)
+                           st.ctypes.data_as(C.POINTER(C.c_int)), threads, order)
     assert rc == 0, "non-uniform barrier" if rc == -2 else rc
     return go, vm, ch, ni, st
 
@@ -73,10 +73,12 @@ def _vred(n, T, seed_wid=90, snr=10.0):
     return vr, g, pos, types, pairs, tix
 
 
-@pytest.mark.parametrize("lds", [1, 0])
-def test_emulated_solver_matches_oracle(emu, lds):
-    vr, _, pos, types, pairs, tix = _vred(8, 256)
-    go, vm, ch, ni, st = emu_solve(emu, vr, 8, types, lds=lds)
+# workgroup shapes: 256 (one wave per SIMD, direct reduction), 64 with four
+# antennas per work-item, 1024 (two-level reduction, most work-items idle)
+@pytest.mark.parametrize("n,threads", [(8, 0), (12, 64), (8, 1024)])
+def test_emulated_solver_matches_oracle(emu, n, threads):
+    vr, _, pos, types, pairs, tix = _vred(n, 256)
+    go, vm, ch, ni, st = emu_solve(emu, vr, n, types, threads=threads)
     ref = OR.calibrate(vr[0].astype(np.complex128), pos, types, pairs, tix)
     assert st[0] == 0
     assert np.max(np.abs(go[0] - ref["g"]) / np.abs(ref["g"])) <= TOL_GAINS
@@ -109,11 +111,11 @@ def test_emulated_solver_maxiter_status(emu):
     assert st[0] == 1 and ni[0] == 1
 
 
-@pytest.mark.parametrize("lds", [1, 0])
-def test_emulated_solver_has_no_data_race(emu, lds):
+@pytest.mark.parametrize("n,threads", [(8, 0), (10, 64)])
+def test_emulated_solver_has_no_data_race(emu, n, threads):
     # the result must not depend on the order work-items run between barriers
-    vr, _, pos, types, pairs, tix = _vred(8, 256)
-    outs = [emu_solve(emu, vr, 8, types, lds=lds, order=o) for o in (0, 1, 2)]
+    vr, _, pos, types, pairs, tix = _vred(n, 256)
+    outs = [emu_solve(emu, vr, n, types, threads=threads, order=o) for o in (0, 1, 2)]
     for o in outs[1:]:
         for a, b in zip(outs[0], o):
             assert np.array_equal(a, b)
