@@ -91,11 +91,11 @@ typedef struct rrc_plan rrc_plan;
 typedef struct {
     int32_t init_mode;   /* RRC_INIT_*                                            */
     int32_t degen_mode;  /* RRC_DEGEN_*                                           */
-    int32_t max_gn;      /* Gauss-Newton steps with an FP32 residual (>= 1)       */
-    int32_t fp64_steps;  /* further steps with the residual in FP64 (>= 0)        */
+    int32_t max_gn;      /* Gauss-Newton steps of the main stage (>= 1)           */
+    int32_t fp64_steps;  /* refinement steps after the main stage (>= 0)          */
     int32_t max_cg;      /* CG iterations per normal-equation solve (>= 1)        */
     float   cg_tol;      /* CG stops at ||r|| <= cg_tol ||b||                     */
-    float   tol32;       /* FP32 stage stops once the rms log-step is below this  */
+    float   tol32;       /* main stage stops once the rms log-step is below this  */
 } rrc_solver_opts;
 
 typedef struct {
@@ -112,8 +112,11 @@ typedef struct {
     uint64_t workspace_bytes;
 } rrc_plan_info;
 
-/* Default solver options (FIRSTCAL, REFANT, 12 FP32 steps, 2 FP64 steps,
- * 400 CG iterations, cg_tol 1e-2, tol32 1e-6). */
+/* Default solver options (FIRSTCAL, REFANT, at most 12 main steps, tol32
+ * 1e-5, 1 refinement step, 400 CG iterations, cg_tol 1e-2).  Every step
+ * takes its residual and right-hand side in FP64 and solves the normal
+ * equations in FP32 (iterative refinement), so the error after the last
+ * step is about cg_tol times the previous step's size. */
 void rrc_default_opts(rrc_solver_opts* opts);
 
 /* Subset redundant-calibration selection (Sec. 5.1, Sec. 5.4

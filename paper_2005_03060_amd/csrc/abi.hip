@@ -161,10 +161,10 @@ void rrc_default_opts(rrc_solver_opts* o) {
     o->init_mode = RRC_INIT_FIRSTCAL;
     o->degen_mode = RRC_DEGEN_REFANT;
     o->max_gn = 12;
-    o->fp64_steps = 2;
+    o->fp64_steps = 1;
     o->max_cg = 400;
     o->cg_tol = 1e-2f;
-    o->tol32 = 1e-6f;
+    o->tol32 = 1e-5f;
 }
 
 const char* rrc_strerror(int code) {

@@ -68,6 +68,45 @@ __device__ __forceinline__ int lag_index(int n, int dx, int dy) {
 // dx in (-n, n) and dy in [0, n) are needed; two threads per column
 // transform the even and odd rows, and X_dy = E_dy + w^dy O_dy.
 // `lds` must hold M (M+1) + M^2 complex values.
+// Sum of a unit's nchunk partial power grids, element by element in chunk
+// order (deterministic).  Each work-item takes four consecutive grid points
+// (16-byte loads) and keeps eight chunks' loads in flight at a time; the
+// totals go to dst[row * RS + col].
+template <int M, int NT, int RS>
+__device__ __forceinline__ void sum_partials(const float* __restrict__ src, int nchunk, float* dst) {
+    constexpr int Q4 = M * M / 4;
+    const float4* s4 = reinterpret_cast<const float4*>(src);
+    for (int q4 = threadIdx.x; q4 < Q4; q4 += NT) {
+        float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+        int c = 0;
+        for (; c + 8 <= nchunk; c += 8) {
+            float4 v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = s4[(size_t)(c + u) * Q4 + q4];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                acc.x += v[u].x;
+                acc.y += v[u].y;
+                acc.z += v[u].z;
+                acc.w += v[u].w;
+            }
+        }
+        for (; c < nchunk; ++c) {
+            const float4 v = s4[(size_t)c * Q4 + q4];
+            acc.x += v.x;
+            acc.y += v.y;
+            acc.z += v.z;
+            acc.w += v.w;
+        }
+        const int q = 4 * q4, row = q / M, col = q % M;
+        float* d = dst + row * RS + col;
+        d[0] = acc.x;
+        d[1] = acc.y;
+        d[2] = acc.z;
+        d[3] = acc.w;
+    }
+}
+
 template <int M>
 __device__ __forceinline__ void inverse_to_lags(float2* lds, const float* __restrict__ src, int nchunk,
                                                 int n, int T, float2* __restrict__ vunique,
@@ -77,11 +116,7 @@ __device__ __forceinline__ void inverse_to_lags(float2* lds, const float* __rest
     float* psum = reinterpret_cast<float*>(lds + M * RS);  // [M][RS] integrated power
     float2* eo = lds + M * RS;                             // [2][M][H], reuses psum's space
     const int tid = threadIdx.x;
-    for (int q = tid; q < M * M; q += NT) {
-        float acc2 = 0.0f;
-        for (int c = 0; c < nchunk; ++c) acc2 += src[(size_t)c * (M * M) + q];
-        psum[(q / M) * RS + (q % M)] = acc2;
-    }
+    sum_partials<M, NT, RS>(src, nchunk, psum);
     __syncthreads();
     if (tid < M) {
         float2 z[H];
@@ -143,6 +178,8 @@ __global__ __launch_bounds__(kFftThreads) void k_fftcorr(const void* __restrict_
     constexpr int RS = M + 1;                     // padded LDS row stride (complex)
     constexpr int CPT = 2 * M * S / NT;           // column tasks per thread (1 or 2)
     constexpr int G = S / CPT;                    // threads sharing one column half
+    static_assert(G * M == NT / 2, "column tasks fill half the workgroup per half");
+    static_assert(S * M / 2 <= NT / 2, "row tasks fit half the workgroup per half");
     static_assert(CPT == 1 || CPT == 2, "column tasks per thread");
     static_assert(M * M <= 2 * S * H * RS, "power grid must fit in the row buffer");
 
@@ -156,23 +193,39 @@ __global__ __launch_bounds__(kFftThreads) void k_fftcorr(const void* __restrict_
     const int tb = chunk * tchunk;
     const int te = min(T, tb + tchunk);
 
-    for (int a = tid; a < N; a += NT) {
-        const float2 g = gains[(size_t)unit * N + a];
-        const float d = 1.0f / cabs2(g);
-        hinv[(a / n) * (H + 1) + (a % n)] = make_float2(g.x * d, -g.y * d);   // 1/g
+    // 1/g on an H x H table, zero outside the n x n grid: the padded inputs
+    // of a row then come out zero without a branch per element.
+    for (int q = tid; q < H * (H + 1); q += NT) {
+        const int y = q / (H + 1), k = q % (H + 1);
+        float2 h = make_float2(0.0f, 0.0f);
+        if (y < n && k < n) {
+            const float2 g = gains[(size_t)unit * N + y * n + k];
+            const float d = 1.0f / cabs2(g);
+            h = make_float2(g.x * d, -g.y * d);
+        }
+        hinv[q] = h;
+    }
+    // rows n..H-1 of every sample's row buffer stay zero
+    if (n < H) {
+        for (int q = tid; q < S * (H - n) * RS; q += NT) {
+            const int s = q / ((H - n) * RS), r = q % ((H - n) * RS);
+            rbuf[(s * H + n) * RS + r] = make_float2(0.0f, 0.0f);
+        }
     }
 
     float acc[H];
 #pragma unroll
     for (int r = 0; r < H; ++r) acc[r] = 0.0f;
 
-    const int rh = tid & 1;
-    const int ry = (tid >> 1) % n;
-    const int rs = (tid >> 1) / n;
+    // The half (even / odd outputs) is uniform per wave, so only the waves
+    // of the odd half run the pre-twiddle.
+    const int rh = tid / (NT / 2);
+    const int ry = (tid % (NT / 2)) % n;
+    const int rs = (tid % (NT / 2)) / n;
     const bool row_active = rs < S;
-    const int ch = tid & 1;
-    const int cu = (tid >> 1) % M;
-    const int cs0 = (tid >> 1) / M;
+    const int ch = tid / (NT / 2);
+    const int cu = (tid % (NT / 2)) % M;
+    const int cs0 = (tid % (NT / 2)) / M;
 
     __syncthreads();
 
@@ -181,15 +234,15 @@ __global__ __launch_bounds__(kFftThreads) void k_fftcorr(const void* __restrict_
             float2 x[H];
             const int t = t0 + rs;
             const bool live = t < te;
-            const size_t rowbase = ((size_t)unit * T + (live ? t : tb)) * N + (size_t)ry * n;
+            const size_t rowbase = ((size_t)unit * T + t) * N + (size_t)ry * n;
             const float2* hrow = hinv + ry * (H + 1);
+            if (live) {
+                // columns k >= n re-read column n-1 (finite) and meet 1/g = 0
 #pragma unroll
-            for (int k = 0; k < H; ++k) {
-                if (k < n && live) {
-                    x[k] = cmul(load_volt<CI4>(volt, rowbase + k), hrow[k]);
-                } else {
-                    x[k] = make_float2(0.0f, 0.0f);
-                }
+                for (int k = 0; k < H; ++k) x[k] = cmul(load_volt<CI4>(volt, rowbase + min(k, n - 1)), hrow[k]);
+            } else {
+#pragma unroll
+                for (int k = 0; k < H; ++k) x[k] = make_float2(0.0f, 0.0f);
             }
             if (rh) {
 #pragma unroll
@@ -206,9 +259,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fftcorr(const void* __restrict_
             const int s = cs0 + c * G;
             float2 x[H];
 #pragma unroll
-            for (int k = 0; k < H; ++k) {
-                x[k] = (k < n) ? rbuf[(s * H + k) * RS + cu] : make_float2(0.0f, 0.0f);
-            }
+            for (int k = 0; k < H; ++k) x[k] = rbuf[(s * H + k) * RS + cu];
             if (ch) {
 #pragma unroll
                 for (int k = 0; k < H; ++k) x[k] = twmul<M>(x[k], k);
@@ -253,11 +304,7 @@ __global__ __launch_bounds__(kFinThreads) void k_fftfin(const float* __restrict_
     const int N = n * n;
     const int nlag = 2 * n * (n - 1);
     const float* src = ppart + (size_t)unit * nchunk * (M * M);
-    for (int q = tid; q < M * M; q += NT) {
-        float s = 0.0f;
-        for (int c = 0; c < nchunk; ++c) s += src[(size_t)c * (M * M) + q];
-        pw[q] = s;
-    }
+    sum_partials<M, NT, M>(src, nchunk, pw);
     for (int k = tid; k < M; k += NT) twp[k] = make_float2(Tw<M>::t.re[k], -Tw<M>::t.im[k]);
     __syncthreads();
 

@@ -156,6 +156,15 @@ inline T wave_allsum(T v) {
 }
 template <typename T>
 inline T wave_sum_last(T v) { return wave_allsum(v); }
+inline float fast_rcp(float x) { return 1.0f / x; }
+inline float quad_sum(float v) {
+    for (int o = 1; o <= 2; o <<= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+inline float row_sum(float v) {
+    for (int o = 1; o <= 8; o <<= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
 #else
 template <int CTRL>
 __device__ __forceinline__ int dpp_i(int v) {
@@ -191,6 +200,24 @@ __device__ __forceinline__ double wave_allsum(double v) {
     v += dpp_d<0x124>(v);
     v += dpp_d<0x128>(v);
     return (lane_d(v, 0) + lane_d(v, 16)) + (lane_d(v, 32) + lane_d(v, 48));
+}
+
+// Reciprocal by the hardware approximation (v_rcp_f32, about 1 ulp).
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// Sum over each quad of lanes / each row of 16 lanes, returned to every
+// lane of the quad / row.
+__device__ __forceinline__ float quad_sum(float v) {
+    v += dpp_f<0xB1>(v);    // quad_perm [1,0,3,2]
+    v += dpp_f<0x4E>(v);    // quad_perm [2,3,0,1]
+    return v;
+}
+__device__ __forceinline__ float row_sum(float v) {
+    v += dpp_f<0xB1>(v);
+    v += dpp_f<0x4E>(v);
+    v += dpp_f<0x124>(v);   // row_ror:4
+    v += dpp_f<0x128>(v);   // row_ror:8
+    return v;
 }
 
 // Sum over the 64 lanes, complete in lane 63 only (other lanes hold

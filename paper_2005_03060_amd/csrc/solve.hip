@@ -51,7 +51,7 @@
 namespace rrc {
 
 constexpr int kChunk = 8;                     // types per FP64 type-sum reduction
-constexpr int kRedF = 2 * kMaxTypes + 4;      // floats per block reduction (max)
+constexpr int kRedF = 2 * kMaxTypes + 8;      // floats per block reduction (max)
 constexpr int kRedD = 3 * kChunk;             // doubles per block reduction (max)
 
 __host__ __device__ inline size_t align16(size_t v) { return (v + 15) & ~(size_t)15; }
@@ -90,10 +90,24 @@ struct TypeInfo {
     int dx, dy, off, cnt;
 };
 
+// Geometry of the transposed reduction used inside CG (fast_sum): values
+// are first summed over Q lanes by DPP, the P = NT / Q partials of each
+// value go to LDS, and 16 lanes per value add them up.
+template <int NT>
+struct FastRed {
+    static constexpr int Q = NT <= 256 ? 1 : (NT <= 512 ? 4 : 16);
+    static constexpr int P = NT / Q;
+    static constexpr int E = P / 16;       // partials per lane in the second stage
+    static_assert(E >= 1 && E % 4 == 0, "second stage reads whole float4s");
+};
+constexpr int kFastNV = 2 * kMaxTypes + 6;
+
 template <int NW>
 struct Shared {
     Sel sel;                               // copy of the selection
     TypeInfo ty[kMaxTypes];
+    float xbuf[kFastNV * FastRed<NW * 64>::P];
+    float xtot[kFastNV];
     float redf[2 * NW * kRedF];            // block reduction slots (two phases)
     double redd[2 * NW * kRedD];
     float totf[2 * kRedF];
@@ -166,6 +180,50 @@ __device__ __forceinline__ Reducer make_reducer(Shared<NW>& sh) {
     return Reducer{sh.redf, sh.redd, sh.totf, sh.totd};
 }
 
+// Block sum of NV floats, returned to every work-item, with few
+// instructions per wave (the CG loop's reduction): DPP sums over Q lanes,
+// partials to LDS laid out [value][partial], then per value 16 lanes each
+// add E partials and a DPP row sum; totals via LDS.  Two barriers, fixed
+// order (deterministic).  Reusing xbuf / xtot at the next call is safe
+// because every caller passes at least one barrier between a call's last
+// read and the next call's first write.
+template <int NT, int NV>
+__device__ __forceinline__ void fast_sum(float (&v)[NV], float* xbuf, float* xtot) {
+    using G = FastRed<NT>;
+    static_assert(NV <= kFastNV, "fast_sum size");
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        if constexpr (G::Q == 4) v[i] = quad_sum(v[i]);
+        if constexpr (G::Q == 16) v[i] = row_sum(v[i]);
+    }
+    if (tid % G::Q == 0) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) xbuf[i * G::P + tid / G::Q] = v[i];
+    }
+    __syncthreads();
+    for (int i0 = 0; i0 < NV; i0 += NT / 16) {
+        const int i = i0 + tid / 16;
+        float acc = 0.f;
+        if (i < NV) {
+            const float4* src = reinterpret_cast<const float4*>(xbuf + i * G::P + (tid % 16) * G::E);
+#pragma unroll
+            for (int e = 0; e < G::E / 4; ++e) {
+                const float4 q = src[e];
+                acc += q.x;
+                acc += q.y;
+                acc += q.z;
+                acc += q.w;
+            }
+        }
+        acc = row_sum(acc);
+        if (i < NV && tid % 16 == 0) xtot[i] = acc;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[i] = xtot[i];
+}
+
 __device__ __forceinline__ float2 load_vred(const void* v, bool ci4, size_t idx) {
     if (ci4) {
         const int2 q = reinterpret_cast<const int2*>(v)[idx];
@@ -208,6 +266,8 @@ struct Solver {
     const Sel& s;
     const TypeInfo* ty;
     Reducer R;
+    float* xbuf;
+    float* xtot;
     int N, K, n, tid;
     float4* rec;       // [N + K] {p_amp, p_phase, |g|^2 or |V|^2, scratch}
     double2* gd;       // [N] gains
@@ -220,13 +280,19 @@ struct Solver {
     bool live[APT];
     unsigned m1[APT], m2[APT];   // bit t: pair (a, a - d_t) / (a + d_t, a) exists
     float gw[APT];               // own |g|^2 as published in the records
+    // One antenna per work-item and few types: the pair weights and the
+    // neighbours' record indices are kept in registers for a whole CG solve.
+    static constexpr bool PW = APT == 1 && NT <= 512 && KMAX <= 8;
+    float pw1[PW ? KMAX : 1], pw2[PW ? KMAX : 1];
+    int nb1[PW ? KMAX : 1], nb2[PW ? KMAX : 1];
     bool own_t;
-    // CG state of the own rows (index APT: the owned type row)
-    float xa[R1], xp[R1], ra[R1], rp[R1], di[R1], pa[R1], pp[R1];
+    // CG state of the own rows (index APT: the owned type row): solution,
+    // residual, inverse diagonal, preconditioned residual
+    float xa[R1], xp[R1], ra[R1], rp[R1], di[R1], ua[R1], up[R1];
 
-    __device__ Solver(const Sel& sel, const TypeInfo* tyi, Reducer red, unsigned char* lds, const void* vr,
-                      bool c4, size_t vb)
-        : s(sel), ty(tyi), R(red), vred(vr), ci4(c4), vbase(vb) {
+    __device__ Solver(const Sel& sel, const TypeInfo* tyi, Reducer red, float* xb, float* xt,
+                      unsigned char* lds, const void* vr, bool c4, size_t vb)
+        : s(sel), ty(tyi), R(red), xbuf(xb), xtot(xt), vred(vr), ci4(c4), vbase(vb) {
         N = s.N;
         K = s.K;
         n = s.n;
@@ -351,134 +417,191 @@ struct Solver {
         if (own_t) rec[N + tid].z = unit ? 1.f : (float)dabs2(vmd[tid]);
     }
 
-    // q = H p on the own rows of both systems, p read from the records.
-    // The type rows' q are block sums of their pairs' terms (each pair
-    // counted at its first antenna); the same reduction carries p.Hp of the
-    // antenna rows, and every work-item adds the type rows' part of p.Hp
-    // from the totals.
-    __device__ void matvec(float (&qa)[R1], float (&qp)[R1], float& pqa, float& pqp) {
-        float cs[2 * KMAX + 2];
+    // w = H u on the own rows of both systems, u read from the records, and
+    // the dot products of one CG iteration, all in one block reduction:
+    // the type rows' w are sums of their pairs' terms (each pair counted at
+    // its first antenna); dots = {(r,u)_a, (r,u)_p, (u,w)_a, (u,w)_p,
+    // (r,r)_a, (r,r)_p}.  The type rows' part of (u,w), sum_t u_t w_t, is
+    // summed term by term alongside (u_t times each pair term), so nothing
+    // is read from the records after the reduction.
+    // Pair weights |g_i|^2 |g_j|^2 |V_t|^2 and record indices of the own
+    // antenna's pairs (zero weight and index 0 where a pair does not
+    // exist), after the records' weights have been published.
+    __device__ void load_pair_weights() {
+        if constexpr (PW) {
 #pragma unroll
-        for (int i = 0; i < 2 * KMAX + 2; ++i) cs[i] = 0.f;
+            for (int t = 0; t < KMAX; ++t) {
+                pw1[t] = pw2[t] = 0.f;
+                nb1[t] = nb2[t] = 0;
+                if (t >= K) continue;
+                const float vt = rec[N + t].z;
+                const int dt = ty[t].dxy;
+                const bool b1 = live[0] && ((m1[0] >> t) & 1u), b2 = live[0] && ((m2[0] >> t) & 1u);
+                nb1[t] = b1 ? a[0] - dt : 0;
+                nb2[t] = b2 ? a[0] + dt : 0;
+                pw1[t] = b1 ? gw[0] * rec[nb1[t]].z * vt : 0.f;
+                pw2[t] = b2 ? gw[0] * rec[nb2[t]].z * vt : 0.f;
+            }
+        }
+    }
+
+    __device__ void matvec_dots(float (&wa)[R1], float (&wp)[R1], float (&dots)[6]) {
+        constexpr int NV = 2 * KMAX + 6;
+        float cs[NV];
 #pragma unroll
-        for (int k = 0; k < R1; ++k) qa[k] = qp[k] = 0.f;
+        for (int i = 0; i < NV; ++i) cs[i] = 0.f;
+#pragma unroll
+        for (int k = 0; k < R1; ++k) wa[k] = wp[k] = 0.f;
+        // Branch-free: a missing pair reads record 0 with weight 0.
 #pragma unroll
         for (int t = 0; t < KMAX; ++t) {
             if (t >= K) break;
             const float4 rt = rec[N + t];         // .w: d_t
-            const int dt = __float_as_int(rt.w);
 #pragma unroll
             for (int k = 0; k < APT; ++k) {
-                if (!live[k]) continue;
-                if ((m1[k] >> t) & 1u) {          // pair (a, j), j = a - d_t
-                    const float4 rj = rec[a[k] - dt];
-                    const float w = gw[k] * rj.z * rt.z;
-                    const float eA = w * (pa[k] + rj.x + rt.x);
-                    const float eP = w * (pp[k] - rj.y + rt.y);
-                    qa[k] += eA;
-                    qp[k] += eP;
-                    cs[t] += eA;
-                    cs[KMAX + t] += eP;
+                float4 rj, ri;
+                float w1, w2;
+                if constexpr (PW) {
+                    rj = rec[nb1[t]];
+                    ri = rec[nb2[t]];
+                    w1 = pw1[t];
+                    w2 = pw2[t];
+                } else {
+                    const int dt = __float_as_int(rt.w);
+                    const bool b1 = (m1[k] >> t) & 1u, b2 = (m2[k] >> t) & 1u;
+                    rj = rec[b1 ? a[k] - dt : 0];
+                    ri = rec[b2 ? a[k] + dt : 0];
+                    w1 = b1 ? gw[k] * rj.z * rt.z : 0.f;
+                    w2 = b2 ? gw[k] * ri.z * rt.z : 0.f;
                 }
-                if ((m2[k] >> t) & 1u) {          // pair (i, a), i = a + d_t
-                    const float4 ri = rec[a[k] + dt];
-                    const float w = gw[k] * ri.z * rt.z;
-                    qa[k] += w * (ri.x + pa[k] + rt.x);
-                    qp[k] -= w * (ri.y - pp[k] + rt.y);
-                }
+                // pair (a, j), j = a - d_t: a first
+                const float eA = w1 * (ua[k] + rj.x + rt.x);
+                const float eP = w1 * (up[k] - rj.y + rt.y);
+                cs[t] += eA;
+                cs[KMAX + t] += eP;
+                cs[2 * KMAX + 2] += rt.x * eA;
+                cs[2 * KMAX + 3] += rt.y * eP;
+                // pair (i, a), i = a + d_t: a second
+                wa[k] += eA + w2 * (ri.x + ua[k] + rt.x);
+                wp[k] += eP - w2 * (ri.y - up[k] + rt.y);
             }
         }
 #pragma unroll
-        for (int k = 0; k < APT; ++k) {
-            cs[2 * KMAX] += pa[k] * qa[k];
-            cs[2 * KMAX + 1] += pp[k] * qp[k];
+        for (int k = 0; k < R1; ++k) {
+            cs[2 * KMAX + 0] += ra[k] * ua[k];
+            cs[2 * KMAX + 1] += rp[k] * up[k];
+            cs[2 * KMAX + 4] += ra[k] * ra[k];
+            cs[2 * KMAX + 5] += rp[k] * rp[k];
         }
-        block_sum<NW, 2 * KMAX + 2>(cs, R);
-        pqa = cs[2 * KMAX];
-        pqp = cs[2 * KMAX + 1];
+#pragma unroll
+        for (int k = 0; k < APT; ++k) {
+            cs[2 * KMAX + 2] += ua[k] * wa[k];
+            cs[2 * KMAX + 3] += up[k] * wp[k];
+        }
+        fast_sum<NT, NV>(cs, xbuf, xtot);
+#pragma unroll
+        for (int i = 0; i < 6; ++i) dots[i] = cs[2 * KMAX + i];
 #pragma unroll
         for (int t = 0; t < KMAX; ++t) {
             if (t >= K) break;
-            const float4 rt = rec[N + t];       // p is unchanged until write_p
-            pqa += rt.x * cs[t];
-            pqp += rt.y * cs[KMAX + t];
             if (own_t && t == tid) {
-                qa[APT] = cs[t];
-                qp[APT] = cs[KMAX + t];
+                wa[APT] = cs[t];
+                wp[APT] = cs[KMAX + t];
             }
         }
     }
 
-    __device__ void write_p() {
+    __device__ void write_u() {
 #pragma unroll
         for (int k = 0; k < APT; ++k) {
             if (!live[k]) continue;
-            rec[a[k]].x = pa[k];
-            rec[a[k]].y = pp[k];
+            rec[a[k]].x = ua[k];
+            rec[a[k]].y = up[k];
         }
         if (own_t) {
-            rec[N + tid].x = pa[APT];
-            rec[N + tid].y = pp[APT];
+            rec[N + tid].x = ua[APT];
+            rec[N + tid].y = up[APT];
         }
     }
 
-    // Jacobi-preconditioned CG on both systems from x = 0, right-hand sides
-    // in ra / rp, inverse diagonal in di, weights in the records.  Each
-    // system stops when its residual norm has fallen by `tol`.  Returns the
-    // iterations, or -1 if a right-hand side is not finite.
+    // Jacobi-preconditioned conjugate gradients on both systems from x = 0,
+    // right-hand sides in ra / rp, inverse diagonal in di, weights in the
+    // records.  The Chronopoulos-Gear arrangement: the recurrences
+    // p = u + beta p and s = w + beta s (s = H p) need one matrix-vector
+    // product (w = H u, u the preconditioned residual) and one reduction
+    // per iteration.  Each system stops when its residual norm has fallen
+    // by `tol`.  Returns the iterations, or -1 if a right-hand side is not
+    // finite.
     __device__ int pcg(int max_cg, float tol) {
-        float v4[4] = {0.f, 0.f, 0.f, 0.f};
+        float pa[R1], pp[R1], sa[R1], sp[R1], wa[R1], wp[R1], dots[6];
 #pragma unroll
         for (int k = 0; k < R1; ++k) {
             xa[k] = xp[k] = 0.f;
-            pa[k] = ra[k] * di[k];
-            pp[k] = rp[k] * di[k];
-            v4[0] += ra[k] * pa[k];
-            v4[1] += rp[k] * pp[k];
-            v4[2] += ra[k] * ra[k];
-            v4[3] += rp[k] * rp[k];
+            ua[k] = ra[k] * di[k];
+            up[k] = rp[k] * di[k];
         }
-        write_p();
-        block_sum<NW, 4>(v4, R);       // its barrier also publishes p
-        if (!(v4[2] == v4[2]) || !(v4[3] == v4[3]) || isinf(v4[2]) || isinf(v4[3])) return -1;
-        float rza = v4[0], rzp = v4[1];
-        const float stopa = tol * tol * v4[2], stopp = tol * tol * v4[3];
-        bool done_a = !(v4[2] > 0.f), done_p = !(v4[3] > 0.f);
+        write_u();
+        __syncthreads();
+        load_pair_weights();
+        matvec_dots(wa, wp, dots);
+        if (!(dots[4] == dots[4]) || !(dots[5] == dots[5]) || isinf(dots[4]) || isinf(dots[5])) return -1;
+        const float stopa = tol * tol * dots[4], stopp = tol * tol * dots[5];
+        bool done_a = !(dots[4] > 0.f), done_p = !(dots[5] > 0.f);
+        float ga = dots[0], gp = dots[1];
+        float ala = (!done_a && dots[2] > 0.f) ? ga / dots[2] : 0.f;
+        float alp = (!done_p && dots[3] > 0.f) ? gp / dots[3] : 0.f;
+#pragma unroll
+        for (int k = 0; k < R1; ++k) {
+            pa[k] = ua[k];
+            pp[k] = up[k];
+            sa[k] = wa[k];
+            sp[k] = wp[k];
+        }
         int it = 0;
         for (; it < max_cg && !(done_a && done_p); ++it) {
-            float qa[R1], qp[R1], pqa, pqp;
-            matvec(qa, qp, pqa, pqp);
-            const float ala = (!done_a && pqa > 0.f) ? rza / pqa : 0.f;
-            const float alp = (!done_p && pqp > 0.f) ? rzp / pqp : 0.f;
-            float w4[4] = {0.f, 0.f, 0.f, 0.f};
-            float za[R1], zp[R1];
 #pragma unroll
             for (int k = 0; k < R1; ++k) {
                 xa[k] += ala * pa[k];
                 xp[k] += alp * pp[k];
-                ra[k] -= ala * qa[k];
-                rp[k] -= alp * qp[k];
-                za[k] = ra[k] * di[k];
-                zp[k] = rp[k] * di[k];
-                w4[0] += ra[k] * za[k];
-                w4[1] += rp[k] * zp[k];
-                w4[2] += ra[k] * ra[k];
-                w4[3] += rp[k] * rp[k];
+                ra[k] -= ala * sa[k];
+                rp[k] -= alp * sp[k];
+                ua[k] = ra[k] * di[k];
+                up[k] = rp[k] * di[k];
             }
-            block_sum<NW, 4>(w4, R);
-            const float ba = (rza > 0.f) ? w4[0] / rza : 0.f;
-            const float bp = (rzp > 0.f) ? w4[1] / rzp : 0.f;
-            if (!done_a) rza = w4[0];
-            if (!done_p) rzp = w4[1];
-#pragma unroll
-            for (int k = 0; k < R1; ++k) {
-                if (!done_a) pa[k] = za[k] + ba * pa[k];
-                if (!done_p) pp[k] = zp[k] + bp * pp[k];
-            }
-            done_a = done_a || !(w4[2] > stopa);
-            done_p = done_p || !(w4[3] > stopp);
-            write_p();
+            write_u();
             __syncthreads();
+            matvec_dots(wa, wp, dots);
+            done_a = done_a || !(dots[4] > stopa);
+            done_p = done_p || !(dots[5] > stopp);
+            // scalars by hardware reciprocal (about 1 ulp): they only steer CG
+            const float ba = ga > 0.f ? dots[0] * fast_rcp(ga) : 0.f;
+            const float bp = gp > 0.f ? dots[1] * fast_rcp(gp) : 0.f;
+            const float dena = dots[2] - (ala > 0.f ? ba * dots[0] * fast_rcp(ala) : 0.f);
+            const float denp = dots[3] - (alp > 0.f ? bp * dots[1] * fast_rcp(alp) : 0.f);
+            done_a = done_a || !(dena > 0.f);
+            done_p = done_p || !(denp > 0.f);
+            if (!done_a) {
+                ala = dots[0] * fast_rcp(dena);
+                ga = dots[0];
+#pragma unroll
+                for (int k = 0; k < R1; ++k) {
+                    pa[k] = ua[k] + ba * pa[k];
+                    sa[k] = wa[k] + ba * sa[k];
+                }
+            } else {
+                ala = 0.f;
+            }
+            if (!done_p) {
+                alp = dots[1] * fast_rcp(denp);
+                gp = dots[1];
+#pragma unroll
+                for (int k = 0; k < R1; ++k) {
+                    pp[k] = up[k] + bp * pp[k];
+                    sp[k] = wp[k] + bp * sp[k];
+                }
+            } else {
+                alp = 0.f;
+            }
         }
         return it;
     }
@@ -660,7 +783,7 @@ __device__ void solve_unit(const SolveLaunch& L, Shared<NT / 64>& sh, unsigned c
         }
     }
     __syncthreads();
-    Solver<NT, APT, KMAX> S(s, sh.ty, make_reducer(sh), lds, L.vred, L.ci4, (size_t)unit * s.P);
+    Solver<NT, APT, KMAX> S(s, sh.ty, make_reducer(sh), sh.xbuf, sh.xtot, lds, L.vred, L.ci4, (size_t)unit * s.P);
     Reducer& R = S.R;
     const int N = S.N, K = S.K, tid = S.tid;
 

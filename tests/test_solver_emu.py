@@ -40,8 +40,8 @@ def emu():
     return C.CDLL(out)
 
 
-def emu_solve(lib, vred, n, types, init=0, degen=0, gin=None, gref=None, threads=0, max_gn=12, fp64=2,
-              max_cg=400, cg_tol=1e-2, tol32=1e-6, order=0):
+def emu_solve(lib, vred, n, types, init=0, degen=0, gin=None, gref=None, threads=0, max_gn=12, fp64=1,
+              max_cg=400, cg_tol=1e-2, tol32=1e-5, order=0):
     U = vred.shape[0]
     N, K = n * n, len(types)
     txy = (C.c_int * (2 * K))(*[v for t in types for v in t])
