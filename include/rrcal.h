@@ -94,7 +94,8 @@ typedef struct {
     int32_t max_gn;      /* Gauss-Newton steps of the main stage (>= 1)           */
     int32_t fp64_steps;  /* refinement steps after the main stage (>= 0)          */
     int32_t max_cg;      /* CG iterations per normal-equation solve (>= 1)        */
-    float   cg_tol;      /* CG stops at ||r|| <= cg_tol ||b||                     */
+    float   cg_tol;      /* CG stops at ||r|| <= cg_tol ||b|| (refinement steps:  */
+                         /* cg_tol / 10)                                          */
     float   tol32;       /* main stage stops once the rms log-step is below this  */
 } rrc_solver_opts;
 

@@ -33,6 +33,8 @@ struct rrc_plan {
     hipStream_t aux = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     int aux_device = -1;
+    // compute units of the device last launched on
+    int cu_count = 0, cu_device = -1;
 };
 
 namespace {
@@ -414,6 +416,18 @@ int rrc_solve(rrc_plan* p, void* stream, const void* d_vred, const void* d_gains
     L.ci4 = p->dtype == RRC_CI4;
     L.lds = p->solve_lds;
     L.lds_bytes = p->solve_lds_bytes;
+    {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess) return RRC_EDEVICE;
+        if (p->cu_device != dev) {
+            int cus = 0;
+            if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+                return RRC_EDEVICE;
+            p->cu_count = cus;
+            p->cu_device = dev;
+        }
+    }
+    L.exclusive = p->U <= p->cu_count;
     L.slab_bytes = p->slab_bytes;
     L.o = {p->opts.init_mode, p->opts.degen_mode, p->opts.max_gn, p->opts.fp64_steps,
            p->opts.max_cg, p->opts.cg_tol, p->opts.tol32};

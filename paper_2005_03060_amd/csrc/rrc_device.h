@@ -157,11 +157,13 @@ inline T wave_allsum(T v) {
 template <typename T>
 inline T wave_sum_last(T v) { return wave_allsum(v); }
 inline float fast_rcp(float x) { return 1.0f / x; }
-inline float quad_sum(float v) {
+template <typename T>
+inline T quad_sum(T v) {
     for (int o = 1; o <= 2; o <<= 1) v += __shfl_xor(v, o, 64);
     return v;
 }
-inline float row_sum(float v) {
+template <typename T>
+inline T row_sum(T v) {
     for (int o = 1; o <= 8; o <<= 1) v += __shfl_xor(v, o, 64);
     return v;
 }
@@ -217,6 +219,18 @@ __device__ __forceinline__ float row_sum(float v) {
     v += dpp_f<0x4E>(v);
     v += dpp_f<0x124>(v);   // row_ror:4
     v += dpp_f<0x128>(v);   // row_ror:8
+    return v;
+}
+__device__ __forceinline__ double quad_sum(double v) {
+    v += dpp_d<0xB1>(v);
+    v += dpp_d<0x4E>(v);
+    return v;
+}
+__device__ __forceinline__ double row_sum(double v) {
+    v += dpp_d<0xB1>(v);
+    v += dpp_d<0x4E>(v);
+    v += dpp_d<0x124>(v);
+    v += dpp_d<0x128>(v);
     return v;
 }
 

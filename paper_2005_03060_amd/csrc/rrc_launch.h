@@ -43,6 +43,7 @@ struct SolveLaunch {
     int n_units;
     bool ci4;
     bool lds;              // hot arrays in LDS
+    bool exclusive;        // one workgroup per CU (at most as many units as CUs)
     size_t lds_bytes;      // dynamic LDS per workgroup
     size_t slab_bytes;     // per-unit global scratch
     SolveOpts o;

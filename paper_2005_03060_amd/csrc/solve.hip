@@ -51,8 +51,7 @@
 namespace rrc {
 
 constexpr int kChunk = 8;                     // types per FP64 type-sum reduction
-constexpr int kRedF = 2 * kMaxTypes + 8;      // floats per block reduction (max)
-constexpr int kRedD = 3 * kChunk;             // doubles per block reduction (max)
+constexpr size_t kLdsPerCu = 160 * 1024;      // LDS of one gfx950 CU
 
 __host__ __device__ inline size_t align16(size_t v) { return (v + 15) & ~(size_t)15; }
 
@@ -90,134 +89,86 @@ struct TypeInfo {
     int dx, dy, off, cnt;
 };
 
-// Geometry of the transposed reduction used inside CG (fast_sum): values
-// are first summed over Q lanes by DPP, the P = NT / Q partials of each
-// value go to LDS, and 16 lanes per value add them up.
-template <int NT>
-struct FastRed {
-    static constexpr int Q = NT <= 256 ? 1 : (NT <= 512 ? 4 : 16);
-    static constexpr int P = NT / Q;
-    static constexpr int E = P / 16;       // partials per lane in the second stage
-    static_assert(E >= 1 && E % 4 == 0, "second stage reads whole float4s");
-};
-constexpr int kFastNV = 2 * kMaxTypes + 6;
-
-template <int NW>
-struct Shared {
-    Sel sel;                               // copy of the selection
-    TypeInfo ty[kMaxTypes];
-    float xbuf[kFastNV * FastRed<NW * 64>::P];
-    float xtot[kFastNV];
-    float redf[2 * NW * kRedF];            // block reduction slots (two phases)
-    double redd[2 * NW * kRedD];
-    float totf[2 * kRedF];
-    double totd[2 * kRedD];
-    double bcast[8];
-};
-
 // ------------------------------------------------------------ reductions
 //
 // block_sum adds NV values over the workgroup and returns the totals to
-// every work-item, in a fixed order.  Slots alternate between two phases,
-// so a slot is rewritten only two calls later, after a barrier that every
-// reader of its previous use has passed.  With many waves the per-wave
-// partials are first added by NV work-items (one more barrier), so each
-// work-item reads NV values instead of NW * NV.
-struct Reducer {
-    float* sf;
-    double* sd;
-    float* tf;
-    double* td;
-    int pf = 0, pd = 0;
+// every work-item, in a fixed order (deterministic), with few
+// instructions per wave: DPP sums over Q lanes; the P = NT / Q partials of
+// each value go to LDS laid out [value][partial]; per value, 16 lanes add
+// E partials each and a DPP row sum; the totals go back through LDS.  Two
+// barriers.  Consecutive calls may reuse the buffers: a work-item writes
+// the next call's partials only after the previous call's second barrier,
+// which every reader of its partials has passed, and writes totals only
+// after the next call's first barrier, which every reader of the previous
+// totals has passed.  Float and double reductions share the buffers.
+template <int NT, typename T>
+struct RedGeom {
+    static constexpr int Q = sizeof(T) == 4 ? (NT <= 256 ? 1 : (NT <= 512 ? 4 : 16))
+                                            : (NT <= 256 ? 4 : 64);
+    static constexpr int P = NT / Q;
+    static constexpr int E = (P + 15) / 16;   // partials per lane in the second stage
 };
+constexpr int kRedNF = 2 * kMaxTypes + 6;     // floats per reduction (max)
+constexpr int kRedND = 3 * kChunk + 1;        // doubles per reduction (max)
 
-template <int NW, int NV, int STRIDE, typename T>
-__device__ __forceinline__ void block_sum_impl(T (&v)[NV], T* slots, T* tots, int& ph) {
-    T* slot = slots + ph * (NW * STRIDE);
-    T* tot = tots + ph * STRIDE;
-    ph ^= 1;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int i = 0; i < NV; ++i) v[i] = wave_sum_last(v[i]);
-    if (lane == 63) {
-#pragma unroll
-        for (int i = 0; i < NV; ++i) slot[wave * STRIDE + i] = v[i];
-    }
-    __syncthreads();
-    if constexpr (NW * NV <= 64) {
-#pragma unroll
-        for (int i = 0; i < NV; ++i) {
-            T acc = 0;
-#pragma unroll
-            for (int w = 0; w < NW; ++w) acc += slot[w * STRIDE + i];
-            v[i] = acc;
-        }
-    } else {
-        if ((int)threadIdx.x < NV) {
-            T acc = 0;
-#pragma unroll
-            for (int w = 0; w < NW; ++w) acc += slot[w * STRIDE + threadIdx.x];
-            tot[threadIdx.x] = acc;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < NV; ++i) v[i] = tot[i];
-    }
-}
-template <int NW, int NV>
-__device__ __forceinline__ void block_sum(float (&v)[NV], Reducer& R) {
-    static_assert(NV <= kRedF, "float reduction size");
-    block_sum_impl<NW, NV, kRedF, float>(v, R.sf, R.tf, R.pf);
-}
-template <int NW, int NV>
-__device__ __forceinline__ void block_sum(double (&v)[NV], Reducer& R) {
-    static_assert(NV <= kRedD, "double reduction size");
-    block_sum_impl<NW, NV, kRedD, double>(v, R.sd, R.td, R.pd);
+template <int NT>
+constexpr int red_bytes() {
+    constexpr int f = kRedNF * RedGeom<NT, float>::P * 4 + kRedNF * 4;
+    constexpr int d = kRedND * RedGeom<NT, double>::P * 8 + kRedND * 8;
+    return f > d ? f : d;
 }
 
 template <int NW>
-__device__ __forceinline__ Reducer make_reducer(Shared<NW>& sh) {
-    return Reducer{sh.redf, sh.redd, sh.totf, sh.totd};
-}
+struct Shared {
+    Sel sel;                                         // copy of the selection
+    TypeInfo ty[kMaxTypes];
+    __align__(16) unsigned char red[red_bytes<NW * 64>()];   // block_sum partials and totals
+    double bcast[8];
+};
 
-// Block sum of NV floats, returned to every work-item, with few
-// instructions per wave (the CG loop's reduction): DPP sums over Q lanes,
-// partials to LDS laid out [value][partial], then per value 16 lanes each
-// add E partials and a DPP row sum; totals via LDS.  Two barriers, fixed
-// order (deterministic).  Reusing xbuf / xtot at the next call is safe
-// because every caller passes at least one barrier between a call's last
-// read and the next call's first write.
-template <int NT, int NV>
-__device__ __forceinline__ void fast_sum(float (&v)[NV], float* xbuf, float* xtot) {
-    using G = FastRed<NT>;
-    static_assert(NV <= kFastNV, "fast_sum size");
+template <int NT, int NV, typename T>
+__device__ __forceinline__ void block_sum(T (&v)[NV], unsigned char* red) {
+    using G = RedGeom<NT, T>;
+    static_assert(NV <= (sizeof(T) == 4 ? kRedNF : kRedND), "block_sum size");
+    T* xbuf = reinterpret_cast<T*>(red);
+    T* xtot = xbuf + NV * G::P;
     const int tid = threadIdx.x;
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
         if constexpr (G::Q == 4) v[i] = quad_sum(v[i]);
         if constexpr (G::Q == 16) v[i] = row_sum(v[i]);
+        if constexpr (G::Q == 64) v[i] = wave_sum_last(v[i]);
     }
-    if (tid % G::Q == 0) {
+    constexpr int writer = G::Q == 64 ? 63 : 0;     // lane of each Q-group holding its sum
+    if (tid % G::Q == writer) {
 #pragma unroll
         for (int i = 0; i < NV; ++i) xbuf[i * G::P + tid / G::Q] = v[i];
     }
     __syncthreads();
     for (int i0 = 0; i0 < NV; i0 += NT / 16) {
         const int i = i0 + tid / 16;
-        float acc = 0.f;
+        const int j = tid % 16;
+        T acc = 0;
         if (i < NV) {
-            const float4* src = reinterpret_cast<const float4*>(xbuf + i * G::P + (tid % 16) * G::E);
+            const T* src = xbuf + i * G::P + j * G::E;
+            if constexpr (sizeof(T) == 4 && G::E % 4 == 0) {
+                const float4* s4 = reinterpret_cast<const float4*>(src);
 #pragma unroll
-            for (int e = 0; e < G::E / 4; ++e) {
-                const float4 q = src[e];
-                acc += q.x;
-                acc += q.y;
-                acc += q.z;
-                acc += q.w;
+                for (int e = 0; e < G::E / 4; ++e) {
+                    const float4 q = s4[e];
+                    acc += q.x;
+                    acc += q.y;
+                    acc += q.z;
+                    acc += q.w;
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < G::E; ++e)
+                    if (j * G::E + e < G::P) acc += src[e];
             }
         }
         acc = row_sum(acc);
-        if (i < NV && tid % 16 == 0) xtot[i] = acc;
+        if (i < NV && j == 0) xtot[i] = acc;
     }
     __syncthreads();
 #pragma unroll
@@ -265,9 +216,7 @@ struct Solver {
     static constexpr int R1 = APT + 1;     // own rows: APT antennas + one type row
     const Sel& s;
     const TypeInfo* ty;
-    Reducer R;
-    float* xbuf;
-    float* xtot;
+    unsigned char* red;          // block_sum buffers
     int N, K, n, tid;
     float4* rec;       // [N + K] {p_amp, p_phase, |g|^2 or |V|^2, scratch}
     double2* gd;       // [N] gains
@@ -290,9 +239,9 @@ struct Solver {
     // residual, inverse diagonal, preconditioned residual
     float xa[R1], xp[R1], ra[R1], rp[R1], di[R1], ua[R1], up[R1];
 
-    __device__ Solver(const Sel& sel, const TypeInfo* tyi, Reducer red, float* xb, float* xt,
-                      unsigned char* lds, const void* vr, bool c4, size_t vb)
-        : s(sel), ty(tyi), R(red), xbuf(xb), xtot(xt), vred(vr), ci4(c4), vbase(vb) {
+    __device__ Solver(const Sel& sel, const TypeInfo* tyi, unsigned char* rd, unsigned char* lds,
+                      const void* vr, bool c4, size_t vb)
+        : s(sel), ty(tyi), red(rd), vred(vr), ci4(c4), vbase(vb) {
         N = s.N;
         K = s.K;
         n = s.n;
@@ -344,10 +293,11 @@ struct Solver {
             rA[k] = rP[k] = 0.0;
             dd[k] = 0.f;
         }
+        double nrm = 0.0;
 #pragma unroll
         for (int c0 = 0; c0 < KMAX; c0 += kChunk) {
             if (c0 >= K) break;
-            double tq[3 * kChunk];
+            double tq[3 * kChunk + 1];
 #pragma unroll
             for (int i = 0; i < 3 * kChunk; ++i) tq[i] = 0.0;
 #pragma unroll
@@ -378,22 +328,27 @@ struct Solver {
                     }
                 }
             }
-            block_sum<NW, 3 * kChunk>(tq, R);
+            // the antenna rows' |rhs|^2 rides on the last chunk's reduction,
+            // when their right-hand sides are complete
+            tq[3 * kChunk] = 0.0;
+            if (c0 + kChunk >= K) {
+#pragma unroll
+                for (int k = 0; k < APT; ++k)
+                    if (live[k]) tq[3 * kChunk] += rA[k] * rA[k] + rP[k] * rP[k];
+            }
+            block_sum<NT, 3 * kChunk + 1>(tq, red);
 #pragma unroll
             for (int tt = 0; tt < kChunk; ++tt) {
+                if (c0 + tt < K) nrm += tq[tt] * tq[tt] + tq[kChunk + tt] * tq[kChunk + tt];
                 if (own_t && tid == c0 + tt) {
                     rA[APT] = tq[tt];
                     rP[APT] = tq[kChunk + tt];
                     dd[APT] = (float)tq[2 * kChunk + tt];
                 }
             }
+            if (c0 + kChunk >= K) nrm += tq[3 * kChunk];
         }
-        double nrm[1] = {0.0};
-#pragma unroll
-        for (int k = 0; k < R1; ++k)
-            if (mine(k)) nrm[0] += rA[k] * rA[k] + rP[k] * rP[k];
-        block_sum<NW, 1>(nrm, R);
-        const double scale = nrm[0] > 0.0 ? sqrt(nrm[0]) : 1.0;
+        const double scale = nrm > 0.0 ? sqrt(nrm) : 1.0;
         const double inv = 1.0 / scale;
 #pragma unroll
         for (int k = 0; k < R1; ++k) {
@@ -452,11 +407,13 @@ struct Solver {
         for (int i = 0; i < NV; ++i) cs[i] = 0.f;
 #pragma unroll
         for (int k = 0; k < R1; ++k) wa[k] = wp[k] = 0.f;
-        // Branch-free: a missing pair reads record 0 with weight 0.
+        // Branch-free: a missing pair reads record 0 with weight 0; with
+        // register weights the types past K also run, on the last type's
+        // record with weight 0, so the loop is straight-line code.
 #pragma unroll
         for (int t = 0; t < KMAX; ++t) {
-            if (t >= K) break;
-            const float4 rt = rec[N + t];         // .w: d_t
+            if (!PW && t >= K) break;
+            const float4 rt = rec[N + (PW && t >= K ? K - 1 : t)];   // .w: d_t
 #pragma unroll
             for (int k = 0; k < APT; ++k) {
                 float4 rj, ri;
@@ -498,7 +455,7 @@ struct Solver {
             cs[2 * KMAX + 2] += ua[k] * wa[k];
             cs[2 * KMAX + 3] += up[k] * wp[k];
         }
-        fast_sum<NT, NV>(cs, xbuf, xtot);
+        block_sum<NT, NV>(cs, red);
 #pragma unroll
         for (int i = 0; i < 6; ++i) dots[i] = cs[2 * KMAX + i];
 #pragma unroll
@@ -625,7 +582,7 @@ struct Solver {
                 sv[KMAX + t] += q.y * inv;
             }
         }
-        block_sum<NW, 2 * KMAX>(sv, R);
+        block_sum<NT, 2 * KMAX>(sv, red);
 #pragma unroll
         for (int t = 0; t < KMAX; ++t) {
             if (t >= K || !own_t || t != tid) continue;
@@ -665,7 +622,7 @@ struct Solver {
                 }
             }
         }
-        block_sum<NW, 2 * KMAX>(tq, R);
+        block_sum<NT, 2 * KMAX>(tq, red);
 #pragma unroll
         for (int t = 0; t < KMAX; ++t) {
             if (t >= K || !own_t || t != tid) continue;
@@ -755,7 +712,7 @@ struct Solver {
             if (k < APT) gd[a[k]] = dmul(gd[a[k]], f);
             else vmd[tid] = dmul(vmd[tid], f);
         }
-        block_sum<NW, 1>(e2, R);
+        block_sum<NT, 1>(e2, red);
         return sqrtf(e2[0] / (float)(N + K));
     }
 };
@@ -783,8 +740,7 @@ __device__ void solve_unit(const SolveLaunch& L, Shared<NT / 64>& sh, unsigned c
         }
     }
     __syncthreads();
-    Solver<NT, APT, KMAX> S(s, sh.ty, make_reducer(sh), sh.xbuf, sh.xtot, lds, L.vred, L.ci4, (size_t)unit * s.P);
-    Reducer& R = S.R;
+    Solver<NT, APT, KMAX> S(s, sh.ty, sh.red, lds, L.vred, L.ci4, (size_t)unit * s.P);
     const int N = S.N, K = S.K, tid = S.tid;
 
     // ---- start: caller's gains, or the logcal solve (the first CG solve
@@ -812,7 +768,9 @@ __device__ void solve_unit(const SolveLaunch& L, Shared<NT / 64>& sh, unsigned c
             xscale = S.residuals();
             S.publish_weights(false);
         }
-        const int it = S.pcg(op.max_cg, start ? 1e-3f : op.cg_tol);
+        // the refinement steps fix the final accuracy: their CG solves go a
+        // decade further
+        const int it = S.pcg(op.max_cg, start ? 1e-3f : (hi ? 0.1f * op.cg_tol : op.cg_tol));
         if (start) {
             S.firstcal_finish();
             S.group_mean();
@@ -862,7 +820,7 @@ __device__ void solve_unit(const SolveLaunch& L, Shared<NT / 64>& sh, unsigned c
             v9[7] += x * y;
             v9[8] += y * y;
         }
-        block_sum<NW, 9>(v9, R);
+        block_sum<NT, 9>(v9, sh.red);
         if (tid == 0) {
             // [N  Sx  Sy ; Sx Sxx Sxy ; Sy Sxy Syy] c = [S, Sx, Sy] by Cramer's rule
             const double a00 = N, a01 = v9[4], a02 = v9[5], a11 = v9[6], a12 = v9[7], a22 = v9[8];
@@ -886,7 +844,7 @@ __device__ void solve_unit(const SolveLaunch& L, Shared<NT / 64>& sh, unsigned c
 #pragma unroll
         for (int k = 0; k < APT; ++k)
             if (S.live[k]) v1[0] += 0.5 * log(dabs2(S.gd[S.a[k]]));
-        block_sum<NW, 1>(v1, R);
+        block_sum<NT, 1>(v1, sh.red);
         if (tid == 0) {
             const double2 g0 = S.gd[0], g1 = S.gd[1], gn = S.gd[s.n];
             const double2 qx = dmulc(g1, g0), qy = dmulc(gn, g0);
@@ -932,7 +890,7 @@ __device__ void solve_unit(const SolveLaunch& L, Shared<NT / 64>& sh, unsigned c
             c1[0] += dabs2(dsub(load_vred_d(L.vred, L.ci4, S.vbase + b), mm));
         }
     }
-    block_sum<NW, 1>(c1, R);
+    block_sum<NT, 1>(c1, sh.red);
 #pragma unroll
     for (int k = 0; k < APT; ++k)
         if (S.live[k]) L.gains_out[(size_t)unit * N + S.a[k]] = to_f(S.gd[S.a[k]]);
@@ -956,15 +914,24 @@ __global__ __launch_bounds__(NT) void k_solve(SolveLaunch L) {
 template <int NT, int APT, int KMAX>
 static hipError_t launch_solve_k(const SolveLaunch& L, hipStream_t st) {
     auto kern = k_solve<NT, APT, KMAX>;
+    size_t lds = L.lds_bytes;
+    if (L.exclusive) {
+        // a unit per CU at most: claim the CU's whole LDS, so that kernels
+        // running beside the solve (the pipelined FFT) take other CUs
+        // instead of sharing this latency-bound workgroup's SIMDs
+        const size_t whole = kLdsPerCu - sizeof(Shared<NT / 64>);
+        if (whole > lds) lds = whole;
+    }
     if (hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)L.lds_bytes) != hipSuccess)
+                            (int)lds) != hipSuccess)
         return hipErrorInvalidValue;
-    hipLaunchKernelGGL(kern, dim3(L.n_units), dim3(NT), L.lds_bytes, st, L);
+    hipLaunchKernelGGL(kern, dim3(L.n_units), dim3(NT), lds, st, L);
     return hipGetLastError();
 }
 
 template <int NT, int APT>
 static hipError_t launch_solve_shape(const SolveLaunch& L, hipStream_t st) {
+    if (L.sel.K <= 6) return launch_solve_k<NT, APT, 6>(L, st);
     if (L.sel.K <= 8) return launch_solve_k<NT, APT, 8>(L, st);
     return launch_solve_k<NT, APT, kMaxTypes>(L, st);
 }
@@ -991,15 +958,15 @@ constexpr int kCThreads = 256;
 
 template <int APT, bool ADJ>
 __global__ __launch_bounds__(kCThreads) void k_chisq(ChisqLaunch L) {
-    __shared__ Shared<kCThreads / 64> sh;
-    copy_sel(L.sel, sh.sel);
-    const Sel& s = sh.sel;
+    __shared__ Sel ssel;
+    __shared__ __align__(16) unsigned char sred[(RedGeom<kCThreads, double>::P + 1) * 8];
+    copy_sel(L.sel, ssel);
+    const Sel& s = ssel;
     const int unit = blockIdx.x;
     const int N = s.N, K = s.K, n = s.n;
     const float2* g = L.g + (size_t)unit * N;
     const float2* vm = L.vm + (size_t)unit * K;
     const float2* vr = L.vred + (size_t)unit * s.P;
-    Reducer R = make_reducer(sh);
     if constexpr (!ADJ) {
         double c1[1] = {0.0};
         for (int t = 0; t < K; ++t) {
@@ -1014,7 +981,7 @@ __global__ __launch_bounds__(kCThreads) void k_chisq(ChisqLaunch L) {
                 c1[0] += (double)cabs2(r);
             }
         }
-        block_sum<kCThreads / 64, 1>(c1, R);
+        block_sum<kCThreads, 1>(c1, sred);
         if (threadIdx.x == 0) L.chisq[unit] = (float)c1[0];
     } else {
         // antenna rows

@@ -15,6 +15,7 @@ static bool run_unit(const SolveLaunch& L, unsigned char* ldsbuf, int unit) {
 
 template <int NT, int APT>
 static bool run_shape(const SolveLaunch& L, unsigned char* ldsbuf, int unit) {
+    if (L.sel.K <= 6) return run_unit<NT, APT, 6>(L, ldsbuf, unit);
     if (L.sel.K <= 8) return run_unit<NT, APT, 8>(L, ldsbuf, unit);
     return run_unit<NT, APT, kMaxTypes>(L, ldsbuf, unit);
 }
@@ -43,6 +44,7 @@ extern "C" int rrc_emu_solve(int n, const int* types_xy, int K, int U, int ci4, 
     L.n_units = U;
     L.ci4 = ci4 != 0;
     L.lds = true;
+    L.exclusive = false;
     L.lds_bytes = solve_lds_bytes(s, true);
     L.slab_bytes = 0;
     L.o = {iopts[0], iopts[1], iopts[2], iopts[3], iopts[4], fopts[0], fopts[1]};

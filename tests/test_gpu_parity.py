@@ -6,8 +6,8 @@ import torch
 from oracle import correlator as OC
 from oracle import geometry as OG
 from oracle import redcal as OR
-from tests.gpu_util import (TOL_GAINS, TOL_VUNIQUE, TOL_XENG, make_ci4_units, make_units,
-                            oracle_solve, oracle_vunique, pairs_of, rel_l2)
+from tests.gpu_util import (TOL_GAINS, TOL_VUNIQUE, TOL_XENG, linearized_ls_reference, make_ci4_units,
+                            make_units, oracle_solve, oracle_vunique, pairs_of, rel_l2)
 
 pytestmark = pytest.mark.gpu
 
@@ -101,6 +101,54 @@ def test_solve_matches_oracle(rrc, n, U, T, snr):
         assert gerr <= TOL_GAINS
         assert verr <= 1e-5
         assert cerr <= 1e-5
+
+
+@pytest.mark.parametrize("n", [24, 48, 64])
+def test_solve_large_grid_recovers_noise_free_gains(rrc, n):
+    # V_b = g_i conj(g_j) V_alpha (eq. redcal without noise), rounded to
+    # complex64: the solve must return the least-squares answer for the
+    # rounded data (first-order reference from the injected truth) up to the
+    # four degeneracies, at the sizes of the uneven-batch and 4-bit
+    # workloads (2 and 4 antennas per work-item, up to 16 types, the whole
+    # unit state in LDS).
+    U = 2
+    types, _ = rrc.select_subset(n)
+    pos = OG.square_positions(n)
+    pairs, tix = pairs_of(n, types)
+    rng = np.random.default_rng(1000 + n)
+    vred = np.empty((U, len(pairs)), np.complex64)
+    truth = []
+    for u in range(U):
+        g = (1 + 0.05 * rng.standard_normal(n * n)) * np.exp(1j * rng.uniform(-np.pi, np.pi, n * n))
+        vm = (0.2 + rng.random(len(types))) * np.exp(1j * rng.uniform(-np.pi, np.pi, len(types)))
+        vred[u] = OR.model_vis(g, vm, pairs, tix).astype(np.complex64)
+        gl, vl = linearized_ls_reference(vred[u], g, vm, pairs, tix, len(types))
+        truth.append(OR.fix_refant(gl, vl, pos, types))
+    plan = rrc.Plan(n, types, U, 64)
+    out = plan.solve(torch.from_numpy(vred).to(DEV))
+    for u in range(U):
+        g = out["gains"][u].cpu().numpy().astype(np.complex128)
+        gerr = np.max(np.abs(g - truth[u][0]) / np.abs(truth[u][0]))
+        print(f"n={n} unit {u}: gains {gerr:.2e} niter {int(out['niter'][u])} status {int(out['status'][u])}")
+        assert int(out["status"][u]) == 0
+        assert gerr <= TOL_GAINS
+
+
+def test_solve_n24_matches_oracle(rrc):
+    # a grid between the power-of-two sizes (ragged last wave, 7 types)
+    n, U, T = 24, 2, 512
+    v, _ = make_units(n, U, T)
+    plan, types = _plan(rrc, n, U, T)
+    vr_d = plan.xengine(torch.from_numpy(v).to(DEV))
+    out = plan.solve(vr_d)
+    vr = vr_d.cpu().numpy()
+    for u in range(U):
+        ref = oracle_solve(vr[u].astype(np.complex128), n, types)
+        g = out["gains"][u].cpu().numpy().astype(np.complex128)
+        gerr = np.max(np.abs(g - ref["g"]) / np.abs(ref["g"]))
+        print(f"n={n} unit {u}: gains {gerr:.2e} niter {int(out['niter'][u])}")
+        assert int(out["status"][u]) == 0
+        assert gerr <= TOL_GAINS
 
 
 def test_solve_ci4_matches_oracle(rrc):
