@@ -139,7 +139,10 @@ int rrc_degeneracy_count(int32_t n, const int32_t* types_xy, int32_t k,
 /* Create a plan for U units of an n x n grid with T samples each.  The
  * selection must satisfy the degeneracy criterion (else RRC_EDEGEN) and,
  * for RRC_INIT_FIRSTCAL, contain the types (1,0) and (0,1).  opts may be
- * NULL (defaults).  n in [2, RRC_MAX_GRID], K in [1, RRC_MAX_TYPES]. */
+ * NULL (defaults).  n in [2, RRC_MAX_GRID], K in [1, RRC_MAX_TYPES].
+ * RRC_ENOTIMPL if a selected type reaches more than 248 antennas back in
+ * raster order (dy n + dx > 248), or for RRC_CI4 when n*n is not a
+ * multiple of 4 (the X-engine stages whole 32-bit words of 4-bit samples). */
 int rrc_plan_create(rrc_plan** out, int32_t n, const int32_t* types_xy, int32_t k,
                     int32_t n_units, int32_t n_time, int32_t dtype,
                     const rrc_solver_opts* opts);

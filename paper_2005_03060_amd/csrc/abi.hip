@@ -23,7 +23,7 @@ struct rrc_plan {
     // FFT-correlator
     int fft_tchunk, fft_nchunk;
     // X-engine
-    int x_tchunk, x_nchunk, x_ppt, x_npblk, x_xs;
+    int x_tchunk, x_nchunk, x_nablk, x_S, x_halo;
     // solver
     bool solve_lds;
     size_t solve_lds_bytes, slab_bytes;
@@ -287,16 +287,29 @@ int rrc_plan_create(rrc_plan** out, int32_t n, const int32_t* types_xy, int32_t 
     p->fft_tchunk = tch;
     p->fft_nchunk = ceil_div(n_time, tch);
 
-    // X-engine
-    p->x_ppt = s.P <= 1024 ? 4 : (s.P <= 2048 ? 8 : 16);
-    p->x_npblk = ceil_div(s.P, 256 * p->x_ppt);
-    const int bytes_per = dtype == RRC_CI4 ? 1 : 8;
-    p->x_xs = std::max(1, 32768 / (s.N * bytes_per));
-    const long wg = (long)n_units * p->x_npblk;
-    int xn = std::max(1, std::min(ceil_div(2048, wg), n_time / (4 * p->x_xs)));
-    int xt = ceil_div(ceil_div(n_time, xn), p->x_xs) * p->x_xs;
-    p->x_tchunk = xt;
-    p->x_nchunk = ceil_div(n_time, xt);
+    // X-engine: blocks of 256 antennas, S samples staged per step, time
+    // chunks (whole steps) so that the launch has >= 2048 workgroups while
+    // each still runs >= 4 steps
+    {
+        int halo = 0;
+        for (int t = 0; t < s.K; ++t) halo = std::max(halo, s.dy[t] * s.n + s.dx[t]);
+        const int apb = rrc::xengine_antennas_per_block();
+        // staging limits of the X-engine: partners within 248 antennas in
+        // raster order, and whole 32-bit words of 4-bit samples
+        if (halo > rrc::xengine_max_halo() || (dtype == RRC_CI4 && (s.N & 3))) {
+            delete p;
+            return RRC_ENOTIMPL;
+        }
+        p->x_halo = halo;
+        p->x_nablk = ceil_div(s.N, apb);
+        p->x_S = rrc::xengine_samples_per_step(dtype == RRC_CI4);
+        const long wg = (long)n_units * p->x_nablk;
+        const long want = wg >= 2048 ? 1 : ceil_div(2048, (int)wg);
+        const int xn = (int)std::max(1L, std::min(want, (long)(n_time / (4 * p->x_S))));
+        const int xt = ceil_div(ceil_div(n_time, xn), p->x_S) * p->x_S;
+        p->x_tchunk = xt;
+        p->x_nchunk = ceil_div(n_time, xt);
+    }
 
     // solver
     const size_t hot = rrc::solve_hot_bytes(s);
@@ -308,7 +321,7 @@ int rrc_plan_create(rrc_plan** out, int32_t n, const int32_t* types_xy, int32_t 
     p->off_fft = off;
     off = align256(off + (size_t)n_units * p->fft_nchunk * M * M * sizeof(float));
     p->off_x = off;
-    off = align256(off + (size_t)n_units * p->x_nchunk * s.P * 8);
+    off = align256(off + (p->x_nchunk > 1 ? (size_t)n_units * p->x_nchunk * s.P * 8 : 0));
     p->off_slab = off;
     off = align256(off + (size_t)n_units * p->slab_bytes);
     p->ws_bytes = off;
@@ -393,9 +406,9 @@ int rrc_xengine(rrc_plan* p, void* stream, const void* d_volt, void* d_vred, voi
     L.n_units = p->U;
     L.tchunk = p->x_tchunk;
     L.nchunk = p->x_nchunk;
-    L.ppt = p->x_ppt;
-    L.npblk = p->x_npblk;
-    L.xs = p->x_xs;
+    L.nablk = p->x_nablk;
+    L.halo = p->x_halo;
+    L.inv_t = 1.0f / (float)p->T;
     L.ci4 = p->dtype == RRC_CI4;
     L.volt = d_volt;
     L.vpart = static_cast<char*>(d_work) + p->off_x;

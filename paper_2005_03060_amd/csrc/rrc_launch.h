@@ -24,12 +24,12 @@ struct XengLaunch {
     Sel sel;
     int T, n_units;
     int tchunk, nchunk;    // time chunks per unit
-    int ppt;               // pairs per thread (template selector)
-    int npblk;             // pair blocks per unit
-    int xs;                // samples staged in LDS per step
+    int nablk;             // blocks of 256 antennas per unit
+    int halo;              // largest raster offset d_t of the selection
+    float inv_t;           // 1/T (float outputs)
     bool ci4;
     const void* volt;
-    void* vpart;           // workspace: [U][nchunk][P] float2 or int2
+    void* vpart;           // workspace: [U][nchunk][P] float2 or int2 (nchunk > 1)
     void* vred;            // output: [U][P] float2 (scaled by 1/T) or int2
 };
 
@@ -75,6 +75,10 @@ struct ChisqLaunch {
 int fft_samples_per_step_for(int M);
 hipError_t launch_fftcorr(const FftLaunch& L, hipStream_t st);
 hipError_t launch_xengine(const XengLaunch& L, hipStream_t st);
+size_t xengine_lds_bytes(int halo, bool ci4);
+int xengine_antennas_per_block();
+int xengine_max_halo();
+int xengine_samples_per_step(bool ci4);
 size_t solve_hot_bytes(const Sel& s);
 size_t solve_slab_bytes(const Sel& s, bool lds);
 size_t solve_lds_bytes(const Sel& s, bool lds);

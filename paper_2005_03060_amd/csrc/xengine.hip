@@ -5,130 +5,191 @@
 // int32: |Re q_i conj(q_j)| <= 2*7*7 = 98 per sample, so 98 * T fits in
 // int32 for any T below 2^31 / 98.
 //
-// A workgroup owns one unit, one chunk of samples and one block of
-// NT * PPT pairs.  Each step stages XS samples of the unit's voltages in LDS
-// with coalesced loads; every thread then updates its PPT pair accumulators
-// from LDS.  Partial sums per time chunk go to the workspace and a second
-// kernel adds them in a fixed order.
+// Antenna-centric: every selected pair (i, j) has r_i - r_j = d_t with d_t
+// in the canonical half-plane, so in raster order j = i - (dy n + dx) < i.
+// Work-item a owns antenna a and the (at most K) pairs with a first; it
+// reads v_a once per sample and its K partners, all from LDS, so a sample
+// costs K + 1 LDS reads for K pairs (a pair-centric layout costs 2K).  A
+// workgroup owns one unit, one block of 256 consecutive antennas and one
+// chunk of samples; each step stages S samples of the antennas
+// [a0 - halo, a0 + 256) (halo = the largest d_t) with coalesced loads.
+// Pairs that do not exist are computed against the antenna itself and
+// never written, so the inner loop has no branches.  Partial sums per time
+// chunk go to the workspace and a second kernel adds them in a fixed
+// order; with a single chunk the first kernel writes V^reduced itself.
 #include "rrc_device.h"
 #include "rrc_launch.h"
+
+#include <type_traits>
 
 namespace rrc {
 
 constexpr int kXThreads = 256;
-constexpr int kXLdsBytes = 32768;
+constexpr int kXHaloMax = 248;   // largest raster offset d_t the staging covers
 
-__device__ __forceinline__ int2 unpack_ci4(uint8_t b) {
-    const int v = b;
-    return make_int2((v << 24) >> 28, (v << 28) >> 28);
+__device__ __forceinline__ int2 unpack_ci4(int b) {
+    return make_int2((b << 24) >> 28, (b << 28) >> 28);   // sign-extended nibbles
 }
 
-template <int PPT, bool CI4>
-__global__ __launch_bounds__(kXThreads) void k_xeng(const void* __restrict__ volt, Sel sel, int T,
-                                                    int tchunk, int nchunk, int xs,
-                                                    void* __restrict__ vpart) {
-    constexpr int NT = kXThreads;
-    extern __shared__ __align__(16) unsigned char xsm[];
-    const int tid = threadIdx.x;
-    const int chunk = blockIdx.x;
-    const int pblk = blockIdx.y;
-    const int unit = blockIdx.z;
-    const int N = sel.N, P = sel.P;
-    const int tb = chunk * tchunk;
-    const int te = min(T, tb + tchunk);
+// Samples staged per step: 16 complex64 rows or 64 rows of 4-bit bytes.
+template <bool CI4>
+constexpr int xeng_samples() { return CI4 ? 64 : 16; }
 
-    int ii[PPT], jj[PPT];
+// Two complex64 values as one 16-byte load (a native vector type, so arrays
+// of it stay in registers).
+typedef float c64x2 __attribute__((ext_vector_type(4)));
+
+// Antennas per staged load: 4-bit rows move as 32-bit words (4 antennas),
+// float rows as 16-byte pairs of antennas when N is even, else singly.
+template <bool CI4, bool WIDE>
+struct XStage {
+    static constexpr int W = CI4 ? 4 : (WIDE ? 2 : 1);
+    using RT = typename std::conditional<CI4, uint32_t,
+                                         typename std::conditional<WIDE, c64x2, float2>::type>::type;
+    static constexpr int KPT = W == 1 ? 2 : 1;   // loads per work-item and row
+};
+
+template <bool CI4, bool WIDE, int KMAX>
+__global__ __launch_bounds__(kXThreads, 2) void k_xant(XengLaunch L) {
+    constexpr int NT = kXThreads;
+    constexpr int S = xeng_samples<CI4>();
+    using G = XStage<CI4, WIDE>;
+    using RT = typename G::RT;
+    constexpr int W = G::W, KPT = G::KPT;
+    extern __shared__ __align__(16) unsigned char xsm[];
+
+    const int tid = threadIdx.x;
+    const int ablk = blockIdx.x;
+    const int chunk = blockIdx.y;
+    const int unit = blockIdx.z;
+    const Sel& s = L.sel;
+    const int n = s.n, N = s.N, K = s.K, T = L.T;
+    const int a0 = ablk * NT;
+    // staged antennas [lo, hi), widened to whole load units (N is a multiple
+    // of W on every path)
+    const int lo = max(0, a0 - L.halo) / W * W;
+    const int hi = (min(N, a0 + NT) + W - 1) / W * W;
+    const int cnt = hi - lo;                 // antennas staged per sample
+    const int upr = cnt / W;                 // load units per row
+    const int a = a0 + tid;
+    const bool live = a < N;
+    const int ax = a % n, ay = a / n;
+
+    // LDS index of each partner (the antenna itself where the pair does not
+    // exist) and the pair's index in V^reduced (-1 if it does not exist)
+    int poff[KMAX], pidx[KMAX];
 #pragma unroll
-    for (int k = 0; k < PPT; ++k) {
-        const int p = (pblk * PPT + k) * NT + tid;
-        ii[k] = -1;
-        jj[k] = 0;
-        if (p < P) {
-            const int t = type_of(sel, p);
-            pair_ij(sel, t, p - sel.off[t], ii[k], jj[k]);
+    for (int t = 0; t < KMAX; ++t) {
+        poff[t] = live ? a - lo : 0;
+        pidx[t] = -1;
+        if (t >= K || !live) continue;
+        const int dx = s.dx[t], dy = s.dy[t];
+        const int jx = ax - dx, jy = ay - dy;
+        if (jx >= 0 && jx < n && jy >= 0) {
+            const int w = n - (dx < 0 ? -dx : dx);
+            poff[t] = a - (dy * n + dx) - lo;
+            pidx[t] = s.off[t] + jy * w + (ax - (dx > 0 ? dx : 0));
         }
     }
+    const int own = live ? a - lo : 0;
 
-    if constexpr (CI4) {
-        int2 acc[PPT];
+    using AT = typename std::conditional<CI4, int, float>::type;
+    AT accr[KMAX], acci[KMAX];
 #pragma unroll
-        for (int k = 0; k < PPT; ++k) acc[k] = make_int2(0, 0);
-        uint8_t* vs = reinterpret_cast<uint8_t*>(xsm);
-        const uint8_t* src = reinterpret_cast<const uint8_t*>(volt) + (size_t)unit * T * N;
-        for (int t0 = tb; t0 < te; t0 += xs) {
-            const int ns = min(xs, te - t0);
-            // stage ns samples (contiguous bytes), 4 bytes per thread-load
-            const int nbytes = ns * N;
-            const uint8_t* s8 = src + (size_t)t0 * N;
-            if ((reinterpret_cast<uintptr_t>(s8) & 3) == 0) {
-                const uint32_t* s32 = reinterpret_cast<const uint32_t*>(s8);
-                uint32_t* d32 = reinterpret_cast<uint32_t*>(vs);
-                for (int q = tid; q < nbytes / 4; q += NT) d32[q] = s32[q];
-                for (int q = (nbytes / 4) * 4 + tid; q < nbytes; q += NT) vs[q] = s8[q];
+    for (int t = 0; t < KMAX; ++t) accr[t] = acci[t] = 0;
+
+    const int tb = chunk * L.tchunk;
+    const int te = min(T, tb + L.tchunk);
+
+    // Staging: every work-item loads its share of the next S rows into
+    // registers (all loads in flight together), then writes them to LDS.
+    // Indices are clamped instead of predicated (a row past the chunk's end
+    // repeats the last one, a unit past the row's end repeats the last unit;
+    // neither is read), so the copy has no branches.
+    const RT* vol = reinterpret_cast<const RT*>(L.volt);
+    const size_t rowstride = (size_t)N / W;
+    RT r[S][KPT];
+    auto load = [&](int t0) {
+        const int last = min(S, te - t0) - 1;
+        const RT* base = vol + (((size_t)unit * T + t0) * N + lo) / W;
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+#pragma unroll
+            for (int u = 0; u < KPT; ++u)
+                r[q][u] = base[(size_t)min(q, last) * rowstride + min(tid + u * NT, upr - 1)];
+        }
+    };
+    auto store = [&]() {
+        RT* st = reinterpret_cast<RT*>(xsm);
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+#pragma unroll
+            for (int u = 0; u < KPT; ++u) st[q * upr + min(tid + u * NT, upr - 1)] = r[q][u];
+        }
+    };
+
+    if (tb < te) load(tb);
+    for (int t0 = tb; t0 < te; t0 += S) {
+        const int ns = min(S, te - t0);
+        store();
+        __syncthreads();
+        if (t0 + S < te) load(t0 + S);       // in flight during the products
+        // KMAX is the selection's K (or above it, the extra pairs being the
+        // antenna with itself, never written): no branch per type
+#pragma unroll 2
+        for (int q = 0; q < ns; ++q) {
+            if constexpr (CI4) {
+                const uint8_t* srow = reinterpret_cast<const uint8_t*>(xsm) + q * cnt;
+                const int2 va = unpack_ci4(srow[own]);
+#pragma unroll
+                for (int t = 0; t < KMAX; ++t) {
+                    const int2 vb = unpack_ci4(srow[poff[t]]);
+                    accr[t] += va.x * vb.x + va.y * vb.y;
+                    acci[t] += va.y * vb.x - va.x * vb.y;
+                }
             } else {
-                for (int q = tid; q < nbytes; q += NT) vs[q] = s8[q];
-            }
-            __syncthreads();
-            for (int s = 0; s < ns; ++s) {
-                const uint8_t* row = vs + s * N;
+                const float2* srow = reinterpret_cast<const float2*>(xsm) + q * cnt;
+                const float2 va = srow[own];
 #pragma unroll
-                for (int k = 0; k < PPT; ++k) {
-                    if (ii[k] >= 0) {
-                        const int2 a = unpack_ci4(row[ii[k]]);
-                        const int2 b = unpack_ci4(row[jj[k]]);
-                        acc[k].x += a.x * b.x + a.y * b.y;
-                        acc[k].y += a.y * b.x - a.x * b.y;
-                    }
+                for (int t = 0; t < KMAX; ++t) {
+                    const float2 vb = srow[poff[t]];
+                    accr[t] += va.x * vb.x + va.y * vb.y;
+                    acci[t] += va.y * vb.x - va.x * vb.y;
                 }
             }
-            __syncthreads();
         }
-        int2* out = reinterpret_cast<int2*>(vpart) + ((size_t)unit * nchunk + chunk) * P;
+        __syncthreads();
+    }
+
+    if (L.nchunk == 1) {
 #pragma unroll
-        for (int k = 0; k < PPT; ++k) {
-            const int p = (pblk * PPT + k) * NT + tid;
-            if (p < P) out[p] = acc[k];
+        for (int t = 0; t < KMAX; ++t) {
+            if (t >= K || pidx[t] < 0) continue;
+            const size_t o = (size_t)unit * s.P + pidx[t];
+            if constexpr (CI4) reinterpret_cast<int2*>(L.vred)[o] = make_int2(accr[t], acci[t]);
+            else reinterpret_cast<float2*>(L.vred)[o] = make_float2(accr[t] * L.inv_t, acci[t] * L.inv_t);
         }
     } else {
-        float2 acc[PPT];
+        const size_t base = ((size_t)unit * L.nchunk + chunk) * s.P;
 #pragma unroll
-        for (int k = 0; k < PPT; ++k) acc[k] = make_float2(0.0f, 0.0f);
-        float2* vs = reinterpret_cast<float2*>(xsm);
-        const float2* src = reinterpret_cast<const float2*>(volt) + (size_t)unit * T * N;
-        for (int t0 = tb; t0 < te; t0 += xs) {
-            const int ns = min(xs, te - t0);
-            const int nel = ns * N;
-            // N is even for every supported grid except odd n; fall back to 8-byte loads then
-            if ((N & 1) == 0) {
-                const float4* s4 = reinterpret_cast<const float4*>(src + (size_t)t0 * N);
-                float4* d4 = reinterpret_cast<float4*>(vs);
-                for (int q = tid; q < nel / 2; q += NT) d4[q] = s4[q];
-            } else {
-                for (int q = tid; q < nel; q += NT) vs[q] = src[(size_t)t0 * N + q];
-            }
-            __syncthreads();
-            for (int s = 0; s < ns; ++s) {
-                const float2* row = vs + s * N;
-#pragma unroll
-                for (int k = 0; k < PPT; ++k) {
-                    if (ii[k] >= 0) {
-                        const float2 a = row[ii[k]];
-                        const float2 b = row[jj[k]];
-                        acc[k].x += a.x * b.x + a.y * b.y;
-                        acc[k].y += a.y * b.x - a.x * b.y;
-                    }
-                }
-            }
-            __syncthreads();
-        }
-        float2* out = reinterpret_cast<float2*>(vpart) + ((size_t)unit * nchunk + chunk) * P;
-#pragma unroll
-        for (int k = 0; k < PPT; ++k) {
-            const int p = (pblk * PPT + k) * NT + tid;
-            if (p < P) out[p] = acc[k];
+        for (int t = 0; t < KMAX; ++t) {
+            if (t >= K || pidx[t] < 0) continue;
+            if constexpr (CI4) reinterpret_cast<int2*>(L.vpart)[base + pidx[t]] = make_int2(accr[t], acci[t]);
+            else reinterpret_cast<float2*>(L.vpart)[base + pidx[t]] = make_float2(accr[t], acci[t]);
         }
     }
 }
+
+// LDS of one workgroup: S staged rows of (256 + halo) antennas, 4-bit rows
+// widened by up to 6 bytes to whole words.
+size_t xengine_lds_bytes(int halo, bool ci4) {
+    return ci4 ? (size_t)xeng_samples<true>() * (kXThreads + halo + 6)
+               : (size_t)xeng_samples<false>() * (kXThreads + halo + 2) * 8;
+}
+
+int xengine_antennas_per_block() { return kXThreads; }
+int xengine_max_halo() { return kXHaloMax; }
+int xengine_samples_per_step(bool ci4) { return ci4 ? xeng_samples<true>() : xeng_samples<false>(); }
 
 // Sum the time-chunk partials in chunk order; float results are scaled by 1/T.
 template <bool CI4>
@@ -154,27 +215,38 @@ __global__ __launch_bounds__(256) void k_xfin(const void* __restrict__ vpart, in
     }
 }
 
-template <int PPT, bool CI4>
+template <bool CI4, bool WIDE, int KMAX>
 static hipError_t launch_x(const XengLaunch& L, hipStream_t st) {
-    const size_t lds = (size_t)L.xs * L.sel.N * (CI4 ? 1 : 8);
-    dim3 grid(L.nchunk, L.npblk, L.n_units);
-    hipLaunchKernelGGL((k_xeng<PPT, CI4>), grid, dim3(kXThreads), lds, st, L.volt, L.sel, L.T,
-                       L.tchunk, L.nchunk, L.xs, L.vpart);
+    const size_t lds = xengine_lds_bytes(L.halo, CI4);
+    dim3 grid(L.nablk, L.nchunk, L.n_units);
+    hipLaunchKernelGGL((k_xant<CI4, WIDE, KMAX>), grid, dim3(kXThreads), lds, st, L);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if (e != hipSuccess || L.nchunk == 1) return e;
     const size_t tot = (size_t)L.n_units * L.sel.P;
     hipLaunchKernelGGL((k_xfin<CI4>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, L.vpart,
-                       L.nchunk, L.sel.P, L.n_units, 1.0f / (float)L.T, L.vred);
+                       L.nchunk, L.sel.P, L.n_units, L.inv_t, L.vred);
     return hipGetLastError();
 }
 
-hipError_t launch_xengine(const XengLaunch& L, hipStream_t st) {
-    switch (L.ppt) {
-        case 4: return L.ci4 ? launch_x<4, true>(L, st) : launch_x<4, false>(L, st);
-        case 8: return L.ci4 ? launch_x<8, true>(L, st) : launch_x<8, false>(L, st);
-        case 16: return L.ci4 ? launch_x<16, true>(L, st) : launch_x<16, false>(L, st);
-        default: return hipErrorInvalidValue;
+template <bool CI4, bool WIDE>
+static hipError_t launch_x_k(const XengLaunch& L, hipStream_t st) {
+    switch (L.sel.K) {
+        case 1: case 2: case 3: case 4: case 5: case 6: return launch_x<CI4, WIDE, 6>(L, st);
+        case 7: return launch_x<CI4, WIDE, 7>(L, st);
+        case 8: return launch_x<CI4, WIDE, 8>(L, st);
+        case 9: return launch_x<CI4, WIDE, 9>(L, st);
+        case 10: case 11: case 12: return launch_x<CI4, WIDE, 12>(L, st);
+        default: return launch_x<CI4, WIDE, kMaxTypes>(L, st);
     }
+}
+
+hipError_t launch_xengine(const XengLaunch& L, hipStream_t st) {
+    if (L.sel.K < 1 || L.sel.K > kMaxTypes) return hipErrorInvalidValue;
+    // staging covers at most 510 antennas per row, in whole words for 4-bit
+    if (L.halo > kXHaloMax || (L.ci4 && (L.sel.N & 3))) return hipErrorInvalidValue;
+    if (L.tchunk % xengine_samples_per_step(L.ci4)) return hipErrorInvalidValue;
+    if (L.ci4) return launch_x_k<true, false>(L, st);
+    return (L.sel.N & 1) ? launch_x_k<false, false>(L, st) : launch_x_k<false, true>(L, st);
 }
 
 }  // namespace rrc
