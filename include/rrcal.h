@@ -202,10 +202,11 @@ int rrc_chisq_adj(rrc_plan* plan, void* stream, const void* d_g, const void* d_v
  * mode RRC_RUN_PIPELINED: the FFT-correlator applies d_gains_in (the
  *   previous integration's solution, Fig. 1 real-time loop) while the
  *   X-engine and the solve run on the same voltages; the solved gains are
- *   for the next integration.  The FFT-correlator is forked onto a stream
- *   the plan owns (created on first use on the current device, default
- *   priority) and joined back into `stream` with events, so all outputs
- *   are ordered on `stream` as usual.
+ *   for the next integration.  After the X-engine the FFT-correlator is
+ *   forked onto a stream the plan owns (created on first use on the current
+ *   device, default priority), runs beside the solve, and is joined back
+ *   into `stream` with events, so all outputs are ordered on `stream` as
+ *   usual.
  * mode RRC_RUN_SELFCAL: X-engine, solve, then the FFT-correlator applies the
  *   just-solved gains (reads the voltages twice).
  * Outputs as in the calls above; d_gains_in may be NULL in SELFCAL mode. */

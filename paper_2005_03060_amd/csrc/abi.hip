@@ -495,10 +495,12 @@ int rrc_run(rrc_plan* p, void* stream, int32_t mode, const rrc_io* io) {
         !io->d_vmodel || !io->d_chisq || !io->d_niter || !io->d_status || !io->d_work)
         return RRC_EINVAL;
     hipStream_t st = as_stream(stream);
-    int rc;
+    int rc = rrc_xengine(p, stream, io->d_volt, io->d_vred, io->d_work);
+    if (rc != RRC_OK) return rc;
     if (mode == RRC_RUN_PIPELINED) {
-        // The FFT-correlator needs only the previous gains: it runs on the
-        // auxiliary stream while the X-engine and the solve run on `stream`.
+        // The FFT-correlator needs only the previous gains: once the X-engine
+        // (the head of the critical path) is done it runs on the auxiliary
+        // stream, beside the latency-bound solve on `stream`.
         if (!ensure_aux(p)) return RRC_EDEVICE;
         if (hipEventRecord(p->ev_fork, st) != hipSuccess) return RRC_EDEVICE;
         if (hipStreamWaitEvent(p->aux, p->ev_fork, 0) != hipSuccess) return RRC_EDEVICE;
@@ -507,8 +509,6 @@ int rrc_run(rrc_plan* p, void* stream, int32_t mode, const rrc_io* io) {
         if (rc != RRC_OK) return rc;
         if (hipEventRecord(p->ev_join, p->aux) != hipSuccess) return RRC_EDEVICE;
     }
-    rc = rrc_xengine(p, stream, io->d_volt, io->d_vred, io->d_work);
-    if (rc != RRC_OK) return rc;
     rc = rrc_solve(p, stream, io->d_vred, io->d_gains_in, io->d_gains_ref, io->d_gains_out,
                    io->d_vmodel, io->d_chisq, io->d_niter, io->d_status, io->d_work);
     if (rc != RRC_OK) return rc;
