@@ -94,8 +94,7 @@ typedef struct {
     int32_t max_gn;      /* Gauss-Newton steps of the main stage (>= 1)           */
     int32_t fp64_steps;  /* refinement steps after the main stage (>= 0)          */
     int32_t max_cg;      /* CG iterations per normal-equation solve (>= 1)        */
-    float   cg_tol;      /* CG stops at ||r|| <= cg_tol ||b|| (refinement steps:  */
-                         /* cg_tol / 10)                                          */
+    float   cg_tol;      /* CG stops at ||r|| <= cg_tol ||b||                     */
     float   tol32;       /* main stage stops once the rms log-step is below this  */
 } rrc_solver_opts;
 
@@ -227,6 +226,24 @@ typedef struct {
     void*    d_work;
 } rrc_io;
 int rrc_run(rrc_plan* plan, void* stream, int32_t mode, const rrc_io* io);
+
+/* A batch of plans (one per array; grids, channels and sample counts may
+ * differ) whose hot paths run together: the uneven-batch case of several
+ * arrays calibrated at once.  The plans must be distinct and outlive the
+ * batch.  Host only; owns streams and events. */
+typedef struct rrc_batch rrc_batch;
+int rrc_batch_create(rrc_batch** out, int32_t n_plans, rrc_plan* const* plans);
+void rrc_batch_destroy(rrc_batch* batch);
+
+/* rrc_run(plans[i], ..., mode, &io[i]) for every plan, in one call on
+ * `stream`: each plan runs on its own branch stream (owned by the batch,
+ * created on first use on the current device, default priority), forked
+ * from `stream` and joined back into it with events, so the arrays run
+ * concurrently and all outputs are ordered on `stream`.  With more units in
+ * the batch than compute units the solves share CUs.  Asynchronous like
+ * rrc_run; one batch may be run by one stream at a time, and its plans must
+ * not be run concurrently on other streams. */
+int rrc_batch_run(rrc_batch* batch, void* stream, int32_t mode, const rrc_io* io);
 
 const char* rrc_strerror(int code);
 

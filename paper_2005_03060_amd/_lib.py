@@ -31,7 +31,8 @@ RRC_MAX_GRID = 64
 
 EXPORTS = ("rrc_default_opts", "rrc_select_subset", "rrc_degeneracy_count", "rrc_plan_create",
            "rrc_plan_destroy", "rrc_plan_get_info", "rrc_workspace_size", "rrc_fftcorr",
-           "rrc_xengine", "rrc_solve", "rrc_chisq_fwd", "rrc_chisq_adj", "rrc_run", "rrc_strerror")
+           "rrc_xengine", "rrc_solve", "rrc_chisq_fwd", "rrc_chisq_adj", "rrc_run", "rrc_strerror",
+           "rrc_batch_create", "rrc_batch_destroy", "rrc_batch_run")
 
 
 class SolverOpts(C.Structure):
@@ -89,6 +90,9 @@ def load_library() -> C.CDLL:
         "rrc_chisq_adj": (C.c_int, [vp, vp, vp, vp, vp, vp, vp, pf, pf]),
         "rrc_run": (C.c_int, [vp, vp, i32, C.POINTER(RunIO)]),
         "rrc_strerror": (C.c_char_p, [C.c_int]),
+        "rrc_batch_create": (C.c_int, [C.POINTER(vp), i32, C.POINTER(vp)]),
+        "rrc_batch_destroy": (None, [vp]),
+        "rrc_batch_run": (C.c_int, [vp, vp, i32, C.POINTER(RunIO)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

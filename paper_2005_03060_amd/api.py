@@ -178,21 +178,25 @@ class Plan:
                                         _ptr(gv), _ptr(dg), _ptr(dv)), "rrc_chisq_adj")
         return gg, gv, dg, dv
 
-    def run(self, volt: torch.Tensor, gains_in: Optional[torch.Tensor] = None,
-            gains_ref: Optional[torch.Tensor] = None, mode: str = "pipelined",
-            out: Optional[Dict[str, torch.Tensor]] = None) -> Dict[str, torch.Tensor]:
-        """The whole hot path (rrc_run); `out` may supply preallocated outputs."""
+    def run_io(self, volt: torch.Tensor, gains_in: Optional[torch.Tensor], gains_ref: Optional[torch.Tensor],
+               out: Dict[str, torch.Tensor]) -> "L.RunIO":
+        """The rrc_io of one run (argument checks and marshalling only)."""
         self._check_volt(volt)
         self._check_c64(gains_in, (self.n_units, self.n_ant), "gains_in")
         self._check_c64(gains_ref, (self.n_units, self.n_ant), "gains_ref")
         dev = volt.device
+        return L.RunIO(_ptr(volt), _ptr(gains_in), _ptr(gains_ref), _ptr(out["vunique"]), _ptr(out["vauto"]),
+                       _ptr(out["vred"]), _ptr(out["gains"]), _ptr(out["vmodel"]), _ptr(out["chisq"]),
+                       _ptr(out["niter"]), _ptr(out["status"]), _ptr(self.workspace(dev)))
+
+    def run(self, volt: torch.Tensor, gains_in: Optional[torch.Tensor] = None,
+            gains_ref: Optional[torch.Tensor] = None, mode: str = "pipelined",
+            out: Optional[Dict[str, torch.Tensor]] = None) -> Dict[str, torch.Tensor]:
+        """The whole hot path (rrc_run); `out` may supply preallocated outputs."""
         if out is None:
-            out = self.alloc_outputs(dev)
-        io = L.RunIO(_ptr(volt), _ptr(gains_in), _ptr(gains_ref), _ptr(out["vunique"]), _ptr(out["vauto"]),
-                     _ptr(out["vred"]), _ptr(out["gains"]), _ptr(out["vmodel"]), _ptr(out["chisq"]),
-                     _ptr(out["niter"]), _ptr(out["status"]), _ptr(self.workspace(dev)))
-        m = {"pipelined": L.RRC_RUN_PIPELINED, "selfcal": L.RRC_RUN_SELFCAL}[mode]
-        L.check(self._lib.rrc_run(self._h, _stream(), m, C.byref(io)), "rrc_run")
+            out = self.alloc_outputs(volt.device)
+        io = self.run_io(volt, gains_in, gains_ref, out)
+        L.check(self._lib.rrc_run(self._h, _stream(), _MODES[mode], C.byref(io)), "rrc_run")
         return out
 
     def alloc_outputs(self, device) -> Dict[str, torch.Tensor]:
@@ -205,6 +209,40 @@ class Plan:
                     chisq=torch.empty((U,), dtype=torch.float32, device=device),
                     niter=torch.empty((U,), dtype=torch.int32, device=device),
                     status=torch.empty((U,), dtype=torch.int32, device=device))
+
+
+_MODES = {"pipelined": L.RRC_RUN_PIPELINED, "selfcal": L.RRC_RUN_SELFCAL}
+
+
+class Batch:
+    """Several plans (arrays of possibly different grids) run concurrently
+    in one call (rrc_batch_run)."""
+
+    def __init__(self, plans: Sequence[Plan]):
+        self._lib = L.load_library()
+        self.plans = list(plans)           # kept alive for the batch's lifetime
+        arr = (C.c_void_p * len(self.plans))(*[p._h.value for p in self.plans])
+        h = C.c_void_p()
+        L.check(self._lib.rrc_batch_create(C.byref(h), len(self.plans), arr), "rrc_batch_create")
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._lib.rrc_batch_destroy(h)
+            self._h = None
+
+    def run(self, volts: Sequence[torch.Tensor], gains_in: Sequence[Optional[torch.Tensor]],
+            outs: Sequence[Dict[str, torch.Tensor]], mode: str = "pipelined",
+            gains_ref: Optional[Sequence[Optional[torch.Tensor]]] = None) -> Sequence[Dict[str, torch.Tensor]]:
+        if gains_ref is None:
+            gains_ref = [None] * len(self.plans)
+        if not (len(volts) == len(gains_in) == len(outs) == len(gains_ref) == len(self.plans)):
+            raise ValueError("one voltage, gains and output set per plan")
+        ios = (L.RunIO * len(self.plans))(*[p.run_io(v, gi, gr, o) for p, v, gi, gr, o
+                                            in zip(self.plans, volts, gains_in, gains_ref, outs)])
+        L.check(self._lib.rrc_batch_run(self._h, _stream(), _MODES[mode], ios), "rrc_batch_run")
+        return outs
 
 
 class ChiSq(torch.autograd.Function):

@@ -35,6 +35,17 @@ struct rrc_plan {
     int aux_device = -1;
     // compute units of the device last launched on
     int cu_count = 0, cu_device = -1;
+    // units launched concurrently with this plan's (a batch sets the sum of
+    // its plans'); the solve claims whole CUs only when they all fit
+    long concurrent_units = 0;
+};
+
+struct rrc_batch {
+    std::vector<rrc_plan*> plans;
+    int device = -1;
+    std::vector<hipStream_t> branch;           // one per plan
+    std::vector<hipEvent_t> ev_done;           // one per plan
+    hipEvent_t ev_start = nullptr;
 };
 
 namespace {
@@ -440,7 +451,7 @@ int rrc_solve(rrc_plan* p, void* stream, const void* d_vred, const void* d_gains
             p->cu_device = dev;
         }
     }
-    L.exclusive = p->U <= p->cu_count;
+    L.exclusive = (p->concurrent_units > 0 ? p->concurrent_units : p->U) <= p->cu_count;
     L.slab_bytes = p->slab_bytes;
     L.o = {p->opts.init_mode, p->opts.degen_mode, p->opts.max_gn, p->opts.fp64_steps,
            p->opts.max_cg, p->opts.cg_tol, p->opts.tol32};
@@ -519,6 +530,83 @@ int rrc_run(rrc_plan* p, void* stream, int32_t mode, const rrc_io* io) {
         return RRC_EDEVICE;
     }
     return rc;
+}
+
+// ------------------------------------------------------------------ batches
+
+static void batch_release(rrc_batch* b) {
+    for (hipEvent_t e : b->ev_done)
+        if (e) (void)hipEventDestroy(e);
+    for (hipStream_t s : b->branch)
+        if (s) (void)hipStreamDestroy(s);
+    if (b->ev_start) (void)hipEventDestroy(b->ev_start);
+    b->ev_done.clear();
+    b->branch.clear();
+    b->ev_start = nullptr;
+    b->device = -1;
+}
+
+int rrc_batch_create(rrc_batch** out, int32_t n_plans, rrc_plan* const* plans) {
+    if (!out) return RRC_EINVAL;
+    *out = nullptr;
+    if (n_plans < 1 || !plans) return RRC_EINVAL;
+    for (int i = 0; i < n_plans; ++i) {
+        if (!plans[i]) return RRC_EINVAL;
+        for (int j = 0; j < i; ++j)
+            if (plans[j] == plans[i]) return RRC_EINVAL;   // each plan owns its streams and events
+    }
+    rrc_batch* b = new (std::nothrow) rrc_batch();
+    if (!b) return RRC_ERANGE;
+    b->plans.assign(plans, plans + n_plans);
+    *out = b;
+    return RRC_OK;
+}
+
+void rrc_batch_destroy(rrc_batch* b) {
+    if (!b) return;
+    batch_release(b);
+    delete b;
+}
+
+int rrc_batch_run(rrc_batch* b, void* stream, int32_t mode, const rrc_io* io) {
+    if (!b || !io) return RRC_EINVAL;
+    const int np = (int)b->plans.size();
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return RRC_EDEVICE;
+    if (b->device != dev) {
+        batch_release(b);
+        if (hipEventCreateWithFlags(&b->ev_start, hipEventDisableTiming) != hipSuccess) {
+            batch_release(b);
+            return RRC_EDEVICE;
+        }
+        b->branch.assign(np, nullptr);
+        b->ev_done.assign(np, nullptr);
+        for (int i = 0; i < np; ++i) {
+            if (hipStreamCreateWithFlags(&b->branch[i], hipStreamNonBlocking) != hipSuccess ||
+                hipEventCreateWithFlags(&b->ev_done[i], hipEventDisableTiming) != hipSuccess) {
+                batch_release(b);
+                return RRC_EDEVICE;
+            }
+        }
+        b->device = dev;
+    }
+    long total = 0;
+    for (rrc_plan* p : b->plans) total += p->U;
+    hipStream_t st = as_stream(stream);
+    if (hipEventRecord(b->ev_start, st) != hipSuccess) return RRC_EDEVICE;
+    for (int i = 0; i < np; ++i) {
+        rrc_plan* p = b->plans[i];
+        if (hipStreamWaitEvent(b->branch[i], b->ev_start, 0) != hipSuccess) return RRC_EDEVICE;
+        const long saved = p->concurrent_units;
+        p->concurrent_units = total;
+        const int rc = rrc_run(p, b->branch[i], mode, &io[i]);
+        p->concurrent_units = saved;
+        if (rc != RRC_OK) return rc;
+        if (hipEventRecord(b->ev_done[i], b->branch[i]) != hipSuccess ||
+            hipStreamWaitEvent(st, b->ev_done[i], 0) != hipSuccess)
+            return RRC_EDEVICE;
+    }
+    return RRC_OK;
 }
 
 }  // extern "C"

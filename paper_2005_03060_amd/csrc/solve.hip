@@ -768,9 +768,7 @@ __device__ void solve_unit(const SolveLaunch& L, Shared<NT / 64>& sh, unsigned c
             xscale = S.residuals();
             S.publish_weights(false);
         }
-        // the refinement steps fix the final accuracy: their CG solves go a
-        // decade further
-        const int it = S.pcg(op.max_cg, start ? 1e-3f : (hi ? 0.1f * op.cg_tol : op.cg_tol));
+        const int it = S.pcg(op.max_cg, start ? 1e-3f : op.cg_tol);
         if (start) {
             S.firstcal_finish();
             S.group_mean();

@@ -271,3 +271,54 @@ def test_repeat_is_bitwise_deterministic(rrc):
     b = plan.run(vd, mode="selfcal", out=plan.alloc_outputs(DEV))
     for k in ("vunique", "vred", "gains", "vmodel", "chisq"):
         assert torch.equal(a[k], b[k]), k
+
+
+# ------------------------------------------------------------ uneven batches
+
+def _batch_inputs(rrc):
+    shapes = [(8, 3, 256), (12, 2, 300), (16, 4, 512), (5, 2, 97)]
+    plans, volts, gins = [], [], []
+    for k, (n, U, T) in enumerate(shapes):
+        v, g = make_units(n, U, T, wid=200 + k)
+        p, _ = _plan(rrc, n, U, T)
+        plans.append(p)
+        volts.append(torch.from_numpy(v).to(DEV))
+        gins.append(torch.from_numpy(g.astype(np.complex64)).to(DEV))
+    return plans, volts, gins
+
+
+def test_batch_matches_eager_runs(rrc):
+    # arrays of different grids (and chunkings) run concurrently on branch
+    # streams; every repeat, with eager work and synchronisation in between,
+    # must equal the plans run one by one (all kernels are deterministic)
+    plans, volts, gins = _batch_inputs(rrc)
+    for mode in ("pipelined", "selfcal"):
+        ref = [p.run(v, gains_in=gi, mode=mode) for p, v, gi in zip(plans, volts, gins)]
+        torch.cuda.synchronize()
+        batch = rrc.Batch(plans)
+        outs = [p.alloc_outputs(DEV) for p in plans]
+        for rep in range(3):
+            for o in outs:
+                for t in o.values():
+                    t.fill_(7)                      # eager work between repeats
+            batch.run(volts, gins, outs, mode=mode)
+            torch.cuda.synchronize()
+            for k, (o, r) in enumerate(zip(outs, ref)):
+                for key in ("vunique", "vauto", "vred", "gains", "vmodel", "chisq", "status"):
+                    assert torch.equal(o[key], r[key]), (mode, rep, k, key)
+        del batch
+
+
+@pytest.mark.skip(reason="capturing the batch into a HIP graph ended the test process with a host "
+                         "segmentation fault inside rrc_batch_run; no cause was found in this code, so "
+                         "the graph path was removed and the batch launches its branches eagerly")
+def test_batch_graph_matches_eager_runs(rrc):
+    plans, volts, gins = _batch_inputs(rrc)
+    batch = rrc.Batch(plans)
+    outs = [p.alloc_outputs(DEV) for p in plans]
+    ref = [p.run(v, gains_in=gi, mode="pipelined") for p, v, gi in zip(plans, volts, gins)]
+    for rep in range(3):
+        batch.run(volts, gins, outs, mode="pipelined")
+        torch.cuda.synchronize()
+        for o, r in zip(outs, ref):
+            assert torch.equal(o["gains"], r["gains"])
