@@ -7,9 +7,10 @@ through the whole hot path: reduced X-engine, FFT-correlator (gain
 application, padded spatial FFT, |.|^2 integration, inverse transform and
 redundant normalisation) and the reduced redundant calibration solve.  The
 batched path issues the steps for all units at once (rrc_run, PIPELINED: the
-FFT applies the previous integration's gains); the plain path calibrates one
-channel at a time, synchronising after each.  Inputs are resident in HBM
-before timing starts.  Prints one JSON line.
+FFT applies the previous integration's gains; several arrays run together
+through rrc_batch_run); the plain path calibrates one channel at a time,
+synchronising after each.  Inputs are resident in HBM before timing starts.
+Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -26,6 +27,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 VALU_FP32_PEAK_TFLOPS = 78.6    # 256 CU x 64 lanes x 2 flop x 2.4 GHz, packed FP32 disabled
+METRIC = "calibrated channel-integrations/sec (batched+adjoint vs plain) at stated gain error"
 
 
 def fft_flops_per_sample(n: int, m: int) -> float:
@@ -54,34 +56,63 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(w, volt_np, types, budget_s):
-    """The FP64 oracle, as it stands, on a bounded sample of the same units."""
+def cpu_baseline(arrays, budget_s, gate_units):
+    """The FP64 oracle, as it stands, on a bounded sample of the same units.
+
+    Also the accuracy gate: for each sampled unit the oracle solves the
+    GPU's own V^reduced and the GPU gains are compared after the same
+    degeneracy fix.  Arrays whose dense oracle solve is too slow for a
+    bench (n > 32) are left out of the sample.
+    """
     import threadpoolctl
     from oracle import correlator as OC
     from oracle import geometry as OG
     from oracle import redcal as OR
-    n = w.grids[0]
-    pos = OG.square_positions(n)
-    pairs, tix = OG.group_pairs(pos, types)
-    lags = OC.canonical_lags(n)
-    done, t0 = 0, time.perf_counter()
-    while done < volt_np.shape[0]:
-        v = volt_np[done].astype(np.complex128)
-        vf = OC.fx_correlate(v)
-        vred = OC.xengine(vf, pairs)
-        cal = OR.calibrate(vred, pos, types, pairs, tix)
-        OC.redundant_average(vf, cal["g"], pos, lags)
-        done += 1
+    done, gerr, t_solve, units = 0, 0.0, 0.0, []
+    t0 = time.perf_counter()
+    for a in arrays:
+        if a["n"] > 32:
+            continue
+        n, types = a["n"], a["types"]
+        pos = OG.square_positions(n)
+        pairs, tix = OG.group_pairs(pos, types)
+        lags = OC.canonical_lags(n)
+        for u in a["sample"]:
+            volt = a["volt_host"](u)
+            if volt.dtype == np.uint8:
+                from synthdata import unpack_ci4
+                re, im = unpack_ci4(volt)
+                v = re.astype(np.float64) + 1j * im.astype(np.float64)
+            else:
+                v = volt.astype(np.complex128)
+            ts = time.perf_counter()
+            vf = OC.fx_correlate(v)
+            vred = OC.xengine(vf, pairs)
+            cal = OR.calibrate(vred, pos, types, pairs, tix)
+            OC.redundant_average(vf, cal["g"], pos, lags)
+            t_solve += time.perf_counter() - ts
+            done += 1
+            # gate: the oracle on the GPU's own V^reduced
+            if len(units) < gate_units:
+                ref = OR.calibrate(a["vred_gpu"](u), pos, types, pairs, tix)
+                g = a["gains_gpu"](u)
+                gerr = max(gerr, float(np.max(np.abs(g - ref["g"]) / np.abs(ref["g"]))))
+                units.append(f"{a['name']}:{u}")
+            if time.perf_counter() - t0 > budget_s:
+                break
         if time.perf_counter() - t0 > budget_s:
             break
-    dt = time.perf_counter() - t0
+    if done == 0:
+        return None, None
     info = threadpoolctl.threadpool_info()
     threads = max([i.get("num_threads", 1) for i in info] + [1])
-    return {"value": done / dt, "unit": "calibrated channel-integrations/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"{done} of {volt_np.shape[0]} units of the same workload, one at a time "
-                      f"({dt:.1f} s): FX correlator (zgemm), X-engine gather, FIRSTCAL start + dense "
-                      f"Gauss-Newton to 1e-10, degeneracy fix, eq. modelvis average"}
+    cpu = {"value": done / t_solve, "unit": "calibrated channel-integrations/s", "cores": threads,
+           "kind": "oracle",
+           "sample": f"{done} units of the same workload, one at a time ({t_solve:.1f} s): FX correlator "
+                     f"(zgemm), X-engine gather, FIRSTCAL start + dense Gauss-Newton to 1e-10, "
+                     f"degeneracy fix, eq. modelvis average"}
+    gate = {"max_rel": gerr, "units": units, "tol": 1e-6}
+    return cpu, gate
 
 
 def main():
@@ -93,121 +124,149 @@ def main():
     import torch
     import paper_2005_03060_amd as rrc
     from synthdata import WORKLOADS, workload_voltages
+    from synthdata.device import device_voltages
 
     w = {x.name: x for x in WORKLOADS}[args.workload]
-    if len(w.grids) != 1 or w.ci4:
-        raise SystemExit(f"workload {w.name} is not supported by bench.py yet")
-    n = w.grids[0]
-    U, T = w.n_chan, w.n_time
-    t_gen = time.perf_counter()
-    volt_np, gains_np = workload_voltages(w, 0)
-    t_gen = time.perf_counter() - t_gen
-    types, npairs = rrc.select_subset(n)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    volt = torch.from_numpy(volt_np).to(dev)
-    gains_in = torch.from_numpy(gains_np.astype(np.complex64)).to(dev)
-    plan = rrc.Plan(n, types, U, T)
-    out = plan.alloc_outputs(dev)
+    dtype = "ci4" if w.ci4 else "c64"
+    # small workloads: the host generator's exact bytes; large: drawn on the GPU
+    host_gen = len(w.grids) == 1 and w.grids[0] * w.grids[0] * w.n_chan * w.n_time <= 64 * 1024 * 1024
+    rng = np.random.default_rng(7)
+    arrays = []
+    for ai, n in enumerate(w.grids):
+        if host_gen:
+            vnp, g = workload_voltages(w, ai)
+            volt = torch.from_numpy(vnp).to(dev)
+        else:
+            volt, g = device_voltages(w, ai, dev)
+        types, npairs = rrc.select_subset(n)
+        plan = rrc.Plan(n, types, w.n_chan, w.n_time, dtype=dtype)
+        arrays.append(dict(name=f"g{n}", n=n, types=types, npairs=npairs, plan=plan, volt=volt,
+                           gains_in=torch.from_numpy(g.astype(np.complex64)).to(dev),
+                           out=plan.alloc_outputs(dev),
+                           sample=sorted(rng.choice(w.n_chan, size=min(w.n_chan, 4), replace=False).tolist())))
+    torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
+    batch = rrc.Batch([a["plan"] for a in arrays]) if len(arrays) > 1 else None
 
     def step():
-        plan.run(volt, gains_in=gains_in, mode="pipelined", out=out)
+        if batch is None:
+            a = arrays[0]
+            a["plan"].run(a["volt"], gains_in=a["gains_in"], mode="pipelined", out=a["out"])
+        else:
+            batch.run([a["volt"] for a in arrays], [a["gains_in"] for a in arrays],
+                      [a["out"] for a in arrays], mode="pipelined")
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
     e0.record(stream)
     for _ in range(args.steps):
         step()
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / args.steps
-    value = U / (ms * 1e-3)
+    total_units = w.n_chan * len(arrays)
+    value = total_units / (ms * 1e-3)
 
-    # per-stage times with HIP events on the launch stream
-    def time_stage(fn, reps):
+    # per-stage times with HIP events on the launch stream, each array alone
+    def time_fn(fn, reps):
         for _ in range(2):
             fn()
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a_, b_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
-        a.record(stream)
+        a_.record(stream)
         for _ in range(reps):
             fn()
-        b.record(stream)
+        b_.record(stream)
         torch.cuda.synchronize()
-        return a.elapsed_time(b) / reps
+        return a_.elapsed_time(b_) / reps
 
-    vred = out["vred"]
-    ws = plan.workspace(dev)
-    stage_ms = {
-        "xengine": time_stage(lambda: plan.xengine(volt), args.steps),
-        "fftcorr": time_stage(lambda: plan.fftcorr(volt, gains_in), args.steps),
-        "solve": time_stage(lambda: plan.solve(vred), args.steps),
-    }
-    del ws
+    stages = {"xengine": 0.0, "fftcorr": 0.0, "solve": 0.0}
+    flops = vbytes = 0.0
+    latency = {}
+    for a in arrays:
+        p = a["plan"]
+        stages["xengine"] += time_fn(lambda: p.xengine(a["volt"]), args.steps)
+        stages["fftcorr"] += time_fn(lambda: p.fftcorr(a["volt"], a["gains_in"]), args.steps)
+        stages["solve"] += time_fn(lambda: p.solve(a["out"]["vred"]), args.steps)
+        m = p.info["fft_size"]
+        flops += fft_flops_per_sample(a["n"], m) * w.n_time * w.n_chan
+        vbytes += (1.0 if w.ci4 else 8.0) * a["n"] ** 2 * w.n_time * w.n_chan
+        if len(arrays) > 1:
+            # per-array latency of one whole-path run of the array alone
+            t = []
+            for _ in range(max(5, args.steps)):
+                s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                s0.record(stream)
+                p.run(a["volt"], gains_in=a["gains_in"], mode="pipelined", out=a["out"])
+                s1.record(stream)
+                torch.cuda.synchronize()
+                t.append(s0.elapsed_time(s1))
+            latency[a["name"]] = {"p50_ms": float(np.percentile(t, 50)), "p99_ms": float(np.percentile(t, 99))}
 
     # plain per-channel form: one plan per channel, host sync after each
-    plan1 = rrc.Plan(n, types, 1, T)
-    out1 = plan1.alloc_outputs(dev)
     plain_ms = None
     if args.plain_steps > 0:
-        for c in range(2):
-            plan1.run(volt[c:c + 1], gains_in=gains_in[c:c + 1], mode="pipelined", out=out1)
+        plain1 = []
+        for a in arrays:
+            p1 = rrc.Plan(a["n"], a["types"], 1, w.n_time, dtype=dtype)
+            plain1.append((a, p1, p1.alloc_outputs(dev)))
+        for a, p1, o1 in plain1:
+            for c in range(min(2, w.n_chan)):
+                p1.run(a["volt"][c:c + 1], gains_in=a["gains_in"][c:c + 1], mode="pipelined", out=o1)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.plain_steps):
-            for c in range(U):
-                plan1.run(volt[c:c + 1], gains_in=gains_in[c:c + 1], mode="pipelined", out=out1)
-                torch.cuda.synchronize()
+            for a, p1, o1 in plain1:
+                for c in range(w.n_chan):
+                    p1.run(a["volt"][c:c + 1], gains_in=a["gains_in"][c:c + 1], mode="pipelined", out=o1)
+                    torch.cuda.synchronize()
         plain_ms = (time.perf_counter() - t0) * 1e3 / args.plain_steps
 
-    # accuracy gate on a seeded sample of units: gains vs the oracle
-    from oracle import geometry as OG
-    from oracle import redcal as OR
-    pos = OG.square_positions(n)
-    pairs, tix = OG.group_pairs(pos, types)
-    rng = np.random.default_rng(7)
-    sample = sorted(rng.choice(U, size=min(U, 4), replace=False).tolist())
-    gerr = 0.0
-    st = out["status"].cpu().numpy()
-    for u in sample:
-        ref = OR.calibrate(out["vred"][u].cpu().numpy().astype(np.complex128), pos, types, pairs, tix)
-        g = out["gains"][u].cpu().numpy().astype(np.complex128)
-        gerr = max(gerr, float(np.max(np.abs(g - ref["g"]) / np.abs(ref["g"]))))
-
     # roofline of the FFT-correlator stage (the O(N log N) core)
-    m = plan.info["fft_size"]
-    flops = fft_flops_per_sample(n, m) * T * U
-    vbytes = 8.0 * n * n * T * U
-    fft_s = stage_ms["fftcorr"] * 1e-3
+    fft_s = stages["fftcorr"] * 1e-3
     roof = {"bound": "alu", "achieved": flops / fft_s / 1e12, "peak": VALU_FP32_PEAK_TFLOPS,
             "unit": "TFLOP/s", "frac": flops / fft_s / 1e12 / VALU_FP32_PEAK_TFLOPS, "traffic": None,
-            "kernel": "k_fftcorr + k_fftfin (fftcorr stage)",
+            "kernel": "k_fftcorr + k_fftfin_fft (FFT-correlator stage)",
             "hbm_achieved_GBs": vbytes / fft_s / 1e9, "hbm_frac": vbytes / fft_s / 1e9 / HBM_PEAK_GBS}
 
-    cpu = None
+    status_nonzero = int(sum(int((a["out"]["status"] != 0).sum()) for a in arrays))
+    cpu, gate = None, None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(w, volt_np, types, args.cpu_seconds)
+        for a in arrays:
+            a["volt_host"] = (lambda u, a=a: a["volt"][u].cpu().numpy())
+            a["vred_gpu"] = (lambda u, a=a: (lambda x: x[..., 0] + 1j * x[..., 1] if x.ndim == 2 else x)(
+                a["out"]["vred"][u].cpu().numpy()).astype(np.complex128))
+            a["gains_gpu"] = (lambda u, a=a: a["out"]["gains"][u].cpu().numpy().astype(np.complex128))
+        cpu, gate = cpu_baseline(arrays, args.cpu_seconds, gate_units=4)
 
+    n0 = arrays[0]["n"]
     rec = {
-        "metric": "calibrated channel-integrations/sec (batched+adjoint vs plain) at stated gain error",
+        "metric": METRIC,
         "value": value, "unit": "channel-integrations/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": w.name, "grid": f"{n}x{n}", "antennas": n * n, "channels": U,
-                   "samples": T, "fft_size": m, "types": len(types), "pairs": npairs,
-                   "mode": "pipelined, all channels per launch", "parallelism": "none (1 GPU)"},
-        "stages_ms": stage_ms,
+        "vs_baseline": None, "dtype": "ci4->i32/f32" if w.ci4 else "f32",
+        "data": "synthetic" + ("" if host_gen else " (drawn on the GPU)"),
+        "config": {"workload": w.name, "grids": [f"{a['n']}x{a['n']}" for a in arrays],
+                   "antennas": [a["n"] ** 2 for a in arrays], "channels": w.n_chan, "samples": w.n_time,
+                   "fft_size": [a["plan"].info["fft_size"] for a in arrays],
+                   "types": [len(a["types"]) for a in arrays], "pairs": [a["npairs"] for a in arrays],
+                   "mode": "pipelined, all channels per launch" + (", arrays concurrently" if batch else ""),
+                   "parallelism": "none (1 GPU)"},
+        "stages_ms": stages,
         "plain_per_channel": None if plain_ms is None else
-        {"ms_per_step": plain_ms, "value": U / (plain_ms * 1e-3), "speedup_batched": plain_ms / ms},
-        "gain_error_vs_oracle": {"max_rel": gerr, "units": sample, "tol": 1e-6,
-                                 "status_nonzero": int(np.sum(st != 0))},
+        {"ms_per_step": plain_ms, "value": total_units / (plain_ms * 1e-3), "speedup_batched": plain_ms / ms},
+        "gain_error_vs_oracle": None if gate is None else dict(gate, status_nonzero=status_nonzero),
         "roofline": roof,
         "cpu_baseline": cpu,
     }
+    if latency:
+        rec["per_array_latency"] = latency
+    if n0 and len(arrays) == 1:
+        rec["config"].update({"grid": f"{n0}x{n0}", "antennas": n0 * n0})
     print(json.dumps(rec), flush=True)
 
 
