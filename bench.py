@@ -44,6 +44,24 @@ def fft_flops_per_sample(n: int, m: int) -> float:
     return (n + m) * per_tf + 3 * m * m + 6 * n * n
 
 
+def measured_traffic(workload: str):
+    """HBM bytes per launch of the FFT-correlator stage from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE runs (scaled by a copy of known size),
+    or None when none was taken for this workload or the kernels' sources
+    have changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"traffic_fftcorr_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    for src, h in d["sources_sha1"].items():
+        with open(os.path.join(ROOT, src), "rb") as f:
+            if hashlib.sha1(f.read()).hexdigest() != h:
+                return None
+    return d["hbm_bytes_per_launch"]
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -59,10 +77,11 @@ def parse():
 def cpu_baseline(arrays, budget_s, gate_units):
     """The FP64 oracle, as it stands, on a bounded sample of the same units.
 
-    Also the accuracy gate: for each sampled unit the oracle solves the
-    GPU's own V^reduced and the GPU gains are compared after the same
-    degeneracy fix.  Arrays whose dense oracle solve is too slow for a
-    bench (n > 32) are left out of the sample.
+    Units are taken in a seeded random order until the time budget is
+    spent.  Also the accuracy gate: for the first `gate_units` of them the
+    oracle solves the GPU's own V^reduced and the GPU gains are compared
+    after the same degeneracy fix.  Arrays whose dense oracle solve is too
+    slow for a bench (n > 32) are left out of the sample.
     """
     import threadpoolctl
     from oracle import correlator as OC
@@ -145,7 +164,7 @@ def main():
         arrays.append(dict(name=f"g{n}", n=n, types=types, npairs=npairs, plan=plan, volt=volt,
                            gains_in=torch.from_numpy(g.astype(np.complex64)).to(dev),
                            out=plan.alloc_outputs(dev),
-                           sample=sorted(rng.choice(w.n_chan, size=min(w.n_chan, 4), replace=False).tolist())))
+                           sample=rng.permutation(w.n_chan).tolist()))
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     batch = rrc.Batch([a["plan"] for a in arrays]) if len(arrays) > 1 else None
@@ -229,7 +248,9 @@ def main():
     # roofline of the FFT-correlator stage (the O(N log N) core)
     fft_s = stages["fftcorr"] * 1e-3
     roof = {"bound": "alu", "achieved": flops / fft_s / 1e12, "peak": VALU_FP32_PEAK_TFLOPS,
-            "unit": "TFLOP/s", "frac": flops / fft_s / 1e12 / VALU_FP32_PEAK_TFLOPS, "traffic": None,
+            "unit": "TFLOP/s", "frac": flops / fft_s / 1e12 / VALU_FP32_PEAK_TFLOPS,
+            "traffic": measured_traffic(w.name) if len(arrays) == 1 else None,
+            "algorithmic_bytes": vbytes,
             "kernel": "k_fftcorr + k_fftfin_fft (FFT-correlator stage)",
             "hbm_achieved_GBs": vbytes / fft_s / 1e9, "hbm_frac": vbytes / fft_s / 1e9 / HBM_PEAK_GBS}
 

@@ -23,7 +23,8 @@ def _plan(rrc, n, U, T, dtype="c64", types=None, **kw):
 # ------------------------------------------------------------------ (a1)-(a3)
 
 @pytest.mark.parametrize("n,U,T", [(8, 1, 256), (16, 6, 1024), (3, 2, 37), (5, 3, 250),
-                                   (12, 2, 333), (24, 2, 200), (32, 2, 512)])
+                                   (12, 2, 333), (24, 2, 200), (32, 2, 512), (40, 1, 33),
+                                   (48, 2, 64), (64, 1, 40), (16, 1, 4096)])
 def test_fftcorr_matches_oracle(rrc, n, U, T):
     v, g = make_units(n, U, T)
     plan, _ = _plan(rrc, n, U, T)
@@ -34,6 +35,23 @@ def test_fftcorr_matches_oracle(rrc, n, U, T):
         ref, aref = oracle_vunique(v[u], g64[u].astype(np.complex128), n)
         err = rel_l2(vu[u], ref)
         print(f"n={n} T={T} unit {u}: V^unique rel L2 {err:.2e}, auto {abs(va[u] - aref) / aref:.2e}")
+        assert err <= TOL_VUNIQUE
+        assert abs(va[u] - aref) <= 1e-5 * aref
+
+
+@pytest.mark.parametrize("n,U,T", [(16, 2, 256), (64, 1, 40)])
+def test_fftcorr_ci4_matches_oracle(rrc, n, U, T):
+    # 4-bit voltages: the oracle is fed the same integers
+    b, re, im, g = make_ci4_units(n, U, T)
+    plan, _ = _plan(rrc, n, U, T, dtype="ci4")
+    g64 = g.astype(np.complex64)
+    vu, va = plan.fftcorr(torch.from_numpy(b).to(DEV), torch.from_numpy(g64).to(DEV))
+    vu, va = vu.cpu().numpy(), va.cpu().numpy()
+    for u in range(U):
+        v = re[u].astype(np.complex128) + 1j * im[u].astype(np.complex128)
+        ref, aref = oracle_vunique(v, g64[u].astype(np.complex128), n)
+        err = rel_l2(vu[u], ref)
+        print(f"ci4 n={n} T={T} unit {u}: V^unique rel L2 {err:.2e}")
         assert err <= TOL_VUNIQUE
         assert abs(va[u] - aref) <= 1e-5 * aref
 
@@ -221,6 +239,47 @@ def test_chisq_and_adjoint_match_oracle(rrc):
         assert np.max(np.abs(gv[u] - 2 * rv)) <= 1e-5 * np.max(np.abs(2 * rv))
         assert np.max(np.abs(dg[u] - hg) / hg) <= 1e-5
         assert np.max(np.abs(dv[u] - hv) / hv) <= 1e-5
+
+
+def test_adjoint_matches_central_finite_differences(rrc):
+    # chi^2 is quadratic in each single complex parameter (no pair has
+    # i = j), so central differences of the FP64 chi^2 with step 1e-3 are
+    # exact up to rounding: d chi2/d Re z + i d chi2/d Im z = 2 d chi2/d conj(z),
+    # which is what rrc_chisq_adj returns
+    n, U, T = 8, 1, 256
+    v, gtrue = make_units(n, U, T)
+    plan, types = _plan(rrc, n, U, T)
+    pairs, tix = pairs_of(n, types)
+    vr_d = plan.xengine(torch.from_numpy(v).to(DEV))
+    vr = vr_d.cpu().numpy()[0].astype(np.complex128)
+    rng = np.random.default_rng(11)
+    g = (gtrue[0] * (1 + 0.02 * (rng.standard_normal(n * n) + 1j * rng.standard_normal(n * n)))).astype(np.complex64)
+    vm = OR.group_mean(vr, gtrue[0], pairs, tix, len(types)).astype(np.complex64)
+    gg, gv, _, _ = plan.chisq_adj(torch.from_numpy(g[None]).to(DEV), torch.from_numpy(vm[None]).to(DEV), vr_d)
+    gg, gv = gg.cpu().numpy()[0], gv.cpu().numpy()[0]
+    g64, v64 = g.astype(np.complex128), vm.astype(np.complex128)
+    h = 1e-3
+
+    def fd(vec_g, vec_v, which, k):
+        out = 0j
+        for part, unit in ((0, 1.0), (1, 1j)):
+            gp, gm, vp, vmn = vec_g.copy(), vec_g.copy(), vec_v.copy(), vec_v.copy()
+            if which == "g":
+                gp[k] += h * unit
+                gm[k] -= h * unit
+            else:
+                vp[k] += h * unit
+                vmn[k] -= h * unit
+            d = (OR.chisq(vr, gp, vp, pairs, tix) - OR.chisq(vr, gm, vmn, pairs, tix)) / (2 * h)
+            out += d * (1 if part == 0 else 1j)
+        return out
+
+    sc_g = np.max(np.abs(gg))
+    for k in rng.choice(n * n, size=8, replace=False):
+        assert abs(gg[k] - fd(g64, v64, "g", k)) <= 1e-5 * sc_g, k
+    sc_v = np.max(np.abs(gv))
+    for k in range(len(types)):
+        assert abs(gv[k] - fd(g64, v64, "v", k)) <= 1e-5 * sc_v, k
 
 
 def test_chisq_autograd_function(rrc):
