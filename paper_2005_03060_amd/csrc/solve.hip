@@ -76,8 +76,8 @@ size_t solve_slab_bytes(const Sel&, bool) { return 0; }
 size_t solve_lds_bytes(const Sel& s, bool) { return solve_layout(s).bytes; }
 
 // Workgroup shape: one antenna per work-item up to 1024 antennas, then
-// 2 or 4 per work-item.
-inline int solve_threads_for(int N) { return N <= 256 ? 256 : (N <= 512 ? 512 : 1024); }
+// 512 work-items with 4 or 8 antennas each.
+inline int solve_threads_for(int N) { return N <= 256 ? 256 : (N <= 512 || N > 1024 ? 512 : 1024); }
 
 // Per-type constants of the selection, in LDS: the raster offset d_t of
 // the type and the pair indices as affine functions of an antenna's
@@ -931,6 +931,7 @@ template <int NT, int APT>
 static hipError_t launch_solve_shape(const SolveLaunch& L, hipStream_t st) {
     if (L.sel.K <= 6) return launch_solve_k<NT, APT, 6>(L, st);
     if (L.sel.K <= 8) return launch_solve_k<NT, APT, 8>(L, st);
+    if (L.sel.K <= 10) return launch_solve_k<NT, APT, 10>(L, st);
     return launch_solve_k<NT, APT, kMaxTypes>(L, st);
 }
 
@@ -940,8 +941,9 @@ hipError_t launch_solve(const SolveLaunch& L, hipStream_t st) {
     if (N <= 256) return launch_solve_shape<256, 1>(L, st);
     if (N <= 512) return launch_solve_shape<512, 1>(L, st);
     if (N <= 1024) return launch_solve_shape<1024, 1>(L, st);
-    if (N <= 2048) return launch_solve_shape<1024, 2>(L, st);
-    if (N <= 4096) return launch_solve_shape<1024, 4>(L, st);
+    // larger grids: 512 work-items (256 VGPRs each) rather than 1024 (128)
+    if (N <= 2048) return launch_solve_shape<512, 4>(L, st);
+    if (N <= 4096) return launch_solve_shape<512, 8>(L, st);
     return hipErrorInvalidValue;
 }
 

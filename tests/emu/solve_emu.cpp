@@ -17,6 +17,7 @@ template <int NT, int APT>
 static bool run_shape(const SolveLaunch& L, unsigned char* ldsbuf, int unit) {
     if (L.sel.K <= 6) return run_unit<NT, APT, 6>(L, ldsbuf, unit);
     if (L.sel.K <= 8) return run_unit<NT, APT, 8>(L, ldsbuf, unit);
+    if (L.sel.K <= 10) return run_unit<NT, APT, 10>(L, ldsbuf, unit);
     return run_unit<NT, APT, kMaxTypes>(L, ldsbuf, unit);
 }
 
