@@ -2,8 +2,8 @@
 // antenna pairs of the selected redundant groups,
 //     V_ij = (1/T) sum_t v_i(t) conj(v_j(t)),
 // on the raw (uncalibrated) voltages.  4-bit voltages are summed exactly in
-// int32: |Re q_i conj(q_j)| <= 2*7*7 = 98 per sample, so 98 * T fits in
-// int32 for any T below 2^31 / 98.
+// int32: |Re q_i conj(q_j)| <= 2*8*8 = 128 per sample, so the sums fit in
+// int32 for any T below 2^24.
 //
 // Antenna-centric: every selected pair (i, j) has r_i - r_j = d_t with d_t
 // in the canonical half-plane, so in raster order j = i - (dy n + dx) < i.
@@ -17,6 +17,19 @@
 // never written, so the inner loop has no branches.  Partial sums per time
 // chunk go to the workspace and a second kernel adds them in a fixed
 // order; with a single chunk the first kernel writes V^reduced itself.
+//
+// 4-bit voltages stay packed (one byte: real part in the high nibble,
+// imaginary in the low one) and are multiplied four samples at a time with
+// the signed 4-bit dot product (eight nibble products per instruction).  The
+// staging transposes 4 x 4 byte blocks so that one LDS word holds four
+// consecutive samples of one antenna.  With A the own word and B a
+// partner's, dot(A, B) sums ar br + ai bi (the real part), and moving the
+// own nibbles to the other half of each byte (A << 4 keeps ai against br,
+// A >> 4 keeps ar against bi, the other nibbles zeroed) gives the two terms
+// of the imaginary part ai br - ar bi: three instructions for four samples
+// of one pair, where the unpacked form takes four multiply-adds per sample.
+// A dense MFMA product of antenna patches would waste all but the K
+// diagonals of each output tile, which leaves no gain over this form.
 #include "rrc_device.h"
 #include "rrc_launch.h"
 
@@ -27,8 +40,22 @@ namespace rrc {
 constexpr int kXThreads = 256;
 constexpr int kXHaloMax = 248;   // largest raster offset d_t the staging covers
 
-__device__ __forceinline__ int2 unpack_ci4(int b) {
-    return make_int2((b << 24) >> 28, (b << 28) >> 28);   // sign-extended nibbles
+// Transpose a 4 x 4 block of bytes: out[k] byte q = in[q] byte k.
+__device__ __forceinline__ void transpose4x4(const uint32_t (&w)[4], uint32_t (&o)[4]) {
+    // interleave bytes of rows (0, 1) and (2, 3), then 16-bit halves
+    const uint32_t t0 = __builtin_amdgcn_perm(w[1], w[0], 0x05010400u);
+    const uint32_t t1 = __builtin_amdgcn_perm(w[1], w[0], 0x07030602u);
+    const uint32_t t2 = __builtin_amdgcn_perm(w[3], w[2], 0x05010400u);
+    const uint32_t t3 = __builtin_amdgcn_perm(w[3], w[2], 0x07030602u);
+    o[0] = __builtin_amdgcn_perm(t2, t0, 0x05040100u);
+    o[1] = __builtin_amdgcn_perm(t2, t0, 0x07060302u);
+    o[2] = __builtin_amdgcn_perm(t3, t1, 0x05040100u);
+    o[3] = __builtin_amdgcn_perm(t3, t1, 0x07060302u);
+}
+
+// Signed 4-bit dot product of eight nibble pairs, accumulated.
+__device__ __forceinline__ int dot8(uint32_t a, uint32_t b, int c) {
+    return __builtin_amdgcn_sdot8((int)a, (int)b, c, false);
 }
 
 // Samples staged per step: 16 complex64 rows or 64 rows of 4-bit bytes.
@@ -93,10 +120,12 @@ __global__ __launch_bounds__(kXThreads, 2) void k_xant(XengLaunch L) {
     }
     const int own = live ? a - lo : 0;
 
+    // float: real and imaginary sums; 4-bit: the real sum and the two terms
+    // of the imaginary one (acci - accn)
     using AT = typename std::conditional<CI4, int, float>::type;
-    AT accr[KMAX], acci[KMAX];
+    AT accr[KMAX], acci[KMAX], accn[KMAX];
 #pragma unroll
-    for (int t = 0; t < KMAX; ++t) accr[t] = acci[t] = 0;
+    for (int t = 0; t < KMAX; ++t) accr[t] = acci[t] = accn[t] = 0;
 
     const int tb = chunk * L.tchunk;
     const int te = min(T, tb + L.tchunk);
@@ -105,7 +134,10 @@ __global__ __launch_bounds__(kXThreads, 2) void k_xant(XengLaunch L) {
     // registers (all loads in flight together), then writes them to LDS.
     // Indices are clamped instead of predicated (a row past the chunk's end
     // repeats the last one, a unit past the row's end repeats the last unit;
-    // neither is read), so the copy has no branches.
+    // neither is read), so the copy has no branches.  4-bit rows past the
+    // end are zeroed instead, since they are summed in groups of four, and
+    // stored transposed: LDS word (g, a) holds samples 4g .. 4g + 3 of
+    // antenna a.
     const RT* vol = reinterpret_cast<const RT*>(L.volt);
     const size_t rowstride = (size_t)N / W;
     RT r[S][KPT];
@@ -115,16 +147,30 @@ __global__ __launch_bounds__(kXThreads, 2) void k_xant(XengLaunch L) {
 #pragma unroll
         for (int q = 0; q < S; ++q) {
 #pragma unroll
-            for (int u = 0; u < KPT; ++u)
+            for (int u = 0; u < KPT; ++u) {
                 r[q][u] = base[(size_t)min(q, last) * rowstride + min(tid + u * NT, upr - 1)];
+                if constexpr (CI4) r[q][u] = q <= last ? r[q][u] : 0u;
+            }
         }
     };
     auto store = [&]() {
-        RT* st = reinterpret_cast<RT*>(xsm);
+        if constexpr (CI4) {
+            uint4* st = reinterpret_cast<uint4*>(xsm);
+            const int col = min(tid, upr - 1);
 #pragma unroll
-        for (int q = 0; q < S; ++q) {
+            for (int g = 0; g < S / 4; ++g) {
+                const uint32_t w[4] = {r[4 * g][0], r[4 * g + 1][0], r[4 * g + 2][0], r[4 * g + 3][0]};
+                uint32_t o[4];
+                transpose4x4(w, o);
+                st[g * upr + col] = make_uint4(o[0], o[1], o[2], o[3]);
+            }
+        } else {
+            RT* st = reinterpret_cast<RT*>(xsm);
 #pragma unroll
-            for (int u = 0; u < KPT; ++u) st[q * upr + min(tid + u * NT, upr - 1)] = r[q][u];
+            for (int q = 0; q < S; ++q) {
+#pragma unroll
+                for (int u = 0; u < KPT; ++u) st[q * upr + min(tid + u * NT, upr - 1)] = r[q][u];
+            }
         }
     };
 
@@ -136,18 +182,25 @@ __global__ __launch_bounds__(kXThreads, 2) void k_xant(XengLaunch L) {
         if (t0 + S < te) load(t0 + S);       // in flight during the products
         // KMAX is the selection's K (or above it, the extra pairs being the
         // antenna with itself, never written): no branch per type
+        if constexpr (CI4) {
+            const int ng = (ns + 3) >> 2;
 #pragma unroll 2
-        for (int q = 0; q < ns; ++q) {
-            if constexpr (CI4) {
-                const uint8_t* srow = reinterpret_cast<const uint8_t*>(xsm) + q * cnt;
-                const int2 va = unpack_ci4(srow[own]);
+            for (int g = 0; g < ng; ++g) {
+                const uint32_t* srow = reinterpret_cast<const uint32_t*>(xsm) + g * cnt;
+                const uint32_t va = srow[own];
+                const uint32_t vi = (va << 4) & 0xF0F0F0F0u;   // ai in the real slots
+                const uint32_t vr = (va >> 4) & 0x0F0F0F0Fu;   // ar in the imaginary slots
 #pragma unroll
                 for (int t = 0; t < KMAX; ++t) {
-                    const int2 vb = unpack_ci4(srow[poff[t]]);
-                    accr[t] += va.x * vb.x + va.y * vb.y;
-                    acci[t] += va.y * vb.x - va.x * vb.y;
+                    const uint32_t vb = srow[poff[t]];
+                    accr[t] = dot8(va, vb, accr[t]);
+                    acci[t] = dot8(vi, vb, acci[t]);
+                    accn[t] = dot8(vr, vb, accn[t]);
                 }
-            } else {
+            }
+        } else {
+#pragma unroll 2
+            for (int q = 0; q < ns; ++q) {
                 const float2* srow = reinterpret_cast<const float2*>(xsm) + q * cnt;
                 const float2 va = srow[own];
 #pragma unroll
@@ -166,7 +219,7 @@ __global__ __launch_bounds__(kXThreads, 2) void k_xant(XengLaunch L) {
         for (int t = 0; t < KMAX; ++t) {
             if (t >= K || pidx[t] < 0) continue;
             const size_t o = (size_t)unit * s.P + pidx[t];
-            if constexpr (CI4) reinterpret_cast<int2*>(L.vred)[o] = make_int2(accr[t], acci[t]);
+            if constexpr (CI4) reinterpret_cast<int2*>(L.vred)[o] = make_int2(accr[t], acci[t] - accn[t]);
             else reinterpret_cast<float2*>(L.vred)[o] = make_float2(accr[t] * L.inv_t, acci[t] * L.inv_t);
         }
     } else {
@@ -174,14 +227,14 @@ __global__ __launch_bounds__(kXThreads, 2) void k_xant(XengLaunch L) {
 #pragma unroll
         for (int t = 0; t < KMAX; ++t) {
             if (t >= K || pidx[t] < 0) continue;
-            if constexpr (CI4) reinterpret_cast<int2*>(L.vpart)[base + pidx[t]] = make_int2(accr[t], acci[t]);
+            if constexpr (CI4) reinterpret_cast<int2*>(L.vpart)[base + pidx[t]] = make_int2(accr[t], acci[t] - accn[t]);
             else reinterpret_cast<float2*>(L.vpart)[base + pidx[t]] = make_float2(accr[t], acci[t]);
         }
     }
 }
 
 // LDS of one workgroup: S staged rows of (256 + halo) antennas, 4-bit rows
-// widened by up to 6 bytes to whole words.
+// widened by up to 6 bytes to whole words (stored as S/4 rows of words).
 size_t xengine_lds_bytes(int halo, bool ci4) {
     return ci4 ? (size_t)xeng_samples<true>() * (kXThreads + halo + 6)
                : (size_t)xeng_samples<false>() * (kXThreads + halo + 2) * 8;

@@ -87,7 +87,8 @@ def test_xengine_float_matches_oracle(rrc, n, U, T):
         assert err <= TOL_XENG
 
 
-@pytest.mark.parametrize("n,U,T", [(8, 2, 300), (16, 2, 1024), (64, 2, 4096)])
+@pytest.mark.parametrize("n,U,T", [(8, 2, 300), (8, 3, 301), (12, 2, 130), (16, 1, 1027), (16, 2, 1024),
+                                   (64, 2, 4096)])
 def test_xengine_ci4_bit_exact(rrc, n, U, T):
     b, re, im, _ = make_ci4_units(n, U, T)
     plan, types = _plan(rrc, n, U, T, dtype="ci4")
@@ -95,6 +96,22 @@ def test_xengine_ci4_bit_exact(rrc, n, U, T):
     pairs, _ = pairs_of(n, types)
     for u in range(U):
         ref = OC.xengine_int(re[u], im[u], pairs)
+        assert np.array_equal(vr[u], ref), f"unit {u}: {np.sum(vr[u] != ref)} mismatches"
+
+
+@pytest.mark.parametrize("n,T", [(8, 259), (16, 1024)])
+def test_xengine_ci4_full_nibble_range(rrc, n, T):
+    # every byte value, so both nibbles take -8 .. 7 (the -8 products included)
+    from synthdata.generate import unpack_ci4
+    rng = np.random.default_rng(17)
+    b = rng.integers(0, 256, size=(2, T, n * n), dtype=np.uint8)
+    b[:, :4, :] = 0x88                       # (-8, -8) at the start of each unit
+    plan, types = _plan(rrc, n, 2, T, dtype="ci4")
+    vr = plan.xengine(torch.from_numpy(b).to(DEV)).cpu().numpy().astype(np.int64)
+    pairs, _ = pairs_of(n, types)
+    for u in range(2):
+        re, im = unpack_ci4(b[u])
+        ref = OC.xengine_int(re, im, pairs)
         assert np.array_equal(vr[u], ref), f"unit {u}: {np.sum(vr[u] != ref)} mismatches"
 
 
