@@ -253,6 +253,19 @@ def main():
             "algorithmic_bytes": vbytes,
             "kernel": "k_fftcorr + k_fftfin_fft (FFT-correlator stage)",
             "hbm_achieved_GBs": vbytes / fft_s / 1e9, "hbm_frac": vbytes / fft_s / 1e9 / HBM_PEAK_GBS}
+    # the other two stages: the X-engine streams the same voltages (HBM roof);
+    # the solve runs one workgroup per unit and is bound by the latency of
+    # its serial CG iterations, so its figure is time per unit and CU usage
+    x_s = stages["xengine"] * 1e-3
+    cus = torch.cuda.get_device_properties(dev).multi_processor_count
+    other = [
+        {"kernel": "k_xant + k_xfin (reduced X-engine)", "bound": "hbm",
+         "achieved": vbytes / x_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+         "frac": vbytes / x_s / 1e9 / HBM_PEAK_GBS, "algorithmic_bytes": vbytes},
+        {"kernel": "k_solve (reduced redundant calibration)", "bound": "latency",
+         "ms_per_launch": stages["solve"], "units_per_launch": total_units,
+         "workgroups_per_unit": 1, "cus": cus},
+    ]
 
     status_nonzero = int(sum(int((a["out"]["status"] != 0).sum()) for a in arrays))
     cpu, gate = None, None
@@ -282,6 +295,7 @@ def main():
         {"ms_per_step": plain_ms, "value": total_units / (plain_ms * 1e-3), "speedup_batched": plain_ms / ms},
         "gain_error_vs_oracle": None if gate is None else dict(gate, status_nonzero=status_nonzero),
         "roofline": roof,
+        "roofline_other": other,
         "cpu_baseline": cpu,
     }
     if latency:
