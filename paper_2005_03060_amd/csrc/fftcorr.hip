@@ -30,7 +30,7 @@ template <int M> struct FftCfg;
 template <> struct FftCfg<16>  { static constexpr int S = 16; };
 template <> struct FftCfg<32>  { static constexpr int S = 8; };
 template <> struct FftCfg<64>  { static constexpr int S = 4; };
-template <> struct FftCfg<128> { static constexpr int S = 1; };
+template <> struct FftCfg<128> { static constexpr int S = 2; };   // k_fftcorr_q
 
 constexpr int kFftThreads = 256;
 
@@ -286,6 +286,206 @@ __global__ __launch_bounds__(kFftThreads) void k_fftcorr(const void* __restrict_
     for (int q = tid; q < M * M; q += NT) dst[q] = pl[q];
 }
 
+
+// ---------------------------------------------------------------- M = 128
+// For 33 <= n <= 64 a whole M/2 = 64-point transform per work-item needs
+// 128 registers of data plus 64 accumulators, and two samples' row buffers
+// fill the LDS, so the M <= 64 kernel would run one wave per SIMD.  Here
+// each transform is split by output residue mod 4 (a wave-uniform
+// "quarter" q): with j' < 32,
+//     E(4m + q) = sum_j' w_32^{j'm} w_128^{j'q} [x_j' + (-i)^q x_{j'+32}],
+// a 32-point FFT after a fold of the 64 inputs.  512 work-items process two
+// samples per step: in the row stage wave (s, q) takes quarter q of the
+// rows of sample s (one row per lane); in the column stage wave (q, h)
+// takes quarter q of columns 64h .. 64h + 63 of both samples, so each
+// work-item owns 32 grid points of |E|^2 outright and writes them with no
+// reduction.
+//
+// LDS: the two row buffers (128 KB) and the 1/g table (32 KB) fill the
+// 160 KB, so nothing is padded.  The table is stored transposed ([k][y]),
+// which makes the row stage's reads (lanes on rows) consecutive.  Row
+// buffer entry (y, k) sits at column k ^ (y mod 32): row-stage writes
+// (lanes on rows, one k) then spread over the banks, and column-stage
+// reads (lanes on columns, one row) stay a permutation of consecutive
+// words.  The XOR acts below bit 10 of the byte address, so every access
+// is one XOR of a per-lane base with a constant plus an immediate offset.
+constexpr int kQThreads = 512;
+
+// W consecutive voltages from element idx (W divides n, so a group never
+// straddles the end of a row): 4-bit as one 16- or 32-bit word, complex64
+// as one 16-byte pair.
+template <bool CI4, int W>
+__device__ __forceinline__ void load_group(const void* base, size_t idx, float2 (&v)[W]) {
+    if constexpr (CI4) {
+        const uint8_t* b = reinterpret_cast<const uint8_t*>(base) + idx;
+        uint32_t word;
+        if constexpr (W == 4) word = *reinterpret_cast<const uint32_t*>(b);
+        else if constexpr (W == 2) word = *reinterpret_cast<const uint16_t*>(b);
+        else word = *b;
+#pragma unroll
+        for (int e = 0; e < W; ++e) {
+            const int by = (int)((word >> (8 * e)) & 0xFFu);
+            v[e] = make_float2((float)((by << 24) >> 28), (float)((by << 28) >> 28));
+        }
+    } else {
+        const float2* f = reinterpret_cast<const float2*>(base) + idx;
+        if constexpr (W == 2) {
+            const float4 q = *reinterpret_cast<const float4*>(f);
+            v[0] = make_float2(q.x, q.y);
+            v[1] = make_float2(q.z, q.w);
+        } else {
+            v[0] = f[0];
+        }
+    }
+}
+
+__device__ __forceinline__ const float2& lds_at(const float2* lds, uint32_t byte_off) {
+    return *reinterpret_cast<const float2*>(reinterpret_cast<const char*>(lds) + byte_off);
+}
+
+// Quarter Q of one row: inputs x_j = v_j / g_j (zero for j >= n through the
+// table), outputs E(4m + Q) to the swizzled LDS row.  hcol = table + y;
+// wbase = byte offset of the row | (y mod 32) << 3.
+template <int Q, bool CI4, int W>
+__device__ __forceinline__ void row_quarter(const void* __restrict__ volt, size_t rowbase, int n,
+                                            const float2* hcol, float2* rbuf, uint32_t wbase) {
+    float2 u[32];
+    // inputs 32 .. 63 may lie past the row (n >= 33 keeps 0 .. 31 inside):
+    // clamp their groups to the last one; the table zeroes them.  nw is
+    // re-read here so the 32 clamped offsets are not kept for the whole loop.
+    int nw = n - W;
+    asm volatile("" : "+s"(nw));
+#pragma unroll
+    for (int j = 0; j < 32; j += W) {
+        float2 a[W], b[W];
+        load_group<CI4, W>(volt, rowbase + j, a);
+        load_group<CI4, W>(volt, rowbase + min(j + 32, nw), b);
+#pragma unroll
+        for (int e = 0; e < W; ++e) {
+            const float2 xa = cmul(a[e], hcol[(j + e) * 64]);
+            const float2 xb = cmul(b[e], hcol[(j + 32 + e) * 64]);
+            u[j + e] = twmul<128>(cadd(xa, twmul<4>(xb, Q)), (j + e) * Q);
+        }
+        // complex64 rows: finish each 8 inputs before the next loads issue.
+        // Issuing all 64 at once (what the scheduler prefers) holds 128
+        // registers of voltages plus 128 of 1/g and spills.  The empty asm
+        // consumes the 8 results and orders memory, so it is a fence for both.
+        if constexpr (!CI4) {
+            if ((j + W) % 8 == 0) {
+                const int b = (j + W) - 8;
+                asm volatile("" : "+v"(u[b].x), "+v"(u[b].y), "+v"(u[b + 1].x), "+v"(u[b + 1].y),
+                             "+v"(u[b + 2].x), "+v"(u[b + 2].y), "+v"(u[b + 3].x), "+v"(u[b + 3].y),
+                             "+v"(u[b + 4].x), "+v"(u[b + 4].y), "+v"(u[b + 5].x), "+v"(u[b + 5].y),
+                             "+v"(u[b + 6].x), "+v"(u[b + 6].y), "+v"(u[b + 7].x), "+v"(u[b + 7].y)
+                             :: "memory");
+            }
+        }
+    }
+    fft_dif<32>(u);
+    char* rb = reinterpret_cast<char*>(rbuf);
+#pragma unroll
+    for (int r = 0; r < 32; ++r)
+        *reinterpret_cast<float2*>(rb + (wbase ^ ((4 * bitrev<32>(r) + Q) << 3))) = u[r];
+}
+
+// Quarter Q of one column of one sample's row buffer; |E|^2 into acc.
+// rbase = byte offset of the sample's buffer | u << 3.
+template <int Q>
+__device__ __forceinline__ void col_quarter(const float2* rbuf, uint32_t rbase, float (&acc)[32]) {
+    float2 v[32];
+#pragma unroll
+    for (int j = 0; j < 32; ++j) {
+        const uint32_t o = rbase ^ (j << 3);
+        const float2 a = lds_at(rbuf, o + j * 1024);
+        const float2 b = lds_at(rbuf, o + (j + 32) * 1024);
+        v[j] = twmul<128>(cadd(a, twmul<4>(b, Q)), j * Q);
+    }
+    fft_dif<32>(v);
+#pragma unroll
+    for (int r = 0; r < 32; ++r) acc[r] += cabs2(v[r]);
+}
+
+template <bool CI4, int W>
+__global__ __launch_bounds__(kQThreads) void k_fftcorr_q(const void* __restrict__ volt,
+                                                         const float2* __restrict__ gains,
+                                                         float* __restrict__ ppart, int n, int T,
+                                                         int tchunk, int nchunk) {
+    constexpr int M = 128, H = 64, S = FftCfg<128>::S, NT = kQThreads;
+    static_assert(NT == 4 * 64 * S, "one row quarter per wave and sample");
+    static_assert(M * 8 == 1024, "row stride of 1 KiB: the swizzle stays below bit 10");
+    // (the launcher guarantees 33 <= n <= 64)
+    __shared__ float2 rbuf[S * H * M];   // [s][y][k ^ (y mod 32)]
+    __shared__ float2 hinv[H * H];       // [k][y], zero outside the grid
+
+    const int tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63;
+    const int unit = blockIdx.y;
+    const int chunk = blockIdx.x;
+    const int N = n * n;
+    const int tb = chunk * tchunk;
+    const int te = min(T, tb + tchunk);
+
+    for (int q = tid; q < H * H; q += NT) {
+        const int k = q / H, y = q % H;
+        float2 h = make_float2(0.0f, 0.0f);
+        if (y < n && k < n) {
+            const float2 g = gains[(size_t)unit * N + y * n + k];
+            const float d = 1.0f / cabs2(g);
+            h = make_float2(g.x * d, -g.y * d);
+        }
+        hinv[q] = h;
+    }
+    // rows n .. H-1 of both sample buffers stay zero
+    for (int q = tid; q < S * (H - n) * M; q += NT) {
+        const int s = q / ((H - n) * M), r = q % ((H - n) * M);
+        rbuf[(s * H + n) * M + r] = make_float2(0.0f, 0.0f);
+    }
+
+    float acc[32];
+#pragma unroll
+    for (int r = 0; r < 32; ++r) acc[r] = 0.0f;
+    const int rs = wave >> 2, rq = wave & 3;                 // row stage: sample, quarter
+    const int cq = wave >> 1, cu = (wave & 1) * 64 + lane;   // column stage
+    const int y = lane;
+    __syncthreads();
+
+    for (int t0 = tb; t0 < te; t0 += S) {
+        const int t = t0 + rs;
+        if (t < te && y < n) {
+            const size_t rowbase = ((size_t)unit * T + t) * N + (size_t)y * n;
+            uint32_t wbase = (uint32_t)((rs * H + y) * M * 8) | (uint32_t)((y & 31) << 3);
+            // recomputed per step, so the 32 swizzled addresses are not
+            // hoisted into registers for the whole loop
+            asm volatile("" : "+v"(wbase));
+            switch (rq) {
+                case 0: row_quarter<0, CI4, W>(volt, rowbase, n, hinv + y, rbuf, wbase); break;
+                case 1: row_quarter<1, CI4, W>(volt, rowbase, n, hinv + y, rbuf, wbase); break;
+                case 2: row_quarter<2, CI4, W>(volt, rowbase, n, hinv + y, rbuf, wbase); break;
+                default: row_quarter<3, CI4, W>(volt, rowbase, n, hinv + y, rbuf, wbase); break;
+            }
+        }
+        __syncthreads();
+        const int ns = min(S, te - t0);
+        for (int s = 0; s < ns; ++s) {
+            uint32_t rbase = (uint32_t)(s * H * M * 8) | (uint32_t)(cu << 3);
+            asm volatile("" : "+v"(rbase));
+            switch (cq) {
+                case 0: col_quarter<0>(rbuf, rbase, acc); break;
+                case 1: col_quarter<1>(rbuf, rbase, acc); break;
+                case 2: col_quarter<2>(rbuf, rbase, acc); break;
+                default: col_quarter<3>(rbuf, rbase, acc); break;
+            }
+        }
+        __syncthreads();
+    }
+
+    // grid point (ky, kx) = (4 bitrev(r) + cq, cu): lanes write consecutive kx
+    float* dst = ppart + ((size_t)unit * nchunk + chunk) * (M * M);
+#pragma unroll
+    for (int r = 0; r < 32; ++r) dst[(4 * bitrev<32>(r) + cq) * M + cu] = acc[r];
+}
+
 constexpr int kFinThreads = 256;
 constexpr int kFinDxBlock = 32;
 
@@ -359,11 +559,29 @@ __global__ __launch_bounds__(kFftThreads) void k_fftfin_fft(const float* __restr
     inverse_to_lags<M>(lds, ppart + (size_t)unit * nchunk * (M * M), nchunk, n, T, vunique, vauto, unit);
 }
 
+template <bool CI4, int W>
+static void launch_q(const FftLaunch& L, hipStream_t st) {
+    hipLaunchKernelGGL((k_fftcorr_q<CI4, W>), dim3(L.nchunk, L.n_units), dim3(kQThreads), 0, st, L.volt,
+                       L.gains, L.ppart, L.n, L.T, L.tchunk, L.nchunk);
+}
+
 template <int M, bool CI4>
 static hipError_t launch_fft_m(const FftLaunch& L, hipStream_t st) {
-    dim3 grid1(L.nchunk, L.n_units);
-    hipLaunchKernelGGL((k_fftcorr<M, CI4>), grid1, dim3(kFftThreads), 0, st, L.volt, L.gains,
-                       L.ppart, L.n, L.T, L.tchunk, L.nchunk);
+    if constexpr (M == 128) {
+        // widest load group that divides n (4-bit plans have n even)
+        if (L.n < 33 || L.n > 64 || (CI4 && (L.n & 1))) return hipErrorInvalidValue;
+        if constexpr (CI4) {
+            if (L.n % 4 == 0) launch_q<true, 4>(L, st);
+            else launch_q<true, 2>(L, st);
+        } else {
+            if (L.n % 2 == 0) launch_q<false, 2>(L, st);
+            else launch_q<false, 1>(L, st);
+        }
+    } else {
+        dim3 grid1(L.nchunk, L.n_units);
+        hipLaunchKernelGGL((k_fftcorr<M, CI4>), grid1, dim3(kFftThreads), 0, st, L.volt, L.gains,
+                           L.ppart, L.n, L.T, L.tchunk, L.nchunk);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if constexpr (M <= 64) {

@@ -24,7 +24,7 @@ def _plan(rrc, n, U, T, dtype="c64", types=None, **kw):
 
 @pytest.mark.parametrize("n,U,T", [(8, 1, 256), (16, 6, 1024), (3, 2, 37), (5, 3, 250),
                                    (12, 2, 333), (24, 2, 200), (32, 2, 512), (40, 1, 33),
-                                   (48, 2, 64), (64, 1, 40), (16, 1, 4096)])
+                                   (48, 2, 64), (64, 1, 40), (16, 1, 4096), (33, 1, 31), (45, 2, 17)])
 def test_fftcorr_matches_oracle(rrc, n, U, T):
     v, g = make_units(n, U, T)
     plan, _ = _plan(rrc, n, U, T)
@@ -39,7 +39,7 @@ def test_fftcorr_matches_oracle(rrc, n, U, T):
         assert abs(va[u] - aref) <= 1e-5 * aref
 
 
-@pytest.mark.parametrize("n,U,T", [(16, 2, 256), (64, 1, 40)])
+@pytest.mark.parametrize("n,U,T", [(16, 2, 256), (64, 1, 40), (34, 1, 21), (36, 2, 64), (64, 2, 131)])
 def test_fftcorr_ci4_matches_oracle(rrc, n, U, T):
     # 4-bit voltages: the oracle is fed the same integers
     b, re, im, g = make_ci4_units(n, U, T)
