@@ -25,10 +25,10 @@ struct rrc_plan {
     // X-engine
     int x_tchunk, x_nchunk, x_nablk, x_S, x_halo;
     // solver
-    bool solve_lds;
-    size_t solve_lds_bytes, slab_bytes;
+    bool solve_vcache;
+    size_t solve_lds_bytes;
     // workspace layout
-    size_t off_fft, off_x, off_slab, ws_bytes;
+    size_t off_fft, off_x, ws_bytes;
     // fork/join of the pipelined run (created on first use, default priority)
     hipStream_t aux = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
@@ -323,18 +323,17 @@ int rrc_plan_create(rrc_plan** out, int32_t n, const int32_t* types_xy, int32_t 
     }
 
     // solver
-    const size_t hot = rrc::solve_hot_bytes(s);
-    p->solve_lds = hot <= 150 * 1024;
-    p->solve_lds_bytes = rrc::solve_lds_bytes(s, p->solve_lds);
-    p->slab_bytes = align256(rrc::solve_slab_bytes(s, p->solve_lds));
+    // the solver's state always fits in LDS (131 KB at 4096 antennas);
+    // V^reduced joins it when there is room, on one-antenna-per-work-item
+    // shapes (up to 1024 antennas)
+    p->solve_vcache = s.N <= 1024 && rrc::solve_lds_bytes(s, true) <= 150 * 1024;
+    p->solve_lds_bytes = rrc::solve_lds_bytes(s, p->solve_vcache);
 
     size_t off = 0;
     p->off_fft = off;
     off = align256(off + (size_t)n_units * p->fft_nchunk * M * M * sizeof(float));
     p->off_x = off;
     off = align256(off + (p->x_nchunk > 1 ? (size_t)n_units * p->x_nchunk * s.P * 8 : 0));
-    p->off_slab = off;
-    off = align256(off + (size_t)n_units * p->slab_bytes);
     p->ws_bytes = off;
     *out = p;
     return RRC_OK;
@@ -438,7 +437,7 @@ int rrc_solve(rrc_plan* p, void* stream, const void* d_vred, const void* d_gains
     L.sel = p->sel;
     L.n_units = p->U;
     L.ci4 = p->dtype == RRC_CI4;
-    L.lds = p->solve_lds;
+    L.vcache = p->solve_vcache;
     L.lds_bytes = p->solve_lds_bytes;
     {
         int dev = 0;
@@ -452,7 +451,6 @@ int rrc_solve(rrc_plan* p, void* stream, const void* d_vred, const void* d_gains
         }
     }
     L.exclusive = (p->concurrent_units > 0 ? p->concurrent_units : p->U) <= p->cu_count;
-    L.slab_bytes = p->slab_bytes;
     L.o = {p->opts.init_mode, p->opts.degen_mode, p->opts.max_gn, p->opts.fp64_steps,
            p->opts.max_cg, p->opts.cg_tol, p->opts.tol32};
     L.vred = d_vred;
@@ -463,7 +461,6 @@ int rrc_solve(rrc_plan* p, void* stream, const void* d_vred, const void* d_gains
     L.chisq = d_chisq;
     L.niter = d_niter;
     L.status = d_status;
-    L.slab = static_cast<char*>(d_work) + p->off_slab;
     return rrc::launch_solve(L, as_stream(stream)) == hipSuccess ? RRC_OK : RRC_EDEVICE;
 }
 
@@ -506,23 +503,29 @@ int rrc_run(rrc_plan* p, void* stream, int32_t mode, const rrc_io* io) {
         !io->d_vmodel || !io->d_chisq || !io->d_niter || !io->d_status || !io->d_work)
         return RRC_EINVAL;
     hipStream_t st = as_stream(stream);
+    if (p->opts.init_mode == RRC_INIT_GAINS && !io->d_gains_in) return RRC_EINVAL;
+    if (p->opts.degen_mode == RRC_DEGEN_MATCH && !io->d_gains_ref) return RRC_EINVAL;
     int rc = rrc_xengine(p, stream, io->d_volt, io->d_vred, io->d_work);
     if (rc != RRC_OK) return rc;
     if (mode == RRC_RUN_PIPELINED) {
         // The FFT-correlator needs only the previous gains: once the X-engine
         // (the head of the critical path) is done it runs on the auxiliary
-        // stream, beside the latency-bound solve on `stream`.
+        // stream, beside the latency-bound solve on `stream`.  The solve is
+        // queued first: it follows the X-engine on its own stream and so
+        // takes its CUs before the FFT's workgroups fill the device.
         if (!ensure_aux(p)) return RRC_EDEVICE;
         if (hipEventRecord(p->ev_fork, st) != hipSuccess) return RRC_EDEVICE;
+    }
+    rc = rrc_solve(p, stream, io->d_vred, io->d_gains_in, io->d_gains_ref, io->d_gains_out,
+                   io->d_vmodel, io->d_chisq, io->d_niter, io->d_status, io->d_work);
+    if (rc != RRC_OK) return rc;
+    if (mode == RRC_RUN_PIPELINED) {
         if (hipStreamWaitEvent(p->aux, p->ev_fork, 0) != hipSuccess) return RRC_EDEVICE;
         rc = rrc_fftcorr(p, p->aux, io->d_volt, io->d_gains_in, io->d_vunique, io->d_vauto,
                          io->d_work);
         if (rc != RRC_OK) return rc;
         if (hipEventRecord(p->ev_join, p->aux) != hipSuccess) return RRC_EDEVICE;
     }
-    rc = rrc_solve(p, stream, io->d_vred, io->d_gains_in, io->d_gains_ref, io->d_gains_out,
-                   io->d_vmodel, io->d_chisq, io->d_niter, io->d_status, io->d_work);
-    if (rc != RRC_OK) return rc;
     if (mode == RRC_RUN_SELFCAL) {
         rc = rrc_fftcorr(p, stream, io->d_volt, io->d_gains_out, io->d_vunique, io->d_vauto,
                          io->d_work);

@@ -29,6 +29,8 @@
 struct float2 { float x, y; };
 struct double2 { double x, y; };
 struct int2 { int x, y; };
+struct uint2 { unsigned x, y; };
+inline uint2 make_uint2(unsigned a, unsigned b) { return uint2{a, b}; }
 struct float4 { float x, y, z, w; };
 inline float2 make_float2(float a, float b) { return float2{a, b}; }
 inline double2 make_double2(double a, double b) { return double2{a, b}; }

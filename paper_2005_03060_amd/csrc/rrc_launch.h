@@ -42,10 +42,9 @@ struct SolveLaunch {
     Sel sel;
     int n_units;
     bool ci4;
-    bool lds;              // hot arrays in LDS
+    bool vcache;           // V^reduced copied into LDS beside the state
     bool exclusive;        // one workgroup per CU (at most as many units as CUs)
     size_t lds_bytes;      // dynamic LDS per workgroup
-    size_t slab_bytes;     // per-unit global scratch
     SolveOpts o;
     const void* vred;
     const float2* gains_in;
@@ -55,7 +54,6 @@ struct SolveLaunch {
     float* chisq;
     int* niter;
     int* status;
-    char* slab;            // workspace: [U][slab_bytes]
 };
 
 struct ChisqLaunch {
@@ -79,9 +77,7 @@ size_t xengine_lds_bytes(int halo, bool ci4);
 int xengine_antennas_per_block();
 int xengine_max_halo();
 int xengine_samples_per_step(bool ci4);
-size_t solve_hot_bytes(const Sel& s);
-size_t solve_slab_bytes(const Sel& s, bool lds);
-size_t solve_lds_bytes(const Sel& s, bool lds);
+size_t solve_lds_bytes(const Sel& s, bool vcache);
 hipError_t launch_solve(const SolveLaunch& L, hipStream_t st);
 hipError_t launch_chisq(const ChisqLaunch& L, hipStream_t st, bool adjoint);
 #endif

@@ -58,22 +58,24 @@ __host__ __device__ inline size_t align16(size_t v) { return (v + 15) & ~(size_t
 // Dynamic LDS of one unit's solve.
 // Parameters are held in FP64 throughout; in the FP32 phase they carry
 // FP32 values (exactly) and are read and updated in FP32.
+// With vcache the unit's V^reduced (8 bytes per pair, as stored: complex64
+// or the 4-bit path's int32 pairs) follows, read once from HBM instead of
+// at every residual pass.
 struct SolveLayout {
-    size_t rec, gd, vmd, bytes;
+    size_t rec, gd, vmd, vr, bytes;
 };
-__host__ __device__ inline SolveLayout solve_layout(const Sel& s) {
+__host__ __device__ inline SolveLayout solve_layout(const Sel& s, bool vcache) {
     SolveLayout L{};
     size_t o = 0;
     L.rec = o; o = align16(o + 16 * ((size_t)s.N + s.K));
     L.gd = o;  o = align16(o + 16 * (size_t)s.N);
     L.vmd = o; o = align16(o + 16 * (size_t)s.K);
+    L.vr = o;  if (vcache) o = align16(o + 8 * (size_t)s.P);
     L.bytes = o;
     return L;
 }
 
-size_t solve_hot_bytes(const Sel& s) { return solve_layout(s).bytes; }
-size_t solve_slab_bytes(const Sel&, bool) { return 0; }
-size_t solve_lds_bytes(const Sel& s, bool) { return solve_layout(s).bytes; }
+size_t solve_lds_bytes(const Sel& s, bool vcache) { return solve_layout(s, vcache).bytes; }
 
 // Workgroup shape: one antenna per work-item up to 1024 antennas, then
 // 512 work-items with 4 or 8 antennas each.
@@ -224,6 +226,11 @@ struct Solver {
     const void* vred;
     bool ci4;
     size_t vbase;
+    const uint2* vl;   // the unit's V^reduced in LDS (raw 8-byte entries), or null
+    // Only the one-antenna-per-work-item shapes (N <= 1024) take the LDS
+    // copy: the larger grids' pairs do not fit beside the state, and their
+    // register-bound kernels are left without the extra branches.
+    static constexpr bool kVcache = APT == 1;
     // own antenna rows
     int a[APT], ax_[APT], ay_[APT];
     bool live[APT];
@@ -239,17 +246,26 @@ struct Solver {
     // residual, inverse diagonal, preconditioned residual
     float xa[R1], xp[R1], ra[R1], rp[R1], di[R1], ua[R1], up[R1];
 
-    __device__ Solver(const Sel& sel, const TypeInfo* tyi, unsigned char* rd, unsigned char* lds,
-                      const void* vr, bool c4, size_t vb)
-        : s(sel), ty(tyi), red(rd), vred(vr), ci4(c4), vbase(vb) {
+    __device__ Solver(const SolveLaunch& L, const TypeInfo* tyi, unsigned char* rd, unsigned char* lds,
+                      int unit)
+        : s(L.sel), ty(tyi), red(rd), vred(L.vred), ci4(L.ci4), vbase((size_t)unit * L.sel.P) {
+        const bool vcache = L.vcache;
         N = s.N;
         K = s.K;
         n = s.n;
         tid = threadIdx.x;
-        const SolveLayout Ly = solve_layout(s);
+        const SolveLayout Ly = solve_layout(s, vcache);
         rec = reinterpret_cast<float4*>(lds + Ly.rec);
         gd = reinterpret_cast<double2*>(lds + Ly.gd);
         vmd = reinterpret_cast<double2*>(lds + Ly.vmd);
+        vl = nullptr;
+        if (kVcache && vcache) {
+            // one coalesced pass (published by a barrier before first use)
+            uint2* dst = reinterpret_cast<uint2*>(lds + Ly.vr);
+            const uint2* src = reinterpret_cast<const uint2*>(vred) + vbase;
+            for (int b = tid; b < s.P; b += NT) dst[b] = src[b];
+            vl = dst;
+        }
         own_t = tid < K;
         if (own_t) rec[N + tid].w = __int_as_float(ty[tid].dxy);
 #pragma unroll
@@ -279,12 +295,30 @@ struct Solver {
     __device__ int ax(int k) const { return ax_[k]; }
     __device__ int ay(int k) const { return ay_[k]; }
 
+    // V^reduced of the unit's pair b, from the LDS copy when there is one
+    __device__ float2 vr32(int b) const {
+        if (kVcache && vl) {
+            const uint2 q = vl[b];
+            return ci4 ? make_float2((float)(int)q.x, (float)(int)q.y)
+                       : make_float2(__int_as_float((int)q.x), __int_as_float((int)q.y));
+        }
+        return load_vred(vred, ci4, vbase + b);
+    }
+    __device__ double2 vr64(int b) const {
+        if (kVcache && vl) {
+            const uint2 q = vl[b];
+            return ci4 ? make_double2((double)(int)q.x, (double)(int)q.y)
+                       : make_double2(__int_as_float((int)q.x), __int_as_float((int)q.y));
+        }
+        return load_vred_d(vred, ci4, vbase + b);
+    }
+
     // ---- residual pass: the right-hand sides ra, rp (J^H r split into its
     // amplitude and phase parts, scaled to unit norm; the scale is
     // returned), the inverse diagonal di of J^H J, and the weights of the
     // records.  FP64 throughout.  Each work-item recomputes the residuals
     // of its antennas' pairs; type rows are block sums over the pairs (each
-    // pair counted at its first antenna), kChunk types at a time.
+    // pair counted at its first antenna), up to kChunk types at a time.
     __device__ double residuals() {
         double rA[R1], rP[R1];
         float dd[R1];
@@ -294,59 +328,75 @@ struct Solver {
             dd[k] = 0.f;
         }
         double nrm = 0.0;
+        constexpr int KC = KMAX < kChunk ? KMAX : kChunk;   // types per reduction
 #pragma unroll
-        for (int c0 = 0; c0 < KMAX; c0 += kChunk) {
+        for (int c0 = 0; c0 < KMAX; c0 += KC) {
             if (c0 >= K) break;
-            double tq[3 * kChunk + 1];
+            double tq[3 * KC + 1];
 #pragma unroll
-            for (int i = 0; i < 3 * kChunk; ++i) tq[i] = 0.0;
+            for (int i = 0; i < 3 * KC; ++i) tq[i] = 0.0;
 #pragma unroll
-            for (int tt = 0; tt < kChunk; ++tt) {
+            for (int tt = 0; tt < KC; ++tt) {
                 const int t = c0 + tt;
                 if (t >= K) break;
                 const double2 vt = vmd[t];
+                // e = 0: pair (a, a - d_t); e = 1: pair (a + d_t, a).  A
+                // missing pair reads entry 0 and is dropped by a select.
+                auto term = [&](int k, int e) {
+                    const bool ok = live[k] && (((e ? m2[k] : m1[k]) >> t) & 1u);
+                    const int i = ok ? (e ? a[k] + dxy(t) : a[k]) : 0;
+                    const int j = ok ? i - dxy(t) : 0;
+                    const int b = ok ? (e ? b2(t, k) : b1(t, k)) : 0;
+                    const double2 mm = dmul(dmulc(gd[i], gd[j]), vt);
+                    const double2 q = dmulc(dsub(vr64(b), mm), mm);
+                    const double wb = ok ? dabs2(mm) : 0.0;
+                    const double qx = ok ? q.x : 0.0, qy = ok ? q.y : 0.0;
+                    rA[k] += qx;
+                    rP[k] += e ? -qy : qy;
+                    dd[k] += (float)wb;
+                    if (!e) {
+                        tq[tt] += qx;
+                        tq[KC + tt] += qy;
+                        tq[2 * KC + tt] += wb;
+                    }
+                };
+                if constexpr (APT == 1) {
+                    // straight-line, so every term's loads are in flight together
+                    term(0, 0);
+                    term(0, 1);
+                } else {
+                    // several antennas per work-item: a rolled loop that skips
+                    // the missing pairs keeps registers and FP64 work down
 #pragma unroll
-                for (int k = 0; k < APT; ++k) {
-                    if (!live[k]) continue;
-                    // e = 0: pair (a, a - d_t); e = 1: pair (a + d_t, a)
+                    for (int k = 0; k < APT; ++k) {
+                        if (!live[k]) continue;
 #pragma unroll 1
-                    for (int e = 0; e < 2; ++e) {
-                        if (!(((e ? m2[k] : m1[k]) >> t) & 1u)) continue;
-                        const int i = e ? a[k] + dxy(t) : a[k];
-                        const int b = e ? b2(t, k) : b1(t, k);
-                        const double2 mm = dmul(dmulc(gd[i], gd[i - dxy(t)]), vt);
-                        const double2 q = dmulc(dsub(load_vred_d(vred, ci4, vbase + b), mm), mm);
-                        const double wb = dabs2(mm);
-                        rA[k] += q.x;
-                        rP[k] += e ? -q.y : q.y;
-                        dd[k] += (float)wb;
-                        if (!e) {
-                            tq[tt] += q.x;
-                            tq[kChunk + tt] += q.y;
-                            tq[2 * kChunk + tt] += wb;
+                        for (int e = 0; e < 2; ++e) {
+                            if (!(((e ? m2[k] : m1[k]) >> t) & 1u)) continue;
+                            term(k, e);
                         }
                     }
                 }
             }
             // the antenna rows' |rhs|^2 rides on the last chunk's reduction,
             // when their right-hand sides are complete
-            tq[3 * kChunk] = 0.0;
-            if (c0 + kChunk >= K) {
+            tq[3 * KC] = 0.0;
+            if (c0 + KC >= K) {
 #pragma unroll
                 for (int k = 0; k < APT; ++k)
-                    if (live[k]) tq[3 * kChunk] += rA[k] * rA[k] + rP[k] * rP[k];
+                    if (live[k]) tq[3 * KC] += rA[k] * rA[k] + rP[k] * rP[k];
             }
-            block_sum<NT, 3 * kChunk + 1>(tq, red);
+            block_sum<NT, 3 * KC + 1>(tq, red);
 #pragma unroll
-            for (int tt = 0; tt < kChunk; ++tt) {
-                if (c0 + tt < K) nrm += tq[tt] * tq[tt] + tq[kChunk + tt] * tq[kChunk + tt];
+            for (int tt = 0; tt < KC; ++tt) {
+                if (c0 + tt < K) nrm += tq[tt] * tq[tt] + tq[KC + tt] * tq[KC + tt];
                 if (own_t && tid == c0 + tt) {
                     rA[APT] = tq[tt];
-                    rP[APT] = tq[kChunk + tt];
-                    dd[APT] = (float)tq[2 * kChunk + tt];
+                    rP[APT] = tq[KC + tt];
+                    dd[APT] = (float)tq[2 * KC + tt];
                 }
             }
-            if (c0 + kChunk >= K) nrm += tq[3 * kChunk];
+            if (c0 + KC >= K) nrm += tq[3 * KC];
         }
         const double scale = nrm > 0.0 ? sqrt(nrm) : 1.0;
         const double inv = 1.0 / scale;
@@ -576,7 +626,7 @@ struct Solver {
                 if (!live[k] || !((m1[k] >> t) & 1u)) continue;
                 const int b = b1(t, k);
                 const float2 gg = cmulc(to_f(gd[a[k]]), to_f(gd[a[k] - dxy(t)]));
-                const float2 q = cmulc(load_vred(vred, ci4, vbase + b), gg);
+                const float2 q = cmulc(vr32(b), gg);
                 const float inv = 1.0f / cabs2(gg);
                 sv[t] += q.x * inv;
                 sv[KMAX + t] += q.y * inv;
@@ -609,7 +659,7 @@ struct Solver {
                 if (!live[k]) continue;
                 if ((m1[k] >> t) & 1u) {
                     const int b = b1(t, k);
-                    const float lv = 0.5f * logf(fmaxf(cabs2(load_vred(vred, ci4, vbase + b)), 1e-30f));
+                    const float lv = 0.5f * logf(fmaxf(cabs2(vr32(b)), 1e-30f));
                     rA[k] += lv;
                     dd[k] += 1.f;
                     tq[t] += lv;
@@ -617,7 +667,7 @@ struct Solver {
                 }
                 if ((m2[k] >> t) & 1u) {
                     const int b = b2(t, k);
-                    rA[k] += 0.5f * logf(fmaxf(cabs2(load_vred(vred, ci4, vbase + b)), 1e-30f));
+                    rA[k] += 0.5f * logf(fmaxf(cabs2(vr32(b)), 1e-30f));
                     dd[k] += 1.f;
                 }
             }
@@ -650,8 +700,8 @@ struct Solver {
             if (ty[t].dx == 1 && ty[t].dy == 0) off10 = ty[t].off;
             if (ty[t].dx == 0 && ty[t].dy == 1) off01 = ty[t].off;
         }
-        const float2 v10 = load_vred(vred, ci4, vbase + off10);
-        const float2 v01 = load_vred(vred, ci4, vbase + off01);
+        const float2 v10 = vr32(off10);
+        const float2 v01 = vr32(off01);
         const float psi10 = atan2f(v10.y, v10.x), psi01 = atan2f(v01.y, v01.x);
         const float2 r10 = make_float2(cosf(psi10), -sinf(psi10));
         const float2 r01 = make_float2(cosf(psi01), -sinf(psi01));
@@ -661,10 +711,10 @@ struct Solver {
             const int x = ax(k), y = ay(k);
             float inc = 0.f;
             if (y == 0 && x >= 1) {           // pair ((x,0), (x-1,0))
-                const float2 v = cmul(load_vred(vred, ci4, vbase + off10 + (x - 1)), r10);
+                const float2 v = cmul(vr32(off10 + (x - 1)), r10);
                 inc = atan2f(v.y, v.x);
             } else if (y >= 1) {              // pair ((x,y), (x,y-1))
-                const float2 v = cmul(load_vred(vred, ci4, vbase + off01 + (y - 1) * n + x), r01);
+                const float2 v = cmul(vr32(off01 + (y - 1) * n + x), r01);
                 inc = atan2f(v.y, v.x);
             }
             rec[a[k]].w = inc;
@@ -740,8 +790,9 @@ __device__ void solve_unit(const SolveLaunch& L, Shared<NT / 64>& sh, unsigned c
         }
     }
     __syncthreads();
-    Solver<NT, APT, KMAX> S(s, sh.ty, sh.red, lds, L.vred, L.ci4, (size_t)unit * s.P);
+    Solver<NT, APT, KMAX> S(L, sh.ty, sh.red, lds, unit);
     const int N = S.N, K = S.K, tid = S.tid;
+    __syncthreads();     // the LDS copy of V^reduced
 
     // ---- start: caller's gains, or the logcal solve (the first CG solve
     // of the loop below)
@@ -885,7 +936,7 @@ __device__ void solve_unit(const SolveLaunch& L, Shared<NT / 64>& sh, unsigned c
             if (!S.live[k] || !((S.m1[k] >> t) & 1u)) continue;
             const int b = S.b1(t, k);
             const double2 mm = dmul(dmulc(S.gd[S.a[k]], S.gd[S.a[k] - S.dxy(t)]), S.vmd[t]);
-            c1[0] += dabs2(dsub(load_vred_d(L.vred, L.ci4, S.vbase + b), mm));
+            c1[0] += dabs2(dsub(S.vr64(b), mm));
         }
     }
     block_sum<NT, 1>(c1, sh.red);

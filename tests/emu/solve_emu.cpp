@@ -24,7 +24,7 @@ static bool run_shape(const SolveLaunch& L, unsigned char* ldsbuf, int unit) {
 extern "C" int rrc_emu_solve(int n, const int* types_xy, int K, int U, int ci4, const void* vred,
                              const void* gains_in, const void* gains_ref, const int* iopts,
                              const float* fopts, void* gains_out, void* vmodel, float* chisq,
-                             int* niter, int* status, int threads, int order) {
+                             int* niter, int* status, int threads, int order, int vcache) {
     rrc_emu::group().order = order;
     rrc_emu::group().seed = 12345u;
     Sel s{};
@@ -44,10 +44,9 @@ extern "C" int rrc_emu_solve(int n, const int* types_xy, int K, int U, int ci4, 
     L.sel = s;
     L.n_units = U;
     L.ci4 = ci4 != 0;
-    L.lds = true;
+    L.vcache = vcache != 0;
     L.exclusive = false;
-    L.lds_bytes = solve_lds_bytes(s, true);
-    L.slab_bytes = 0;
+    L.lds_bytes = solve_lds_bytes(s, vcache);
     L.o = {iopts[0], iopts[1], iopts[2], iopts[3], iopts[4], fopts[0], fopts[1]};
     L.vred = vred;
     L.gains_in = reinterpret_cast<const float2*>(gains_in);
@@ -58,7 +57,6 @@ extern "C" int rrc_emu_solve(int n, const int* types_xy, int K, int U, int ci4, 
     L.niter = niter;
     L.status = status;
     std::vector<unsigned char> ldsbuf(L.lds_bytes + 256, 0xCD);
-    L.slab = nullptr;
     for (int u = 0; u < U; ++u) {
         bool ok;
         // the same workgroup shapes as the GPU launch; `threads` = 0 picks

@@ -338,6 +338,26 @@ def test_run_modes_consistent(rrc):
         assert rel_l2(b["vunique"][u].cpu().numpy(), vref) <= TOL_VUNIQUE
 
 
+@pytest.mark.parametrize("dtype", ["c64", "ci4"])
+def test_run_matches_separate_stages_bitwise(rrc, dtype):
+    # the whole path in one call gives the same bits as the stages called
+    # one at a time (X-engine with several time chunks, solve from its output)
+    n, U, T = 16, 3, 1024
+    if dtype == "ci4":
+        b, _, _, _ = make_ci4_units(n, U, T)
+        vd = torch.from_numpy(b).to(DEV)
+    else:
+        v, _ = make_units(n, U, T)
+        vd = torch.from_numpy(v).to(DEV)
+    plan, _ = _plan(rrc, n, U, T, dtype=dtype)
+    a = plan.run(vd, mode="selfcal")
+    vr = plan.xengine(vd)
+    assert torch.equal(a["vred"], vr)
+    s = plan.solve(vr)
+    for k in ("gains", "vmodel", "chisq", "niter", "status"):
+        assert torch.equal(a[k], s[k]), k
+
+
 def test_repeat_is_bitwise_deterministic(rrc):
     n, U, T = 16, 4, 512
     v, _ = make_units(n, U, T)

@@ -41,7 +41,7 @@ def emu():
 
 
 def emu_solve(lib, vred, n, types, init=0, degen=0, gin=None, gref=None, threads=0, max_gn=12, fp64=1,
-              max_cg=400, cg_tol=1e-2, tol32=1e-5, order=0):
+              max_cg=400, cg_tol=1e-2, tol32=1e-5, order=0, vcache=1):
     U = vred.shape[0]
     N, K = n * n, len(types)
     txy = (C.c_int * (2 * K))(*[v for t in types for v in t])
@@ -59,7 +59,7 @@ def emu_solve(lib, vred, n, types, init=0, degen=0, gin=None, gref=None, threads
 
     rc = lib.rrc_emu_solve(n, txy, K, U, 0, p(vr), p(gin), p(gref), io, fo, p(go), p(vm),
                            ch.ctypes.data_as(C.POINTER(C.c_float)), ni.ctypes.data_as(C.POINTER(C.c_int)),
-                           st.ctypes.data_as(C.POINTER(C.c_int)), threads, order)
+                           st.ctypes.data_as(C.POINTER(C.c_int)), threads, order, vcache)
     assert rc == 0, "non-uniform barrier" if rc == -2 else rc
     return go, vm, ch, ni, st
 
@@ -75,10 +75,10 @@ def _vred(n, T, seed_wid=90, snr=10.0):
 
 # workgroup shapes: 256 (one wave per SIMD, direct reduction), 64 with four
 # antennas per work-item, 1024 (two-level reduction, most work-items idle)
-@pytest.mark.parametrize("n,threads", [(8, 0), (12, 64), (8, 1024)])
-def test_emulated_solver_matches_oracle(emu, n, threads):
+@pytest.mark.parametrize("n,threads,vcache", [(8, 0, 1), (12, 64, 1), (8, 1024, 1), (8, 0, 0), (12, 64, 0)])
+def test_emulated_solver_matches_oracle(emu, n, threads, vcache):
     vr, _, pos, types, pairs, tix = _vred(n, 256)
-    go, vm, ch, ni, st = emu_solve(emu, vr, n, types, threads=threads)
+    go, vm, ch, ni, st = emu_solve(emu, vr, n, types, threads=threads, vcache=vcache)
     ref = OR.calibrate(vr[0].astype(np.complex128), pos, types, pairs, tix)
     assert st[0] == 0
     assert np.max(np.abs(go[0] - ref["g"]) / np.abs(ref["g"])) <= TOL_GAINS
