@@ -167,6 +167,11 @@ inline T row_sum(T v) {
     for (int o = 1; o <= 8; o <<= 1) v += __shfl_xor(v, o, 64);
     return v;
 }
+template <typename T>
+inline T oct_sum(T v) {
+    for (int o = 1; o <= 4; o <<= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
 #else
 template <int CTRL>
 __device__ __forceinline__ int dpp_i(int v) {
@@ -231,6 +236,20 @@ __device__ __forceinline__ double row_sum(double v) {
     v += dpp_d<0x4E>(v);
     v += dpp_d<0x124>(v);
     v += dpp_d<0x128>(v);
+    return v;
+}
+// Sum over each group of 8 lanes: the quad sums, then row_half_mirror
+// (lane i of the group reads lane 7 - i, which lies in the other quad).
+__device__ __forceinline__ float oct_sum(float v) {
+    v += dpp_f<0xB1>(v);
+    v += dpp_f<0x4E>(v);
+    v += dpp_f<0x141>(v);   // row_half_mirror
+    return v;
+}
+__device__ __forceinline__ double oct_sum(double v) {
+    v += dpp_d<0xB1>(v);
+    v += dpp_d<0x4E>(v);
+    v += dpp_d<0x141>(v);
     return v;
 }
 

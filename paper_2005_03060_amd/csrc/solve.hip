@@ -96,8 +96,9 @@ struct TypeInfo {
 // block_sum adds NV values over the workgroup and returns the totals to
 // every work-item, in a fixed order (deterministic), with few
 // instructions per wave: DPP sums over Q lanes; the P = NT / Q partials of
-// each value go to LDS laid out [value][partial]; per value, 16 lanes add
-// E partials each and a DPP row sum; the totals go back through LDS.  Two
+// each value go to LDS laid out [value][partial]; per value, 16 (or 8)
+// lanes add a share of them each and a DPP sum over those lanes; the
+// totals go back through LDS.  Two
 // barriers.  Consecutive calls may reuse the buffers: a work-item writes
 // the next call's partials only after the previous call's second barrier,
 // which every reader of its partials has passed, and writes totals only
@@ -108,15 +109,18 @@ struct RedGeom {
     static constexpr int Q = sizeof(T) == 4 ? (NT <= 256 ? 1 : (NT <= 512 ? 4 : 16))
                                             : (NT <= 256 ? 4 : 64);
     static constexpr int P = NT / Q;
-    static constexpr int E = (P + 15) / 16;   // partials per lane in the second stage
+    // row stride of the partials in LDS: 64 bytes of padding, so that the
+    // second stage's lane groups (32 consecutive words each) start 16 banks
+    // apart and a wave's reads take the minimum number of passes
+    static constexpr int PS = P + 64 / (int)sizeof(T);
 };
 constexpr int kRedNF = 2 * kMaxTypes + 6;     // floats per reduction (max)
 constexpr int kRedND = 3 * kChunk + 1;        // doubles per reduction (max)
 
 template <int NT>
 constexpr int red_bytes() {
-    constexpr int f = kRedNF * RedGeom<NT, float>::P * 4 + kRedNF * 4;
-    constexpr int d = kRedND * RedGeom<NT, double>::P * 8 + kRedND * 8;
+    constexpr int f = kRedNF * RedGeom<NT, float>::PS * 4 + kRedNF * 4;
+    constexpr int d = kRedND * RedGeom<NT, double>::PS * 8 + kRedND * 8;
     return f > d ? f : d;
 }
 
@@ -128,12 +132,14 @@ struct Shared {
     double bcast[8];
 };
 
+// Returns the totals in LDS (valid until the next reduction's first
+// barrier); block_sum copies them to every work-item.
 template <int NT, int NV, typename T>
-__device__ __forceinline__ void block_sum(T (&v)[NV], unsigned char* red) {
+__device__ __forceinline__ const T* block_sum_lds(T (&v)[NV], unsigned char* red) {
     using G = RedGeom<NT, T>;
     static_assert(NV <= (sizeof(T) == 4 ? kRedNF : kRedND), "block_sum size");
     T* xbuf = reinterpret_cast<T*>(red);
-    T* xtot = xbuf + NV * G::P;
+    T* xtot = xbuf + NV * G::PS;
     const int tid = threadIdx.x;
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
@@ -144,37 +150,54 @@ __device__ __forceinline__ void block_sum(T (&v)[NV], unsigned char* red) {
     constexpr int writer = G::Q == 64 ? 63 : 0;     // lane of each Q-group holding its sum
     if (tid % G::Q == writer) {
 #pragma unroll
-        for (int i = 0; i < NV; ++i) xbuf[i * G::P + tid / G::Q] = v[i];
+        for (int i = 0; i < NV; ++i) xbuf[i * G::PS + tid / G::Q] = v[i];
     }
     __syncthreads();
-    for (int i0 = 0; i0 < NV; i0 += NT / 16) {
-        const int i = i0 + tid / 16;
-        const int j = tid % 16;
+    // second stage: LPV lanes per value, so that all values fit one round
+    // when 16 lanes each would need two.  Lane j of a value's group takes
+    // the 16-byte slots j, j + LPV, ...: the group reads consecutive words.
+    constexpr int LPV = (NV > NT / 16 && NV <= NT / 8) ? 8 : 16;
+    for (int i0 = 0; i0 < NV; i0 += NT / LPV) {
+        const int i = i0 + tid / LPV;
+        const int j = tid % LPV;
         T acc = 0;
         if (i < NV) {
-            const T* src = xbuf + i * G::P + j * G::E;
-            if constexpr (sizeof(T) == 4 && G::E % 4 == 0) {
+            const T* src = xbuf + i * G::PS;
+            if constexpr (sizeof(T) == 4 && G::P % (4 * LPV) == 0) {
+                // four running sums (one per component), so the chain of
+                // dependent adds is short
+                constexpr int E4 = G::P / (4 * LPV);
                 const float4* s4 = reinterpret_cast<const float4*>(src);
+                float4 a4 = s4[j];
 #pragma unroll
-                for (int e = 0; e < G::E / 4; ++e) {
-                    const float4 q = s4[e];
-                    acc += q.x;
-                    acc += q.y;
-                    acc += q.z;
-                    acc += q.w;
+                for (int e = 1; e < E4; ++e) {
+                    const float4 q = s4[j + e * LPV];
+                    a4.x += q.x;
+                    a4.y += q.y;
+                    a4.z += q.z;
+                    a4.w += q.w;
                 }
+                acc = (a4.x + a4.y) + (a4.z + a4.w);
             } else {
+                constexpr int E = (G::P + LPV - 1) / LPV;
 #pragma unroll
-                for (int e = 0; e < G::E; ++e)
-                    if (j * G::E + e < G::P) acc += src[e];
+                for (int e = 0; e < E; ++e)
+                    if (j + e * LPV < G::P) acc += src[j + e * LPV];
             }
         }
-        acc = row_sum(acc);
+        if constexpr (LPV == 16) acc = row_sum(acc);
+        else acc = oct_sum(acc);
         if (i < NV && j == 0) xtot[i] = acc;
     }
     __syncthreads();
+    return xtot;
+}
+
+template <int NT, int NV, typename T>
+__device__ __forceinline__ void block_sum(T (&v)[NV], unsigned char* red) {
+    const T* tot = block_sum_lds<NT, NV>(v, red);
 #pragma unroll
-    for (int i = 0; i < NV; ++i) v[i] = xtot[i];
+    for (int i = 0; i < NV; ++i) v[i] = tot[i];
 }
 
 __device__ __forceinline__ float2 load_vred(const void* v, bool ci4, size_t idx) {
@@ -505,16 +528,14 @@ struct Solver {
             cs[2 * KMAX + 2] += ua[k] * wa[k];
             cs[2 * KMAX + 3] += up[k] * wp[k];
         }
-        block_sum<NT, NV>(cs, red);
+        // every work-item needs the six dots; only the type-row owners
+        // need their two type sums
+        const float* tot = block_sum_lds<NT, NV>(cs, red);
 #pragma unroll
-        for (int i = 0; i < 6; ++i) dots[i] = cs[2 * KMAX + i];
-#pragma unroll
-        for (int t = 0; t < KMAX; ++t) {
-            if (t >= K) break;
-            if (own_t && t == tid) {
-                wa[APT] = cs[t];
-                wp[APT] = cs[KMAX + t];
-            }
+        for (int i = 0; i < 6; ++i) dots[i] = tot[2 * KMAX + i];
+        if (own_t) {
+            wa[APT] = tot[tid];
+            wp[APT] = tot[KMAX + tid];
         }
     }
 
@@ -1010,7 +1031,7 @@ constexpr int kCThreads = 256;
 template <int APT, bool ADJ>
 __global__ __launch_bounds__(kCThreads) void k_chisq(ChisqLaunch L) {
     __shared__ Sel ssel;
-    __shared__ __align__(16) unsigned char sred[(RedGeom<kCThreads, double>::P + 1) * 8];
+    __shared__ __align__(16) unsigned char sred[(RedGeom<kCThreads, double>::PS + 1) * 8];
     copy_sel(L.sel, ssel);
     const Sel& s = ssel;
     const int unit = blockIdx.x;
