@@ -94,7 +94,8 @@ typedef struct {
     int32_t max_gn;      /* Gauss-Newton steps of the main stage (>= 1)           */
     int32_t fp64_steps;  /* refinement steps after the main stage (>= 0)          */
     int32_t max_cg;      /* CG iterations per normal-equation solve (>= 1)        */
-    float   cg_tol;      /* CG stops at ||r|| <= cg_tol ||b||                     */
+    float   cg_tol;      /* CG stops at ||r|| <= cg_tol ||b|| (sqrt(cg_tol) in    */
+                         /* the refinement steps)                                 */
     float   tol32;       /* main stage stops once the rms log-step is below this  */
 } rrc_solver_opts;
 
@@ -115,8 +116,9 @@ typedef struct {
 /* Default solver options (FIRSTCAL, REFANT, at most 12 main steps, tol32
  * 1e-5, 1 refinement step, 400 CG iterations, cg_tol 1e-2).  Every step
  * takes its residual and right-hand side in FP64 and solves the normal
- * equations in FP32 (iterative refinement), so the error after the last
- * step is about cg_tol times the previous step's size. */
+ * equations in FP32 (iterative refinement), so the error after a main step
+ * is about cg_tol times the step's size, and a refinement step (CG to
+ * sqrt(cg_tol)) divides what is left by about 1/sqrt(cg_tol). */
 void rrc_default_opts(rrc_solver_opts* opts);
 
 /* Subset redundant-calibration selection (Sec. 5.1, Sec. 5.4

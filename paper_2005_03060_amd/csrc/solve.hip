@@ -840,7 +840,9 @@ __device__ void solve_unit(const SolveLaunch& L, Shared<NT / 64>& sh, unsigned c
             xscale = S.residuals();
             S.publish_weights(false);
         }
-        const int it = S.pcg(op.max_cg, start ? 1e-3f : op.cg_tol);
+        // refinement steps start within about cg_tol of the solution, so
+        // their normal equations need only sqrt(cg_tol)
+        const int it = S.pcg(op.max_cg, start ? 1e-3f : (hi ? sqrtf(op.cg_tol) : op.cg_tol));
         if (start) {
             S.firstcal_finish();
             S.group_mean();
