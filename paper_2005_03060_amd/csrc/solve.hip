@@ -335,6 +335,24 @@ struct Solver {
         }
         return load_vred_d(vred, ci4, vbase + b);
     }
+    // the same with the source fixed at compile time (VM bit 0: 4-bit sums,
+    // bit 1: the LDS copy), for loops that must stay free of branches
+    template <int VM>
+    __device__ double2 vr64v(int b) const {
+        if constexpr ((VM & 2) != 0) {
+            const uint2 q = vl[b];
+            if constexpr ((VM & 1) != 0) return make_double2((double)(int)q.x, (double)(int)q.y);
+            else return make_double2(__int_as_float((int)q.x), __int_as_float((int)q.y));
+        } else {
+            if constexpr ((VM & 1) != 0) {
+                const int2 q = reinterpret_cast<const int2*>(vred)[vbase + b];
+                return make_double2((double)q.x, (double)q.y);
+            } else {
+                const float2 f = reinterpret_cast<const float2*>(vred)[vbase + b];
+                return make_double2(f.x, f.y);
+            }
+        }
+    }
 
     // ---- residual pass: the right-hand sides ra, rp (J^H r split into its
     // amplitude and phase parts, scaled to unit norm; the scale is
@@ -343,6 +361,15 @@ struct Solver {
     // of its antennas' pairs; type rows are block sums over the pairs (each
     // pair counted at its first antenna), up to kChunk types at a time.
     __device__ double residuals() {
+        // one straight-line instance per V^reduced source
+        if constexpr (kVcache) {
+            if (vl) return ci4 ? residuals_v<3>() : residuals_v<2>();
+        }
+        return ci4 ? residuals_v<1>() : residuals_v<0>();
+    }
+
+    template <int VM>
+    __device__ double residuals_v() {
         double rA[R1], rP[R1];
         float dd[R1];
 #pragma unroll
@@ -371,7 +398,7 @@ struct Solver {
                     const int j = ok ? i - dxy(t) : 0;
                     const int b = ok ? (e ? b2(t, k) : b1(t, k)) : 0;
                     const double2 mm = dmul(dmulc(gd[i], gd[j]), vt);
-                    const double2 q = dmulc(dsub(vr64(b), mm), mm);
+                    const double2 q = dmulc(dsub(vr64v<VM>(b), mm), mm);
                     const double wb = ok ? dabs2(mm) : 0.0;
                     const double qx = ok ? q.x : 0.0, qy = ok ? q.y : 0.0;
                     rA[k] += qx;
