@@ -475,8 +475,8 @@ struct Solver {
     // w = H u on the own rows of both systems, u read from the records, and
     // the dot products of one CG iteration, all in one block reduction:
     // the type rows' w are sums of their pairs' terms (each pair counted at
-    // its first antenna); dots = {(r,u)_a, (r,u)_p, (u,w)_a, (u,w)_p,
-    // (r,r)_a, (r,r)_p}.  The type rows' part of (u,w), sum_t u_t w_t, is
+    // its first antenna); dots = {(r,u)_a, (r,u)_p, (u,w)_a, (u,w)_p}.
+    // The type rows' part of (u,w), sum_t u_t w_t, is
     // summed term by term alongside (u_t times each pair term), so nothing
     // is read from the records after the reduction.
     // Pair weights |g_i|^2 |g_j|^2 |V_t|^2 and record indices of the own
@@ -500,8 +500,8 @@ struct Solver {
         }
     }
 
-    __device__ void matvec_dots(float (&wa)[R1], float (&wp)[R1], float (&dots)[6]) {
-        constexpr int NV = 2 * KMAX + 6;
+    __device__ void matvec_dots(float (&wa)[R1], float (&wp)[R1], float (&dots)[4]) {
+        constexpr int NV = 2 * KMAX + 4;
         float cs[NV];
 #pragma unroll
         for (int i = 0; i < NV; ++i) cs[i] = 0.f;
@@ -547,19 +547,17 @@ struct Solver {
         for (int k = 0; k < R1; ++k) {
             cs[2 * KMAX + 0] += ra[k] * ua[k];
             cs[2 * KMAX + 1] += rp[k] * up[k];
-            cs[2 * KMAX + 4] += ra[k] * ra[k];
-            cs[2 * KMAX + 5] += rp[k] * rp[k];
         }
 #pragma unroll
         for (int k = 0; k < APT; ++k) {
             cs[2 * KMAX + 2] += ua[k] * wa[k];
             cs[2 * KMAX + 3] += up[k] * wp[k];
         }
-        // every work-item needs the six dots; only the type-row owners
+        // every work-item needs the four dots; only the type-row owners
         // need their two type sums
         const float* tot = block_sum_lds<NT, NV>(cs, red);
 #pragma unroll
-        for (int i = 0; i < 6; ++i) dots[i] = tot[2 * KMAX + i];
+        for (int i = 0; i < 4; ++i) dots[i] = tot[2 * KMAX + i];
         if (own_t) {
             wa[APT] = tot[tid];
             wp[APT] = tot[KMAX + tid];
@@ -584,11 +582,12 @@ struct Solver {
     // records.  The Chronopoulos-Gear arrangement: the recurrences
     // p = u + beta p and s = w + beta s (s = H p) need one matrix-vector
     // product (w = H u, u the preconditioned residual) and one reduction
-    // per iteration.  Each system stops when its residual norm has fallen
-    // by `tol`.  Returns the iterations, or -1 if a right-hand side is not
+    // per iteration.  Each system stops when its residual's preconditioned
+    // norm (r, D^-1 r), a dot the iteration needs anyway, has fallen by
+    // `tol`.  Returns the iterations, or -1 if a right-hand side is not
     // finite.
     __device__ int pcg(int max_cg, float tol) {
-        float pa[R1], pp[R1], sa[R1], sp[R1], wa[R1], wp[R1], dots[6];
+        float pa[R1], pp[R1], sa[R1], sp[R1], wa[R1], wp[R1], dots[4];
 #pragma unroll
         for (int k = 0; k < R1; ++k) {
             xa[k] = xp[k] = 0.f;
@@ -599,9 +598,9 @@ struct Solver {
         __syncthreads();
         load_pair_weights();
         matvec_dots(wa, wp, dots);
-        if (!(dots[4] == dots[4]) || !(dots[5] == dots[5]) || isinf(dots[4]) || isinf(dots[5])) return -1;
-        const float stopa = tol * tol * dots[4], stopp = tol * tol * dots[5];
-        bool done_a = !(dots[4] > 0.f), done_p = !(dots[5] > 0.f);
+        if (!(dots[0] == dots[0]) || !(dots[1] == dots[1]) || isinf(dots[0]) || isinf(dots[1])) return -1;
+        const float stopa = tol * tol * dots[0], stopp = tol * tol * dots[1];
+        bool done_a = !(dots[0] > 0.f), done_p = !(dots[1] > 0.f);
         float ga = dots[0], gp = dots[1];
         float ala = (!done_a && dots[2] > 0.f) ? ga / dots[2] : 0.f;
         float alp = (!done_p && dots[3] > 0.f) ? gp / dots[3] : 0.f;
@@ -626,8 +625,8 @@ struct Solver {
             write_u();
             __syncthreads();
             matvec_dots(wa, wp, dots);
-            done_a = done_a || !(dots[4] > stopa);
-            done_p = done_p || !(dots[5] > stopp);
+            done_a = done_a || !(dots[0] > stopa);
+            done_p = done_p || !(dots[1] > stopp);
             // scalars by hardware reciprocal (about 1 ulp): they only steer CG
             const float ba = ga > 0.f ? dots[0] * fast_rcp(ga) : 0.f;
             const float bp = gp > 0.f ? dots[1] * fast_rcp(gp) : 0.f;
