@@ -32,6 +32,7 @@ struct int2 { int x, y; };
 struct uint2 { unsigned x, y; };
 inline uint2 make_uint2(unsigned a, unsigned b) { return uint2{a, b}; }
 struct float4 { float x, y, z, w; };
+inline float4 make_float4(float a, float b, float c, float d) { return float4{a, b, c, d}; }
 inline float2 make_float2(float a, float b) { return float2{a, b}; }
 inline double2 make_double2(double a, double b) { return double2{a, b}; }
 inline int2 make_int2(int a, int b) { return int2{a, b}; }

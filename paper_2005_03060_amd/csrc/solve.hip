@@ -509,18 +509,31 @@ struct Solver {
         for (int k = 0; k < R1; ++k) wa[k] = wp[k] = 0.f;
         // Branch-free: a missing pair reads record 0 with weight 0; with
         // register weights the types past K also run, on the last type's
-        // record with weight 0, so the loop is straight-line code.
+        // record with weight 0, so the loop is straight-line code, and all
+        // the (u_amp, u_phase) reads are issued before any product.
+        float2 qt[PW ? KMAX : 1], qj[PW ? KMAX : 1], qi[PW ? KMAX : 1];
+        if constexpr (PW) {
+            const float2* r2 = reinterpret_cast<const float2*>(rec);   // stride: 2 float2
+#pragma unroll
+            for (int t = 0; t < KMAX; ++t) {
+                qt[t] = r2[2 * (N + (t >= K ? K - 1 : t))];
+                qj[t] = r2[2 * nb1[t]];
+                qi[t] = r2[2 * nb2[t]];
+            }
+        }
 #pragma unroll
         for (int t = 0; t < KMAX; ++t) {
             if (!PW && t >= K) break;
-            const float4 rt = rec[N + (PW && t >= K ? K - 1 : t)];   // .w: d_t
+            float4 rt;
+            if constexpr (PW) rt = make_float4(qt[t].x, qt[t].y, 0.f, 0.f);
+            else rt = rec[N + t];   // .z: |V_t|^2, .w: d_t
 #pragma unroll
             for (int k = 0; k < APT; ++k) {
                 float4 rj, ri;
                 float w1, w2;
                 if constexpr (PW) {
-                    rj = rec[nb1[t]];
-                    ri = rec[nb2[t]];
+                    rj = make_float4(qj[t].x, qj[t].y, 0.f, 0.f);
+                    ri = make_float4(qi[t].x, qi[t].y, 0.f, 0.f);
                     w1 = pw1[t];
                     w2 = pw2[t];
                 } else {
