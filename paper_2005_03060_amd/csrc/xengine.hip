@@ -58,9 +58,9 @@ __device__ __forceinline__ int dot8(uint32_t a, uint32_t b, int c) {
     return __builtin_amdgcn_sdot8((int)a, (int)b, c, false);
 }
 
-// Samples staged per step: 16 complex64 rows or 64 rows of 4-bit bytes.
+// Samples staged per step: 8 complex64 rows or 64 rows of 4-bit bytes.
 template <bool CI4>
-constexpr int xeng_samples() { return CI4 ? 64 : 16; }
+constexpr int xeng_samples() { return CI4 ? 64 : 8; }
 
 // Two complex64 values as one 16-byte load (a native vector type, so arrays
 // of it stay in registers).
