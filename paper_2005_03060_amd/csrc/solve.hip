@@ -269,7 +269,7 @@ struct Solver {
     // residual, inverse diagonal, preconditioned residual
     float xa[R1], xp[R1], ra[R1], rp[R1], di[R1], ua[R1], up[R1];
 
-    __device__ Solver(const SolveLaunch& L, const TypeInfo* tyi, unsigned char* rd, unsigned char* lds,
+    __device__ __forceinline__ Solver(const SolveLaunch& L, const TypeInfo* tyi, unsigned char* rd, unsigned char* lds,
                       int unit)
         : s(L.sel), ty(tyi), red(rd), vred(L.vred), ci4(L.ci4), vbase((size_t)unit * L.sel.P) {
         const bool vcache = L.vcache;
@@ -310,16 +310,16 @@ struct Solver {
         }
     }
 
-    __device__ bool mine(int k) const { return k < APT ? live[k] : own_t; }
-    __device__ int dxy(int t) const { return ty[t].dxy; }
+    __device__ __forceinline__ bool mine(int k) const { return k < APT ? live[k] : own_t; }
+    __device__ __forceinline__ int dxy(int t) const { return ty[t].dxy; }
     // pair (a, a - d_t) / (a + d_t, a) of own antenna k
-    __device__ int b1(int t, int k) const { return ty[t].c1 + ay_[k] * ty[t].w + ax_[k]; }
-    __device__ int b2(int t, int k) const { return ty[t].c2 + ay_[k] * ty[t].w + ax_[k]; }
-    __device__ int ax(int k) const { return ax_[k]; }
-    __device__ int ay(int k) const { return ay_[k]; }
+    __device__ __forceinline__ int b1(int t, int k) const { return ty[t].c1 + ay_[k] * ty[t].w + ax_[k]; }
+    __device__ __forceinline__ int b2(int t, int k) const { return ty[t].c2 + ay_[k] * ty[t].w + ax_[k]; }
+    __device__ __forceinline__ int ax(int k) const { return ax_[k]; }
+    __device__ __forceinline__ int ay(int k) const { return ay_[k]; }
 
     // V^reduced of the unit's pair b, from the LDS copy when there is one
-    __device__ float2 vr32(int b) const {
+    __device__ __forceinline__ float2 vr32(int b) const {
         if (kVcache && vl) {
             const uint2 q = vl[b];
             return ci4 ? make_float2((float)(int)q.x, (float)(int)q.y)
@@ -327,7 +327,7 @@ struct Solver {
         }
         return load_vred(vred, ci4, vbase + b);
     }
-    __device__ double2 vr64(int b) const {
+    __device__ __forceinline__ double2 vr64(int b) const {
         if (kVcache && vl) {
             const uint2 q = vl[b];
             return ci4 ? make_double2((double)(int)q.x, (double)(int)q.y)
@@ -338,7 +338,7 @@ struct Solver {
     // the same with the source fixed at compile time (VM bit 0: 4-bit sums,
     // bit 1: the LDS copy), for loops that must stay free of branches
     template <int VM>
-    __device__ double2 vr64v(int b) const {
+    __device__ __forceinline__ double2 vr64v(int b) const {
         if constexpr ((VM & 2) != 0) {
             const uint2 q = vl[b];
             if constexpr ((VM & 1) != 0) return make_double2((double)(int)q.x, (double)(int)q.y);
@@ -360,7 +360,7 @@ struct Solver {
     // records.  FP64 throughout.  Each work-item recomputes the residuals
     // of its antennas' pairs; type rows are block sums over the pairs (each
     // pair counted at its first antenna), up to kChunk types at a time.
-    __device__ double residuals() {
+    __device__ __forceinline__ double residuals() {
         // one straight-line instance per V^reduced source
         if constexpr (kVcache) {
             if (vl) return ci4 ? residuals_v<3>() : residuals_v<2>();
@@ -369,7 +369,7 @@ struct Solver {
     }
 
     template <int VM>
-    __device__ double residuals_v() {
+    __device__ __forceinline__ double residuals_v() {
         double rA[R1], rP[R1];
         float dd[R1];
 #pragma unroll
@@ -462,7 +462,7 @@ struct Solver {
     // |g|^2 of the own antennas and |V_t|^2 of the own type row into the
     // records, for the neighbours' matrix-vector products (published by the
     // barrier of the first reduction of the following CG solve).
-    __device__ void publish_weights(bool unit) {
+    __device__ __forceinline__ void publish_weights(bool unit) {
 #pragma unroll
         for (int k = 0; k < APT; ++k) {
             if (!live[k]) continue;
@@ -482,7 +482,7 @@ struct Solver {
     // Pair weights |g_i|^2 |g_j|^2 |V_t|^2 and record indices of the own
     // antenna's pairs (zero weight and index 0 where a pair does not
     // exist), after the records' weights have been published.
-    __device__ void load_pair_weights() {
+    __device__ __forceinline__ void load_pair_weights() {
         if constexpr (PW) {
 #pragma unroll
             for (int t = 0; t < KMAX; ++t) {
@@ -500,7 +500,7 @@ struct Solver {
         }
     }
 
-    __device__ void matvec_dots(float (&wa)[R1], float (&wp)[R1], float (&dots)[4]) {
+    __device__ __forceinline__ void matvec_dots(float (&wa)[R1], float (&wp)[R1], float (&dots)[4]) {
         constexpr int NV = 2 * KMAX + 4;
         float cs[NV];
 #pragma unroll
@@ -577,7 +577,7 @@ struct Solver {
         }
     }
 
-    __device__ void write_u() {
+    __device__ __forceinline__ void write_u() {
 #pragma unroll
         for (int k = 0; k < APT; ++k) {
             if (!live[k]) continue;
@@ -599,7 +599,7 @@ struct Solver {
     // norm (r, D^-1 r), a dot the iteration needs anyway, has fallen by
     // `tol`.  Returns the iterations, or -1 if a right-hand side is not
     // finite.
-    __device__ int pcg(int max_cg, float tol) {
+    __device__ __forceinline__ int pcg(int max_cg, float tol) {
         float pa[R1], pp[R1], sa[R1], sp[R1], wa[R1], wp[R1], dots[4];
 #pragma unroll
         for (int k = 0; k < R1; ++k) {
@@ -674,7 +674,7 @@ struct Solver {
     }
 
     // V_t = mean over the group of V_b / (g_i conj(g_j)), in FP32.
-    __device__ void group_mean() {
+    __device__ __forceinline__ void group_mean() {
         float sv[2 * KMAX];
 #pragma unroll
         for (int i = 0; i < 2 * KMAX; ++i) sv[i] = 0.f;
@@ -704,7 +704,7 @@ struct Solver {
 
     // Start, part 1: the logcal amplitude system (unit weights, right-hand
     // side sum of ln|V_b|) in ra / di, phase system empty.
-    __device__ void firstcal_rhs() {
+    __device__ __forceinline__ void firstcal_rhs() {
         float tq[2 * KMAX];
 #pragma unroll
         for (int i = 0; i < 2 * KMAX; ++i) tq[i] = 0.f;
@@ -752,7 +752,7 @@ struct Solver {
     // antenna (0,0) along the (1,0) group in the first row and the (0,1)
     // group up each column (each link's phase taken relative to the first
     // visibility of its group), into gd.
-    __device__ void firstcal_finish() {
+    __device__ __forceinline__ void firstcal_finish() {
         int off10 = 0, off01 = 0;
 #pragma unroll
         for (int t = 0; t < KMAX; ++t) {
@@ -806,7 +806,7 @@ struct Solver {
     // in FP32 to full relative precision, so the update keeps FP64 accuracy
     // however small the step.  Returns the rms step; the reduction's barrier
     // publishes g and V.
-    __device__ float update(double xscale) {
+    __device__ __forceinline__ float update(double xscale) {
         float e2[1] = {0.f};
 #pragma unroll
         for (int k = 0; k < R1; ++k) {
@@ -829,7 +829,7 @@ struct Solver {
 
 // The whole solve of one unit by one workgroup of NT work-items.
 template <int NT, int APT, int KMAX>
-__device__ void solve_unit(const SolveLaunch& L, Shared<NT / 64>& sh, unsigned char* lds, int unit) {
+__device__ __forceinline__ void solve_unit(const SolveLaunch& L, Shared<NT / 64>& sh, unsigned char* lds, int unit) {
     constexpr int NW = NT / 64;
     const Sel& s = L.sel;
     const SolveOpts op = L.o;
