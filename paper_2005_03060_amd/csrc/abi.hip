@@ -300,7 +300,8 @@ int rrc_plan_create(rrc_plan** out, int32_t n, const int32_t* types_xy, int32_t 
 
     // X-engine: blocks of 256 antennas, S samples staged per step, time
     // chunks (whole steps) so that the launch has >= 2048 workgroups while
-    // each still runs >= 4 steps
+    // each still runs >= 4 steps and >= 64 samples (fewer chunk partials
+    // for the finishing pass to add)
     {
         int halo = 0;
         for (int t = 0; t < s.K; ++t) halo = std::max(halo, s.dy[t] * s.n + s.dx[t]);
@@ -316,7 +317,7 @@ int rrc_plan_create(rrc_plan** out, int32_t n, const int32_t* types_xy, int32_t 
         p->x_S = rrc::xengine_samples_per_step(dtype == RRC_CI4);
         const long wg = (long)n_units * p->x_nablk;
         const long want = wg >= 2048 ? 1 : ceil_div(2048, (int)wg);
-        const int xn = (int)std::max(1L, std::min(want, (long)(n_time / (4 * p->x_S))));
+        const int xn = (int)std::max(1L, std::min(want, (long)(n_time / std::max(4 * p->x_S, 64))));
         const int xt = ceil_div(ceil_div(n_time, xn), p->x_S) * p->x_S;
         p->x_tchunk = xt;
         p->x_nchunk = ceil_div(n_time, xt);
