@@ -167,7 +167,10 @@ __device__ __forceinline__ void inverse_to_lags(float2* lds, const float* __rest
     }
 }
 
-template <int M, bool CI4>
+// W2: complex64 rows of even n, loaded as 16-byte pairs (half the load
+// instructions; each lane reads its own row, so every load touches as many
+// cache lines as there are lanes).
+template <int M, bool CI4, bool W2 = false>
 __global__ __launch_bounds__(kFftThreads) void k_fftcorr(const void* __restrict__ volt,
                                                          const float2* __restrict__ gains,
                                                          float* __restrict__ ppart, int n, int T,
@@ -238,8 +241,19 @@ __global__ __launch_bounds__(kFftThreads) void k_fftcorr(const void* __restrict_
             const float2* hrow = hinv + ry * (H + 1);
             if (live) {
                 // columns k >= n re-read column n-1 (finite) and meet 1/g = 0
+                if constexpr (W2) {
+                    const float2* vr = reinterpret_cast<const float2*>(volt) + rowbase;
 #pragma unroll
-                for (int k = 0; k < H; ++k) x[k] = cmul(load_volt<CI4>(volt, rowbase + min(k, n - 1)), hrow[k]);
+                    for (int k = 0; k < H; k += 2) {
+                        const float4 q = *reinterpret_cast<const float4*>(vr + min(k, n - 2));
+                        x[k] = cmul(make_float2(q.x, q.y), hrow[k]);
+                        x[k + 1] = cmul(make_float2(q.z, q.w), hrow[k + 1]);
+                    }
+                } else {
+#pragma unroll
+                    for (int k = 0; k < H; ++k)
+                        x[k] = cmul(load_volt<CI4>(volt, rowbase + min(k, n - 1)), hrow[k]);
+                }
             } else {
 #pragma unroll
                 for (int k = 0; k < H; ++k) x[k] = make_float2(0.0f, 0.0f);
@@ -579,8 +593,12 @@ static hipError_t launch_fft_m(const FftLaunch& L, hipStream_t st) {
         }
     } else {
         dim3 grid1(L.nchunk, L.n_units);
-        hipLaunchKernelGGL((k_fftcorr<M, CI4>), grid1, dim3(kFftThreads), 0, st, L.volt, L.gains,
-                           L.ppart, L.n, L.T, L.tchunk, L.nchunk);
+        if (!CI4 && L.n % 2 == 0)
+            hipLaunchKernelGGL((k_fftcorr<M, CI4, !CI4>), grid1, dim3(kFftThreads), 0, st, L.volt, L.gains,
+                               L.ppart, L.n, L.T, L.tchunk, L.nchunk);
+        else
+            hipLaunchKernelGGL((k_fftcorr<M, CI4, false>), grid1, dim3(kFftThreads), 0, st, L.volt, L.gains,
+                               L.ppart, L.n, L.T, L.tchunk, L.nchunk);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
