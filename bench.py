@@ -65,12 +65,16 @@ def measured_traffic(workload: str):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="g16_c64_t1024")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--plain-steps", type=int, default=2)
+    ap.add_argument("--inflight", type=int, default=0,
+                    help="batches in flight: step i runs on lane i mod D, each lane with its own "
+                         "stream, plans, input copy and outputs; 0 picks enough for the solves "
+                         "(one workgroup per unit) of all lanes to cover the CUs, at most 4")
     return ap.parse_args()
 
 
@@ -165,30 +169,68 @@ def main():
                            gains_in=torch.from_numpy(g.astype(np.complex64)).to(dev),
                            out=plan.alloc_outputs(dev),
                            sample=rng.permutation(w.n_chan).tolist()))
+    # Batches in flight: consecutive steps alternate over D lanes, each with
+    # its own stream, plans (so their own auxiliary streams and workspaces),
+    # copy of the input and outputs, so one batch's X-engine and
+    # FFT-correlator can run beside the previous batch's latency-bound solve.
+    # Lane 0 holds the arrays above; the other lanes copy their inputs.
+    cus = torch.cuda.get_device_properties(dev).multi_processor_count
+    D = args.inflight if args.inflight > 0 else \
+        max(1, min(4, -(-cus // (w.n_chan * len(arrays)))))
+    lanes = []
+    for li in range(D):
+        la = arrays if li == 0 else [
+            dict(a, plan=rrc.Plan(a["n"], a["types"], w.n_chan, w.n_time, dtype=dtype),
+                 volt=a["volt"].clone(), gains_in=a["gains_in"].clone()) for a in arrays]
+        for a in la:
+            if li:
+                a["out"] = a["plan"].alloc_outputs(dev)
+        lanes.append(dict(arrays=la, stream=torch.cuda.Stream(dev),
+                          batch=rrc.Batch([a["plan"] for a in la]) if len(la) > 1 else None))
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
-    batch = rrc.Batch([a["plan"] for a in arrays]) if len(arrays) > 1 else None
+    batch = lanes[0]["batch"]
 
-    def step():
-        if batch is None:
-            a = arrays[0]
+    def run_lane(ln):
+        if ln["batch"] is None:
+            a = ln["arrays"][0]
             a["plan"].run(a["volt"], gains_in=a["gains_in"], mode="pipelined", out=a["out"])
         else:
-            batch.run([a["volt"] for a in arrays], [a["gains_in"] for a in arrays],
-                      [a["out"] for a in arrays], mode="pipelined")
+            la = ln["arrays"]
+            ln["batch"].run([a["volt"] for a in la], [a["gains_in"] for a in la],
+                            [a["out"] for a in la], mode="pipelined")
 
-    for _ in range(args.warmup):
-        step()
+    def step(i):
+        ln = lanes[i % D]
+        with torch.cuda.stream(ln["stream"]):
+            run_lane(ln)
+
+    for i in range(args.warmup):
+        step(i)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
-    for _ in range(args.steps):
-        step()
+    for ln in lanes:
+        ln["stream"].wait_event(e0)
+    for i in range(args.steps):
+        step(i)
+    for ln in lanes:
+        stream.wait_stream(ln["stream"])
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / args.steps
     total_units = w.n_chan * len(arrays)
     value = total_units / (ms * 1e-3)
+
+    # one batch at a time on the launch stream: the time per step when each
+    # batch waits for the one before it
+    s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s0.record(stream)
+    for _ in range(args.steps):
+        run_lane(lanes[0])
+    s1.record(stream)
+    torch.cuda.synchronize()
+    serial_ms = s0.elapsed_time(s1) / args.steps
 
     # per-stage times with HIP events on the launch stream, each array alone
     def time_fn(fn, reps):
@@ -257,7 +299,6 @@ def main():
     # the solve runs one workgroup per unit and is bound by the latency of
     # its serial CG iterations, so its figure is time per unit and CU usage
     x_s = stages["xengine"] * 1e-3
-    cus = torch.cuda.get_device_properties(dev).multi_processor_count
     other = [
         {"kernel": "k_xant + k_xfin (reduced X-engine)", "bound": "hbm",
          "achieved": vbytes / x_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -289,8 +330,10 @@ def main():
                    "fft_size": [a["plan"].info["fft_size"] for a in arrays],
                    "types": [len(a["types"]) for a in arrays], "pairs": [a["npairs"] for a in arrays],
                    "mode": "pipelined, all channels per launch" + (", arrays concurrently" if batch else ""),
+                   "batches_in_flight": D,
                    "parallelism": "none (1 GPU)"},
         "stages_ms": stages,
+        "one_batch_at_a_time": {"ms_per_step": serial_ms, "value": total_units / (serial_ms * 1e-3)},
         "plain_per_channel": None if plain_ms is None else
         {"ms_per_step": plain_ms, "value": total_units / (plain_ms * 1e-3), "speedup_batched": plain_ms / ms},
         "gain_error_vs_oracle": None if gate is None else dict(gate, status_nonzero=status_nonzero),
