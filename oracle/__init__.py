@@ -16,8 +16,11 @@ redcal     the redundant-calibration model (eq. redcal), chi^2 (eq. redchi),
            degrees of freedom (eq. dof), its Wirtinger gradient, logcal
            (eq. logcal), Gauss-Newton (Taylor-expansion lincal, Sec. 2),
            omnical-style damped updates (Sec. 3) and degeneracy fixing.
+stats      the predicted gain covariance of eq. cov / eq. gaincov (the
+           linearised system's pseudo-inverse, degeneracies projected out)
+           and chi^2_r of eq. redchi.
 
 Parity status of each function is stated in its docstring; every function
 here is pinned by a `-m "not gpu"` test against something other than itself.
 """
-from . import geometry, correlator, redcal  # noqa: F401
+from . import geometry, correlator, redcal, stats  # noqa: F401

@@ -1,7 +1,8 @@
 """Seeded synthetic inputs for the calibrated FFT-correlator.
 
 This package only draws random numbers and builds the instrument model's
-inputs (sky, gains, noise, voltages).  It contains none of the correlator's
+inputs (sky, gains, noise, voltages; and, in `visibilities`, the
+visibility-level simulation of the paper's Sec. 3).  It contains none of the correlator's
 or the calibrator's arithmetic, so both the CPU oracle and the HIP path can
 consume the very same bytes without sharing any of the method's code.
 """

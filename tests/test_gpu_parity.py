@@ -369,6 +369,36 @@ def test_repeat_is_bitwise_deterministic(rrc):
         assert torch.equal(a[k], b[k]), k
 
 
+def test_lanes_on_separate_streams_match_serial_runs(rrc):
+    # several batches in flight: one plan, stream, input and output set per
+    # lane, steps launched round-robin with no synchronisation between them,
+    # give the bits of each batch run alone
+    n, U, T, D = 16, 8, 512, 3
+    lanes = []
+    for k in range(D):
+        v, g = make_units(n, U, T, wid=300 + k)
+        p, _ = _plan(rrc, n, U, T)
+        lanes.append(dict(plan=p, v=torch.from_numpy(v).to(DEV), g=torch.from_numpy(g.astype(np.complex64)).to(DEV),
+                          out=p.alloc_outputs(DEV), stream=torch.cuda.Stream(DEV)))
+    ref = []
+    for ln in lanes:
+        p1, _ = _plan(rrc, n, U, T)
+        ref.append(p1.run(ln["v"], gains_in=ln["g"], mode="pipelined"))
+    torch.cuda.synchronize()
+    start = torch.cuda.Event()
+    start.record()
+    for ln in lanes:
+        ln["stream"].wait_event(start)
+    for i in range(3 * D):
+        ln = lanes[i % D]
+        with torch.cuda.stream(ln["stream"]):
+            ln["plan"].run(ln["v"], gains_in=ln["g"], mode="pipelined", out=ln["out"])
+    torch.cuda.synchronize()
+    for ln, r in zip(lanes, ref):
+        for k in ("vunique", "vauto", "vred", "gains", "vmodel", "chisq", "niter", "status"):
+            assert torch.equal(ln["out"][k], r[k]), k
+
+
 # ------------------------------------------------------------ uneven batches
 
 def _batch_inputs(rrc):
