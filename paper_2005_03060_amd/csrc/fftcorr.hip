@@ -167,6 +167,35 @@ __device__ __forceinline__ void inverse_to_lags(float2* lds, const float* __rest
     }
 }
 
+// One half of a padded M-point transform whose upper M/2 inputs are zero:
+// outputs 2r + ODD are the M/2-point transform of x, pre-twiddled by
+// w_M^k for the odd ones.  Row stage: store them in natural order.
+template <int M, bool ODD>
+__device__ __forceinline__ void row_half(float2 (&x)[M / 2], float2* out) {
+    constexpr int H = M / 2;
+    if constexpr (ODD) {
+#pragma unroll
+        for (int k = 0; k < H; ++k) x[k] = twmul<M>(x[k], k);
+    }
+    fft_dif<H>(x);
+#pragma unroll
+    for (int r = 0; r < H; ++r) out[2 * bitrev<H>(r) + ODD] = x[r];
+}
+
+// Column stage: add the powers of the half's outputs (in bit-reversed
+// order; the final reduction places them).
+template <int M, bool ODD>
+__device__ __forceinline__ void col_half(float2 (&x)[M / 2], float (&acc)[M / 2]) {
+    constexpr int H = M / 2;
+    if constexpr (ODD) {
+#pragma unroll
+        for (int k = 0; k < H; ++k) x[k] = twmul<M>(x[k], k);
+    }
+    fft_dif<H>(x);
+#pragma unroll
+    for (int r = 0; r < H; ++r) acc[r] += cabs2(x[r]);
+}
+
 // W2: complex64 rows of even n, loaded as 16-byte pairs (half the load
 // instructions; each lane reads its own row, so every load touches as many
 // cache lines as there are lanes).
@@ -187,7 +216,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fftcorr(const void* __restrict_
     static_assert(M * M <= 2 * S * H * RS, "power grid must fit in the row buffer");
 
     __shared__ float2 rbuf[S * H * RS];
-    __shared__ float2 hinv[H * (H + 1)];
+    __shared__ float2 hinv[(H + 1) * (H + 1)];
 
     const int tid = threadIdx.x;
     const int unit = blockIdx.y;
@@ -196,9 +225,10 @@ __global__ __launch_bounds__(kFftThreads) void k_fftcorr(const void* __restrict_
     const int tb = chunk * tchunk;
     const int te = min(T, tb + tchunk);
 
-    // 1/g on an H x H table, zero outside the n x n grid: the padded inputs
-    // of a row then come out zero without a branch per element.
-    for (int q = tid; q < H * (H + 1); q += NT) {
+    // 1/g on an (H+1) x (H+1) table, zero outside the n x n grid: the
+    // padded inputs of a row then come out zero without a branch per
+    // element, and row H (all zero) serves the samples past the chunk end.
+    for (int q = tid; q < (H + 1) * (H + 1); q += NT) {
         const int y = q / (H + 1), k = q % (H + 1);
         float2 h = make_float2(0.0f, 0.0f);
         if (y < n && k < n) {
@@ -221,7 +251,9 @@ __global__ __launch_bounds__(kFftThreads) void k_fftcorr(const void* __restrict_
     for (int r = 0; r < H; ++r) acc[r] = 0.0f;
 
     // The half (even / odd outputs) is uniform per wave, so only the waves
-    // of the odd half run the pre-twiddle.
+    // of the odd half run the pre-twiddle.  Each branch on it runs through
+    // to the store (or the power sums), so the 16-element arrays of the two
+    // paths never have to be merged.
     const int rh = tid / (NT / 2);
     const int ry = (tid % (NT / 2)) % n;
     const int rs = (tid % (NT / 2)) / n;
@@ -235,11 +267,13 @@ __global__ __launch_bounds__(kFftThreads) void k_fftcorr(const void* __restrict_
     for (int t0 = tb; t0 < te; t0 += S) {
         if (row_active) {
             float2 x[H];
-            const int t = t0 + rs;
-            const bool live = t < te;
+            // a sample past the chunk end re-reads the last one and meets the
+            // zero row of the table
+            const bool live = t0 + rs < te;
+            const int t = live ? t0 + rs : te - 1;
             const size_t rowbase = ((size_t)unit * T + t) * N + (size_t)ry * n;
-            const float2* hrow = hinv + ry * (H + 1);
-            if (live) {
+            const float2* hrow = hinv + (live ? ry : H) * (H + 1);
+            {
                 // columns k >= n re-read column n-1 (finite) and meet 1/g = 0
                 if constexpr (W2) {
                     const float2* vr = reinterpret_cast<const float2*>(volt) + rowbase;
@@ -254,18 +288,12 @@ __global__ __launch_bounds__(kFftThreads) void k_fftcorr(const void* __restrict_
                     for (int k = 0; k < H; ++k)
                         x[k] = cmul(load_volt<CI4>(volt, rowbase + min(k, n - 1)), hrow[k]);
                 }
-            } else {
-#pragma unroll
-                for (int k = 0; k < H; ++k) x[k] = make_float2(0.0f, 0.0f);
             }
-            if (rh) {
-#pragma unroll
-                for (int k = 0; k < H; ++k) x[k] = twmul<M>(x[k], k);
-            }
-            fft_dif<H>(x);
             float2* out = rbuf + (rs * H + ry) * RS;
-#pragma unroll
-            for (int r = 0; r < H; ++r) out[2 * bitrev<H>(r) + rh] = x[r];
+            if (rh)
+                row_half<M, true>(x, out);
+            else
+                row_half<M, false>(x, out);
         }
         __syncthreads();
 #pragma unroll
@@ -274,13 +302,10 @@ __global__ __launch_bounds__(kFftThreads) void k_fftcorr(const void* __restrict_
             float2 x[H];
 #pragma unroll
             for (int k = 0; k < H; ++k) x[k] = rbuf[(s * H + k) * RS + cu];
-            if (ch) {
-#pragma unroll
-                for (int k = 0; k < H; ++k) x[k] = twmul<M>(x[k], k);
-            }
-            fft_dif<H>(x);
-#pragma unroll
-            for (int r = 0; r < H; ++r) acc[r] += cabs2(x[r]);
+            if (ch)
+                col_half<M, true>(x, acc);
+            else
+                col_half<M, false>(x, acc);
         }
         __syncthreads();
     }
