@@ -85,6 +85,25 @@ def test_plan_errors():
         rrc.Plan(65, [(1, 0)], 1, 16)
     with pytest.raises(rrc.RRCError):
         rrc.Plan(8, [(1, 0), (0, 1), (1, 1)], 0, 16)
+    with pytest.raises(rrc.RRCError) as e:               # no samples
+        rrc.Plan(8, [(1, 0), (0, 1), (1, 1)], 1, 0)
+    assert e.value.code == _lib.RRC_EINVAL
+
+
+def test_smallest_grids():
+    # 2 x 2: every type set leaves more than the four degeneracies, so the
+    # selection refuses it; 3 x 3 with one sample is the smallest plan
+    with pytest.raises(rrc.RRCError) as e:
+        rrc.select_subset(2)
+    assert e.value.code == _lib.RRC_EDEGEN
+    types, npairs = rrc.select_subset(3)
+    p = rrc.Plan(3, types, 1, 1)
+    assert p.info["n_pairs"] == npairs and p.info["dof"] == npairs - 9 - len(types) + 2
+    # 4-bit samples are staged as whole 32-bit words of four antennas
+    with pytest.raises(rrc.RRCError) as e:
+        rrc.Plan(3, types, 1, 1, dtype="ci4")
+    assert e.value.code == _lib.RRC_ENOTIMPL
+    rrc.Plan(4, rrc.select_subset(4)[0], 1, 1, dtype="ci4")
 
 
 def test_plan_info_sizes():

@@ -24,7 +24,8 @@ def _plan(rrc, n, U, T, dtype="c64", types=None, **kw):
 
 @pytest.mark.parametrize("n,U,T", [(8, 1, 256), (16, 6, 1024), (3, 2, 37), (5, 3, 250),
                                    (12, 2, 333), (24, 2, 200), (32, 2, 512), (40, 1, 33),
-                                   (48, 2, 64), (64, 1, 40), (16, 1, 4096), (33, 1, 31), (45, 2, 17)])
+                                   (48, 2, 64), (64, 1, 40), (16, 1, 4096), (33, 1, 31), (45, 2, 17),
+                                   (3, 1, 1), (16, 2, 1), (40, 1, 1)])
 def test_fftcorr_matches_oracle(rrc, n, U, T):
     v, g = make_units(n, U, T)
     plan, _ = _plan(rrc, n, U, T)
@@ -73,7 +74,7 @@ def test_fftcorr_single_mode_closed_form(rrc):
 
 # ----------------------------------------------------------------------- (a4)
 
-@pytest.mark.parametrize("n,U,T", [(8, 1, 256), (16, 4, 1024), (5, 2, 97), (32, 2, 2048)])
+@pytest.mark.parametrize("n,U,T", [(8, 1, 256), (16, 4, 1024), (5, 2, 97), (32, 2, 2048), (3, 2, 1), (16, 1, 1)])
 def test_xengine_float_matches_oracle(rrc, n, U, T):
     v, _ = make_units(n, U, T)
     plan, types = _plan(rrc, n, U, T)
@@ -88,7 +89,7 @@ def test_xengine_float_matches_oracle(rrc, n, U, T):
 
 
 @pytest.mark.parametrize("n,U,T", [(8, 2, 300), (8, 3, 301), (12, 2, 130), (16, 1, 1027), (16, 2, 1024),
-                                   (64, 2, 4096)])
+                                   (64, 2, 4096), (4, 1, 1), (64, 1, 1)])
 def test_xengine_ci4_bit_exact(rrc, n, U, T):
     b, re, im, _ = make_ci4_units(n, U, T)
     plan, types = _plan(rrc, n, U, T, dtype="ci4")
