@@ -1,5 +1,5 @@
 // Device-side helpers shared by the HIP kernels: complex arithmetic,
-// compile-time twiddles, an in-register radix-2 FFT, and the implicit
+// compile-time twiddles, an in-register radix-2^2 FFT, and the implicit
 // geometry of a square grid with a list of selected baseline-types.
 #pragma once
 
@@ -112,21 +112,45 @@ RRC_HD float2 twmul(float2 d, int k) {
     return make_float2(d.x * c - d.y * sn, d.x * sn + d.y * c);
 }
 
-// In-register radix-2 decimation-in-frequency FFT of length L:
+// In-register decimation-in-frequency FFT of length L (a power of two):
 // X[f] = sum_k x[k] e^{-2 pi i f k / L}, natural-order input, output
 // element r holds frequency bitrev(r).
+//
+// The radix-2 stages are taken two at a time (radix 2^2).  In a block of
+// 2h elements, the first stage's twiddle on element j + h/2 is w_2h^j
+// times w_2h^{h/2} = -i, so the -i is applied inside the butterfly and
+// w_2h^j moves past the second stage; the four outputs of (j, j + h/2,
+// j + h, j + 3h/2) then carry the twiddles 1, w_2h^2j, w_2h^j, w_2h^3j,
+// three general multiplies where two radix-2 stages take four.  Same
+// positions as the radix-2 form, so the same output order.  An odd number
+// of stages ends with one radix-2 stage (no twiddles).
 template <int L>
 RRC_HD void fft_dif(float2 (&a)[L]) {
 #pragma unroll
-    for (int h = L / 2; h >= 1; h >>= 1) {
+    for (int h = L / 2; h >= 2; h >>= 2) {
+        const int q = h / 2;
+        const int tw = L / (2 * h);              // w_2h^m = w_L^{m tw}
 #pragma unroll
         for (int b = 0; b < L; b += 2 * h) {
 #pragma unroll
-            for (int j = 0; j < h; ++j) {
-                const float2 u = a[b + j], v = a[b + j + h];
-                a[b + j] = cadd(u, v);
-                a[b + j + h] = twmul<L>(csub(u, v), j * (L / (2 * h)));
+            for (int j = 0; j < q; ++j) {
+                const float2 a0 = a[b + j], a1 = a[b + j + q], a2 = a[b + j + h], a3 = a[b + j + h + q];
+                const float2 s02 = cadd(a0, a2), d02 = csub(a0, a2);
+                const float2 s13 = cadd(a1, a3), d13 = csub(a1, a3);
+                const float2 md13 = make_float2(d13.y, -d13.x);      // -i (a1 - a3)
+                a[b + j] = cadd(s02, s13);
+                a[b + j + q] = twmul<L>(csub(s02, s13), 2 * j * tw);
+                a[b + j + h] = twmul<L>(cadd(d02, md13), j * tw);
+                a[b + j + h + q] = twmul<L>(csub(d02, md13), 3 * j * tw);
             }
+        }
+    }
+    if constexpr ((__builtin_ctz(L) & 1) != 0) {
+#pragma unroll
+        for (int b = 0; b < L; b += 2) {
+            const float2 u = a[b], v = a[b + 1];
+            a[b] = cadd(u, v);
+            a[b + 1] = csub(u, v);
         }
     }
 }
