@@ -26,10 +26,12 @@
 
 namespace rrc {
 
+// S samples per step; BOTH: one work-item computes both halves of a row,
+// so the row is loaded and divided by the gains once
 template <int M> struct FftCfg;
-template <> struct FftCfg<16>  { static constexpr int S = 16; };
-template <> struct FftCfg<32>  { static constexpr int S = 8; };
-template <> struct FftCfg<64>  { static constexpr int S = 4; };
+template <> struct FftCfg<16>  { static constexpr int S = 16; static constexpr bool BOTH = true; };
+template <> struct FftCfg<32>  { static constexpr int S = 8; static constexpr bool BOTH = true; };
+template <> struct FftCfg<64>  { static constexpr int S = 4; static constexpr bool BOTH = false; };
 template <> struct FftCfg<128> { static constexpr int S = 2; };   // k_fftcorr_q
 
 constexpr int kFftThreads = 256;
@@ -208,10 +210,11 @@ __global__ __launch_bounds__(kFftThreads) void k_fftcorr(const void* __restrict_
     constexpr int S = FftCfg<M>::S;
     constexpr int NT = kFftThreads;
     constexpr int RS = M + 1;                     // padded LDS row stride (complex)
+    constexpr bool BOTH = FftCfg<M>::BOTH;
     constexpr int CPT = 2 * M * S / NT;           // column tasks per thread (1 or 2)
     constexpr int G = S / CPT;                    // threads sharing one column half
     static_assert(G * M == NT / 2, "column tasks fill half the workgroup per half");
-    static_assert(S * M / 2 <= NT / 2, "row tasks fit half the workgroup per half");
+    static_assert(S * M / 2 <= (BOTH ? NT : NT / 2), "row tasks fit the workgroup");
     static_assert(CPT == 1 || CPT == 2, "column tasks per thread");
     static_assert(M * M <= 2 * S * H * RS, "power grid must fit in the row buffer");
 
@@ -250,13 +253,14 @@ __global__ __launch_bounds__(kFftThreads) void k_fftcorr(const void* __restrict_
 #pragma unroll
     for (int r = 0; r < H; ++r) acc[r] = 0.0f;
 
-    // The half (even / odd outputs) is uniform per wave, so only the waves
-    // of the odd half run the pre-twiddle.  Each branch on it runs through
-    // to the store (or the power sums), so the 16-element arrays of the two
-    // paths never have to be merged.
-    const int rh = tid / (NT / 2);
-    const int ry = (tid % (NT / 2)) % n;
-    const int rs = (tid % (NT / 2)) / n;
+    // Row stage: with BOTH a work-item takes both halves of its row (one row
+    // per work-item); otherwise the half (even / odd outputs) is uniform per
+    // wave and only the waves of the odd half run the pre-twiddle.  Each
+    // branch on a half runs through to the store (or, in the column stage,
+    // the power sums), so the arrays of the two paths are never merged.
+    const int rh = BOTH ? 0 : tid / (NT / 2);
+    const int ry = BOTH ? tid % n : (tid % (NT / 2)) % n;
+    const int rs = BOTH ? tid / n : (tid % (NT / 2)) / n;
     const bool row_active = rs < S;
     const int ch = tid / (NT / 2);
     const int cu = (tid % (NT / 2)) % M;
@@ -290,10 +294,17 @@ __global__ __launch_bounds__(kFftThreads) void k_fftcorr(const void* __restrict_
                 }
             }
             float2* out = rbuf + (rs * H + ry) * RS;
-            if (rh)
-                row_half<M, true>(x, out);
-            else
+            if constexpr (BOTH) {
+                float2 y[H];
+#pragma unroll
+                for (int k = 0; k < H; ++k) y[k] = x[k];
                 row_half<M, false>(x, out);
+                row_half<M, true>(y, out);
+            } else if (rh) {
+                row_half<M, true>(x, out);
+            } else {
+                row_half<M, false>(x, out);
+            }
         }
         __syncthreads();
 #pragma unroll
