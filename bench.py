@@ -185,6 +185,7 @@ def main():
         for a in la:
             if li:
                 a["out"] = a["plan"].alloc_outputs(dev)
+            a["plan"].workspace(dev)      # allocated here, not in a timed step
         lanes.append(dict(arrays=la, stream=torch.cuda.Stream(dev),
                           batch=rrc.Batch([a["plan"] for a in la]) if len(la) > 1 else None))
     torch.cuda.synchronize()
