@@ -205,9 +205,14 @@ __global__ __launch_bounds__(kXThreads, 2) void k_xant(XengLaunch L) {
                 const float2 va = srow[own];
 #pragma unroll
                 for (int t = 0; t < KMAX; ++t) {
+                    // two chained FMAs per component: written as one sum of
+                    // products, the compiler forms the products' sum first
+                    // (a multiply, an FMA and an add)
                     const float2 vb = srow[poff[t]];
-                    accr[t] += va.x * vb.x + va.y * vb.y;
-                    acci[t] += va.y * vb.x - va.x * vb.y;
+                    accr[t] = fmaf(va.x, vb.x, accr[t]);
+                    accr[t] = fmaf(va.y, vb.y, accr[t]);
+                    acci[t] = fmaf(va.y, vb.x, acci[t]);
+                    acci[t] = fmaf(-va.x, vb.y, acci[t]);
                 }
             }
         }
