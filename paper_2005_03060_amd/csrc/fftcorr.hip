@@ -169,6 +169,12 @@ __device__ __forceinline__ void inverse_to_lags(float2* lds, const float* __rest
     }
 }
 
+// acc + |x|^2 as two chained FMAs (written as acc + (x.x x.x + x.y x.y) it
+// compiles to a multiply, an FMA and an add)
+__device__ __forceinline__ float acc_power(float acc, float2 x) {
+    return fmaf(x.x, x.x, fmaf(x.y, x.y, acc));
+}
+
 // One half of a padded M-point transform whose upper M/2 inputs are zero:
 // outputs 2r + ODD are the M/2-point transform of x, pre-twiddled by
 // w_M^k for the odd ones.  Row stage: store them in natural order.
@@ -195,7 +201,7 @@ __device__ __forceinline__ void col_half(float2 (&x)[M / 2], float (&acc)[M / 2]
     }
     fft_dif<H>(x);
 #pragma unroll
-    for (int r = 0; r < H; ++r) acc[r] += cabs2(x[r]);
+    for (int r = 0; r < H; ++r) acc[r] = acc_power(acc[r], x[r]);
 }
 
 // W2: complex64 rows of even n, loaded as 16-byte pairs (half the load
@@ -452,7 +458,7 @@ __device__ __forceinline__ void col_quarter(const float2* rbuf, uint32_t rbase, 
     }
     fft_dif<32>(v);
 #pragma unroll
-    for (int r = 0; r < 32; ++r) acc[r] += cabs2(v[r]);
+    for (int r = 0; r < 32; ++r) acc[r] = acc_power(acc[r], v[r]);
 }
 
 template <bool CI4, int W>
