@@ -39,6 +39,10 @@ namespace rrc {
 
 constexpr int kXThreads = 256;
 constexpr int kXHaloMax = 248;   // largest raster offset d_t the staging covers
+// LDS row stride of a staged complex64 sample (float2 units), fixed at the
+// largest halo: a compile-time stride turns the sample offset of every LDS
+// read into an immediate, so the products need no address arithmetic
+constexpr int kXRowF = kXThreads + kXHaloMax + 2;
 
 // Transpose a 4 x 4 block of bytes: out[k] byte q = in[q] byte k.
 __device__ __forceinline__ void transpose4x4(const uint32_t (&w)[4], uint32_t (&o)[4]) {
@@ -169,7 +173,7 @@ __global__ __launch_bounds__(kXThreads, 2) void k_xant(XengLaunch L) {
 #pragma unroll
             for (int q = 0; q < S; ++q) {
 #pragma unroll
-                for (int u = 0; u < KPT; ++u) st[q * upr + min(tid + u * NT, upr - 1)] = r[q][u];
+                for (int u = 0; u < KPT; ++u) st[q * (kXRowF / W) + min(tid + u * NT, upr - 1)] = r[q][u];
             }
         }
     };
@@ -199,9 +203,7 @@ __global__ __launch_bounds__(kXThreads, 2) void k_xant(XengLaunch L) {
                 }
             }
         } else {
-#pragma unroll 2
-            for (int q = 0; q < ns; ++q) {
-                const float2* srow = reinterpret_cast<const float2*>(xsm) + q * cnt;
+            auto products = [&](const float2* srow) {
                 const float2 va = srow[own];
 #pragma unroll
                 for (int t = 0; t < KMAX; ++t) {
@@ -214,6 +216,14 @@ __global__ __launch_bounds__(kXThreads, 2) void k_xant(XengLaunch L) {
                     acci[t] = fmaf(va.y, vb.x, acci[t]);
                     acci[t] = fmaf(-va.x, vb.y, acci[t]);
                 }
+            };
+            const float2* sb = reinterpret_cast<const float2*>(xsm);
+            if (ns == S) {
+#pragma unroll
+                for (int q = 0; q < S; ++q) products(sb + q * kXRowF);
+            } else {
+#pragma unroll 2
+                for (int q = 0; q < ns; ++q) products(sb + q * kXRowF);
             }
         }
         __syncthreads();
@@ -242,7 +252,7 @@ __global__ __launch_bounds__(kXThreads, 2) void k_xant(XengLaunch L) {
 // widened by up to 6 bytes to whole words (stored as S/4 rows of words).
 size_t xengine_lds_bytes(int halo, bool ci4) {
     return ci4 ? (size_t)xeng_samples<true>() * (kXThreads + halo + 6)
-               : (size_t)xeng_samples<false>() * (kXThreads + halo + 2) * 8;
+               : (size_t)xeng_samples<false>() * kXRowF * 8;
 }
 
 int xengine_antennas_per_block() { return kXThreads; }
