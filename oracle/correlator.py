@@ -62,10 +62,13 @@ def xengine_int(re: np.ndarray, im: np.ndarray, pairs: np.ndarray) -> np.ndarray
     """
     a = np.asarray(re, dtype=np.int64)
     b = np.asarray(im, dtype=np.int64)
-    i, j = pairs[:, 0], pairs[:, 1]
-    sre = np.einsum("tp,tp->p", a[:, i], a[:, j]) + np.einsum("tp,tp->p", b[:, i], b[:, j])
-    sim = np.einsum("tp,tp->p", b[:, i], a[:, j]) - np.einsum("tp,tp->p", a[:, i], b[:, j])
-    return np.stack([sre, sim], axis=1)
+    out = np.empty((len(pairs), 2), dtype=np.int64)
+    # slices of pairs bound the [T, pairs] gathers' memory
+    for s in range(0, len(pairs), 2048):
+        i, j = pairs[s:s + 2048, 0], pairs[s:s + 2048, 1]
+        out[s:s + 2048, 0] = np.einsum("tp,tp->p", a[:, i], a[:, j]) + np.einsum("tp,tp->p", b[:, i], b[:, j])
+        out[s:s + 2048, 1] = np.einsum("tp,tp->p", b[:, i], a[:, j]) - np.einsum("tp,tp->p", a[:, i], b[:, j])
+    return out
 
 
 def canonical_lags(n: int):

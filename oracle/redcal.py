@@ -17,9 +17,11 @@ Solvers
   (0,1) redundant groups (a definition of this build; the paper does not
   say how its solver was started).
 * `lincal`: Gauss-Newton on the Taylor-expanded model (the "Taylor
-  expansion" linearisation of Sec. 2): dense FP64 normal equations of the
-  real-stacked Jacobian, with the four degenerate directions of Sec. 5.2
-  added as constraints, iterated until ||dx|| / ||x|| < 1e-10 (Sec. 3).
+  expansion" linearisation of Sec. 2): FP64 normal equations of the
+  real-stacked Jacobian, assembled pair by pair from each pair's 6 x 6
+  block, solved for the minimum-norm step (orthogonal to the four
+  degenerate directions of Sec. 5.2) by a sparse direct solve of the
+  bordered system, iterated until ||dx|| / ||x|| < 1e-10 (Sec. 3).
 * `omnical`: per-parameter least-squares updates blended with a damping
   factor of 0.3 (the paper's omnical settings, Sec. 3; its update rule is
   only cited there, this is the reading used here).
@@ -86,14 +88,18 @@ def jhj_diag(g, vm, pairs, tix):
 def logcal_amplitude(vred, pairs, tix, n_ant: int, n_types: int):
     """Real part of eq. logcal: ln|V_b| = eta_i + eta_j + A_alpha, least squares.
 
-    Returns (|g| [N], |V| [K]) from the minimum-norm solution.
+    Returns (|g| [N], |V| [K]) from the minimum-norm solution.  The system
+    A (one row per pair, ones at eta_i, eta_j and A_alpha) is singular along
+    the amplitude degeneracy (eta += c, A -= 2c, Sec. 5.2); its normal
+    equations are solved orthogonally to that direction (`min_norm_solve`).
     """
-    rows = np.arange(len(pairs))
-    a = np.zeros((len(pairs), n_ant + n_types))
-    a[rows, pairs[:, 0]] += 1.0
-    a[rows, pairs[:, 1]] += 1.0
-    a[rows, n_ant + tix] += 1.0
-    x = np.linalg.lstsq(a, np.log(np.abs(vred)), rcond=None)[0]
+    import scipy.sparse as sp
+    npair = len(pairs)
+    rows = np.repeat(np.arange(npair), 3)
+    cols = np.stack([pairs[:, 0], pairs[:, 1], n_ant + tix], axis=1).ravel()
+    a = sp.csr_matrix((np.ones(3 * npair), (rows, cols)), shape=(npair, n_ant + n_types))
+    z = np.concatenate([np.ones(n_ant), -2.0 * np.ones(n_types)])[None, :]
+    x = min_norm_solve((a.T @ a).tocsc(), a.T @ np.log(np.abs(vred)), z)
     return np.exp(x[:n_ant]), np.exp(x[n_ant:])
 
 
@@ -180,23 +186,88 @@ def jacobian_real(g, vm, pairs, tix):
     return np.vstack([jc.real, jc.imag])
 
 
-def lincal(vred, pos, types, pairs, tix, g0, v0, tol: float = 1e-10, max_iter: int = 100):
-    """Gauss-Newton on the Taylor-expanded redcal model, dense FP64.
+def pair_columns(nant: int, nt: int, pairs, tix):
+    """Columns of each pair's six real unknowns in [Re g, Im g, Re V, Im V] order.
 
-    Each step solves (J^T J + s Z Z^T) dx = J^T r, where Z spans the four
-    degenerate directions (so dx is the minimum-norm least-squares step).
-    Stops when ||dx|| / ||x|| < tol.  Returns (g, V, n_iter, converged).
+    Pair b = (i, j) of type alpha depends on g_i, g_j and V_alpha only:
+    columns (Re g_i, Im g_i, Re g_j, Im g_j, Re V_alpha, Im V_alpha).
+    """
+    i, j = pairs[:, 0], pairs[:, 1]
+    return np.stack([i, nant + i, j, nant + j, 2 * nant + tix, 2 * nant + nt + tix], axis=1)
+
+
+def pair_derivatives(g, vm, pairs, tix):
+    """d model_b / d (each of the pair's six real unknowns), complex [P, 6].
+
+    m_b = g_i conj(g_j) V_alpha, so with a = conj(g_j) V_alpha,
+    b = g_i V_alpha, c = g_i conj(g_j):
+    d/dRe g_i = a, d/dIm g_i = i a, d/dRe g_j = b, d/dIm g_j = -i b,
+    d/dRe V = c, d/dIm V = i c.
+    """
+    i, j = pairs[:, 0], pairs[:, 1]
+    a = np.conj(g[j]) * vm[tix]
+    b = g[i] * vm[tix]
+    c = g[i] * np.conj(g[j])
+    return np.stack([a, 1j * a, b, -1j * b, c, 1j * c], axis=1)
+
+
+def normal_equations(vred, g, vm, pairs, tix):
+    """J^T J and J^T r of the real-stacked Gauss-Newton system, per pair.
+
+    J is the real Jacobian of [Re m; Im m] (the Taylor expansion of eq.
+    redcal about the current point, Sec. 2) and r = V^reduced - m.  Each
+    pair touches six real unknowns, so J^T J is a sum of 6 x 6 blocks
+    Re(conj(d_b) d_b^T) and J^T r a sum of 6-vectors Re(conj(d_b) r_b),
+    d_b being the pair's row of complex derivatives.  Returns J^T J as a
+    scipy sparse CSC matrix (entries of coincident columns summed) and
+    J^T r as a dense vector, both FP64.
+    """
+    import scipy.sparse as sp
+    nant, nt = len(g), len(vm)
+    nv = 2 * (nant + nt)
+    cols = pair_columns(nant, nt, pairs, tix)
+    d = pair_derivatives(g, vm, pairs, tix)
+    r = vred - model_vis(g, vm, pairs, tix)
+    blk = np.real(np.conj(d)[:, :, None] * d[:, None, :])
+    rows_ix = np.broadcast_to(cols[:, :, None], blk.shape).ravel()
+    cols_ix = np.broadcast_to(cols[:, None, :], blk.shape).ravel()
+    h = sp.coo_matrix((blk.ravel(), (rows_ix, cols_ix)), shape=(nv, nv)).tocsc()
+    rhs = np.zeros(nv)
+    np.add.at(rhs, cols, np.real(np.conj(d) * r[:, None]))
+    return h, rhs
+
+
+def min_norm_solve(h, rhs, z):
+    """Minimum-norm solution of rank-deficient normal equations h dx = rhs.
+
+    h = J^T J is singular exactly along the degenerate directions z
+    ([k, n] rows, Sec. 5.2), and rhs = J^T r is orthogonal to them.  The
+    solution orthogonal to z is the solution of the bordered system
+    [[h, z^T], [z, 0]] [dx; lam] = [rhs; 0] (lam = 0 at the solution),
+    solved by a sparse direct LU (minimum-degree ordering of h + h^T).
+    """
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spl
+    nv = h.shape[0]
+    kkt = sp.bmat([[h, sp.csc_matrix(z.T)], [sp.csc_matrix(z), None]], format="csc")
+    x = spl.spsolve(kkt, np.concatenate([rhs, np.zeros(len(z))]), permc_spec="MMD_AT_PLUS_A")
+    return x[:nv]
+
+
+def lincal(vred, pos, types, pairs, tix, g0, v0, tol: float = 1e-10, max_iter: int = 100):
+    """Gauss-Newton on the Taylor-expanded redcal model, FP64.
+
+    Each step is the minimum-norm least-squares solution of the linearised
+    system, J^T J dx = J^T r with dx orthogonal to the four degenerate
+    directions (`normal_equations`, `min_norm_solve`).  Stops when
+    ||dx|| / ||x|| < tol.  Returns (g, V, n_iter, converged).
     """
     g = np.array(g0, dtype=np.complex128)
     vm = np.array(v0, dtype=np.complex128)
     nant, nt = len(g), len(vm)
     for it in range(1, max_iter + 1):
-        r = vred - model_vis(g, vm, pairs, tix)
-        jr = jacobian_real(g, vm, pairs, tix)
-        h = jr.T @ jr
-        z, _ = np.linalg.qr(_real(*degenerate_directions(g, vm, pos, types)).T)
-        h += (np.trace(h) / h.shape[0]) * (z @ z.T)
-        dx = np.linalg.solve(h, jr.T @ np.concatenate([r.real, r.imag]))
+        h, rhs = normal_equations(vred, g, vm, pairs, tix)
+        dx = min_norm_solve(h, rhs, _real(*degenerate_directions(g, vm, pos, types)))
         g = g + dx[:nant] + 1j * dx[nant:2 * nant]
         vm = vm + dx[2 * nant:2 * nant + nt] + 1j * dx[2 * nant + nt:]
         x = np.concatenate([g, vm])

@@ -1,7 +1,10 @@
 """Pins for oracle.redcal: exact recovery of noise-free model data, the
 Wirtinger gradient against finite differences (exact: chi^2 is quadratic in
 every single parameter), stationarity, two independent solvers agreeing, the
-DoF count against the Jacobian's null space, and the degeneracy fixes."""
+DoF count against the Jacobian's null space, the degeneracy fixes, and the
+pair-by-pair normal equations against the dense Jacobian (whose columns are
+pinned by exact central differences of the model) and the minimum-norm
+least-squares steps against numpy's pseudo-inverse solution."""
 import numpy as np
 import pytest
 
@@ -178,3 +181,73 @@ def test_voltage_level_end_to_end_basin():
     assert a["converged"] and b["converged"]
     assert np.max(np.abs(a["g"] - b["g"])) < 1e-9
     assert a["chisq"] <= R.chisq(vred, g, R.group_mean(vred, g, pairs, tix, len(types)), pairs, tix)
+
+
+# ------------------------------------------------ normal equations per pair
+
+def test_jacobian_columns_are_central_differences():
+    # the model g_i conj(g_j) V_alpha is linear in each single real unknown,
+    # so central differences of it are exact up to rounding
+    n = 4
+    types = G.square_types(n)[0][:4]
+    pos, pairs, tix, g, vm, _ = _problem(n, types, seed=21)
+    jr = R.jacobian_real(g, vm, pairs, tix)
+    nant, nt = len(g), len(vm)
+    h = 1e-3
+    for col in range(2 * (nant + nt)):
+        x = np.concatenate([g.real, g.imag, vm.real, vm.imag])
+        xp, xm = x.copy(), x.copy()
+        xp[col] += h
+        xm[col] -= h
+
+        def mv(xx):
+            gg = xx[:nant] + 1j * xx[nant:2 * nant]
+            vv = xx[2 * nant:2 * nant + nt] + 1j * xx[2 * nant + nt:]
+            m = R.model_vis(gg, vv, pairs, tix)
+            return np.concatenate([m.real, m.imag])
+
+        fd = (mv(xp) - mv(xm)) / (2 * h)
+        assert np.max(np.abs(fd - jr[:, col])) < 1e-11
+
+
+@pytest.mark.parametrize("n,k", [(4, 3), (6, 5), (10, 7)])
+def test_normal_equations_per_pair_match_dense_jacobian(n, k):
+    types = G.square_types(n)[0][:k]
+    pos, pairs, tix, g, vm, vred = _problem(n, types, seed=30 + n, noise=0.1)
+    h, rhs = R.normal_equations(vred, g, vm, pairs, tix)
+    jr = R.jacobian_real(g, vm, pairs, tix)
+    r = vred - R.model_vis(g, vm, pairs, tix)
+    hd = jr.T @ jr
+    assert np.max(np.abs(h.toarray() - hd)) <= 1e-12 * np.max(np.abs(hd))
+    rd = jr.T @ np.concatenate([r.real, r.imag])
+    assert np.max(np.abs(rhs - rd)) <= 1e-12 * np.max(np.abs(rd))
+
+
+@pytest.mark.parametrize("n,k", [(5, 5), (8, 6)])
+def test_gauss_newton_step_is_the_minimum_norm_least_squares_step(n, k):
+    # the step lincal takes equals the pseudo-inverse solution of the dense
+    # linearised system J dx = r
+    types = G.square_types(n)[0][:k]
+    pos, pairs, tix, g, vm, vred = _problem(n, types, seed=40 + n, noise=0.1)
+    g = g * (1 + 0.05 * np.random.default_rng(n).standard_normal(len(g)))
+    h, rhs = R.normal_equations(vred, g, vm, pairs, tix)
+    dx = R.min_norm_solve(h, rhs, R._real(*R.degenerate_directions(g, vm, pos, types)))
+    jr = R.jacobian_real(g, vm, pairs, tix)
+    r = vred - R.model_vis(g, vm, pairs, tix)
+    ref = np.linalg.lstsq(jr, np.concatenate([r.real, r.imag]), rcond=1e-10)[0]
+    assert np.max(np.abs(dx - ref)) <= 1e-10 * np.max(np.abs(ref))
+
+
+def test_logcal_amplitude_is_the_minimum_norm_least_squares_fit():
+    n = 6
+    types = G.square_types(n)[0][:5]
+    pos, pairs, tix, g, vm, vred = _problem(n, types, seed=50, noise=0.1)
+    amp, vamp = R.logcal_amplitude(vred, pairs, tix, n * n, len(types))
+    a = np.zeros((len(pairs), n * n + len(types)))
+    rows = np.arange(len(pairs))
+    a[rows, pairs[:, 0]] += 1.0
+    a[rows, pairs[:, 1]] += 1.0
+    a[rows, n * n + tix] += 1.0
+    x = np.linalg.lstsq(a, np.log(np.abs(vred)), rcond=None)[0]
+    assert np.max(np.abs(np.log(amp) - x[:n * n])) < 1e-12
+    assert np.max(np.abs(np.log(vamp) - x[n * n:])) < 1e-12
