@@ -1,21 +1,27 @@
 """Throughput of the calibrated FFT-correlator on one MI355X.
 
     python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
+    python bench.py --copy-calibration      # the HBM-counter calibration copy
 
 One step = one integration of every unit (array, channel) of the workload
 through the whole hot path: reduced X-engine, FFT-correlator (gain
 application, padded spatial FFT, |.|^2 integration, inverse transform and
 redundant normalisation) and the reduced redundant calibration solve.  The
-batched path issues the steps for all units at once (rrc_run, PIPELINED: the
-FFT applies the previous integration's gains; several arrays run together
-through rrc_batch_run); the plain path calibrates one channel at a time,
-synchronising after each.  Inputs are resident in HBM before timing starts.
-Prints one JSON line.
+batched path issues the step for all units at once (rrc_run, PIPELINED: the
+FFT applies the previous integration's gains; several arrays run together as
+one captured graph through rrc_batch_run); the plain path calibrates one
+channel at a time, synchronising after each.  Inputs are resident in HBM
+before timing starts.  Prints one JSON line.
+
+The default workload is the 64x64-grid, 1024-channel, 4096-sample 4-bit one
+(the largest single-GPU configuration); the 32x32-grid, 256-channel
+complex64 one is measured beside it under "extra".
 """
 from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -26,22 +32,71 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-VALU_FP32_PEAK_TFLOPS = 78.6    # 256 CU x 64 lanes x 2 flop x 2.4 GHz, packed FP32 disabled
+# 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz; the 157.3 TFLOP/s
+# vector figure counts packed (two-wide) FP32, which this build does not use
+VALU_FP32_PEAK_TFLOPS = 78.6
 METRIC = "calibrated channel-integrations/sec (batched+adjoint vs plain) at stated gain error"
+DEFAULT_WORKLOAD = "g64_c1024_t4096_ci4"
+EXTRA_WORKLOAD = "g32_c256_t2048"
 
 
-def fft_flops_per_sample(n: int, m: int) -> float:
+def pad_size(n: int) -> int:
+    m = 1
+    while m < 2 * n:
+        m *= 2
+    return m
+
+
+def fft_flops_per_sample(n: int) -> float:
     """Algorithmic FP32 flops of one sample's FFT-correlator work.
 
-    Every row (n of them) and column (m) transform is an m-point FFT with
-    only n <= m/2 non-zero inputs, done as two m/2-point FFTs
-    (5 (m/2) log2(m/2) flops each) plus a pre-twiddle (6 flops per input)
-    for the odd half; |E|^2 accumulation is 3 flops per grid point and the
-    gain application 6 flops per antenna.
+    The practical count of the hot-path scope: every row (n of them) and
+    column (M) transform of the padded M-point FFT costs 4.25 M log2 M flops
+    less its first (trivial, half-zero) stage, i.e. 4.25 M (log2 M - 1);
+    |E|^2 accumulation 4 flops per grid point; gain application 6 flops per
+    antenna.  M is the default padded size (the next power of two >= 2n):
+    at n = 16, 32, 64 this gives 32.5 MF, 314 MF and 2.94 GF per unit of
+    1024, 2048 and 4096 samples.
     """
-    half = m // 2
-    per_tf = 2 * 5 * half * np.log2(half) + 6 * half
-    return (n + m) * per_tf + 3 * m * m + 6 * n * n
+    m = pad_size(n)
+    return (n + m) * 4.25 * m * (math.log2(m) - 1) + 4 * m * m + 6 * n * n
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the second (32x32) workload")
+    ap.add_argument("--gate-units", type=int, default=8)
+    ap.add_argument("--plain-units", type=int, default=0,
+                    help="channels timed in the plain per-channel form (0: all, up to 256)")
+    ap.add_argument("--inflight", type=int, default=0,
+                    help="batches in flight: step i runs on lane i mod D, each lane with its own "
+                         "stream, plans, input copy and outputs; 0 picks enough for the solves "
+                         "(one workgroup per unit) of all lanes to cover the CUs, at most 4")
+    ap.add_argument("--order", default="auto", choices=["auto", "xeng_first", "fft_first"],
+                    help="pipelined branch order (auto: FFT first for 4-bit workloads, whose FFT stage "
+                         "is VALU-bound and dominates)")
+    ap.add_argument("--latency-reps", type=int, default=50)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy 256 MiB three times (the run whose FETCH_SIZE / WRITE_SIZE scale "
+                         "the HBM counters of the kernels)")
+    return ap.parse_args()
+
+
+def copy_calibration():
+    import torch
+    n = 256 * 1024 * 1024 // 4
+    a = torch.ones(n, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print("copied 3 x", n * 4, "bytes", flush=True)
 
 
 def measured_traffic(workload: str):
@@ -62,114 +117,15 @@ def measured_traffic(workload: str):
     return d["hbm_bytes_per_launch"]
 
 
-def parse():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="g16_c64_t1024")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--plain-steps", type=int, default=2)
-    ap.add_argument("--inflight", type=int, default=0,
-                    help="batches in flight: step i runs on lane i mod D, each lane with its own "
-                         "stream, plans, input copy and outputs; 0 picks enough for the solves "
-                         "(one workgroup per unit) of all lanes to cover the CUs, at most 4")
-    return ap.parse_args()
+# --------------------------------------------------------------- the GPU run
 
-
-def cpu_baseline(arrays, budget_s, gate_units):
-    """The FP64 oracle, as it stands, on a bounded sample of the same units.
-
-    Units are taken in a seeded random order, in passes over the sample,
-    until at least min(10 s, budget) of oracle work is done, and never past
-    the budget.  Also the accuracy gate: for the first `gate_units` of them the
-    oracle solves the GPU's own V^reduced and the GPU gains are compared
-    after the same degeneracy fix.  Arrays whose dense oracle solve is too
-    slow for a bench (n > 32) are left out of the sample.
-    """
-    import threadpoolctl
-    from oracle import correlator as OC
-    from oracle import geometry as OG
-    from oracle import redcal as OR
-    done, gerr, t_solve, units = 0, 0.0, 0.0, []
-    geo = {}
-    for a in arrays:
-        if a["n"] <= 32:
-            pos = OG.square_positions(a["n"])
-            pairs, tix = OG.group_pairs(pos, a["types"])
-            geo[a["name"]] = (pos, pairs, tix, OC.canonical_lags(a["n"]))
-    # passes over the sampled units until at least min(10 s, budget) of
-    # oracle work, stopping within the budget
-    min_s = min(10.0, budget_s)
-    t0 = time.perf_counter()
-    passes, out_of_time = 0, not geo
-    while not out_of_time:
-        for a in arrays:
-            if a["name"] not in geo:
-                continue
-            pos, pairs, tix, lags = geo[a["name"]]
-            types = a["types"]
-            for u in a["sample"]:
-                volt = a["volt_host"](u)
-                if volt.dtype == np.uint8:
-                    from synthdata import unpack_ci4
-                    re, im = unpack_ci4(volt)
-                    v = re.astype(np.float64) + 1j * im.astype(np.float64)
-                else:
-                    v = volt.astype(np.complex128)
-                ts = time.perf_counter()
-                vf = OC.fx_correlate(v)
-                vred = OC.xengine(vf, pairs)
-                cal = OR.calibrate(vred, pos, types, pairs, tix)
-                OC.redundant_average(vf, cal["g"], pos, lags)
-                t_solve += time.perf_counter() - ts
-                done += 1
-                # gate: the oracle on the GPU's own V^reduced
-                if len(units) < gate_units:
-                    ref = OR.calibrate(a["vred_gpu"](u), pos, types, pairs, tix)
-                    g = a["gains_gpu"](u)
-                    gerr = max(gerr, float(np.max(np.abs(g - ref["g"]) / np.abs(ref["g"]))))
-                    units.append(f"{a['name']}:{u}")
-                if time.perf_counter() - t0 > budget_s:
-                    out_of_time = True
-                    break
-            if out_of_time:
-                break
-        passes += 1
-        if t_solve >= min_s:
-            break
-    if done == 0:
-        return None, None
-    info = threadpoolctl.threadpool_info()
-    threads = max([i.get("num_threads", 1) for i in info] + [1])
-    cpu = {"value": done / t_solve, "unit": "calibrated channel-integrations/s", "cores": threads,
-           "kind": "oracle",
-           "sample": f"{done} unit solves ({passes} pass(es) over the sampled units of the same workload), "
-                     f"one at a time ({t_solve:.1f} s): FX correlator "
-                     f"(zgemm), X-engine gather, FIRSTCAL start + dense Gauss-Newton to 1e-10, "
-                     f"degeneracy fix, eq. modelvis average"}
-    gate = {"max_rel": gerr, "units": units, "tol": 1e-6}
-    return cpu, gate
-
-
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for {args.gpus}); units shard across GPUs "
-              f"with no collective, so the per-GPU figure is the one to scale.", file=sys.stderr)
-        sys.exit(2)
+def setup(w, dev, rrc, inflight, order):
     import torch
-    import paper_2005_03060_amd as rrc
-    from synthdata import WORKLOADS, workload_voltages
+    from synthdata import workload_voltages
     from synthdata.device import device_voltages
-
-    w = {x.name: x for x in WORKLOADS}[args.workload]
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
     dtype = "ci4" if w.ci4 else "c64"
     # small workloads: the host generator's exact bytes; large: drawn on the GPU
-    host_gen = len(w.grids) == 1 and w.grids[0] * w.grids[0] * w.n_chan * w.n_time <= 64 * 1024 * 1024
+    host_gen = len(w.grids) == 1 and w.grids[0] ** 2 * w.n_chan * w.n_time <= 64 * 1024 * 1024
     rng = np.random.default_rng(7)
     arrays = []
     for ai, n in enumerate(w.grids):
@@ -179,188 +135,393 @@ def main():
         else:
             volt, g = device_voltages(w, ai, dev)
         types, npairs = rrc.select_subset(n)
-        plan = rrc.Plan(n, types, w.n_chan, w.n_time, dtype=dtype)
-        arrays.append(dict(name=f"g{n}", n=n, types=types, npairs=npairs, plan=plan, volt=volt,
+        arrays.append(dict(name=f"g{n}", ai=ai, n=n, types=types, npairs=npairs, volt=volt, gains_host=g,
                            gains_in=torch.from_numpy(g.astype(np.complex64)).to(dev),
-                           out=plan.alloc_outputs(dev),
                            sample=rng.permutation(w.n_chan).tolist()))
-    # Batches in flight: consecutive steps alternate over D lanes, each with
-    # its own stream, plans (so their own auxiliary streams and workspaces),
-    # copy of the input and outputs, so one batch's X-engine and
-    # FFT-correlator can run beside the previous batch's latency-bound solve.
-    # Lane 0 holds the arrays above; the other lanes copy their inputs.
     cus = torch.cuda.get_device_properties(dev).multi_processor_count
-    D = args.inflight if args.inflight > 0 else \
-        max(1, min(4, -(-cus // (w.n_chan * len(arrays)))))
+    D = inflight if inflight > 0 else max(1, min(4, -(-cus // (w.n_chan * len(arrays)))))
+    if order == "auto":
+        order = "fft_first" if w.ci4 else "xeng_first"
     lanes = []
     for li in range(D):
-        la = arrays if li == 0 else [
-            dict(a, plan=rrc.Plan(a["n"], a["types"], w.n_chan, w.n_time, dtype=dtype),
-                 volt=a["volt"].clone(), gains_in=a["gains_in"].clone()) for a in arrays]
-        for a in la:
-            if li:
-                a["out"] = a["plan"].alloc_outputs(dev)
-            a["plan"].workspace(dev)      # allocated here, not in a timed step
+        la = []
+        for a in arrays:
+            plan = rrc.Plan(a["n"], a["types"], w.n_chan, w.n_time, dtype=dtype)
+            plan.set_order(order)
+            plan.workspace(dev)            # allocated here, not in a timed step
+            la.append(dict(a, plan=plan, out=plan.alloc_outputs(dev),
+                           volt=a["volt"] if li == 0 else a["volt"].clone(),
+                           gains_in=a["gains_in"] if li == 0 else a["gains_in"].clone()))
         lanes.append(dict(arrays=la, stream=torch.cuda.Stream(dev),
-                          batch=rrc.Batch([a["plan"] for a in la]) if len(la) > 1 else None))
+                          batch=rrc.Batch([a["plan"] for a in la], graph=True) if len(la) > 1 else None))
     torch.cuda.synchronize()
-    stream = torch.cuda.current_stream()
-    batch = lanes[0]["batch"]
+    return dict(arrays=lanes[0]["arrays"], lanes=lanes, D=D, cus=cus, dtype=dtype, host_gen=host_gen,
+                order=order)
 
-    def run_lane(ln):
-        if ln["batch"] is None:
-            a = ln["arrays"][0]
-            a["plan"].run(a["volt"], gains_in=a["gains_in"], mode="pipelined", out=a["out"])
-        else:
-            la = ln["arrays"]
-            ln["batch"].run([a["volt"] for a in la], [a["gains_in"] for a in la],
-                            [a["out"] for a in la], mode="pipelined")
+
+def run_lane(ln):
+    if ln["batch"] is None:
+        a = ln["arrays"][0]
+        a["plan"].run(a["volt"], gains_in=a["gains_in"], mode="pipelined", out=a["out"])
+    else:
+        la = ln["arrays"]
+        ln["batch"].run([a["volt"] for a in la], [a["gains_in"] for a in la], [a["out"] for a in la],
+                        mode="pipelined")
+
+
+def time_steps(S, steps, warmup):
+    """W untimed steps, then K steps between HIP events on the launch
+    stream (every lane waits for the start event; the launch stream waits
+    for every lane before the end event); synchronised on both sides."""
+    import torch
+    lanes, D = S["lanes"], S["D"]
+    stream = torch.cuda.current_stream()
 
     def step(i):
         ln = lanes[i % D]
         with torch.cuda.stream(ln["stream"]):
             run_lane(ln)
 
-    for i in range(args.warmup):
+    for i in range(warmup):
         step(i)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     for ln in lanes:
         ln["stream"].wait_event(e0)
-    for i in range(args.steps):
+    for i in range(steps):
         step(i)
     for ln in lanes:
         stream.wait_stream(ln["stream"])
     e1.record(stream)
     torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / args.steps
-    total_units = w.n_chan * len(arrays)
-    value = total_units / (ms * 1e-3)
+    return e0.elapsed_time(e1) / steps
 
-    # one batch at a time on the launch stream: the time per step when each
-    # batch waits for the one before it
-    s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    s0.record(stream)
-    for _ in range(args.steps):
-        run_lane(lanes[0])
-    s1.record(stream)
+
+def time_fn(fn, reps):
+    """Average time per call of fn, HIP events on the current stream."""
+    import torch
+    stream = torch.cuda.current_stream()
+    fn()
     torch.cuda.synchronize()
-    serial_ms = s0.elapsed_time(s1) / args.steps
+    a_, b_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a_.record(stream)
+    for _ in range(reps):
+        fn()
+    b_.record(stream)
+    torch.cuda.synchronize()
+    return a_.elapsed_time(b_) / reps
 
-    # per-stage times with HIP events on the launch stream, each array alone
-    def time_fn(fn, reps):
-        for _ in range(2):
-            fn()
-        a_, b_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        a_.record(stream)
-        for _ in range(reps):
-            fn()
-        b_.record(stream)
-        torch.cuda.synchronize()
-        return a_.elapsed_time(b_) / reps
 
-    stages = {"xengine": 0.0, "fftcorr": 0.0, "solve": 0.0}
-    flops = vbytes = 0.0
-    latency = {}
-    for a in arrays:
+def stage_times(S, w, reps):
+    """Each stage alone, per launch (all channels of an array), summed over arrays."""
+    st = {"xengine": 0.0, "fftcorr": 0.0, "solve": 0.0}
+    for a in S["arrays"]:
         p = a["plan"]
-        stages["xengine"] += time_fn(lambda: p.xengine(a["volt"]), args.steps)
-        stages["fftcorr"] += time_fn(lambda: p.fftcorr(a["volt"], a["gains_in"]), args.steps)
-        stages["solve"] += time_fn(lambda: p.solve(a["out"]["vred"]), args.steps)
-        m = p.info["fft_size"]
-        flops += fft_flops_per_sample(a["n"], m) * w.n_time * w.n_chan
-        vbytes += (1.0 if w.ci4 else 8.0) * a["n"] ** 2 * w.n_time * w.n_chan
-        if len(arrays) > 1:
-            # per-array latency of one whole-path run of the array alone
-            t = []
-            for _ in range(max(5, args.steps)):
-                s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                s0.record(stream)
-                p.run(a["volt"], gains_in=a["gains_in"], mode="pipelined", out=a["out"])
-                s1.record(stream)
-                torch.cuda.synchronize()
-                t.append(s0.elapsed_time(s1))
-            latency[a["name"]] = {"p50_ms": float(np.percentile(t, 50)), "p99_ms": float(np.percentile(t, 99))}
+        st["xengine"] += time_fn(lambda: p.xengine(a["volt"]), reps)
+        st["fftcorr"] += time_fn(lambda: p.fftcorr(a["volt"], a["gains_in"]), reps)
+        st["solve"] += time_fn(lambda: p.solve(a["out"]["vred"]), reps)
+    return st
 
-    # plain per-channel form: one plan per channel, host sync after each
-    plain_ms = None
-    if args.plain_steps > 0:
-        plain1 = []
-        for a in arrays:
-            p1 = rrc.Plan(a["n"], a["types"], 1, w.n_time, dtype=dtype)
-            plain1.append((a, p1, p1.alloc_outputs(dev)))
-        for a, p1, o1 in plain1:
-            for c in range(min(2, w.n_chan)):
-                p1.run(a["volt"][c:c + 1], gains_in=a["gains_in"][c:c + 1], mode="pipelined", out=o1)
+
+def latency_from_stamps(S, reps):
+    """Per-array latency of the batched step from the device's own stamps:
+    for each array, the time from its run's start on the device until the
+    last of its units' outputs is written; p50 / p99 over `reps` steps."""
+    import torch
+    import paper_2005_03060_amd as rrc
+    ln = S["lanes"][0]
+    for a in ln["arrays"]:
+        a["out"]["stamps"] = torch.zeros(1 + a["plan"].n_units, dtype=torch.int64, device=a["volt"].device)
+    # (the io now differs from the captured one: a graph batch re-captures once)
+    hz = rrc.wall_clock_hz()
+    lat = {a["name"]: [] for a in ln["arrays"]}
+    first = []
+    for _ in range(reps):
+        run_lane(ln)
+        torch.cuda.synchronize()
+        t0 = min(int(a["out"]["stamps"][0]) for a in ln["arrays"])
+        first.append(t0)
+        for a in ln["arrays"]:
+            s = a["out"]["stamps"].cpu().numpy()
+            lat[a["name"]].append((int(s[1:].max()) - t0) / hz * 1e3)
+    for a in ln["arrays"]:
+        a["out"].pop("stamps")
+    return {k: {"p50_ms": float(np.percentile(v, 50)), "p99_ms": float(np.percentile(v, 99)),
+                "reps": len(v), "source": "device wall-clock stamps (rrc_io.d_stamps)"} for k, v in lat.items()}
+
+
+def plain_per_channel(S, w, rrc, dev, max_units):
+    """One plan per channel, host synchronisation after each channel; time
+    per channel on the first `max_units` channels, scaled to all."""
+    import torch
+    res = []
+    for a in S["arrays"]:
+        p1 = rrc.Plan(a["n"], a["types"], 1, w.n_time, dtype=S["dtype"])
+        o1 = p1.alloc_outputs(dev)
+        nc = w.n_chan if max_units <= 0 else min(w.n_chan, max_units)
+        nc = min(nc, 256)
+        for c in range(min(2, nc)):
+            p1.run(a["volt"][c:c + 1], gains_in=a["gains_in"][c:c + 1], mode="pipelined", out=o1)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(args.plain_steps):
-            for a, p1, o1 in plain1:
-                for c in range(w.n_chan):
-                    p1.run(a["volt"][c:c + 1], gains_in=a["gains_in"][c:c + 1], mode="pipelined", out=o1)
-                    torch.cuda.synchronize()
-        plain_ms = (time.perf_counter() - t0) * 1e3 / args.plain_steps
+        for c in range(nc):
+            p1.run(a["volt"][c:c + 1], gains_in=a["gains_in"][c:c + 1], mode="pipelined", out=o1)
+            torch.cuda.synchronize()
+        res.append((time.perf_counter() - t0) / nc * w.n_chan)
+    return sum(res) * 1e3, min(w.n_chan, 256 if max_units <= 0 else min(max_units, 256))
 
-    # roofline of the FFT-correlator stage (the O(N log N) core)
+
+# ------------------------------------------------------------- oracle legs
+
+def unpack(volt_u):
+    from synthdata import unpack_ci4
+    re, im = unpack_ci4(volt_u)
+    return re, im
+
+
+def gate_units(S, w, n_units):
+    """Accuracy gate on seeded units: V^reduced (bit for bit for 4-bit data,
+    else against the FP64 X-engine), the solved gains against the oracle's
+    solve of the oracle's own V^reduced (identical integers for 4-bit data,
+    FP64 sums for float), V^unique against eq. modelvis with the gains the
+    FFT applied (every lag up to 32x32 grids; sampled lags from exact
+    integer correlations beyond)."""
+    from oracle import correlator as OC
+    from oracle import geometry as OG
+    from oracle import redcal as OR
+    rep = {"units": [], "vred_bit_exact": None, "vred_max_rel": 0.0, "gains_max_rel": 0.0,
+           "vunique_max_rel_l2": 0.0, "vunique_sampled_lag_max": None, "tol_gains": 1e-6,
+           "tol_vunique": 1e-5, "status_nonzero": 0}
+    per = max(1, n_units // len(S["arrays"]))
+    exact = True
+    for a in S["arrays"]:
+        n, types = a["n"], a["types"]
+        pos = OG.square_positions(n)
+        idx = OG.PositionIndex(pos)
+        pairs, tix = OG.group_pairs(pos, types)
+        lags = OC.canonical_lags(n)
+        out = a["out"]
+        rep["status_nonzero"] += int((out["status"] != 0).sum())
+        for u in a["sample"][:per]:
+            g_in = a["gains_in"][u].cpu().numpy().astype(np.complex128)
+            vr_gpu = out["vred"][u].cpu().numpy()
+            if S["dtype"] == "ci4":
+                re, im = unpack(a["volt"][u].cpu().numpy())
+                sums = OC.xengine_int(re, im, pairs)
+                exact &= bool(np.array_equal(vr_gpu.astype(np.int64), sums))
+                vref = sums[:, 0] + 1j * sums[:, 1]
+                # V^unique at sampled lags from exact integer correlations
+                N, T = n * n, w.n_time
+                rng = np.random.default_rng(u)
+                pick = sorted(set([0, 1, n - 1, n, 2 * n]) | set(rng.choice(len(lags), 11, replace=False).tolist()))
+                sel = [lags[k] for k in pick]
+                vfull = np.zeros((N, N), dtype=np.complex128)
+                for dx, dy in sel:
+                    i, j = idx.pairs_of(dx, dy)
+                    s = OC.xengine_int(re, im, np.stack([i, j], axis=1))
+                    vfull[i, j] = (s[:, 0] + 1j * s[:, 1]) / T
+                d = np.arange(N)
+                s = OC.xengine_int(re, im, np.stack([d, d], axis=1))
+                vfull[d, d] = s[:, 0] / T
+                ref = OC.redundant_average(vfull, g_in, pos, sel)
+                aref = OC.calibrated_auto(vfull, g_in)
+                got = out["vunique"][u].cpu().numpy()[pick]
+                nd = np.array([len(idx.pairs_of(dx, dy)[0]) for dx, dy in sel])
+                # error uniform in the un-normalised correlation N_d T V(d)
+                errn = float(np.max(np.abs(got - ref) * nd / (N * aref)))
+                rep["vunique_sampled_lag_max"] = max(rep["vunique_sampled_lag_max"] or 0.0, errn)
+                short = [k for k, (dx, dy) in enumerate(sel) if abs(dx) + dy <= 2]
+                e = float(np.linalg.norm(got[short] - ref[short]) / np.linalg.norm(ref[short]))
+                rep["vunique_max_rel_l2"] = max(rep["vunique_max_rel_l2"], e)
+            else:
+                v = a["volt"][u].cpu().numpy().astype(np.complex128)
+                vf = OC.fx_correlate(v)
+                vref = OC.xengine(vf, pairs)
+                sc = np.mean(np.abs(v) ** 2)
+                rep["vred_max_rel"] = max(rep["vred_max_rel"], float(np.max(np.abs(vr_gpu - vref)) / sc))
+                ref = OC.redundant_average(vf, g_in, pos, lags)
+                e = float(np.linalg.norm(out["vunique"][u].cpu().numpy() - ref) / np.linalg.norm(ref))
+                rep["vunique_max_rel_l2"] = max(rep["vunique_max_rel_l2"], e)
+            sol = OR.calibrate(vref, pos, types, pairs, tix)
+            g = out["gains"][u].cpu().numpy().astype(np.complex128)
+            rep["gains_max_rel"] = max(rep["gains_max_rel"], float(np.max(np.abs(g - sol["g"]) / np.abs(sol["g"]))))
+            rep["units"].append(f"{a['name']}:{u}")
+    if S["dtype"] == "ci4":
+        rep["vred_bit_exact"] = exact
+        rep.pop("vred_max_rel")
+    else:
+        rep["tol_gains"] = 1e-4      # whole float path: FP32 X-engine, then the solve
+        rep.pop("vunique_sampled_lag_max")
+    rep["n_units"] = len(rep["units"])
+    return rep
+
+
+def cpu_baseline(S, w, budget_s):
+    """The FP64 oracle as it stands on a bounded sample of the same units:
+    FX correlator (zgemm), X-engine, FIRSTCAL + Gauss-Newton to 1e-10,
+    degeneracy fix, eq. modelvis average over every lag.  Whole units, one
+    at a time, until at least min(10 s, budget) of work; at 4096 antennas a
+    unit alone takes longer, so one unit is run.  Also a one-thread figure:
+    the same unit with BLAS limited to one thread, its FX correlation timed
+    on 1/16 of the samples and scaled by 16 (zgemm cost is linear in T)."""
+    import threadpoolctl
+    from oracle import correlator as OC
+    from oracle import geometry as OG
+    from oracle import redcal as OR
+    a = S["arrays"][-1]
+    n, types = a["n"], a["types"]
+    pos = OG.square_positions(n)
+    pairs, tix = OG.group_pairs(pos, types)
+    lags = OC.canonical_lags(n)
+
+    def volt64(u):
+        vv = a["volt"][u].cpu().numpy()
+        if vv.dtype == np.uint8:
+            re, im = unpack(vv)
+            return re.astype(np.float64) + 1j * im.astype(np.float64)
+        return vv.astype(np.complex128)
+
+    def one_unit(v, t_fx_scale=1):
+        t = time.perf_counter()
+        vf = OC.fx_correlate(v)
+        t_fx = (time.perf_counter() - t) * t_fx_scale
+        t = time.perf_counter()
+        vred = OC.xengine(vf, pairs)
+        cal = OR.calibrate(vred, pos, types, pairs, tix)
+        OC.redundant_average(vf, cal["g"], pos, lags)
+        return t_fx + (time.perf_counter() - t)
+
+    done, t_all = 0, 0.0
+    min_s = min(10.0, budget_s)
+    for u in a["sample"]:
+        t_all += one_unit(volt64(u))
+        done += 1
+        if t_all >= min_s or t_all * (done + 1) / done > budget_s:
+            break
+    info = threadpoolctl.threadpool_info()
+    threads = max([i.get("num_threads", 1) for i in info] + [1])
+    v = volt64(a["sample"][0])
+    with threadpoolctl.threadpool_limits(1):
+        t1 = one_unit(v[: max(1, v.shape[0] // 16)], t_fx_scale=16)
+    return {"value": done / t_all, "unit": "calibrated channel-integrations/s", "cores": threads,
+            "kind": "oracle", "os_cpu_count": os.cpu_count(),
+            "one_thread_value": 1.0 / t1,
+            "sample": f"{done} whole unit(s) of array {a['name']} of {w.name}, one at a time ({t_all:.1f} s, "
+                      f"BLAS on {threads} threads): FX correlator (zgemm), X-engine gather, FIRSTCAL + "
+                      f"Gauss-Newton to 1e-10, degeneracy fix, eq. modelvis average; one-thread figure: one "
+                      f"unit, FX correlation on 1/16 of the samples scaled by 16"}
+
+
+# ------------------------------------------------------------------ record
+
+def measure(w, args, rrc, dev, with_oracle):
+    S = setup(w, dev, rrc, args.inflight, args.order)
+    ms = time_steps(S, args.steps, args.warmup)
+    total_units = w.n_chan * len(S["arrays"])
+    import torch
+    serial_ms = time_fn(lambda: run_lane(S["lanes"][0]), args.steps)
+    stages = stage_times(S, w, max(3, min(args.steps, 20)))
+    flops = sum(fft_flops_per_sample(a["n"]) * w.n_time * w.n_chan for a in S["arrays"])
+    vbytes = sum((1.0 if w.ci4 else 8.0) * a["n"] ** 2 * w.n_time * w.n_chan for a in S["arrays"])
     fft_s = stages["fftcorr"] * 1e-3
-    roof = {"bound": "alu", "achieved": flops / fft_s / 1e12, "peak": VALU_FP32_PEAK_TFLOPS,
-            "unit": "TFLOP/s", "frac": flops / fft_s / 1e12 / VALU_FP32_PEAK_TFLOPS,
-            "traffic": measured_traffic(w.name) if len(arrays) == 1 else None,
-            "algorithmic_bytes": vbytes,
-            "kernel": "k_fftcorr + k_fftfin_fft (FFT-correlator stage)",
-            "hbm_achieved_GBs": vbytes / fft_s / 1e9, "hbm_frac": vbytes / fft_s / 1e9 / HBM_PEAK_GBS}
-    # the other two stages: the X-engine streams the same voltages (HBM roof);
-    # the solve runs one workgroup per unit and is bound by the latency of
-    # its serial CG iterations, so its figure is time per unit and CU usage
     x_s = stages["xengine"] * 1e-3
+    tf = flops / fft_s / 1e12
+    gbs = vbytes / fft_s / 1e9
+    # the roof that binds: flop/B of the stage against the ridge of the
+    # non-packed FP32 VALU and HBM peaks (9.8 flop/B)
+    alu = flops / vbytes > VALU_FP32_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
+    kernel = "FFT-correlator stage (k_fftcorr_q + k_fftfin)" if max(a["n"] for a in S["arrays"]) > 32 else \
+        "FFT-correlator stage (k_fftcorr + k_fftfin_fft)"
+    traffic = measured_traffic(w.name) if len(S["arrays"]) == 1 else None
+    if alu:
+        roof = {"bound": "alu", "achieved": tf, "peak": VALU_FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": tf / VALU_FP32_PEAK_TFLOPS, "traffic": traffic}
+    else:
+        roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": gbs / HBM_PEAK_GBS, "traffic": traffic}
+    roof.update({"kernel": kernel, "ms_per_launch": stages["fftcorr"], "units_per_launch": total_units,
+                 "algorithmic_flops_per_launch": flops, "algorithmic_bytes_per_launch": vbytes,
+                 "hbm_achieved_GBs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS,
+                 "valu_achieved_TFLOPs": tf, "valu_frac": tf / VALU_FP32_PEAK_TFLOPS})
     other = [
-        {"kernel": "k_xant + k_xfin (reduced X-engine)", "bound": "hbm",
+        {"kernel": "k_xant + k_xfin (reduced X-engine)", "bound": "hbm", "ms_per_launch": stages["xengine"],
          "achieved": vbytes / x_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-         "frac": vbytes / x_s / 1e9 / HBM_PEAK_GBS, "algorithmic_bytes": vbytes},
+         "frac": vbytes / x_s / 1e9 / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": vbytes},
         {"kernel": "k_solve (reduced redundant calibration)", "bound": "latency",
-         "ms_per_launch": stages["solve"], "units_per_launch": total_units,
-         "workgroups_per_unit": 1, "cus": cus},
+         "ms_per_launch": stages["solve"], "units_per_launch": total_units, "workgroups_per_unit": 1,
+         "cus": S["cus"]},
     ]
-
-    status_nonzero = int(sum(int((a["out"]["status"] != 0).sum()) for a in arrays))
-    cpu, gate = None, None
-    if not args.no_cpu_baseline:
-        for a in arrays:
-            a["volt_host"] = (lambda u, a=a: a["volt"][u].cpu().numpy())
-            a["vred_gpu"] = (lambda u, a=a: (lambda x: x[..., 0] + 1j * x[..., 1] if x.ndim == 2 else x)(
-                a["out"]["vred"][u].cpu().numpy()).astype(np.complex128))
-            a["gains_gpu"] = (lambda u, a=a: a["out"]["gains"][u].cpu().numpy().astype(np.complex128))
-        cpu, gate = cpu_baseline(arrays, args.cpu_seconds, gate_units=4)
-
-    n0 = arrays[0]["n"]
+    plain_ms, plain_n = plain_per_channel(S, w, rrc, dev, args.plain_units)
     rec = {
-        "metric": METRIC,
-        "value": value, "unit": "channel-integrations/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "ci4->i32/f32" if w.ci4 else "f32",
-        "data": "synthetic" + ("" if host_gen else " (drawn on the GPU)"),
-        "config": {"workload": w.name, "grids": [f"{a['n']}x{a['n']}" for a in arrays],
-                   "antennas": [a["n"] ** 2 for a in arrays], "channels": w.n_chan, "samples": w.n_time,
-                   "fft_size": [a["plan"].info["fft_size"] for a in arrays],
-                   "types": [len(a["types"]) for a in arrays], "pairs": [a["npairs"] for a in arrays],
-                   "mode": "pipelined, all channels per launch" + (", arrays concurrently" if batch else ""),
-                   "batches_in_flight": D,
-                   "parallelism": "none (1 GPU)"},
+        "value": total_units / (ms * 1e-3), "ms_per_step": ms,
+        "config": {"workload": w.name, "grids": [f"{a['n']}x{a['n']}" for a in S["arrays"]],
+                   "antennas": [a["n"] ** 2 for a in S["arrays"]], "channels": w.n_chan, "samples": w.n_time,
+                   "voltage_format": "ci4" if w.ci4 else "complex64",
+                   "fft_size": [a["plan"].info["fft_size"] for a in S["arrays"]],
+                   "types": [len(a["types"]) for a in S["arrays"]], "pairs": [a["npairs"] for a in S["arrays"]],
+                   "mode": "pipelined, all channels per launch" +
+                           (", arrays as one captured graph" if len(S["arrays"]) > 1 else ""),
+                   "branch_order": S["order"], "batches_in_flight": S["D"], "parallelism": "none (1 GPU)"},
         "stages_ms": stages,
         "one_batch_at_a_time": {"ms_per_step": serial_ms, "value": total_units / (serial_ms * 1e-3)},
-        "plain_per_channel": None if plain_ms is None else
-        {"ms_per_step": plain_ms, "value": total_units / (plain_ms * 1e-3), "speedup_batched": plain_ms / ms},
-        "gain_error_vs_oracle": None if gate is None else dict(gate, status_nonzero=status_nonzero),
+        "plain_per_channel": {"ms_per_step": plain_ms, "value": total_units / (plain_ms * 1e-3),
+                              "speedup_batched": plain_ms / ms, "channels_timed_per_array": plain_n,
+                              "form": "one plan per channel, host synchronisation after each channel"},
         "roofline": roof,
         "roofline_other": other,
-        "cpu_baseline": cpu,
+        "data": "synthetic" + ("" if S["host_gen"] else " (drawn on the GPU)"),
     }
-    if latency:
-        rec["per_array_latency"] = latency
-    if n0 and len(arrays) == 1:
-        rec["config"].update({"grid": f"{n0}x{n0}", "antennas": n0 * n0})
+    if len(S["arrays"]) > 1:
+        rec["per_array_latency"] = latency_from_stamps(S, args.latency_reps)
+    if with_oracle:
+        rec["gate"] = gate_units(S, w, args.gate_units)
+        rec["cpu_baseline"] = cpu_baseline(S, w, 30.0)
+    for ln in S["lanes"]:
+        for a in ln["arrays"]:
+            del a["volt"]
+    del S
+    torch.cuda.empty_cache()
+    return rec
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for {args.gpus}); units shard across GPUs "
+              f"with no collective, so the per-GPU figure is the one to scale.", file=sys.stderr)
+        sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
+    import torch
+    import paper_2005_03060_amd as rrc
+    from synthdata import WORKLOADS
+
+    wl = {x.name: x for x in WORKLOADS}
+    w = wl[args.workload]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    r = measure(w, args, rrc, dev, with_oracle=not args.no_cpu_baseline)
+    rec = {
+        "metric": METRIC,
+        "value": r["value"], "unit": "channel-integrations/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": r["data"], "config": r["config"],
+        "stages_ms": r["stages_ms"], "one_batch_at_a_time": r["one_batch_at_a_time"],
+        "plain_per_channel": r["plain_per_channel"], "roofline": r["roofline"],
+        "roofline_other": r["roofline_other"],
+        "gate": r.get("gate"), "cpu_baseline": r.get("cpu_baseline"),
+    }
+    if "per_array_latency" in r:
+        rec["per_array_latency"] = r["per_array_latency"]
+    if args.workload == DEFAULT_WORKLOAD and not args.no_extra:
+        a2 = argparse.Namespace(**vars(args))
+        a2.steps = max(args.steps, 20)
+        a2.gate_units = min(args.gate_units, 8)
+        x = measure(wl[EXTRA_WORKLOAD], a2, rrc, dev, with_oracle=False)
+        rec["extra"] = {EXTRA_WORKLOAD: {k: x[k] for k in ("value", "ms_per_step", "config", "stages_ms",
+                                                           "roofline", "roofline_other", "plain_per_channel")}}
     print(json.dumps(rec), flush=True)
 
 

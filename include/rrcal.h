@@ -42,6 +42,14 @@
  * the stream reaches that point.  A plan (and its workspace) may be used by
  * one stream at a time.
  *
+ * Devices: plan creation is host only.  The first call that enqueues device
+ * work (or rrc_plan_prepare) binds the plan to the device current then and
+ * makes its device resources there: one auxiliary stream and two events
+ * (default priority), the device's CU count, the solve kernel's LDS limit.
+ * After that, device calls only enqueue kernel launches and event
+ * operations, so a caller may capture them into a HIP graph.  Use a plan
+ * on the device it is bound to.
+ *
  * Errors: every int-returning call returns RRC_OK (0) or a negative code
  * (rrc_strerror() names it).  Invalid arguments are detected on the host
  * before anything is enqueued.  Numerical outcomes of the solve (not
@@ -121,7 +129,7 @@ typedef struct {
  * sqrt(cg_tol)) divides what is left by about 1/sqrt(cg_tol). */
 void rrc_default_opts(rrc_solver_opts* opts);
 
-/* Subset redundant-calibration selection (Sec. 5.1, Sec. 5.4
+/* Subset redundant-calibration selection (Sec. 5.1, Sec. 5.5
  * eq. subredcal_frac_bls, Sec. 6.1): whole redundant groups in ascending
  * baseline length (ties: dy, then dx), the prefix whose pair count is
  * closest to p N log_b N (ties to the shorter prefix), extended until the
@@ -150,6 +158,20 @@ int rrc_plan_create(rrc_plan** out, int32_t n, const int32_t* types_xy, int32_t 
 void rrc_plan_destroy(rrc_plan* plan);
 int rrc_plan_get_info(const rrc_plan* plan, rrc_plan_info* info);
 int rrc_workspace_size(const rrc_plan* plan, size_t* bytes);
+
+/* Bind the plan to the current device and make its device resources now
+ * (see "Devices" above); idempotent. */
+int rrc_plan_prepare(rrc_plan* plan);
+
+/* Order of the pipelined run's two branches (see rrc_run):
+ * RRC_ORDER_XENG_FIRST (default): X-engine, then the FFT-correlator forked
+ *   beside the solve -- for FFT stages that are short or HBM-bound;
+ * RRC_ORDER_FFT_FIRST: the FFT-correlator forked first, the X-engine and
+ *   the solve beside it -- for a VALU-bound FFT stage that dominates.
+ * Results are identical either way. */
+#define RRC_ORDER_XENG_FIRST 0
+#define RRC_ORDER_FFT_FIRST  1
+int rrc_plan_set_order(rrc_plan* plan, int32_t order);
 
 /* (a1)-(a3) FFT-correlator (Fig. 1(b) yellow box; Sec. 2 eq. modelvis).
  * d_volt:   [U][T][N] voltages (complex64, or 1 byte each for RRC_CI4).
@@ -203,14 +225,19 @@ int rrc_chisq_adj(rrc_plan* plan, void* stream, const void* d_g, const void* d_v
  * mode RRC_RUN_PIPELINED: the FFT-correlator applies d_gains_in (the
  *   previous integration's solution, Fig. 1 real-time loop) while the
  *   X-engine and the solve run on the same voltages; the solved gains are
- *   for the next integration.  After the X-engine the FFT-correlator is
- *   forked onto a stream the plan owns (created on first use on the current
- *   device, default priority), runs beside the solve, and is joined back
- *   into `stream` with events, so all outputs are ordered on `stream` as
- *   usual.
+ *   for the next integration.  The FFT-correlator runs on the plan's
+ *   auxiliary stream, forked from `stream` after the X-engine (or before it,
+ *   see rrc_plan_set_order) and joined back into it with events, so all
+ *   outputs are ordered on `stream` as usual.  d_gains_out may be the same
+ *   buffer as d_gains_in (the loop feeding its solution back): the FFT then
+ *   reads a copy of the gains taken in the workspace before the solve.
  * mode RRC_RUN_SELFCAL: X-engine, solve, then the FFT-correlator applies the
  *   just-solved gains (reads the voltages twice).
- * Outputs as in the calls above; d_gains_in may be NULL in SELFCAL mode. */
+ * Outputs as in the calls above; d_gains_in may be NULL in SELFCAL mode.
+ * d_stamps (optional, may be NULL): [1 + U] uint64 device-clock stamps --
+ *   d_stamps[0] when the run starts on the device, d_stamps[1 + u] when the
+ *   last of unit u's outputs (solve, V^unique) is written; ticks of the
+ *   constant-rate wall clock, rrc_wall_clock_hz() per second. */
 #define RRC_RUN_PIPELINED 1
 #define RRC_RUN_SELFCAL   2
 typedef struct {
@@ -226,26 +253,39 @@ typedef struct {
     int32_t* d_niter;
     int32_t* d_status;
     void*    d_work;
+    uint64_t* d_stamps;
 } rrc_io;
 int rrc_run(rrc_plan* plan, void* stream, int32_t mode, const rrc_io* io);
 
 /* A batch of plans (one per array; grids, channels and sample counts may
  * differ) whose hot paths run together: the uneven-batch case of several
- * arrays calibrated at once.  The plans must be distinct and outlive the
- * batch.  Host only; owns streams and events. */
+ * arrays calibrated at once (Fig. 1 real-time loop over every channel of
+ * every array).  The plans must be distinct and outlive the batch.  Host
+ * only; owns streams, events and (RRC_BATCH_GRAPH) a HIP graph.
+ * flags: 0, or RRC_BATCH_GRAPH to replay the whole batch as one captured
+ * graph launch (below). */
+#define RRC_BATCH_GRAPH 1u
 typedef struct rrc_batch rrc_batch;
-int rrc_batch_create(rrc_batch** out, int32_t n_plans, rrc_plan* const* plans);
+int rrc_batch_create(rrc_batch** out, int32_t n_plans, rrc_plan* const* plans, uint32_t flags);
 void rrc_batch_destroy(rrc_batch* batch);
 
 /* rrc_run(plans[i], ..., mode, &io[i]) for every plan, in one call on
  * `stream`: each plan runs on its own branch stream (owned by the batch,
- * created on first use on the current device, default priority), forked
+ * made at the first run on the current device, default priority), forked
  * from `stream` and joined back into it with events, so the arrays run
  * concurrently and all outputs are ordered on `stream`.  With more units in
- * the batch than compute units the solves share CUs.  Asynchronous like
- * rrc_run; one batch may be run by one stream at a time, and its plans must
- * not be run concurrently on other streams. */
+ * the batch than compute units the solves share CUs.
+ * RRC_BATCH_GRAPH: the first run (and any run whose mode or io differs from
+ * the captured one) captures that sequence on a stream of the batch and
+ * instantiates it; every run then enqueues one graph launch on `stream`.
+ * The graph holds the io pointers it was captured with.
+ * Asynchronous like rrc_run; one batch may be run by one stream at a time,
+ * and its plans must not be run concurrently on other streams. */
 int rrc_batch_run(rrc_batch* batch, void* stream, int32_t mode, const rrc_io* io);
+
+/* Ticks per second of the device wall clock that d_stamps count (current
+ * device). */
+int rrc_wall_clock_hz(double* hz);
 
 const char* rrc_strerror(int code);
 

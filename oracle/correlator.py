@@ -60,14 +60,16 @@ def xengine_int(re: np.ndarray, im: np.ndarray, pairs: np.ndarray) -> np.ndarray
     [P, 2] int64 (real, imaginary).  q_i conj(q_j) = (a_i a_j + b_i b_j)
     + i (b_i a_j - a_i b_j) with q = a + i b.
     """
-    a = np.asarray(re, dtype=np.int64)
-    b = np.asarray(im, dtype=np.int64)
+    # antenna-major copies, so that a pair's samples are contiguous rows
+    a = np.ascontiguousarray(np.asarray(re, dtype=np.int64).T)
+    b = np.ascontiguousarray(np.asarray(im, dtype=np.int64).T)
     out = np.empty((len(pairs), 2), dtype=np.int64)
-    # slices of pairs bound the [T, pairs] gathers' memory
-    for s in range(0, len(pairs), 2048):
-        i, j = pairs[s:s + 2048, 0], pairs[s:s + 2048, 1]
-        out[s:s + 2048, 0] = np.einsum("tp,tp->p", a[:, i], a[:, j]) + np.einsum("tp,tp->p", b[:, i], b[:, j])
-        out[s:s + 2048, 1] = np.einsum("tp,tp->p", b[:, i], a[:, j]) - np.einsum("tp,tp->p", a[:, i], b[:, j])
+    # slices of pairs bound the [pairs, T] gathers' memory
+    for s in range(0, len(pairs), 1024):
+        i, j = pairs[s:s + 1024, 0], pairs[s:s + 1024, 1]
+        ai, aj, bi, bj = a[i], a[j], b[i], b[j]
+        out[s:s + 1024, 0] = np.einsum("pt,pt->p", ai, aj) + np.einsum("pt,pt->p", bi, bj)
+        out[s:s + 1024, 1] = np.einsum("pt,pt->p", bi, aj) - np.einsum("pt,pt->p", ai, bj)
     return out
 
 

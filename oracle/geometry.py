@@ -161,7 +161,7 @@ def nullity(pos: np.ndarray, types: Sequence[Tuple[int, int]]) -> Tuple[int, int
 
 
 def subset_budget(nant: int, p: float = 1.0, log_base: float = math.e) -> float:
-    """Pairs a p N log N calibrator can correlate (Sec. 5.4, eq. subredcal_frac_bls)."""
+    """Pairs a p N log N calibrator can correlate (Sec. 5.5, eq. subredcal_frac_bls)."""
     return p * nant * math.log(nant) / math.log(log_base)
 
 

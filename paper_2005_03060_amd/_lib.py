@@ -26,13 +26,17 @@ RRC_DEGEN_REFANT = 0
 RRC_DEGEN_MATCH = 1
 RRC_RUN_PIPELINED = 1
 RRC_RUN_SELFCAL = 2
+RRC_ORDER_XENG_FIRST = 0
+RRC_ORDER_FFT_FIRST = 1
+RRC_BATCH_GRAPH = 1
 RRC_MAX_TYPES = 16
 RRC_MAX_GRID = 64
 
 EXPORTS = ("rrc_default_opts", "rrc_select_subset", "rrc_degeneracy_count", "rrc_plan_create",
            "rrc_plan_destroy", "rrc_plan_get_info", "rrc_workspace_size", "rrc_fftcorr",
            "rrc_xengine", "rrc_solve", "rrc_chisq_fwd", "rrc_chisq_adj", "rrc_run", "rrc_strerror",
-           "rrc_batch_create", "rrc_batch_destroy", "rrc_batch_run")
+           "rrc_batch_create", "rrc_batch_destroy", "rrc_batch_run", "rrc_plan_prepare",
+           "rrc_plan_set_order", "rrc_wall_clock_hz")
 
 
 class SolverOpts(C.Structure):
@@ -52,7 +56,8 @@ class RunIO(C.Structure):
     _fields_ = [("d_volt", C.c_void_p), ("d_gains_in", C.c_void_p), ("d_gains_ref", C.c_void_p),
                 ("d_vunique", C.c_void_p), ("d_vauto", C.c_void_p), ("d_vred", C.c_void_p),
                 ("d_gains_out", C.c_void_p), ("d_vmodel", C.c_void_p), ("d_chisq", C.c_void_p),
-                ("d_niter", C.c_void_p), ("d_status", C.c_void_p), ("d_work", C.c_void_p)]
+                ("d_niter", C.c_void_p), ("d_status", C.c_void_p), ("d_work", C.c_void_p),
+                ("d_stamps", C.c_void_p)]
 
 
 class RRCError(RuntimeError):
@@ -90,9 +95,12 @@ def load_library() -> C.CDLL:
         "rrc_chisq_adj": (C.c_int, [vp, vp, vp, vp, vp, vp, vp, pf, pf]),
         "rrc_run": (C.c_int, [vp, vp, i32, C.POINTER(RunIO)]),
         "rrc_strerror": (C.c_char_p, [C.c_int]),
-        "rrc_batch_create": (C.c_int, [C.POINTER(vp), i32, C.POINTER(vp)]),
+        "rrc_batch_create": (C.c_int, [C.POINTER(vp), i32, C.POINTER(vp), C.c_uint32]),
         "rrc_batch_destroy": (None, [vp]),
         "rrc_batch_run": (C.c_int, [vp, vp, i32, C.POINTER(RunIO)]),
+        "rrc_plan_prepare": (C.c_int, [vp]),
+        "rrc_plan_set_order": (C.c_int, [vp, i32]),
+        "rrc_wall_clock_hz": (C.c_int, [C.POINTER(C.c_double)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

@@ -179,15 +179,22 @@ class Plan:
         return gg, gv, dg, dv
 
     def run_io(self, volt: torch.Tensor, gains_in: Optional[torch.Tensor], gains_ref: Optional[torch.Tensor],
-               out: Dict[str, torch.Tensor]) -> "L.RunIO":
-        """The rrc_io of one run (argument checks and marshalling only)."""
+               out: Dict[str, torch.Tensor], work: Optional[torch.Tensor] = None) -> "L.RunIO":
+        """The rrc_io of one run (argument checks and marshalling only).
+        `out` may hold "stamps": [1 + U] int64 (device-clock stamps)."""
         self._check_volt(volt)
         self._check_c64(gains_in, (self.n_units, self.n_ant), "gains_in")
         self._check_c64(gains_ref, (self.n_units, self.n_ant), "gains_ref")
+        st = out.get("stamps")
+        if st is not None and (tuple(st.shape) != (1 + self.n_units,) or st.dtype != torch.int64
+                               or not st.is_cuda or not st.is_contiguous()):
+            raise ValueError(f"stamps must be a contiguous int64 CUDA tensor of shape ({1 + self.n_units},)")
         dev = volt.device
+        if work is None:
+            work = self.workspace(dev)
         return L.RunIO(_ptr(volt), _ptr(gains_in), _ptr(gains_ref), _ptr(out["vunique"]), _ptr(out["vauto"]),
                        _ptr(out["vred"]), _ptr(out["gains"]), _ptr(out["vmodel"]), _ptr(out["chisq"]),
-                       _ptr(out["niter"]), _ptr(out["status"]), _ptr(self.workspace(dev)))
+                       _ptr(out["niter"]), _ptr(out["status"]), _ptr(work), _ptr(st))
 
     def run(self, volt: torch.Tensor, gains_in: Optional[torch.Tensor] = None,
             gains_ref: Optional[torch.Tensor] = None, mode: str = "pipelined",
@@ -198,6 +205,15 @@ class Plan:
         io = self.run_io(volt, gains_in, gains_ref, out)
         L.check(self._lib.rrc_run(self._h, _stream(), _MODES[mode], C.byref(io)), "rrc_run")
         return out
+
+    def set_order(self, order: str) -> None:
+        """Branch order of the pipelined run: "xeng_first" or "fft_first"."""
+        code = {"xeng_first": L.RRC_ORDER_XENG_FIRST, "fft_first": L.RRC_ORDER_FFT_FIRST}[order]
+        L.check(self._lib.rrc_plan_set_order(self._h, code), "rrc_plan_set_order")
+
+    def prepare(self) -> None:
+        """Bind the plan to the current device and make its device resources."""
+        L.check(self._lib.rrc_plan_prepare(self._h), "rrc_plan_prepare")
 
     def alloc_outputs(self, device) -> Dict[str, torch.Tensor]:
         U = self.n_units
@@ -218,13 +234,15 @@ class Batch:
     """Several plans (arrays of possibly different grids) run concurrently
     in one call (rrc_batch_run)."""
 
-    def __init__(self, plans: Sequence[Plan]):
+    def __init__(self, plans: Sequence[Plan], graph: bool = False):
         self._lib = L.load_library()
         self.plans = list(plans)           # kept alive for the batch's lifetime
         arr = (C.c_void_p * len(self.plans))(*[p._h.value for p in self.plans])
         h = C.c_void_p()
-        L.check(self._lib.rrc_batch_create(C.byref(h), len(self.plans), arr), "rrc_batch_create")
+        flags = L.RRC_BATCH_GRAPH if graph else 0
+        L.check(self._lib.rrc_batch_create(C.byref(h), len(self.plans), arr, flags), "rrc_batch_create")
         self._h = h
+        self._ios = None
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -242,7 +260,16 @@ class Batch:
         ios = (L.RunIO * len(self.plans))(*[p.run_io(v, gi, gr, o) for p, v, gi, gr, o
                                             in zip(self.plans, volts, gains_in, gains_ref, outs)])
         L.check(self._lib.rrc_batch_run(self._h, _stream(), _MODES[mode], ios), "rrc_batch_run")
+        self._ios = ios
         return outs
+
+
+def wall_clock_hz() -> float:
+    """Ticks per second of the device clock that run stamps count."""
+    lib = L.load_library()
+    hz = C.c_double()
+    L.check(lib.rrc_wall_clock_hz(C.byref(hz)), "rrc_wall_clock_hz")
+    return hz.value
 
 
 class ChiSq(torch.autograd.Function):

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -28,13 +29,18 @@ struct rrc_plan {
     bool solve_vcache;
     size_t solve_lds_bytes;
     // workspace layout
-    size_t off_fft, off_x, ws_bytes;
-    // fork/join of the pipelined run (created on first use, default priority)
+    size_t off_fft, off_x, off_gcopy, ws_bytes;
+    // pipelined run: the FFT-correlator forked after the X-engine (default)
+    // or before it (RRC_ORDER_FFT_FIRST)
+    int32_t order = RRC_ORDER_XENG_FIRST;
+    // device resources, made by prepare() on the first device call (the
+    // device current then): the fork/join stream and events of the
+    // pipelined run (default priority), the CU count, the solve's LDS limit
+    bool prepared = false;
+    int device = -1;
     hipStream_t aux = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-    int aux_device = -1;
-    // compute units of the device last launched on
-    int cu_count = 0, cu_device = -1;
+    int cu_count = 0;
     // units launched concurrently with this plan's (a batch sets the sum of
     // its plans'); the solve claims whole CUs only when they all fit
     long concurrent_units = 0;
@@ -42,10 +48,17 @@ struct rrc_plan {
 
 struct rrc_batch {
     std::vector<rrc_plan*> plans;
-    int device = -1;
+    uint32_t flags = 0;
+    bool prepared = false;
     std::vector<hipStream_t> branch;           // one per plan
     std::vector<hipEvent_t> ev_done;           // one per plan
     hipEvent_t ev_start = nullptr;
+    // RRC_BATCH_GRAPH: the stream the batch is captured on and the
+    // instantiated graph of the last (mode, io) captured
+    hipStream_t cap = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int32_t cap_mode = 0;
+    std::vector<rrc_io> cap_io;
 };
 
 namespace {
@@ -166,6 +179,36 @@ hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 int ceil_div(long a, long b) { return (int)((a + b - 1) / b); }
 
 }  // namespace
+
+namespace rrc {
+
+// stamps[0] = now; stamps[1 .. U] = 0 (raised by each stage's atomic max)
+__global__ __launch_bounds__(256) void k_stamp_start(unsigned long long* stamps, int n_units) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q == 0) stamps[0] = (unsigned long long)wall_clock64();
+    else if (q <= n_units) stamps[q] = 0ull;
+}
+
+hipError_t launch_stamp_start(unsigned long long* stamps, int n_units, hipStream_t st) {
+    hipLaunchKernelGGL(k_stamp_start, dim3((unsigned)((n_units + 256) / 256)), dim3(256), 0, st, stamps, n_units);
+    return hipGetLastError();
+}
+
+// Copy of n8 8-byte words (complex64 arrays), one per work-item.
+__global__ __launch_bounds__(256) void k_copy(uint2* __restrict__ dst, const uint2* __restrict__ src, size_t n8) {
+    const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n8) dst[q] = src[q];
+}
+
+hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st) {
+    const size_t n8 = bytes / 8;
+    if (n8 == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_copy, dim3((unsigned)((n8 + 255) / 256)), dim3(256), 0, st, static_cast<uint2*>(dst),
+                       static_cast<const uint2*>(src), n8);
+    return hipGetLastError();
+}
+
+}  // namespace rrc
 
 extern "C" {
 
@@ -335,37 +378,62 @@ int rrc_plan_create(rrc_plan** out, int32_t n, const int32_t* types_xy, int32_t 
     off = align256(off + (size_t)n_units * p->fft_nchunk * M * M * sizeof(float));
     p->off_x = off;
     off = align256(off + (p->x_nchunk > 1 ? (size_t)n_units * p->x_nchunk * s.P * 8 : 0));
+    p->off_gcopy = off;                      // copy of gains_in when it aliases gains_out
+    off = align256(off + (size_t)n_units * s.N * 8);
     p->ws_bytes = off;
     *out = p;
     return RRC_OK;
 }
 
-static void release_aux(rrc_plan* p) {
+static void release_device(rrc_plan* p) {
     if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
     if (p->ev_join) (void)hipEventDestroy(p->ev_join);
     if (p->aux) (void)hipStreamDestroy(p->aux);
     p->aux = nullptr;
     p->ev_fork = p->ev_join = nullptr;
-    p->aux_device = -1;
+    p->prepared = false;
+    p->device = -1;
 }
 
-// The auxiliary stream and events live on the device that is current.
-static bool ensure_aux(rrc_plan* p) {
-    int dev = -1;
-    if (hipGetDevice(&dev) != hipSuccess) return false;
-    if (p->aux && p->aux_device == dev) return true;
-    release_aux(p);
-    if (hipStreamCreateWithFlags(&p->aux, hipStreamNonBlocking) != hipSuccess) return false;
-    if (hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming) != hipSuccess) return false;
-    if (hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming) != hipSuccess) return false;
-    p->aux_device = dev;
-    return true;
+static rrc::SolveLaunch solve_launch(const rrc_plan* p);
+
+// Device resources of a plan, made once on the device current at the first
+// device call, so that later calls enqueue launches and event operations
+// only (and can be captured into a graph by the caller).
+static int prepare(rrc_plan* p) {
+    if (p->prepared) return RRC_OK;
+    int dev = -1, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return RRC_EDEVICE;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return RRC_EDEVICE;
+    if (hipStreamCreateWithFlags(&p->aux, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming) != hipSuccess ||
+        rrc::prepare_solve(solve_launch(p)) != hipSuccess) {
+        release_device(p);
+        return RRC_EDEVICE;
+    }
+    p->cu_count = cus;
+    p->device = dev;
+    p->prepared = true;
+    return RRC_OK;
 }
 
 void rrc_plan_destroy(rrc_plan* p) {
     if (!p) return;
-    release_aux(p);
+    release_device(p);
     delete p;
+}
+
+int rrc_plan_set_order(rrc_plan* p, int32_t order) {
+    if (!p || (order != RRC_ORDER_XENG_FIRST && order != RRC_ORDER_FFT_FIRST)) return RRC_EINVAL;
+    p->order = order;
+    return RRC_OK;
+}
+
+int rrc_plan_prepare(rrc_plan* p) {
+    if (!p) return RRC_EINVAL;
+    return prepare(p);
 }
 
 int rrc_plan_get_info(const rrc_plan* p, rrc_plan_info* info) {
@@ -390,10 +458,11 @@ int rrc_workspace_size(const rrc_plan* p, size_t* bytes) {
     return RRC_OK;
 }
 
-int rrc_fftcorr(rrc_plan* p, void* stream, const void* d_volt, const void* d_gains, void* d_vunique,
-                float* d_vauto, void* d_work) {
+static int fftcorr_impl(rrc_plan* p, void* stream, const void* d_volt, const void* d_gains,
+                        void* d_vunique, float* d_vauto, void* d_work, uint64_t* d_stamps) {
     if (!p || !d_volt || !d_gains || !d_vunique || !d_vauto || !d_work) return RRC_EINVAL;
-    rrc::FftLaunch L;
+    rrc::FftLaunch L{};
+    L.stamps = reinterpret_cast<unsigned long long*>(d_stamps);
     L.M = p->M;
     L.n = p->sel.n;
     L.T = p->T;
@@ -407,6 +476,11 @@ int rrc_fftcorr(rrc_plan* p, void* stream, const void* d_volt, const void* d_gai
     L.vunique = reinterpret_cast<float2*>(d_vunique);
     L.vauto = d_vauto;
     return rrc::launch_fftcorr(L, as_stream(stream)) == hipSuccess ? RRC_OK : RRC_EDEVICE;
+}
+
+int rrc_fftcorr(rrc_plan* p, void* stream, const void* d_volt, const void* d_gains, void* d_vunique,
+                float* d_vauto, void* d_work) {
+    return fftcorr_impl(p, stream, d_volt, d_gains, d_vunique, d_vauto, d_work, nullptr);
 }
 
 int rrc_xengine(rrc_plan* p, void* stream, const void* d_volt, void* d_vred, void* d_work) {
@@ -427,33 +501,29 @@ int rrc_xengine(rrc_plan* p, void* stream, const void* d_volt, void* d_vred, voi
     return rrc::launch_xengine(L, as_stream(stream)) == hipSuccess ? RRC_OK : RRC_EDEVICE;
 }
 
-int rrc_solve(rrc_plan* p, void* stream, const void* d_vred, const void* d_gains_in,
-              const void* d_gains_ref, void* d_gains_out, void* d_vmodel, float* d_chisq,
-              int32_t* d_niter, int32_t* d_status, void* d_work) {
-    if (!p || !d_vred || !d_gains_out || !d_vmodel || !d_chisq || !d_niter || !d_status || !d_work)
-        return RRC_EINVAL;
-    if (p->opts.init_mode == RRC_INIT_GAINS && !d_gains_in) return RRC_EINVAL;
-    if (p->opts.degen_mode == RRC_DEGEN_MATCH && !d_gains_ref) return RRC_EINVAL;
-    rrc::SolveLaunch L;
+static rrc::SolveLaunch solve_launch(const rrc_plan* p) {
+    rrc::SolveLaunch L{};
     L.sel = p->sel;
     L.n_units = p->U;
     L.ci4 = p->dtype == RRC_CI4;
     L.vcache = p->solve_vcache;
     L.lds_bytes = p->solve_lds_bytes;
-    {
-        int dev = 0;
-        if (hipGetDevice(&dev) != hipSuccess) return RRC_EDEVICE;
-        if (p->cu_device != dev) {
-            int cus = 0;
-            if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-                return RRC_EDEVICE;
-            p->cu_count = cus;
-            p->cu_device = dev;
-        }
-    }
-    L.exclusive = (p->concurrent_units > 0 ? p->concurrent_units : p->U) <= p->cu_count;
     L.o = {p->opts.init_mode, p->opts.degen_mode, p->opts.max_gn, p->opts.fp64_steps,
            p->opts.max_cg, p->opts.cg_tol, p->opts.tol32};
+    return L;
+}
+
+static int solve_impl(rrc_plan* p, void* stream, const void* d_vred, const void* d_gains_in,
+                      const void* d_gains_ref, void* d_gains_out, void* d_vmodel, float* d_chisq,
+                      int32_t* d_niter, int32_t* d_status, uint64_t* d_stamps) {
+    if (!p || !d_vred || !d_gains_out || !d_vmodel || !d_chisq || !d_niter || !d_status)
+        return RRC_EINVAL;
+    if (p->opts.init_mode == RRC_INIT_GAINS && !d_gains_in) return RRC_EINVAL;
+    if (p->opts.degen_mode == RRC_DEGEN_MATCH && !d_gains_ref) return RRC_EINVAL;
+    const int rc = prepare(p);
+    if (rc != RRC_OK) return rc;
+    rrc::SolveLaunch L = solve_launch(p);
+    L.exclusive = (p->concurrent_units > 0 ? p->concurrent_units : p->U) <= p->cu_count;
     L.vred = d_vred;
     L.gains_in = reinterpret_cast<const float2*>(d_gains_in);
     L.gains_ref = reinterpret_cast<const float2*>(d_gains_ref);
@@ -462,7 +532,16 @@ int rrc_solve(rrc_plan* p, void* stream, const void* d_vred, const void* d_gains
     L.chisq = d_chisq;
     L.niter = d_niter;
     L.status = d_status;
+    L.stamps = reinterpret_cast<unsigned long long*>(d_stamps);
     return rrc::launch_solve(L, as_stream(stream)) == hipSuccess ? RRC_OK : RRC_EDEVICE;
+}
+
+int rrc_solve(rrc_plan* p, void* stream, const void* d_vred, const void* d_gains_in,
+              const void* d_gains_ref, void* d_gains_out, void* d_vmodel, float* d_chisq,
+              int32_t* d_niter, int32_t* d_status, void* d_work) {
+    (void)d_work;   // the solve keeps its whole state in LDS
+    return solve_impl(p, stream, d_vred, d_gains_in, d_gains_ref, d_gains_out, d_vmodel, d_chisq,
+                      d_niter, d_status, nullptr);
 }
 
 static int chisq_common(rrc_plan* p, void* stream, const void* d_g, const void* d_vm,
@@ -503,57 +582,101 @@ int rrc_run(rrc_plan* p, void* stream, int32_t mode, const rrc_io* io) {
     if (!io->d_volt || !io->d_vunique || !io->d_vauto || !io->d_vred || !io->d_gains_out ||
         !io->d_vmodel || !io->d_chisq || !io->d_niter || !io->d_status || !io->d_work)
         return RRC_EINVAL;
-    hipStream_t st = as_stream(stream);
     if (p->opts.init_mode == RRC_INIT_GAINS && !io->d_gains_in) return RRC_EINVAL;
     if (p->opts.degen_mode == RRC_DEGEN_MATCH && !io->d_gains_ref) return RRC_EINVAL;
-    int rc = rrc_xengine(p, stream, io->d_volt, io->d_vred, io->d_work);
+    int rc = prepare(p);
     if (rc != RRC_OK) return rc;
-    if (mode == RRC_RUN_PIPELINED) {
-        // The FFT-correlator needs only the previous gains: once the X-engine
-        // (the head of the critical path) is done it runs on the auxiliary
-        // stream, beside the latency-bound solve on `stream`.  The solve is
-        // queued first: it follows the X-engine on its own stream and so
-        // takes its CUs before the FFT's workgroups fill the device.
-        if (!ensure_aux(p)) return RRC_EDEVICE;
-        if (hipEventRecord(p->ev_fork, st) != hipSuccess) return RRC_EDEVICE;
-    }
-    rc = rrc_solve(p, stream, io->d_vred, io->d_gains_in, io->d_gains_ref, io->d_gains_out,
-                   io->d_vmodel, io->d_chisq, io->d_niter, io->d_status, io->d_work);
-    if (rc != RRC_OK) return rc;
-    if (mode == RRC_RUN_PIPELINED) {
-        if (hipStreamWaitEvent(p->aux, p->ev_fork, 0) != hipSuccess) return RRC_EDEVICE;
-        rc = rrc_fftcorr(p, p->aux, io->d_volt, io->d_gains_in, io->d_vunique, io->d_vauto,
-                         io->d_work);
-        if (rc != RRC_OK) return rc;
-        if (hipEventRecord(p->ev_join, p->aux) != hipSuccess) return RRC_EDEVICE;
-    }
-    if (mode == RRC_RUN_SELFCAL) {
-        rc = rrc_fftcorr(p, stream, io->d_volt, io->d_gains_out, io->d_vunique, io->d_vauto,
-                         io->d_work);
-    } else if (hipStreamWaitEvent(st, p->ev_join, 0) != hipSuccess) {
+    hipStream_t st = as_stream(stream);
+    char* work = static_cast<char*>(io->d_work);
+    if (io->d_stamps && rrc::launch_stamp_start(reinterpret_cast<unsigned long long*>(io->d_stamps),
+                                                p->U, st) != hipSuccess)
         return RRC_EDEVICE;
+    if (mode == RRC_RUN_SELFCAL) {
+        // X-engine, solve, then the FFT-correlator with the solved gains
+        rc = rrc_xengine(p, stream, io->d_volt, io->d_vred, io->d_work);
+        if (rc == RRC_OK)
+            rc = solve_impl(p, stream, io->d_vred, io->d_gains_in, io->d_gains_ref, io->d_gains_out,
+                            io->d_vmodel, io->d_chisq, io->d_niter, io->d_status, io->d_stamps);
+        if (rc == RRC_OK)
+            rc = fftcorr_impl(p, stream, io->d_volt, io->d_gains_out, io->d_vunique, io->d_vauto,
+                              io->d_work, io->d_stamps);
+        return rc;
     }
-    return rc;
+    // PIPELINED.  The FFT-correlator applies the previous integration's gains
+    // on the plan's auxiliary stream, beside the X-engine and the solve on
+    // `stream`.  When gains_in and gains_out overlap (the real-time loop
+    // feeding the solution back), the solve would rewrite the gains while
+    // FFT workgroups still read them, so the FFT reads a copy taken first.
+    const void* gfft = io->d_gains_in;
+    {
+        const size_t gb = (size_t)p->U * p->sel.N * 8;
+        const char* gi = static_cast<const char*>(io->d_gains_in);
+        const char* go = static_cast<const char*>(io->d_gains_out);
+        if (gi < go + gb && go < gi + gb) {
+            void* copy = work + p->off_gcopy;
+            if (rrc::launch_copy(copy, io->d_gains_in, gb, st) != hipSuccess) return RRC_EDEVICE;
+            gfft = copy;
+        }
+    }
+    auto fork_fft = [&]() -> int {
+        if (hipEventRecord(p->ev_fork, st) != hipSuccess) return RRC_EDEVICE;
+        if (hipStreamWaitEvent(p->aux, p->ev_fork, 0) != hipSuccess) return RRC_EDEVICE;
+        const int r = fftcorr_impl(p, p->aux, io->d_volt, gfft, io->d_vunique, io->d_vauto, io->d_work,
+                                   io->d_stamps);
+        if (r != RRC_OK) return r;
+        return hipEventRecord(p->ev_join, p->aux) == hipSuccess ? RRC_OK : RRC_EDEVICE;
+    };
+    if (p->order == RRC_ORDER_FFT_FIRST) {
+        // a VALU-bound FFT stage that dominates the step starts at once; the
+        // X-engine and the solve follow on `stream` beside it
+        rc = fork_fft();
+        if (rc == RRC_OK) rc = rrc_xengine(p, stream, io->d_volt, io->d_vred, io->d_work);
+        if (rc == RRC_OK)
+            rc = solve_impl(p, stream, io->d_vred, io->d_gains_in, io->d_gains_ref, io->d_gains_out,
+                            io->d_vmodel, io->d_chisq, io->d_niter, io->d_status, io->d_stamps);
+    } else {
+        // The X-engine heads the critical path; once it is done the FFT
+        // runs beside the latency-bound solve.  The solve is queued first:
+        // it follows the X-engine on its own stream and so takes its CUs
+        // before the FFT's workgroups fill the device.
+        rc = rrc_xengine(p, stream, io->d_volt, io->d_vred, io->d_work);
+        if (rc != RRC_OK) return rc;
+        if (hipEventRecord(p->ev_fork, st) != hipSuccess) return RRC_EDEVICE;
+        rc = solve_impl(p, stream, io->d_vred, io->d_gains_in, io->d_gains_ref, io->d_gains_out,
+                        io->d_vmodel, io->d_chisq, io->d_niter, io->d_status, io->d_stamps);
+        if (rc != RRC_OK) return rc;
+        if (hipStreamWaitEvent(p->aux, p->ev_fork, 0) != hipSuccess) return RRC_EDEVICE;
+        rc = fftcorr_impl(p, p->aux, io->d_volt, gfft, io->d_vunique, io->d_vauto, io->d_work,
+                          io->d_stamps);
+        if (rc == RRC_OK && hipEventRecord(p->ev_join, p->aux) != hipSuccess) rc = RRC_EDEVICE;
+    }
+    if (rc != RRC_OK) return rc;
+    return hipStreamWaitEvent(st, p->ev_join, 0) == hipSuccess ? RRC_OK : RRC_EDEVICE;
 }
 
 // ------------------------------------------------------------------ batches
 
 static void batch_release(rrc_batch* b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    b->exec = nullptr;
+    b->cap_io.clear();
     for (hipEvent_t e : b->ev_done)
         if (e) (void)hipEventDestroy(e);
     for (hipStream_t s : b->branch)
         if (s) (void)hipStreamDestroy(s);
     if (b->ev_start) (void)hipEventDestroy(b->ev_start);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
     b->ev_done.clear();
     b->branch.clear();
     b->ev_start = nullptr;
-    b->device = -1;
+    b->cap = nullptr;
+    b->prepared = false;
 }
 
-int rrc_batch_create(rrc_batch** out, int32_t n_plans, rrc_plan* const* plans) {
+int rrc_batch_create(rrc_batch** out, int32_t n_plans, rrc_plan* const* plans, uint32_t flags) {
     if (!out) return RRC_EINVAL;
     *out = nullptr;
-    if (n_plans < 1 || !plans) return RRC_EINVAL;
+    if (n_plans < 1 || !plans || (flags & ~(uint32_t)RRC_BATCH_GRAPH)) return RRC_EINVAL;
     for (int i = 0; i < n_plans; ++i) {
         if (!plans[i]) return RRC_EINVAL;
         for (int j = 0; j < i; ++j)
@@ -562,6 +685,7 @@ int rrc_batch_create(rrc_batch** out, int32_t n_plans, rrc_plan* const* plans) {
     rrc_batch* b = new (std::nothrow) rrc_batch();
     if (!b) return RRC_ERANGE;
     b->plans.assign(plans, plans + n_plans);
+    b->flags = flags;
     *out = b;
     return RRC_OK;
 }
@@ -572,31 +696,34 @@ void rrc_batch_destroy(rrc_batch* b) {
     delete b;
 }
 
-int rrc_batch_run(rrc_batch* b, void* stream, int32_t mode, const rrc_io* io) {
-    if (!b || !io) return RRC_EINVAL;
+// Streams and events of a batch and of its plans, made on the first run.
+static int batch_prepare(rrc_batch* b) {
+    if (b->prepared) return RRC_OK;
     const int np = (int)b->plans.size();
-    int dev = -1;
-    if (hipGetDevice(&dev) != hipSuccess) return RRC_EDEVICE;
-    if (b->device != dev) {
-        batch_release(b);
-        if (hipEventCreateWithFlags(&b->ev_start, hipEventDisableTiming) != hipSuccess) {
-            batch_release(b);
-            return RRC_EDEVICE;
-        }
-        b->branch.assign(np, nullptr);
-        b->ev_done.assign(np, nullptr);
-        for (int i = 0; i < np; ++i) {
-            if (hipStreamCreateWithFlags(&b->branch[i], hipStreamNonBlocking) != hipSuccess ||
-                hipEventCreateWithFlags(&b->ev_done[i], hipEventDisableTiming) != hipSuccess) {
-                batch_release(b);
-                return RRC_EDEVICE;
-            }
-        }
-        b->device = dev;
+    for (rrc_plan* p : b->plans) {
+        const int rc = prepare(p);
+        if (rc != RRC_OK) return rc;
     }
+    b->branch.assign(np, nullptr);
+    b->ev_done.assign(np, nullptr);
+    bool ok = hipEventCreateWithFlags(&b->ev_start, hipEventDisableTiming) == hipSuccess &&
+              hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) == hipSuccess;
+    for (int i = 0; ok && i < np; ++i)
+        ok = hipStreamCreateWithFlags(&b->branch[i], hipStreamNonBlocking) == hipSuccess &&
+             hipEventCreateWithFlags(&b->ev_done[i], hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+        batch_release(b);
+        return RRC_EDEVICE;
+    }
+    b->prepared = true;
+    return RRC_OK;
+}
+
+// Fork every plan's run from `st` onto its branch stream and join them back.
+static int batch_issue(rrc_batch* b, hipStream_t st, int32_t mode, const rrc_io* io) {
+    const int np = (int)b->plans.size();
     long total = 0;
     for (rrc_plan* p : b->plans) total += p->U;
-    hipStream_t st = as_stream(stream);
     if (hipEventRecord(b->ev_start, st) != hipSuccess) return RRC_EDEVICE;
     for (int i = 0; i < np; ++i) {
         rrc_plan* p = b->plans[i];
@@ -610,6 +737,63 @@ int rrc_batch_run(rrc_batch* b, void* stream, int32_t mode, const rrc_io* io) {
             hipStreamWaitEvent(st, b->ev_done[i], 0) != hipSuccess)
             return RRC_EDEVICE;
     }
+    return RRC_OK;
+}
+
+static bool same_io(const std::vector<rrc_io>& a, const rrc_io* io) {
+    for (size_t i = 0; i < a.size(); ++i)
+        if (std::memcmp(&a[i], &io[i], sizeof(rrc_io)) != 0) return false;
+    return true;
+}
+
+int rrc_batch_run(rrc_batch* b, void* stream, int32_t mode, const rrc_io* io) {
+    if (!b || !io) return RRC_EINVAL;
+    if (mode != RRC_RUN_PIPELINED && mode != RRC_RUN_SELFCAL) return RRC_EINVAL;
+    int rc = batch_prepare(b);
+    if (rc != RRC_OK) return rc;
+    hipStream_t st = as_stream(stream);
+    if (!(b->flags & RRC_BATCH_GRAPH)) return batch_issue(b, st, mode, io);
+    const size_t np = b->plans.size();
+    if (!b->exec || b->cap_mode != mode || !same_io(b->cap_io, io)) {
+        // capture the whole fork/join sequence on the batch's own stream
+        // (never the caller's, which may be the null stream) and instantiate
+        if (b->exec) (void)hipGraphExecDestroy(b->exec);
+        b->exec = nullptr;
+        b->cap_io.clear();
+        if (hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return RRC_EDEVICE;
+        rc = batch_issue(b, b->cap, mode, io);
+        hipGraph_t g = nullptr;
+        const hipError_t ec = hipStreamEndCapture(b->cap, &g);
+        if (rc != RRC_OK || ec != hipSuccess || !g) {
+            if (ec != hipSuccess)
+                std::fprintf(stderr, "rrcal: batch capture failed: %s\n", hipGetErrorString(ec));
+            if (g) (void)hipGraphDestroy(g);
+            return rc != RRC_OK ? rc : RRC_EDEVICE;
+        }
+        // the error node and log are out-parameters the runtime writes when
+        // instantiation fails: they must point at storage
+        hipGraphNode_t err_node = nullptr;
+        char log[1024] = {0};
+        const hipError_t ei = hipGraphInstantiate(&b->exec, g, &err_node, log, sizeof(log));
+        (void)hipGraphDestroy(g);
+        if (ei != hipSuccess) {
+            std::fprintf(stderr, "rrcal: graph instantiation failed: %s %s\n", hipGetErrorString(ei), log);
+            b->exec = nullptr;
+            return RRC_EDEVICE;
+        }
+        b->cap_mode = mode;
+        b->cap_io.assign(io, io + np);
+    }
+    return hipGraphLaunch(b->exec, st) == hipSuccess ? RRC_OK : RRC_EDEVICE;
+}
+
+int rrc_wall_clock_hz(double* hz) {
+    if (!hz) return RRC_EINVAL;
+    int dev = -1, khz = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
+        return RRC_EDEVICE;
+    *hz = 1e3 * (double)khz;
     return RRC_OK;
 }
 

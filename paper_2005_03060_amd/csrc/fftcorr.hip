@@ -548,7 +548,8 @@ constexpr int kFinDxBlock = 32;
 template <int M>
 __global__ __launch_bounds__(kFinThreads) void k_fftfin(const float* __restrict__ ppart, int nchunk,
                                                         int n, int T, float2* __restrict__ vunique,
-                                                        float* __restrict__ vauto) {
+                                                        float* __restrict__ vauto,
+                                                        unsigned long long* __restrict__ stamps) {
     constexpr int NT = kFinThreads;
     constexpr int DB = kFinDxBlock;
     __shared__ float pw[M * M];
@@ -602,6 +603,7 @@ __global__ __launch_bounds__(kFinThreads) void k_fftfin(const float* __restrict_
         }
         __syncthreads();
     }
+    if (stamps && tid == 0) unit_done_stamp(stamps, unit);   // after the loop's last barrier
 }
 
 // Finish for M <= 64: one workgroup per unit, register FFTs (see
@@ -609,10 +611,15 @@ __global__ __launch_bounds__(kFinThreads) void k_fftfin(const float* __restrict_
 template <int M>
 __global__ __launch_bounds__(kFftThreads) void k_fftfin_fft(const float* __restrict__ ppart, int nchunk,
                                                             int n, int T, float2* __restrict__ vunique,
-                                                            float* __restrict__ vauto) {
+                                                            float* __restrict__ vauto,
+                                                            unsigned long long* __restrict__ stamps) {
     __shared__ float2 lds[M * (M + 1) + M * M];
     const int unit = blockIdx.x;
     inverse_to_lags<M>(lds, ppart + (size_t)unit * nchunk * (M * M), nchunk, n, T, vunique, vauto, unit);
+    if (stamps) {
+        __syncthreads();
+        if (threadIdx.x == 0) unit_done_stamp(stamps, unit);
+    }
 }
 
 template <bool CI4, int W>
@@ -646,10 +653,10 @@ static hipError_t launch_fft_m(const FftLaunch& L, hipStream_t st) {
     if (e != hipSuccess) return e;
     if constexpr (M <= 64) {
         hipLaunchKernelGGL((k_fftfin_fft<M>), dim3(L.n_units), dim3(kFftThreads), 0, st, L.ppart,
-                           L.nchunk, L.n, L.T, L.vunique, L.vauto);
+                           L.nchunk, L.n, L.T, L.vunique, L.vauto, L.stamps);
     } else {
         hipLaunchKernelGGL((k_fftfin<M>), dim3(L.n_units), dim3(kFinThreads), 0, st, L.ppart,
-                           L.nchunk, L.n, L.T, L.vunique, L.vauto);
+                           L.nchunk, L.n, L.T, L.vunique, L.vauto, L.stamps);
     }
     return hipGetLastError();
 }

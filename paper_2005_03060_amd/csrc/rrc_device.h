@@ -308,6 +308,16 @@ __device__ __forceinline__ double wave_sum_last(double v) {
 // ------------------------------------------------------------- geometry
 
 // The selected baseline-types of a plan, passed to kernels by value.
+#ifndef RRC_HOST_EMU
+// Per-unit completion stamps of a run: stamps[0] is the run's start and
+// stamps[1 + u] the latest completion time of unit u's outputs, in ticks of
+// the device's constant-rate wall clock.  Each stage that finishes a unit's
+// outputs raises its entry (an atomic max on a vector memory path).
+__device__ __forceinline__ void unit_done_stamp(unsigned long long* stamps, int unit) {
+    atomicMax(stamps + 1 + unit, (unsigned long long)wall_clock64());
+}
+#endif
+
 struct Sel {
     int n;                  // grid side
     int N;                  // n*n

@@ -18,6 +18,7 @@ struct FftLaunch {
     float* ppart;          // workspace: [U][nchunk][M][M]
     float2* vunique;
     float* vauto;
+    unsigned long long* stamps;   // optional [1 + U] run stamps (see unit_done_stamp)
 };
 
 struct XengLaunch {
@@ -54,6 +55,7 @@ struct SolveLaunch {
     float* chisq;
     int* niter;
     int* status;
+    unsigned long long* stamps;   // optional [1 + U] run stamps (see unit_done_stamp)
 };
 
 struct ChisqLaunch {
@@ -78,8 +80,11 @@ int xengine_antennas_per_block();
 int xengine_max_halo();
 int xengine_samples_per_step(bool ci4);
 size_t solve_lds_bytes(const Sel& s, bool vcache);
+hipError_t prepare_solve(const SolveLaunch& L);
 hipError_t launch_solve(const SolveLaunch& L, hipStream_t st);
 hipError_t launch_chisq(const ChisqLaunch& L, hipStream_t st, bool adjoint);
+hipError_t launch_stamp_start(unsigned long long* stamps, int n_units, hipStream_t st);
+hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st);
 #endif
 
 }  // namespace rrc

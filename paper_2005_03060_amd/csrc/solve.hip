@@ -1012,6 +1012,14 @@ __device__ __forceinline__ void solve_unit(const SolveLaunch& L, Shared<NT / 64>
         L.niter[unit] = steps;
         L.status[unit] = fin ? status : 2;
     }
+#ifndef RRC_HOST_EMU
+    if (L.stamps) {
+        // completion time of this unit's solve (every work-item's outputs
+        // are written before the barrier)
+        __syncthreads();
+        if (tid == 0) unit_done_stamp(L.stamps, unit);
+    }
+#endif
 }
 
 #ifndef RRC_HOST_EMU
@@ -1022,46 +1030,52 @@ __global__ __launch_bounds__(NT) void k_solve(SolveLaunch L) {
     solve_unit<NT, APT, KMAX>(L, sh, ssm, blockIdx.x);
 }
 
+// PREP: only raise the instantiation's dynamic-LDS limit to a whole CU's
+// (a host runtime call, made once per plan before any launch, so that the
+// launch path itself -- which a caller may capture into a graph -- makes
+// kernel launches only); otherwise launch.
 template <int NT, int APT, int KMAX>
-static hipError_t launch_solve_k(const SolveLaunch& L, hipStream_t st) {
+static hipError_t launch_solve_k(const SolveLaunch& L, hipStream_t st, bool prep) {
     auto kern = k_solve<NT, APT, KMAX>;
+    const size_t whole = kLdsPerCu - sizeof(Shared<NT / 64>);
+    if (prep)
+        return hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)whole);
     size_t lds = L.lds_bytes;
-    if (L.exclusive) {
-        // a unit per CU at most: claim the CU's whole LDS, so that kernels
-        // running beside the solve (the pipelined FFT) take other CUs
-        // instead of sharing this latency-bound workgroup's SIMDs
-        const size_t whole = kLdsPerCu - sizeof(Shared<NT / 64>);
-        if (whole > lds) lds = whole;
-    }
-    if (hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)lds) != hipSuccess)
-        return hipErrorInvalidValue;
+    // a unit per CU at most: claim the CU's whole LDS, so that kernels
+    // running beside the solve (the pipelined FFT) take other CUs instead of
+    // sharing this latency-bound workgroup's SIMDs
+    if (L.exclusive && whole > lds) lds = whole;
     hipLaunchKernelGGL(kern, dim3(L.n_units), dim3(NT), lds, st, L);
     return hipGetLastError();
 }
 
 template <int NT, int APT>
-static hipError_t launch_solve_shape(const SolveLaunch& L, hipStream_t st) {
-    if (L.sel.K <= 6) return launch_solve_k<NT, APT, 6>(L, st);
-    if (L.sel.K <= 8) return launch_solve_k<NT, APT, 8>(L, st);
-    if (L.sel.K <= 10) return launch_solve_k<NT, APT, 10>(L, st);
-    return launch_solve_k<NT, APT, kMaxTypes>(L, st);
+static hipError_t launch_solve_shape(const SolveLaunch& L, hipStream_t st, bool prep) {
+    if (L.sel.K <= 6) return launch_solve_k<NT, APT, 6>(L, st, prep);
+    if (L.sel.K <= 8) return launch_solve_k<NT, APT, 8>(L, st, prep);
+    if (L.sel.K <= 10) return launch_solve_k<NT, APT, 10>(L, st, prep);
+    return launch_solve_k<NT, APT, kMaxTypes>(L, st, prep);
 }
 
-hipError_t launch_solve(const SolveLaunch& L, hipStream_t st) {
+static hipError_t solve_dispatch(const SolveLaunch& L, hipStream_t st, bool prep) {
     const int N = L.sel.N;
     if (L.sel.K < 1 || L.sel.K > kMaxTypes || L.sel.K > solve_threads_for(N)) return hipErrorInvalidValue;
-    if (N <= 256) return launch_solve_shape<256, 1>(L, st);
-    if (N <= 512) return launch_solve_shape<512, 1>(L, st);
-    if (N <= 1024) return launch_solve_shape<1024, 1>(L, st);
+    if (N <= 256) return launch_solve_shape<256, 1>(L, st, prep);
+    if (N <= 512) return launch_solve_shape<512, 1>(L, st, prep);
+    if (N <= 1024) return launch_solve_shape<1024, 1>(L, st, prep);
     // larger grids: 512 work-items (256 VGPRs each) rather than 1024 (128),
     // with as few antennas per work-item as cover the grid (at 48 x 48, five
     // instead of eight take the solve from 3.5 to 1.2 ms: no spills)
-    if (N <= 2048) return launch_solve_shape<512, 4>(L, st);
-    if (N <= 2560) return launch_solve_shape<512, 5>(L, st);
-    if (N <= 4096) return launch_solve_shape<512, 8>(L, st);
+    if (N <= 2048) return launch_solve_shape<512, 4>(L, st, prep);
+    if (N <= 2560) return launch_solve_shape<512, 5>(L, st, prep);
+    if (N <= 4096) return launch_solve_shape<512, 8>(L, st, prep);
     return hipErrorInvalidValue;
 }
+
+hipError_t prepare_solve(const SolveLaunch& L) { return solve_dispatch(L, nullptr, true); }
+
+hipError_t launch_solve(const SolveLaunch& L, hipStream_t st) { return solve_dispatch(L, st, false); }
 
 // --------------------------------------------------- chi^2 and its adjoint
 //

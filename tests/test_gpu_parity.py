@@ -6,8 +6,9 @@ import torch
 from oracle import correlator as OC
 from oracle import geometry as OG
 from oracle import redcal as OR
-from tests.gpu_util import (TOL_GAINS, TOL_VUNIQUE, TOL_XENG, linearized_ls_reference, make_ci4_units,
-                            make_units, oracle_solve, oracle_vunique, pairs_of, rel_l2)
+from tests.gpu_util import (TOL_GAINS, TOL_GAINS_E2E, TOL_VUNIQUE, TOL_XENG, as_c64, ci4_sums_int32, gain_err,
+                            make_ci4_units, make_units, oracle_solve, oracle_vred, oracle_vunique, pairs_of,
+                            rel_l2)
 
 pytestmark = pytest.mark.gpu
 
@@ -117,18 +118,31 @@ def test_xengine_ci4_full_nibble_range(rrc, n, T):
 
 
 # ----------------------------------------------------------------------- (a5)
+#
+# The solve is fed the oracle's own V^reduced (FP64 X-engine of the FX
+# matrix, or exact integer sums for 4-bit data), rounded to complex64 by the
+# test; the oracle solves the same rounded values promoted to FP64.
 
-@pytest.mark.parametrize("n,U,T,snr", [(8, 1, 256, 10.0), (16, 4, 1024, 10.0), (32, 2, 2048, 5.0)])
-def test_solve_matches_oracle(rrc, n, U, T, snr):
-    v, _ = make_units(n, U, T, snr=snr)
+def _solve_case(rrc, n, U, T, snr, wid=90):
+    v, _ = make_units(n, U, T, snr=snr, wid=wid)
     plan, types = _plan(rrc, n, U, T)
-    vr_d = plan.xengine(torch.from_numpy(v).to(DEV))
-    out = plan.solve(vr_d)
-    vr = vr_d.cpu().numpy()
+    pairs, _ = pairs_of(n, types)
+    vr32 = np.empty((U, len(pairs)), np.complex64)
+    vr64 = []
     for u in range(U):
-        ref = oracle_solve(vr[u].astype(np.complex128), n, types)
-        g = out["gains"][u].cpu().numpy().astype(np.complex128)
-        gerr = np.max(np.abs(g - ref["g"]) / np.abs(ref["g"]))
+        vr32[u], x = as_c64(oracle_vred(v[u], pairs))
+        vr64.append(x)
+    return plan, types, vr32, vr64
+
+
+@pytest.mark.parametrize("n,U,T,snr", [(8, 1, 256, 10.0), (16, 4, 1024, 10.0), (24, 2, 512, 10.0),
+                                       (32, 2, 2048, 5.0), (48, 2, 1024, 10.0)])
+def test_solve_matches_oracle(rrc, n, U, T, snr):
+    plan, types, vr32, vr64 = _solve_case(rrc, n, U, T, snr)
+    out = plan.solve(torch.from_numpy(vr32).to(DEV))
+    for u in range(U):
+        ref = oracle_solve(vr64[u], n, types)
+        gerr = gain_err(out["gains"][u].cpu().numpy(), ref["g"])
         cerr = abs(float(out["chisq"][u]) - ref["chisq"]) / ref["chisq"]
         verr = np.max(np.abs(out["vmodel"][u].cpu().numpy() - ref["vm"]) / np.abs(ref["vm"]))
         print(f"n={n} unit {u}: gains {gerr:.2e} vmodel {verr:.2e} chi2 {cerr:.2e} "
@@ -142,62 +156,51 @@ def test_solve_matches_oracle(rrc, n, U, T, snr):
 @pytest.mark.parametrize("n", [24, 48, 64])
 def test_solve_large_grid_recovers_noise_free_gains(rrc, n):
     # V_b = g_i conj(g_j) V_alpha (eq. redcal without noise), rounded to
-    # complex64: the solve must return the least-squares answer for the
-    # rounded data (first-order reference from the injected truth) up to the
-    # four degeneracies, at the sizes of the uneven-batch and 4-bit
-    # workloads (2 and 4 antennas per work-item, up to 16 types, the whole
-    # unit state in LDS).
+    # complex64: GPU and oracle solve the same rounded values, and both land
+    # within rounding of the injected truth, at the sizes of the uneven-batch
+    # and 4-bit workloads (several antennas per work-item, up to 9 types)
     U = 2
     types, _ = rrc.select_subset(n)
     pos = OG.square_positions(n)
     pairs, tix = pairs_of(n, types)
     rng = np.random.default_rng(1000 + n)
     vred = np.empty((U, len(pairs)), np.complex64)
-    truth = []
+    truth, v64 = [], []
     for u in range(U):
         g = (1 + 0.05 * rng.standard_normal(n * n)) * np.exp(1j * rng.uniform(-np.pi, np.pi, n * n))
         vm = (0.2 + rng.random(len(types))) * np.exp(1j * rng.uniform(-np.pi, np.pi, len(types)))
-        vred[u] = OR.model_vis(g, vm, pairs, tix).astype(np.complex64)
-        gl, vl = linearized_ls_reference(vred[u], g, vm, pairs, tix, len(types))
-        truth.append(OR.fix_refant(gl, vl, pos, types))
+        vred[u], x = as_c64(OR.model_vis(g, vm, pairs, tix))
+        v64.append(x)
+        truth.append(OR.fix_refant(g, vm, pos, types)[0])
     plan = rrc.Plan(n, types, U, 64)
     out = plan.solve(torch.from_numpy(vred).to(DEV))
     for u in range(U):
-        g = out["gains"][u].cpu().numpy().astype(np.complex128)
-        gerr = np.max(np.abs(g - truth[u][0]) / np.abs(truth[u][0]))
-        print(f"n={n} unit {u}: gains {gerr:.2e} niter {int(out['niter'][u])} status {int(out['status'][u])}")
+        ref = oracle_solve(v64[u], n, types)
+        gerr = gain_err(out["gains"][u].cpu().numpy(), ref["g"])
+        terr = float(np.max(np.abs(ref["g"] - truth[u]) / np.abs(truth[u])))
+        print(f"n={n} unit {u}: gains {gerr:.2e} (oracle vs truth {terr:.2e}) niter {int(out['niter'][u])} "
+              f"status {int(out['status'][u])}")
         assert int(out["status"][u]) == 0
         assert gerr <= TOL_GAINS
+        assert terr <= 1e-5
 
 
-def test_solve_n24_matches_oracle(rrc):
-    # a grid between the power-of-two sizes (ragged last wave, 7 types)
-    n, U, T = 24, 2, 512
-    v, _ = make_units(n, U, T)
-    plan, types = _plan(rrc, n, U, T)
-    vr_d = plan.xengine(torch.from_numpy(v).to(DEV))
-    out = plan.solve(vr_d)
-    vr = vr_d.cpu().numpy()
-    for u in range(U):
-        ref = oracle_solve(vr[u].astype(np.complex128), n, types)
-        g = out["gains"][u].cpu().numpy().astype(np.complex128)
-        gerr = np.max(np.abs(g - ref["g"]) / np.abs(ref["g"]))
-        print(f"n={n} unit {u}: gains {gerr:.2e} niter {int(out['niter'][u])}")
-        assert int(out["status"][u]) == 0
-        assert gerr <= TOL_GAINS
-
-
-def test_solve_ci4_matches_oracle(rrc):
-    n, U, T = 16, 2, 1024
+@pytest.mark.parametrize("n,U,T", [(16, 2, 1024), (64, 2, 4096)])
+def test_solve_ci4_matches_oracle(rrc, n, U, T):
+    # 4-bit: the solve reads exact int32 sums; the oracle's integer X-engine
+    # gives the very same integers
     b, re, im, _ = make_ci4_units(n, U, T)
     plan, types = _plan(rrc, n, U, T, dtype="ci4")
-    vr_d = plan.xengine(torch.from_numpy(b).to(DEV))
-    out = plan.solve(vr_d)
-    vr = vr_d.cpu().numpy().astype(np.float64)
+    pairs, _ = pairs_of(n, types)
+    sums = [OC.xengine_int(re[u], im[u], pairs) for u in range(U)]
+    vr = np.stack([ci4_sums_int32(x) for x in sums])
+    out = plan.solve(torch.from_numpy(vr).to(DEV))
     for u in range(U):
-        ref = oracle_solve(vr[u, :, 0] + 1j * vr[u, :, 1], n, types)
-        g = out["gains"][u].cpu().numpy().astype(np.complex128)
-        assert np.max(np.abs(g - ref["g"]) / np.abs(ref["g"])) <= TOL_GAINS
+        ref = oracle_solve(sums[u][:, 0] + 1j * sums[u][:, 1], n, types)
+        gerr = gain_err(out["gains"][u].cpu().numpy(), ref["g"])
+        print(f"ci4 n={n} unit {u}: gains {gerr:.2e} niter {int(out['niter'][u])}")
+        assert int(out["status"][u]) == 0
+        assert gerr <= TOL_GAINS
 
 
 def test_solve_from_gains_and_match_mode(rrc):
@@ -205,18 +208,20 @@ def test_solve_from_gains_and_match_mode(rrc):
     v, gtrue = make_units(n, U, T)
     types, _ = rrc.select_subset(n)
     plan = rrc.Plan(n, types, U, T, init_mode="gains", degen_mode="match")
-    vr_d = plan.xengine(torch.from_numpy(v).to(DEV))
+    pairs, tix = pairs_of(n, types)
+    vr32 = np.empty((U, len(pairs)), np.complex64)
+    vr64 = []
+    for u in range(U):
+        vr32[u], x = as_c64(oracle_vred(v[u], pairs))
+        vr64.append(x)
     gin = torch.from_numpy(gtrue.astype(np.complex64)).to(DEV)
-    out = plan.solve(vr_d, gains_in=gin, gains_ref=gin)
-    vr = vr_d.cpu().numpy().astype(np.complex128)
+    out = plan.solve(torch.from_numpy(vr32).to(DEV), gains_in=gin, gains_ref=gin)
     for u in range(U):
         gref = gtrue[u].astype(np.complex64).astype(np.complex128)
         # matching phases is only well posed near the reference: start both there
-        pairs, tix = pairs_of(n, types)
-        ref = oracle_solve(vr[u], n, types, fix="match", g_ref=gref,
-                           init=(gref, OR.group_mean(vr[u], gref, pairs, tix, len(types))))
-        g = out["gains"][u].cpu().numpy().astype(np.complex128)
-        assert np.max(np.abs(g - ref["g"]) / np.abs(ref["g"])) <= TOL_GAINS
+        ref = oracle_solve(vr64[u], n, types, fix="match", g_ref=gref,
+                           init=(gref, OR.group_mean(vr64[u], gref, pairs, tix, len(types))))
+        assert gain_err(out["gains"][u].cpu().numpy(), ref["g"]) <= TOL_GAINS
         assert int(out["status"][u]) == 0
 
 
@@ -231,57 +236,65 @@ def test_solve_nonfinite_unit_is_flagged(rrc):
 
 
 # ----------------------------------------------------------------------- (a6)
+#
+# Inputs: the oracle's V^reduced rounded to complex64, gains near the truth
+# and group means; the oracle evaluates the same rounded values in FP64.
+# Sizes cover the three work-item shapes of the kernel (one, four and
+# sixteen antennas per work-item: up to 256, 1024 and 4096 antennas).
 
-def test_chisq_and_adjoint_match_oracle(rrc):
-    n, U, T = 16, 3, 512
-    v, gtrue = make_units(n, U, T)
-    plan, types = _plan(rrc, n, U, T)
+def _chisq_case(n, U, T, seed, snr=10.0):
+    v, gtrue = make_units(n, U, T, snr=snr)
+    types = OG.select_subset_square(n)
     pairs, tix = pairs_of(n, types)
-    vr_d = plan.xengine(torch.from_numpy(v).to(DEV))
-    rng = np.random.default_rng(3)
-    g = (gtrue * (1 + 0.03 * (rng.standard_normal(gtrue.shape) + 1j * rng.standard_normal(gtrue.shape)))).astype(np.complex64)
-    vm = np.stack([OR.group_mean(vr_d[u].cpu().numpy().astype(np.complex128), gtrue[u], pairs, tix, len(types))
-                   for u in range(U)]).astype(np.complex64)
-    gd, vmd = torch.from_numpy(g).to(DEV), torch.from_numpy(vm).to(DEV)
-    c = plan.chisq_fwd(gd, vmd, vr_d).cpu().numpy()
-    gg, gv, dg, dv = [x.cpu().numpy() for x in plan.chisq_adj(gd, vmd, vr_d)]
-    vr = vr_d.cpu().numpy()
+    rng = np.random.default_rng(seed)
+    vr32 = np.empty((U, len(pairs)), np.complex64)
+    g = (gtrue * (1 + 0.03 * (rng.standard_normal(gtrue.shape) + 1j * rng.standard_normal(gtrue.shape)))
+         ).astype(np.complex64)
+    vm = np.empty((U, len(types)), np.complex64)
     for u in range(U):
-        g64, v64, r64 = g[u].astype(np.complex128), vm[u].astype(np.complex128), vr[u].astype(np.complex128)
+        vr32[u], x = as_c64(oracle_vred(v[u], pairs))
+        vm[u] = OR.group_mean(x, gtrue[u], pairs, tix, len(types)).astype(np.complex64)
+    return types, pairs, tix, vr32, g, vm
+
+
+@pytest.mark.parametrize("n,U,T", [(16, 3, 512), (32, 2, 256), (64, 1, 64)])
+def test_chisq_and_adjoint_match_oracle(rrc, n, U, T):
+    types, pairs, tix, vr32, g, vm = _chisq_case(n, U, T, seed=3)
+    plan = rrc.Plan(n, types, U, T)
+    gd, vmd, vrd = (torch.from_numpy(x).to(DEV) for x in (g, vm, vr32))
+    c = plan.chisq_fwd(gd, vmd, vrd).cpu().numpy()
+    gg, gv, dg, dv = [x.cpu().numpy() for x in plan.chisq_adj(gd, vmd, vrd)]
+    for u in range(U):
+        g64, v64, r64 = g[u].astype(np.complex128), vm[u].astype(np.complex128), vr32[u].astype(np.complex128)
         cref = OR.chisq(r64, g64, v64, pairs, tix)
-        assert abs(c[u] - cref) <= 1e-5 * cref
         rg, rv = OR.wirtinger_grad(r64, g64, v64, pairs, tix)
         hg, hv = OR.jhj_diag(g64, v64, pairs, tix)
-        sc = np.max(np.abs(2 * rg))
-        assert np.max(np.abs(gg[u] - 2 * rg)) <= 1e-5 * sc
-        assert np.max(np.abs(gv[u] - 2 * rv)) <= 1e-5 * np.max(np.abs(2 * rv))
-        assert np.max(np.abs(dg[u] - hg) / hg) <= 1e-5
-        assert np.max(np.abs(dv[u] - hv) / hv) <= 1e-5
+        errs = (abs(c[u] - cref) / cref, np.max(np.abs(gg[u] - 2 * rg)) / np.max(np.abs(2 * rg)),
+                np.max(np.abs(gv[u] - 2 * rv)) / np.max(np.abs(2 * rv)),
+                np.max(np.abs(dg[u] - hg) / hg), np.max(np.abs(dv[u] - hv) / hv))
+        print(f"n={n} unit {u}: chi2 {errs[0]:.2e} grad_g {errs[1]:.2e} grad_v {errs[2]:.2e} "
+              f"diag_g {errs[3]:.2e} diag_v {errs[4]:.2e}")
+        assert max(errs) <= 1e-5
 
 
-def test_adjoint_matches_central_finite_differences(rrc):
+@pytest.mark.parametrize("n,T,snr", [(8, 256, 10.0), (32, 2048, 5.0), (64, 64, 10.0)])
+def test_adjoint_matches_central_finite_differences(rrc, n, T, snr):
     # chi^2 is quadratic in each single complex parameter (no pair has
     # i = j), so central differences of the FP64 chi^2 with step 1e-3 are
     # exact up to rounding: d chi2/d Re z + i d chi2/d Im z = 2 d chi2/d conj(z),
-    # which is what rrc_chisq_adj returns
-    n, U, T = 8, 1, 256
-    v, gtrue = make_units(n, U, T)
-    plan, types = _plan(rrc, n, U, T)
-    pairs, tix = pairs_of(n, types)
-    vr_d = plan.xengine(torch.from_numpy(v).to(DEV))
-    vr = vr_d.cpu().numpy()[0].astype(np.complex128)
-    rng = np.random.default_rng(11)
-    g = (gtrue[0] * (1 + 0.02 * (rng.standard_normal(n * n) + 1j * rng.standard_normal(n * n)))).astype(np.complex64)
-    vm = OR.group_mean(vr, gtrue[0], pairs, tix, len(types)).astype(np.complex64)
-    gg, gv, _, _ = plan.chisq_adj(torch.from_numpy(g[None]).to(DEV), torch.from_numpy(vm[None]).to(DEV), vr_d)
+    # which is what rrc_chisq_adj returns.  32x32 at SNR 5 and 2048 samples
+    # is the 256-channel workload's unit.
+    types, pairs, tix, vr32, g, vm = _chisq_case(n, 1, T, seed=11, snr=snr)
+    plan = rrc.Plan(n, types, 1, T)
+    gg, gv, _, _ = plan.chisq_adj(*(torch.from_numpy(x).to(DEV) for x in (g, vm, vr32)))
     gg, gv = gg.cpu().numpy()[0], gv.cpu().numpy()[0]
-    g64, v64 = g.astype(np.complex128), vm.astype(np.complex128)
+    g64, v64, vr = g[0].astype(np.complex128), vm[0].astype(np.complex128), vr32[0].astype(np.complex128)
     h = 1e-3
 
-    def fd(vec_g, vec_v, which, k):
+    def fd(which, k):
         out = 0j
-        for part, unit in ((0, 1.0), (1, 1j)):
-            gp, gm, vp, vmn = vec_g.copy(), vec_g.copy(), vec_v.copy(), vec_v.copy()
+        for unit in (1.0, 1j):
+            gp, gm, vp, vmn = g64.copy(), g64.copy(), v64.copy(), v64.copy()
             if which == "g":
                 gp[k] += h * unit
                 gm[k] -= h * unit
@@ -289,23 +302,24 @@ def test_adjoint_matches_central_finite_differences(rrc):
                 vp[k] += h * unit
                 vmn[k] -= h * unit
             d = (OR.chisq(vr, gp, vp, pairs, tix) - OR.chisq(vr, gm, vmn, pairs, tix)) / (2 * h)
-            out += d * (1 if part == 0 else 1j)
+            out += d * unit
         return out
 
+    rng = np.random.default_rng(11)
     sc_g = np.max(np.abs(gg))
-    for k in rng.choice(n * n, size=8, replace=False):
-        assert abs(gg[k] - fd(g64, v64, "g", k)) <= 1e-5 * sc_g, k
+    for k in list(rng.choice(n * n, size=8, replace=False)) + [0, n * n - 1]:
+        assert abs(gg[k] - fd("g", k)) <= 1e-5 * sc_g, k
     sc_v = np.max(np.abs(gv))
     for k in range(len(types)):
-        assert abs(gv[k] - fd(g64, v64, "v", k)) <= 1e-5 * sc_v, k
+        assert abs(gv[k] - fd("v", k)) <= 1e-5 * sc_v, k
 
 
 def test_chisq_autograd_function(rrc):
     n, U, T = 8, 2, 256
-    v, gtrue = make_units(n, U, T)
-    plan, types = _plan(rrc, n, U, T)
-    vr_d = plan.xengine(torch.from_numpy(v).to(DEV))
-    g = torch.from_numpy(gtrue.astype(np.complex64)).to(DEV).requires_grad_(True)
+    types, pairs, tix, vr32, g0, _ = _chisq_case(n, U, T, seed=4)
+    plan = rrc.Plan(n, types, U, T)
+    vr_d = torch.from_numpy(vr32).to(DEV)
+    g = torch.from_numpy(g0).to(DEV).requires_grad_(True)
     vm = torch.full((U, len(types)), 0.3 + 0.1j, dtype=torch.complex64, device=DEV).requires_grad_(True)
     w = torch.tensor([0.7, 1.3], device=DEV)
     loss = (rrc.chisq(g, vm, vr_d, plan) * w).sum()
@@ -330,13 +344,17 @@ def test_run_modes_consistent(rrc):
     vu_b, _ = plan.fftcorr(vd, b["gains"].contiguous())
     assert torch.equal(b["vunique"], vu_b)
     assert torch.equal(a["gains"], b["gains"])
-    # end to end against the oracle: gains from the GPU V^reduced, V^unique with the GPU gains
+    # end to end against the oracle's own chain: its FP64 X-engine, its
+    # solve, and its redundant average with its own gains (eq. modelvis)
+    pairs, _ = pairs_of(n, types)
     for u in range(U):
-        ref = oracle_solve(b["vred"][u].cpu().numpy().astype(np.complex128), n, types)
-        g = b["gains"][u].cpu().numpy().astype(np.complex128)
-        assert np.max(np.abs(g - ref["g"]) / np.abs(ref["g"])) <= TOL_GAINS
-        vref, _ = oracle_vunique(v[u], g, n)
-        assert rel_l2(b["vunique"][u].cpu().numpy(), vref) <= TOL_VUNIQUE
+        ref = oracle_solve(oracle_vred(v[u], pairs), n, types)
+        gerr = gain_err(b["gains"][u].cpu().numpy(), ref["g"])
+        vref, _ = oracle_vunique(v[u], ref["g"], n)
+        verr = rel_l2(b["vunique"][u].cpu().numpy(), vref)
+        print(f"unit {u}: end-to-end gains {gerr:.2e}, V^unique {verr:.2e}")
+        assert gerr <= TOL_GAINS_E2E
+        assert verr <= TOL_VUNIQUE
 
 
 @pytest.mark.parametrize("dtype", ["c64", "ci4"])
@@ -436,16 +454,60 @@ def test_batch_matches_eager_runs(rrc):
         del batch
 
 
-@pytest.mark.skip(reason="capturing the batch into a HIP graph ended the test process with a host "
-                         "segmentation fault inside rrc_batch_run; no cause was found in this code, so "
-                         "the graph path was removed and the batch launches its branches eagerly")
-def test_batch_graph_matches_eager_runs(rrc):
-    plans, volts, gins = _batch_inputs(rrc)
-    batch = rrc.Batch(plans)
-    outs = [p.alloc_outputs(DEV) for p in plans]
-    ref = [p.run(v, gains_in=gi, mode="pipelined") for p, v, gi in zip(plans, volts, gins)]
-    for rep in range(3):
-        batch.run(volts, gins, outs, mode="pipelined")
+def test_run_stamps_cover_every_unit(rrc):
+    n, U, T = 16, 6, 512
+    v, g = make_units(n, U, T)
+    plan, _ = _plan(rrc, n, U, T)
+    vd = torch.from_numpy(v).to(DEV)
+    gin = torch.from_numpy(g.astype(np.complex64)).to(DEV)
+    ref = plan.run(vd, gains_in=gin, mode="pipelined")
+    for mode in ("pipelined", "selfcal"):
+        out = plan.alloc_outputs(DEV)
+        out["stamps"] = torch.full((1 + U,), -1, dtype=torch.int64, device=DEV)
+        plan.run(vd, gains_in=gin, mode=mode, out=out)
         torch.cuda.synchronize()
-        for o, r in zip(outs, ref):
-            assert torch.equal(o["gains"], r["gains"])
+        st = out["stamps"].cpu().numpy()
+        assert st[0] > 0 and np.all(st[1:] >= st[0]), (mode, st)
+        if mode == "pipelined":
+            for key in ("vunique", "gains", "chisq"):
+                assert torch.equal(out[key], ref[key]), key
+    hz = rrc.wall_clock_hz()
+    assert 1e6 <= hz <= 1e10
+    lat = (st[1:] - st[0]) / hz
+    assert np.all(lat < 10.0)
+
+
+def test_pipelined_gains_fed_back_in_place(rrc):
+    # the real-time loop passing one buffer as both gains_in and gains_out:
+    # the FFT-correlator must still apply the old gains (it reads a copy)
+    n, U, T = 16, 16, 2048
+    v, g = make_units(n, U, T)
+    plan, _ = _plan(rrc, n, U, T)
+    vd = torch.from_numpy(v).to(DEV)
+    g32 = torch.from_numpy(g.astype(np.complex64)).to(DEV)
+    ref = plan.run(vd, gains_in=g32.clone(), mode="pipelined")
+    out = plan.alloc_outputs(DEV)
+    out["gains"] = g32.clone()
+    plan.run(vd, gains_in=out["gains"], mode="pipelined", out=out)
+    torch.cuda.synchronize()
+    for key in ("vunique", "vauto", "vred", "gains", "vmodel", "chisq"):
+        assert torch.equal(out[key], ref[key]), key
+
+
+@pytest.mark.parametrize("dtype", ["c64", "ci4"])
+def test_branch_orders_give_identical_results(rrc, dtype):
+    n, U, T = 16, 4, 1024
+    if dtype == "ci4":
+        b, _, _, g = make_ci4_units(n, U, T)
+        vd = torch.from_numpy(b).to(DEV)
+    else:
+        v, g = make_units(n, U, T)
+        vd = torch.from_numpy(v).to(DEV)
+    gin = torch.from_numpy(g.astype(np.complex64)).to(DEV)
+    plan, _ = _plan(rrc, n, U, T, dtype=dtype)
+    a = plan.run(vd, gains_in=gin, mode="pipelined")
+    plan.set_order("fft_first")
+    b2 = plan.run(vd, gains_in=gin, mode="pipelined", out=plan.alloc_outputs(DEV))
+    torch.cuda.synchronize()
+    for key in ("vunique", "vauto", "vred", "gains", "vmodel", "chisq", "niter", "status"):
+        assert torch.equal(a[key], b2[key]), key

@@ -49,7 +49,7 @@ def test_hex_array_counts_from_paper():
     assert len(pos) == 37
     types, groups = G.baseline_types(pos, G.HEX_METRIC)
     assert [len(g) for g in groups[:3]] == [30, 30, 30]
-    # Sec. 5.3: with the three shortest types, a corner antenna takes part in
+    # Sec. 5.4: with the three shortest types, a corner antenna takes part in
     # three measurements, an edge antenna in four and a central one in six.
     deg = np.zeros(len(pos), dtype=int)
     for grp in groups[:3]:
@@ -66,7 +66,7 @@ def test_hex_array_counts_from_paper():
     assert set(deg[corner]) == {3}
     assert set(deg[edge]) == {4}
     assert set(deg[ring < r]) == {6}
-    # Sec. 6.3 studies a 331-antenna array: the hex number of side 11.
+    # Sec. 6.4 studies a 331-antenna array: the hex number of side 11.
     assert len(G.hex_positions(11)) == 331
 
 
