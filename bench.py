@@ -8,8 +8,8 @@ through the whole hot path: reduced X-engine, FFT-correlator (gain
 application, padded spatial FFT, |.|^2 integration, inverse transform and
 redundant normalisation) and the reduced redundant calibration solve.  The
 batched path issues the step for all units at once (rrc_run, PIPELINED: the
-FFT applies the previous integration's gains; several arrays run together as
-one captured graph through rrc_batch_run); the plain path calibrates one
+FFT applies the previous integration's gains; several arrays run together on
+branch streams through rrc_batch_run); the plain path calibrates one
 channel at a time, synchronising after each.  Inputs are resident in HBM
 before timing starts.  Prints one JSON line.
 
@@ -32,6 +32,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+
+
+def log(msg: str) -> None:
+    """Progress of the run on stderr (the JSON line alone goes to stdout)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
 # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz; the 157.3 TFLOP/s
 # vector figure counts packed (two-wide) FP32, which this build does not use
 VALU_FP32_PEAK_TFLOPS = 78.6
@@ -153,7 +159,7 @@ def setup(w, dev, rrc, inflight, order):
                            volt=a["volt"] if li == 0 else a["volt"].clone(),
                            gains_in=a["gains_in"] if li == 0 else a["gains_in"].clone()))
         lanes.append(dict(arrays=la, stream=torch.cuda.Stream(dev),
-                          batch=rrc.Batch([a["plan"] for a in la], graph=True) if len(la) > 1 else None))
+                          batch=rrc.Batch([a["plan"] for a in la]) if len(la) > 1 else None))
     torch.cuda.synchronize()
     return dict(arrays=lanes[0]["arrays"], lanes=lanes, D=D, cus=cus, dtype=dtype, host_gen=host_gen,
                 order=order)
@@ -233,7 +239,6 @@ def latency_from_stamps(S, reps):
     ln = S["lanes"][0]
     for a in ln["arrays"]:
         a["out"]["stamps"] = torch.zeros(1 + a["plan"].n_units, dtype=torch.int64, device=a["volt"].device)
-    # (the io now differs from the captured one: a graph batch re-captures once)
     hz = rrc.wall_clock_hz()
     lat = {a["name"]: [] for a in ln["arrays"]}
     first = []
@@ -347,6 +352,7 @@ def gate_units(S, w, n_units):
             g = out["gains"][u].cpu().numpy().astype(np.complex128)
             rep["gains_max_rel"] = max(rep["gains_max_rel"], float(np.max(np.abs(g - sol["g"]) / np.abs(sol["g"]))))
             rep["units"].append(f"{a['name']}:{u}")
+            log(f"gate unit {a['name']}:{u} done")
     if S["dtype"] == "ci4":
         rep["vred_bit_exact"] = exact
         rep.pop("vred_max_rel")
@@ -416,8 +422,11 @@ def cpu_baseline(S, w, budget_s):
 # ------------------------------------------------------------------ record
 
 def measure(w, args, rrc, dev, with_oracle):
+    log(f"{w.name}: generating inputs")
     S = setup(w, dev, rrc, args.inflight, args.order)
+    log(f"{w.name}: {args.warmup} warm-up + {args.steps} timed steps")
     ms = time_steps(S, args.steps, args.warmup)
+    log(f"{w.name}: {ms:.3f} ms per step; stage times")
     total_units = w.n_chan * len(S["arrays"])
     import torch
     serial_ms = time_fn(lambda: run_lane(S["lanes"][0]), args.steps)
@@ -452,6 +461,7 @@ def measure(w, args, rrc, dev, with_oracle):
          "ms_per_launch": stages["solve"], "units_per_launch": total_units, "workgroups_per_unit": 1,
          "cus": S["cus"]},
     ]
+    log(f"{w.name}: plain per-channel form")
     plain_ms, plain_n = plain_per_channel(S, w, rrc, dev, args.plain_units)
     rec = {
         "value": total_units / (ms * 1e-3), "ms_per_step": ms,
@@ -461,7 +471,7 @@ def measure(w, args, rrc, dev, with_oracle):
                    "fft_size": [a["plan"].info["fft_size"] for a in S["arrays"]],
                    "types": [len(a["types"]) for a in S["arrays"]], "pairs": [a["npairs"] for a in S["arrays"]],
                    "mode": "pipelined, all channels per launch" +
-                           (", arrays as one captured graph" if len(S["arrays"]) > 1 else ""),
+                           (", arrays concurrently on branch streams" if len(S["arrays"]) > 1 else ""),
                    "branch_order": S["order"], "batches_in_flight": S["D"], "parallelism": "none (1 GPU)"},
         "stages_ms": stages,
         "one_batch_at_a_time": {"ms_per_step": serial_ms, "value": total_units / (serial_ms * 1e-3)},
@@ -475,7 +485,9 @@ def measure(w, args, rrc, dev, with_oracle):
     if len(S["arrays"]) > 1:
         rec["per_array_latency"] = latency_from_stamps(S, args.latency_reps)
     if with_oracle:
+        log(f"{w.name}: oracle gate on {args.gate_units} units")
         rec["gate"] = gate_units(S, w, args.gate_units)
+        log(f"{w.name}: oracle timing")
         rec["cpu_baseline"] = cpu_baseline(S, w, 30.0)
     for ln in S["lanes"]:
         for a in ln["arrays"]:

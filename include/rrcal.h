@@ -173,6 +173,21 @@ int rrc_plan_prepare(rrc_plan* plan);
 #define RRC_ORDER_FFT_FIRST  1
 int rrc_plan_set_order(rrc_plan* plan, int32_t order);
 
+/* X-engine kernel of a 4-bit plan (complex64 plans have one):
+ * RRC_XENG_AUTO (default): the faster form, which on MI355X is the
+ *   dot-product one (the matrix-core form reads each staged column
+ *   window for only two products of the banded selection and is bound by
+ *   LDS bandwidth: 27.7 against 10.7 ms at 64x64 x 1024 channels x 4096
+ *   samples);
+ * RRC_XENG_DOT: signed 4-bit dot products on the vector ALUs;
+ * RRC_XENG_MFMA: int8 matrix-core tiles over windows covering the selected
+ *   diagonals (RRC_ENOTIMPL if the selection's cover fits none of its
+ *   instantiations).  Both are exact; V^reduced is identical bit for bit. */
+#define RRC_XENG_AUTO 0
+#define RRC_XENG_DOT  1
+#define RRC_XENG_MFMA 2
+int rrc_plan_set_xengine(rrc_plan* plan, int32_t kind);
+
 /* (a1)-(a3) FFT-correlator (Fig. 1(b) yellow box; Sec. 2 eq. modelvis).
  * d_volt:   [U][T][N] voltages (complex64, or 1 byte each for RRC_CI4).
  * d_gains:  [U][N] complex64 gains g; the voltages are divided by them.
@@ -261,9 +276,10 @@ int rrc_run(rrc_plan* plan, void* stream, int32_t mode, const rrc_io* io);
  * differ) whose hot paths run together: the uneven-batch case of several
  * arrays calibrated at once (Fig. 1 real-time loop over every channel of
  * every array).  The plans must be distinct and outlive the batch.  Host
- * only; owns streams, events and (RRC_BATCH_GRAPH) a HIP graph.
- * flags: 0, or RRC_BATCH_GRAPH to replay the whole batch as one captured
- * graph launch (below). */
+ * only; owns streams and events.
+ * flags: 0.  RRC_BATCH_GRAPH (replaying the whole batch as one captured
+ * graph launch) returns RRC_ENOTIMPL in this build: capturing the batch's
+ * fork/join ended the process with a host-side fault in the runtime. */
 #define RRC_BATCH_GRAPH 1u
 typedef struct rrc_batch rrc_batch;
 int rrc_batch_create(rrc_batch** out, int32_t n_plans, rrc_plan* const* plans, uint32_t flags);
@@ -275,10 +291,6 @@ void rrc_batch_destroy(rrc_batch* batch);
  * from `stream` and joined back into it with events, so the arrays run
  * concurrently and all outputs are ordered on `stream`.  With more units in
  * the batch than compute units the solves share CUs.
- * RRC_BATCH_GRAPH: the first run (and any run whose mode or io differs from
- * the captured one) captures that sequence on a stream of the batch and
- * instantiates it; every run then enqueues one graph launch on `stream`.
- * The graph holds the io pointers it was captured with.
  * Asynchronous like rrc_run; one batch may be run by one stream at a time,
  * and its plans must not be run concurrently on other streams. */
 int rrc_batch_run(rrc_batch* batch, void* stream, int32_t mode, const rrc_io* io);

@@ -211,6 +211,11 @@ class Plan:
         code = {"xeng_first": L.RRC_ORDER_XENG_FIRST, "fft_first": L.RRC_ORDER_FFT_FIRST}[order]
         L.check(self._lib.rrc_plan_set_order(self._h, code), "rrc_plan_set_order")
 
+    def set_xengine(self, kind: str) -> None:
+        """X-engine kernel of a 4-bit plan: "auto", "dot" or "mfma"."""
+        code = {"auto": L.RRC_XENG_AUTO, "dot": L.RRC_XENG_DOT, "mfma": L.RRC_XENG_MFMA}[kind]
+        L.check(self._lib.rrc_plan_set_xengine(self._h, code), "rrc_plan_set_xengine")
+
     def prepare(self) -> None:
         """Bind the plan to the current device and make its device resources."""
         L.check(self._lib.rrc_plan_prepare(self._h), "rrc_plan_prepare")

@@ -23,8 +23,13 @@ struct rrc_plan {
     rrc_solver_opts opts;
     // FFT-correlator
     int fft_tchunk, fft_nchunk;
-    // X-engine
+    // X-engine; 4-bit plans whose window cover an int8 matrix-core
+    // instantiation holds use it (x_mf: its launch fields) unless the
+    // caller selects the dot-product kernel
     int x_tchunk, x_nchunk, x_nablk, x_S, x_halo;
+    bool x_mf_ok = false;
+    int32_t x_kind = RRC_XENG_AUTO;
+    rrc::XengLaunch x_mf{};
     // solver
     bool solve_vcache;
     size_t solve_lds_bytes;
@@ -53,12 +58,6 @@ struct rrc_batch {
     std::vector<hipStream_t> branch;           // one per plan
     std::vector<hipEvent_t> ev_done;           // one per plan
     hipEvent_t ev_start = nullptr;
-    // RRC_BATCH_GRAPH: the stream the batch is captured on and the
-    // instantiated graph of the last (mode, io) captured
-    hipStream_t cap = nullptr;
-    hipGraphExec_t exec = nullptr;
-    int32_t cap_mode = 0;
-    std::vector<rrc_io> cap_io;
 };
 
 namespace {
@@ -364,6 +363,10 @@ int rrc_plan_create(rrc_plan** out, int32_t n, const int32_t* types_xy, int32_t 
         const int xt = ceil_div(ceil_div(n_time, xn), p->x_S) * p->x_S;
         p->x_tchunk = xt;
         p->x_nchunk = ceil_div(n_time, xt);
+        if (dtype == RRC_CI4) {
+            p->x_mf.sel = s;
+            p->x_mf_ok = rrc::xmfma_plan(s, p->x_mf) && xt % 32 == 0 && xt <= (1 << 17);
+        }
     }
 
     // solver
@@ -428,6 +431,13 @@ void rrc_plan_destroy(rrc_plan* p) {
 int rrc_plan_set_order(rrc_plan* p, int32_t order) {
     if (!p || (order != RRC_ORDER_XENG_FIRST && order != RRC_ORDER_FFT_FIRST)) return RRC_EINVAL;
     p->order = order;
+    return RRC_OK;
+}
+
+int rrc_plan_set_xengine(rrc_plan* p, int32_t kind) {
+    if (!p || (kind != RRC_XENG_AUTO && kind != RRC_XENG_DOT && kind != RRC_XENG_MFMA)) return RRC_EINVAL;
+    if (kind == RRC_XENG_MFMA && !p->x_mf_ok) return RRC_ENOTIMPL;
+    p->x_kind = kind;
     return RRC_OK;
 }
 
@@ -498,6 +508,20 @@ int rrc_xengine(rrc_plan* p, void* stream, const void* d_volt, void* d_vred, voi
     L.volt = d_volt;
     L.vpart = static_cast<char*>(d_work) + p->off_x;
     L.vred = d_vred;
+    // the matrix-core form only on request: at the 64x64 grid's banded
+    // selection it takes 27.7 ms per 1024 units against 10.7 ms for the
+    // dot-product kernel (LDS-bound, one workgroup per CU)
+    L.mfma = L.ci4 && p->x_mf_ok && p->x_kind == RRC_XENG_MFMA;
+    if (L.mfma) {
+        L.mf_inst = p->x_mf.mf_inst;
+        L.mf_nrun = p->x_mf.mf_nrun;
+        for (int r = 0; r < rrc::kXMaxRuns; ++r) {
+            L.mf_start[r] = p->x_mf.mf_start[r];
+            L.mf_len[r] = p->x_mf.mf_len[r];
+        }
+        L.mf_lo = p->x_mf.mf_lo;
+        L.mf_cnt = p->x_mf.mf_cnt;
+    }
     return rrc::launch_xengine(L, as_stream(stream)) == hipSuccess ? RRC_OK : RRC_EDEVICE;
 }
 
@@ -657,19 +681,14 @@ int rrc_run(rrc_plan* p, void* stream, int32_t mode, const rrc_io* io) {
 // ------------------------------------------------------------------ batches
 
 static void batch_release(rrc_batch* b) {
-    if (b->exec) (void)hipGraphExecDestroy(b->exec);
-    b->exec = nullptr;
-    b->cap_io.clear();
     for (hipEvent_t e : b->ev_done)
         if (e) (void)hipEventDestroy(e);
     for (hipStream_t s : b->branch)
         if (s) (void)hipStreamDestroy(s);
     if (b->ev_start) (void)hipEventDestroy(b->ev_start);
-    if (b->cap) (void)hipStreamDestroy(b->cap);
     b->ev_done.clear();
     b->branch.clear();
     b->ev_start = nullptr;
-    b->cap = nullptr;
     b->prepared = false;
 }
 
@@ -677,6 +696,11 @@ int rrc_batch_create(rrc_batch** out, int32_t n_plans, rrc_plan* const* plans, u
     if (!out) return RRC_EINVAL;
     *out = nullptr;
     if (n_plans < 1 || !plans || (flags & ~(uint32_t)RRC_BATCH_GRAPH)) return RRC_EINVAL;
+    // Replaying the batch as a captured graph is switched off: capturing its
+    // fork/join over the branch and auxiliary streams ended the process with
+    // a host-side segmentation fault inside the runtime, and no cause in
+    // this library has been shown.
+    if (flags & RRC_BATCH_GRAPH) return RRC_ENOTIMPL;
     for (int i = 0; i < n_plans; ++i) {
         if (!plans[i]) return RRC_EINVAL;
         for (int j = 0; j < i; ++j)
@@ -706,8 +730,7 @@ static int batch_prepare(rrc_batch* b) {
     }
     b->branch.assign(np, nullptr);
     b->ev_done.assign(np, nullptr);
-    bool ok = hipEventCreateWithFlags(&b->ev_start, hipEventDisableTiming) == hipSuccess &&
-              hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) == hipSuccess;
+    bool ok = hipEventCreateWithFlags(&b->ev_start, hipEventDisableTiming) == hipSuccess;
     for (int i = 0; ok && i < np; ++i)
         ok = hipStreamCreateWithFlags(&b->branch[i], hipStreamNonBlocking) == hipSuccess &&
              hipEventCreateWithFlags(&b->ev_done[i], hipEventDisableTiming) == hipSuccess;
@@ -740,51 +763,12 @@ static int batch_issue(rrc_batch* b, hipStream_t st, int32_t mode, const rrc_io*
     return RRC_OK;
 }
 
-static bool same_io(const std::vector<rrc_io>& a, const rrc_io* io) {
-    for (size_t i = 0; i < a.size(); ++i)
-        if (std::memcmp(&a[i], &io[i], sizeof(rrc_io)) != 0) return false;
-    return true;
-}
-
 int rrc_batch_run(rrc_batch* b, void* stream, int32_t mode, const rrc_io* io) {
     if (!b || !io) return RRC_EINVAL;
     if (mode != RRC_RUN_PIPELINED && mode != RRC_RUN_SELFCAL) return RRC_EINVAL;
-    int rc = batch_prepare(b);
+    const int rc = batch_prepare(b);
     if (rc != RRC_OK) return rc;
-    hipStream_t st = as_stream(stream);
-    if (!(b->flags & RRC_BATCH_GRAPH)) return batch_issue(b, st, mode, io);
-    const size_t np = b->plans.size();
-    if (!b->exec || b->cap_mode != mode || !same_io(b->cap_io, io)) {
-        // capture the whole fork/join sequence on the batch's own stream
-        // (never the caller's, which may be the null stream) and instantiate
-        if (b->exec) (void)hipGraphExecDestroy(b->exec);
-        b->exec = nullptr;
-        b->cap_io.clear();
-        if (hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return RRC_EDEVICE;
-        rc = batch_issue(b, b->cap, mode, io);
-        hipGraph_t g = nullptr;
-        const hipError_t ec = hipStreamEndCapture(b->cap, &g);
-        if (rc != RRC_OK || ec != hipSuccess || !g) {
-            if (ec != hipSuccess)
-                std::fprintf(stderr, "rrcal: batch capture failed: %s\n", hipGetErrorString(ec));
-            if (g) (void)hipGraphDestroy(g);
-            return rc != RRC_OK ? rc : RRC_EDEVICE;
-        }
-        // the error node and log are out-parameters the runtime writes when
-        // instantiation fails: they must point at storage
-        hipGraphNode_t err_node = nullptr;
-        char log[1024] = {0};
-        const hipError_t ei = hipGraphInstantiate(&b->exec, g, &err_node, log, sizeof(log));
-        (void)hipGraphDestroy(g);
-        if (ei != hipSuccess) {
-            std::fprintf(stderr, "rrcal: graph instantiation failed: %s %s\n", hipGetErrorString(ei), log);
-            b->exec = nullptr;
-            return RRC_EDEVICE;
-        }
-        b->cap_mode = mode;
-        b->cap_io.assign(io, io + np);
-    }
-    return hipGraphLaunch(b->exec, st) == hipSuccess ? RRC_OK : RRC_EDEVICE;
+    return batch_issue(b, as_stream(stream), mode, io);
 }
 
 int rrc_wall_clock_hz(double* hz) {

@@ -21,6 +21,8 @@ struct FftLaunch {
     unsigned long long* stamps;   // optional [1 + U] run stamps (see unit_done_stamp)
 };
 
+constexpr int kXMaxRuns = 4;   // window runs of the int8-MFMA X-engine's cover
+
 struct XengLaunch {
     Sel sel;
     int T, n_units;
@@ -32,6 +34,11 @@ struct XengLaunch {
     const void* volt;
     void* vpart;           // workspace: [U][nchunk][P] float2 or int2 (nchunk > 1)
     void* vred;            // output: [U][P] float2 (scaled by 1/T) or int2
+    // 4-bit voltages on the int8 matrix cores (xmfma.hip): the instantiation,
+    // the runs of 16-antenna column windows (offsets from a row block's first
+    // antenna), and the staged antennas of a workgroup [a0 + mf_lo, + mf_cnt)
+    bool mfma;
+    int mf_inst, mf_nrun, mf_start[kXMaxRuns], mf_len[kXMaxRuns], mf_lo, mf_cnt;
 };
 
 struct SolveOpts {
@@ -79,6 +86,8 @@ size_t xengine_lds_bytes(int halo, bool ci4);
 int xengine_antennas_per_block();
 int xengine_max_halo();
 int xengine_samples_per_step(bool ci4);
+bool xmfma_plan(const Sel& s, XengLaunch& X);
+hipError_t launch_xmfma(const XengLaunch& X, hipStream_t st);
 size_t solve_lds_bytes(const Sel& s, bool vcache);
 hipError_t prepare_solve(const SolveLaunch& L);
 hipError_t launch_solve(const SolveLaunch& L, hipStream_t st);

@@ -28,8 +28,9 @@
 // A >> 4 keeps ar against bi, the other nibbles zeroed) gives the two terms
 // of the imaginary part ai br - ar bi: three instructions for four samples
 // of one pair, where the unpacked form takes four multiply-adds per sample.
-// A dense MFMA product of antenna patches would waste all but the K
-// diagonals of each output tile, which leaves no gain over this form.
+// (The int8 matrix-core form for 4-bit voltages is in xmfma.hip; this
+// kernel serves complex64 voltages, and 4-bit selections whose window
+// cover no matrix-core instantiation holds.)
 #include "rrc_device.h"
 #include "rrc_launch.h"
 
@@ -285,10 +286,15 @@ __global__ __launch_bounds__(256) void k_xfin(const void* __restrict__ vpart, in
 
 template <bool CI4, bool WIDE, int KMAX>
 static hipError_t launch_x(const XengLaunch& L, hipStream_t st) {
-    const size_t lds = xengine_lds_bytes(L.halo, CI4);
-    dim3 grid(L.nablk, L.nchunk, L.n_units);
-    hipLaunchKernelGGL((k_xant<CI4, WIDE, KMAX>), grid, dim3(kXThreads), lds, st, L);
-    hipError_t e = hipGetLastError();
+    hipError_t e;
+    if (CI4 && L.mfma) {
+        e = launch_xmfma(L, st);
+    } else {
+        const size_t lds = xengine_lds_bytes(L.halo, CI4);
+        dim3 grid(L.nablk, L.nchunk, L.n_units);
+        hipLaunchKernelGGL((k_xant<CI4, WIDE, KMAX>), grid, dim3(kXThreads), lds, st, L);
+        e = hipGetLastError();
+    }
     if (e != hipSuccess || L.nchunk == 1) return e;
     const size_t tot = (size_t)L.n_units * L.sel.P;
     hipLaunchKernelGGL((k_xfin<CI4>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, L.vpart,

@@ -89,11 +89,14 @@ def test_xengine_float_matches_oracle(rrc, n, U, T):
         assert err <= TOL_XENG
 
 
+@pytest.mark.parametrize("kind", ["mfma", "dot"])
 @pytest.mark.parametrize("n,U,T", [(8, 2, 300), (8, 3, 301), (12, 2, 130), (16, 1, 1027), (16, 2, 1024),
-                                   (64, 2, 4096), (4, 1, 1), (64, 1, 1)])
-def test_xengine_ci4_bit_exact(rrc, n, U, T):
+                                   (24, 2, 96), (32, 1, 200), (48, 1, 64), (64, 2, 4096), (4, 1, 1), (64, 1, 1)])
+def test_xengine_ci4_bit_exact(rrc, n, U, T, kind):
+    # the int8 matrix-core and the 4-bit dot-product kernels, both exact
     b, re, im, _ = make_ci4_units(n, U, T)
     plan, types = _plan(rrc, n, U, T, dtype="ci4")
+    plan.set_xengine(kind)
     vr = plan.xengine(torch.from_numpy(b).to(DEV)).cpu().numpy().astype(np.int64)
     pairs, _ = pairs_of(n, types)
     for u in range(U):
@@ -101,14 +104,16 @@ def test_xengine_ci4_bit_exact(rrc, n, U, T):
         assert np.array_equal(vr[u], ref), f"unit {u}: {np.sum(vr[u] != ref)} mismatches"
 
 
-@pytest.mark.parametrize("n,T", [(8, 259), (16, 1024)])
-def test_xengine_ci4_full_nibble_range(rrc, n, T):
+@pytest.mark.parametrize("kind", ["mfma", "dot"])
+@pytest.mark.parametrize("n,T", [(8, 259), (16, 1024), (64, 300)])
+def test_xengine_ci4_full_nibble_range(rrc, n, T, kind):
     # every byte value, so both nibbles take -8 .. 7 (the -8 products included)
     from synthdata.generate import unpack_ci4
     rng = np.random.default_rng(17)
     b = rng.integers(0, 256, size=(2, T, n * n), dtype=np.uint8)
     b[:, :4, :] = 0x88                       # (-8, -8) at the start of each unit
     plan, types = _plan(rrc, n, 2, T, dtype="ci4")
+    plan.set_xengine(kind)
     vr = plan.xengine(torch.from_numpy(b).to(DEV)).cpu().numpy().astype(np.int64)
     pairs, _ = pairs_of(n, types)
     for u in range(2):
@@ -452,6 +457,33 @@ def test_batch_matches_eager_runs(rrc):
                 for key in ("vunique", "vauto", "vred", "gains", "vmodel", "chisq", "status"):
                     assert torch.equal(o[key], r[key]), (mode, rep, k, key)
         del batch
+
+
+@pytest.mark.skip(reason="RRC_BATCH_GRAPH is switched off (rrc_batch_create returns RRC_ENOTIMPL): "
+                         "capturing the batch's fork/join over its branch and auxiliary streams into a HIP "
+                         "graph ended the test process with a host segmentation fault inside rrc_batch_run, "
+                         "also after the graph-instantiate out-parameters were given storage; no cause in "
+                         "this library has been shown")
+def test_batch_graph_matches_eager_runs(rrc):
+    # the whole uneven batch captured once (fork/join over branch and
+    # auxiliary streams) and replayed as one graph launch: every replay, with
+    # eager work and synchronisation in between, equals the eager runs
+    plans, volts, gins = _batch_inputs(rrc)
+    ref = [p.run(v, gains_in=gi, mode="pipelined") for p, v, gi in zip(plans, volts, gins)]
+    torch.cuda.synchronize()
+    batch = rrc.Batch(plans, graph=True)
+    outs = [p.alloc_outputs(DEV) for p in plans]
+    for rep in range(4):
+        for o in outs:
+            for t in o.values():
+                t.fill_(7)
+        torch.cuda.synchronize()
+        batch.run(volts, gins, outs, mode="pipelined")
+        torch.cuda.synchronize()
+        for k, (o, r) in enumerate(zip(outs, ref)):
+            for key in ("vunique", "vauto", "vred", "gains", "vmodel", "chisq", "niter", "status"):
+                assert torch.equal(o[key], r[key]), (rep, k, key)
+    del batch
 
 
 def test_run_stamps_cover_every_unit(rrc):
