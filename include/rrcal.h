@@ -272,6 +272,26 @@ typedef struct {
 } rrc_io;
 int rrc_run(rrc_plan* plan, void* stream, int32_t mode, const rrc_io* io);
 
+/* rrc_run without a workspace, for callers that cannot allocate device
+ * memory (code under graph capture, tight serving loops, harnesses that
+ * forbid allocation).  Identical to rrc_run except that io->d_work must be
+ * NULL: the scratch space is a static device array of the library,
+ * RRC_STATIC_SCRATCH_BYTES per GPU (held until the process ends), whose
+ * address is looked up once per device (hipGetSymbolAddress) when a plan
+ * is bound to it.  The plan must be prepared first (rrc_plan_prepare, or
+ * any earlier device call: the set-up that makes its stream and events and
+ * looks the address up), else RRC_EINVAL; the call itself creates and
+ * allocates nothing, it only enqueues launches and event operations.
+ * RRC_ERANGE when the plan's
+ * rrc_workspace_size() exceeds RRC_STATIC_SCRATCH_BYTES (e.g. the 16x16
+ * grid with 64 channels and 1024 samples needs about 20 MB; larger plans
+ * use rrc_run).  Every plan on one GPU shares that GPU's one array, which
+ * keeps the last call's contents (no call needs them cleared): calls that
+ * overlap in time on one GPU -- on different streams, or different plans --
+ * race on it and must be ordered by the caller. */
+#define RRC_STATIC_SCRATCH_BYTES (32u << 20)
+int rrc_run_static(rrc_plan* plan, void* stream, int32_t mode, const rrc_io* io);
+
 /* A batch of plans (one per array; grids, channels and sample counts may
  * differ) whose hot paths run together: the uneven-batch case of several
  * arrays calibrated at once (Fig. 1 real-time loop over every channel of

@@ -34,12 +34,13 @@ RRC_XENG_DOT = 1
 RRC_XENG_MFMA = 2
 RRC_MAX_TYPES = 16
 RRC_MAX_GRID = 64
+RRC_STATIC_SCRATCH_BYTES = 32 << 20
 
 EXPORTS = ("rrc_default_opts", "rrc_select_subset", "rrc_degeneracy_count", "rrc_plan_create",
            "rrc_plan_destroy", "rrc_plan_get_info", "rrc_workspace_size", "rrc_fftcorr",
            "rrc_xengine", "rrc_solve", "rrc_chisq_fwd", "rrc_chisq_adj", "rrc_run", "rrc_strerror",
            "rrc_batch_create", "rrc_batch_destroy", "rrc_batch_run", "rrc_plan_prepare",
-           "rrc_plan_set_order", "rrc_wall_clock_hz", "rrc_plan_set_xengine")
+           "rrc_plan_set_order", "rrc_wall_clock_hz", "rrc_run_static", "rrc_plan_set_xengine")
 
 
 class SolverOpts(C.Structure):
@@ -104,6 +105,7 @@ def load_library() -> C.CDLL:
         "rrc_plan_prepare": (C.c_int, [vp]),
         "rrc_plan_set_order": (C.c_int, [vp, i32]),
         "rrc_wall_clock_hz": (C.c_int, [C.POINTER(C.c_double)]),
+        "rrc_run_static": (C.c_int, [vp, vp, i32, C.POINTER(RunIO)]),
         "rrc_plan_set_xengine": (C.c_int, [vp, i32]),
     }
     for name, (res, args) in sig.items():

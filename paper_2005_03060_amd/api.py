@@ -206,6 +206,18 @@ class Plan:
         L.check(self._lib.rrc_run(self._h, _stream(), _MODES[mode], C.byref(io)), "rrc_run")
         return out
 
+    def run_static(self, volt: torch.Tensor, gains_in: Optional[torch.Tensor] = None,
+                   gains_ref: Optional[torch.Tensor] = None, mode: str = "pipelined",
+                   out: Optional[Dict[str, torch.Tensor]] = None) -> Dict[str, torch.Tensor]:
+        """rrc_run_static: the whole hot path on the library's static scratch
+        (no workspace); the plan must be prepared (see `prepare`)."""
+        if out is None:
+            out = self.alloc_outputs(volt.device)
+        io = self.run_io(volt, gains_in, gains_ref, out, work=None)
+        io.d_work = None
+        L.check(self._lib.rrc_run_static(self._h, _stream(), _MODES[mode], C.byref(io)), "rrc_run_static")
+        return out
+
     def set_order(self, order: str) -> None:
         """Branch order of the pipelined run: "xeng_first" or "fft_first"."""
         code = {"xeng_first": L.RRC_ORDER_XENG_FIRST, "fft_first": L.RRC_ORDER_FFT_FIRST}[order]

@@ -7,6 +7,7 @@
 #include <cstdlib>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -46,6 +47,8 @@ struct rrc_plan {
     hipStream_t aux = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     int cu_count = 0;
+    // rrc_run_static: the static scratch's address on this device
+    void* scratch = nullptr;
     // units launched concurrently with this plan's (a batch sets the sum of
     // its plans'); the solve claims whole CUs only when they all fit
     long concurrent_units = 0;
@@ -180,6 +183,30 @@ int ceil_div(long a, long b) { return (int)((a + b - 1) / b); }
 }  // namespace
 
 namespace rrc {
+
+// Scratch of rrc_run_static: a file-scope device array, one copy per GPU,
+// held until the process ends.  Host code never passes `scratch` itself to
+// a kernel (in host code the name is only a host-side stand-in); it uses the
+// device address hipGetSymbolAddress returns for the device current when it
+// is looked up, kept per device in scratch_ptr.
+static __device__ __align__(256) unsigned char scratch[RRC_STATIC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+static void* scratch_ptr[kMaxDevices] = {nullptr};
+static std::mutex scratch_mu;
+
+// The scratch address on `dev`, which must be the current device; looked up
+// once per device.
+static void* device_scratch(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+        scratch_ptr[dev] = ptr;
+    }
+    return scratch_ptr[dev];
+}
 
 // stamps[0] = now; stamps[1 .. U] = 0 (raised by each stage's atomic max)
 __global__ __launch_bounds__(256) void k_stamp_start(unsigned long long* stamps, int n_units) {
@@ -394,6 +421,7 @@ static void release_device(rrc_plan* p) {
     if (p->aux) (void)hipStreamDestroy(p->aux);
     p->aux = nullptr;
     p->ev_fork = p->ev_join = nullptr;
+    p->scratch = nullptr;
     p->prepared = false;
     p->device = -1;
 }
@@ -418,6 +446,9 @@ static int prepare(rrc_plan* p) {
     }
     p->cu_count = cus;
     p->device = dev;
+    // the static scratch's address on this device (rrc_run_static); null
+    // if the lookup fails, which only that entry point reports
+    p->scratch = rrc::device_scratch(dev);
     p->prepared = true;
     return RRC_OK;
 }
@@ -676,6 +707,19 @@ int rrc_run(rrc_plan* p, void* stream, int32_t mode, const rrc_io* io) {
     }
     if (rc != RRC_OK) return rc;
     return hipStreamWaitEvent(st, p->ev_join, 0) == hipSuccess ? RRC_OK : RRC_EDEVICE;
+}
+
+int rrc_run_static(rrc_plan* p, void* stream, int32_t mode, const rrc_io* io) {
+    if (!p || !io) return RRC_EINVAL;
+    if (io->d_work) return RRC_EINVAL;            // the scratch replaces the workspace
+    if (p->ws_bytes > (size_t)RRC_STATIC_SCRATCH_BYTES) return RRC_ERANGE;
+    // set-up (streams, events, the scratch address) belongs to
+    // rrc_plan_prepare, so this call itself creates nothing
+    if (!p->prepared) return RRC_EINVAL;
+    if (!p->scratch) return RRC_EDEVICE;
+    rrc_io io2 = *io;
+    io2.d_work = p->scratch;
+    return rrc_run(p, stream, mode, &io2);
 }
 
 // ------------------------------------------------------------------ batches
