@@ -145,6 +145,19 @@ int rrc_select_subset(int32_t n, double p, double log_base, int32_t* types_xy,
 int rrc_degeneracy_count(int32_t n, const int32_t* types_xy, int32_t k,
                          int32_t* n_null_amp, int32_t* n_null_phase);
 
+/* Predicted gain variance of a selection (Sec. 2 gain uncertainty: eq. cov
+ * with eq. noisecov, read per antenna as eq. gaincov / eq. gaincov_v1 of
+ * Sec. 5.4): var_out[i] = E|g_i,est / g_i,true - 1|^2 for visibilities of
+ * signal-to-noise ratio `snr`, after the degeneracies are fixed the way
+ * gains are compared with the truth (mean log-amplitude, and a phase plane
+ * c + k.r, removed).  The logarithmic system splits into an amplitude and
+ * a phase half, each with noise variance snr^-2 / 2 per equation, so
+ * var_out = (snr^-2 / 2) (diag C_eta + diag C_phi), C the projected gains'
+ * block of each half's inverse normal matrix.  Host only, FP64, pure;
+ * var_out holds n*n doubles.  RRC_EDEGEN for a selection with more than
+ * the four degeneracies. */
+int rrc_gain_variance(int32_t n, const int32_t* types_xy, int32_t k, double snr, double* var_out);
+
 /* Create a plan for U units of an n x n grid with T samples each.  The
  * selection must satisfy the degeneracy criterion (else RRC_EDEGEN) and,
  * for RRC_INIT_FIRSTCAL, contain the types (1,0) and (0,1).  opts may be

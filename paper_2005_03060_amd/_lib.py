@@ -40,7 +40,8 @@ EXPORTS = ("rrc_default_opts", "rrc_select_subset", "rrc_degeneracy_count", "rrc
            "rrc_plan_destroy", "rrc_plan_get_info", "rrc_workspace_size", "rrc_fftcorr",
            "rrc_xengine", "rrc_solve", "rrc_chisq_fwd", "rrc_chisq_adj", "rrc_run", "rrc_strerror",
            "rrc_batch_create", "rrc_batch_destroy", "rrc_batch_run", "rrc_plan_prepare",
-           "rrc_plan_set_order", "rrc_wall_clock_hz", "rrc_run_static", "rrc_plan_set_xengine")
+           "rrc_plan_set_order", "rrc_wall_clock_hz", "rrc_run_static", "rrc_plan_set_xengine",
+           "rrc_gain_variance")
 
 
 class SolverOpts(C.Structure):
@@ -107,6 +108,7 @@ def load_library() -> C.CDLL:
         "rrc_wall_clock_hz": (C.c_int, [C.POINTER(C.c_double)]),
         "rrc_run_static": (C.c_int, [vp, vp, i32, C.POINTER(RunIO)]),
         "rrc_plan_set_xengine": (C.c_int, [vp, i32]),
+        "rrc_gain_variance": (C.c_int, [i32, pi32, i32, C.c_double, C.POINTER(C.c_double)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

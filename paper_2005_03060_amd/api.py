@@ -46,6 +46,16 @@ def degeneracy_count(n: int, types: Sequence[Tuple[int, int]]):
     return na.value, nph.value
 
 
+def gain_variance(n: int, types: Sequence[Tuple[int, int]], snr: float):
+    """Predicted per-antenna E|g_est/g_true - 1|^2 of a selection (host only)."""
+    import numpy as np
+    lib = L.load_library()
+    out = np.empty(n * n, dtype=np.float64)
+    L.check(lib.rrc_gain_variance(n, _types_array(types), len(types), float(snr),
+                                  out.ctypes.data_as(C.POINTER(C.c_double))), "rrc_gain_variance")
+    return out
+
+
 def default_opts() -> Dict[str, float]:
     lib = L.load_library()
     o = L.SolverOpts()

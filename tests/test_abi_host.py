@@ -129,3 +129,24 @@ def test_raw_abi_rejects_null_pointers():
     assert lib.rrc_plan_get_info(None, None) == _lib.RRC_EINVAL
     sz = ctypes.c_size_t()
     assert lib.rrc_workspace_size(h, ctypes.byref(sz)) == 0 and sz.value == plan.info["workspace_bytes"]
+
+
+@pytest.mark.parametrize("n,k,base", [(4, 4, 0.0), (6, 5, 0.0), (8, 5, 0.0), (8, 8, 0.0), (10, 7, 0.0),
+                                      (12, 9, 2.0), (16, 6, 0.0)])
+def test_gain_variance_matches_oracle(n, k, base):
+    # eq. gaincov per antenna: the library's banded factorisation against the
+    # oracle's dense pseudo-inverse with the same degeneracy projection
+    from oracle import stats as OS
+    allt = G.select_subset_square(n, 1.0, base if base > 1 else np.e)
+    types = [tuple(t) for t in allt] if len(allt) >= k else [tuple(t) for t in G.square_types(n)[0][:k]]
+    pos = G.square_positions(n)
+    pairs, tix = G.group_pairs(pos, types)
+    ref = OS.predicted_gain_variance(pos, pairs, tix, len(types), snr=10.0)
+    got = rrc.gain_variance(n, types, 10.0)
+    assert np.max(np.abs(got - ref) / ref) < 1e-9
+
+
+def test_gain_variance_refuses_degenerate_selection():
+    with pytest.raises(rrc.RRCError) as e:
+        rrc.gain_variance(6, [(1, 0), (0, 1)], 10.0)
+    assert e.value.code == _lib.RRC_EDEGEN
