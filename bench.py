@@ -78,7 +78,7 @@ def parse():
     ap.add_argument("--no-extra", action="store_true", help="skip the second (32x32) workload")
     ap.add_argument("--gate-units", type=int, default=8)
     ap.add_argument("--plain-units", type=int, default=0,
-                    help="channels timed in the plain per-channel form (0: all, up to 256)")
+                    help="channels timed in the plain per-channel form (0: up to 256, within 20 s)")
     ap.add_argument("--inflight", type=int, default=0,
                     help="batches in flight: step i runs on lane i mod D, each lane with its own "
                          "stream, plans, input copy and outputs; 0 picks enough for the solves "
@@ -87,6 +87,11 @@ def parse():
                     help="pipelined branch order (auto: FFT first for 4-bit workloads, whose FFT stage "
                          "is VALU-bound and dominates)")
     ap.add_argument("--latency-reps", type=int, default=50)
+    ap.add_argument("--xengine", default="auto", choices=["auto", "dot", "mfma"],
+                    help="X-engine kernel of 4-bit plans (auto: the dot-product kernel)")
+    ap.add_argument("--stages-only", action="store_true",
+                    help="only time each stage alone (--steps launches each; the profiling run whose "
+                         "kernel averages are the stage times of the roofline) and print them")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 256 MiB three times (the run whose FETCH_SIZE / WRITE_SIZE scale "
                          "the HBM counters of the kernels)")
@@ -125,7 +130,7 @@ def measured_traffic(workload: str):
 
 # --------------------------------------------------------------- the GPU run
 
-def setup(w, dev, rrc, inflight, order):
+def setup(w, dev, rrc, inflight, order, xengine="auto"):
     import torch
     from synthdata import workload_voltages
     from synthdata.device import device_voltages
@@ -154,6 +159,8 @@ def setup(w, dev, rrc, inflight, order):
         for a in arrays:
             plan = rrc.Plan(a["n"], a["types"], w.n_chan, w.n_time, dtype=dtype)
             plan.set_order(order)
+            if w.ci4:
+                plan.set_xengine(xengine)
             plan.workspace(dev)            # allocated here, not in a timed step
             la.append(dict(a, plan=plan, out=plan.alloc_outputs(dev),
                            volt=a["volt"] if li == 0 else a["volt"].clone(),
@@ -220,13 +227,15 @@ def time_fn(fn, reps):
 
 
 def stage_times(S, w, reps):
-    """Each stage alone, per launch (all channels of an array), summed over arrays."""
+    """Each stage alone, per launch (all channels of an array), summed over
+    arrays; the solve is timed on the X-engine's output."""
     st = {"xengine": 0.0, "fftcorr": 0.0, "solve": 0.0}
     for a in S["arrays"]:
         p = a["plan"]
-        st["xengine"] += time_fn(lambda: p.xengine(a["volt"]), reps)
+        vred = []
+        st["xengine"] += time_fn(lambda: vred.append(p.xengine(a["volt"])) if not vred else p.xengine(a["volt"]), reps)
         st["fftcorr"] += time_fn(lambda: p.fftcorr(a["volt"], a["gains_in"]), reps)
-        st["solve"] += time_fn(lambda: p.solve(a["out"]["vred"]), reps)
+        st["solve"] += time_fn(lambda: p.solve(vred[0]), reps)
     return st
 
 
@@ -256,25 +265,67 @@ def latency_from_stamps(S, reps):
                 "reps": len(v), "source": "device wall-clock stamps (rrc_io.d_stamps)"} for k, v in lat.items()}
 
 
-def plain_per_channel(S, w, rrc, dev, max_units):
-    """One plan per channel, host synchronisation after each channel; time
-    per channel on the first `max_units` channels, scaled to all."""
+OMNI_TOL = 1e-6          # FP32 relative change at which omnical stops
+OMNI_MAX_ITER = 20000
+
+
+def plain_per_channel(S, w, rrc, dev, max_units, budget_s=20.0):
+    """The plain form: one channel at a time, the paper's solver stepped from
+    the host.  Per channel: the X-engine, omnical's damped updates one
+    iteration per launch with the relative change read back after each
+    (the per-iteration convergence check), the finishing launch, then the
+    FFT-correlator, with a host synchronisation at the end.  Time per
+    channel on the first channels (at most `max_units` or 256, and within
+    the budget), scaled to all channels."""
     import torch
-    res = []
+    per_array, timed, iters = [], [], []
     for a in S["arrays"]:
         p1 = rrc.Plan(a["n"], a["types"], 1, w.n_time, dtype=S["dtype"])
-        o1 = p1.alloc_outputs(dev)
-        nc = w.n_chan if max_units <= 0 else min(w.n_chan, max_units)
-        nc = min(nc, 256)
-        for c in range(min(2, nc)):
-            p1.run(a["volt"][c:c + 1], gains_in=a["gains_in"][c:c + 1], mode="pipelined", out=o1)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
+        nc = min(w.n_chan, 256 if max_units <= 0 else max_units)
+        t_all, done = 0.0, 0
         for c in range(nc):
-            p1.run(a["volt"][c:c + 1], gains_in=a["gains_in"][c:c + 1], mode="pipelined", out=o1)
+            v = a["volt"][c:c + 1]
+            gi = a["gains_in"][c:c + 1]
             torch.cuda.synchronize()
-        res.append((time.perf_counter() - t0) / nc * w.n_chan)
-    return sum(res) * 1e3, min(w.n_chan, 256 if max_units <= 0 else min(max_units, 256))
+            t0 = time.perf_counter()
+            vr = p1.xengine(v)
+            st = p1.omnical(vr, gains_in=gi, max_iter=1, tol=OMNI_TOL, finish=False)
+            it = 1
+            while float(st["delta"][0]) >= OMNI_TOL and it < OMNI_MAX_ITER:
+                st = p1.omnical(vr, max_iter=1, tol=OMNI_TOL, finish=False, state=st)
+                it += 1
+            p1.omnical(vr, max_iter=0, tol=OMNI_TOL, finish=True, state=st)
+            p1.fftcorr(v, gi)
+            torch.cuda.synchronize()
+            t_all += time.perf_counter() - t0
+            done += 1
+            iters.append(it)
+            if t_all > budget_s / len(S["arrays"]):
+                break
+        per_array.append(t_all / done * w.n_chan)
+        timed.append(done)
+    return sum(per_array) * 1e3, timed, float(np.mean(iters))
+
+
+def batched_omnical(S, w):
+    """omnical on every unit of each array in one launch (device-side
+    convergence): the solver alone, beside the Gauss-Newton solve's stage
+    time.  Returns (ms, mean iterations, converged units)."""
+    import torch
+    ms, its, conv = 0.0, [], 0
+    for a in S["arrays"]:
+        p = a["plan"]
+        vr = p.xengine(a["volt"])
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        st = p.omnical(vr, gains_in=a["gains_in"], max_iter=OMNI_MAX_ITER, tol=OMNI_TOL, finish=True)
+        e1.record()
+        torch.cuda.synchronize()
+        ms += e0.elapsed_time(e1)
+        its += st["niter"].cpu().tolist()
+        conv += int((st["status"] == 0).sum())
+    return ms, float(np.mean(its)), conv
 
 
 # ------------------------------------------------------------- oracle legs
@@ -423,7 +474,11 @@ def cpu_baseline(S, w, budget_s):
 
 def measure(w, args, rrc, dev, with_oracle):
     log(f"{w.name}: generating inputs")
-    S = setup(w, dev, rrc, args.inflight, args.order)
+    S = setup(w, dev, rrc, args.inflight, args.order, args.xengine)
+    if args.stages_only:
+        log(f"{w.name}: stage times ({args.steps} launches each)")
+        return {"stages_ms": stage_times(S, w, args.steps), "config": {"workload": w.name,
+                                                                       "xengine": args.xengine}}
     log(f"{w.name}: {args.warmup} warm-up + {args.steps} timed steps")
     ms = time_steps(S, args.steps, args.warmup)
     log(f"{w.name}: {ms:.3f} ms per step; stage times")
@@ -461,8 +516,11 @@ def measure(w, args, rrc, dev, with_oracle):
          "ms_per_launch": stages["solve"], "units_per_launch": total_units, "workgroups_per_unit": 1,
          "cus": S["cus"]},
     ]
-    log(f"{w.name}: plain per-channel form")
-    plain_ms, plain_n = plain_per_channel(S, w, rrc, dev, args.plain_units)
+    log(f"{w.name}: plain per-channel form (host-stepped omnical)")
+    plain_ms, plain_n, plain_it = plain_per_channel(S, w, rrc, dev, args.plain_units)
+    log(f"{w.name}: batched omnical")
+    om_ms, om_it, om_conv = batched_omnical(S, w)
+    gn_it = float(np.mean(np.concatenate([a["out"]["niter"].cpu().numpy() for a in S["arrays"]])))
     rec = {
         "value": total_units / (ms * 1e-3), "ms_per_step": ms,
         "config": {"workload": w.name, "grids": [f"{a['n']}x{a['n']}" for a in S["arrays"]],
@@ -477,7 +535,15 @@ def measure(w, args, rrc, dev, with_oracle):
         "one_batch_at_a_time": {"ms_per_step": serial_ms, "value": total_units / (serial_ms * 1e-3)},
         "plain_per_channel": {"ms_per_step": plain_ms, "value": total_units / (plain_ms * 1e-3),
                               "speedup_batched": plain_ms / ms, "channels_timed_per_array": plain_n,
-                              "form": "one plan per channel, host synchronisation after each channel"},
+                              "omnical_iterations_mean": plain_it, "omnical_tol": OMNI_TOL,
+                              "form": "one channel at a time: X-engine, omnical (damping 0.3) one iteration "
+                                      "per launch with the change read back after each, FFT-correlator; "
+                                      "time per channel scaled to all channels"},
+        "solver_comparison": {"gauss_newton_batched_ms": stages["solve"],
+                              "gauss_newton_steps_mean": gn_it, "gauss_newton_start": "FIRSTCAL",
+                              "omnical_batched_ms": om_ms, "omnical_iterations_mean": om_it,
+                              "omnical_converged_units": om_conv, "omnical_start": "the given gains",
+                              "units": total_units},
         "roofline": roof,
         "roofline_other": other,
         "data": "synthetic" + ("" if S["host_gen"] else " (drawn on the GPU)"),
@@ -515,13 +581,17 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     r = measure(w, args, rrc, dev, with_oracle=not args.no_cpu_baseline)
+    if args.stages_only:
+        print(json.dumps(r), flush=True)
+        return
     rec = {
         "metric": METRIC,
         "value": r["value"], "unit": "channel-integrations/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": r["data"], "config": r["config"],
         "stages_ms": r["stages_ms"], "one_batch_at_a_time": r["one_batch_at_a_time"],
-        "plain_per_channel": r["plain_per_channel"], "roofline": r["roofline"],
+        "plain_per_channel": r["plain_per_channel"], "solver_comparison": r["solver_comparison"],
+        "roofline": r["roofline"],
         "roofline_other": r["roofline_other"],
         "gate": r.get("gate"), "cpu_baseline": r.get("cpu_baseline"),
     }
@@ -533,7 +603,8 @@ def main():
         a2.gate_units = min(args.gate_units, 8)
         x = measure(wl[EXTRA_WORKLOAD], a2, rrc, dev, with_oracle=False)
         rec["extra"] = {EXTRA_WORKLOAD: {k: x[k] for k in ("value", "ms_per_step", "config", "stages_ms",
-                                                           "roofline", "roofline_other", "plain_per_channel")}}
+                                                           "roofline", "roofline_other", "plain_per_channel",
+                                                           "solver_comparison")}}
     print(json.dumps(rec), flush=True)
 
 

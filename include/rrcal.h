@@ -230,6 +230,28 @@ int rrc_solve(rrc_plan* plan, void* stream, const void* d_vred, const void* d_ga
               const void* d_gains_ref, void* d_gains_out, void* d_vmodel, float* d_chisq,
               int32_t* d_niter, int32_t* d_status, void* d_work);
 
+/* (a5) The same calibration by omnical's damped simultaneous updates (Sec. 3:
+ * the solver of the paper's simulations, damping 0.3): each single g_i and
+ * V_alpha is replaced by its exact least-squares minimiser with the others
+ * held, blended x <- x + 0.3 (x' - x), until ||x_new - x|| / ||x_new|| < tol
+ * (FP32 state; the finishing call fixes the degeneracies like
+ * RRC_DEGEN_REFANT and sums chi^2 in FP64).  It is the plain form the
+ * adjoint-driven Gauss-Newton solve is measured against.
+ * d_vred:     [U][P] as written by rrc_xengine for this plan's dtype.
+ * d_gains_in: [U][N] start gains (V_alpha from the group means), or NULL to
+ *             continue from the state in d_gains / d_vmodel.
+ * max_iter:   iterations of this call (per unit; a unit stops when
+ *             converged).  One call per iteration with d_delta read back is
+ *             the host-stepped form; one call with many the device form.
+ * finish:     non-zero: degeneracy fix, chi^2 and final status.
+ * d_gains [U][N], d_vmodel [U][K]: complex64 state in, result out;
+ * d_niter [U]: iterations so far (set by a call with d_gains_in, else
+ * increased); d_status [U]: RRC_UNIT_*; d_delta [U] (optional): the last
+ * relative change; d_chisq [U] (finish only). */
+int rrc_omnical(rrc_plan* plan, void* stream, const void* d_vred, const void* d_gains_in, int32_t max_iter,
+                float tol, int32_t finish, void* d_gains, void* d_vmodel, float* d_chisq, int32_t* d_niter,
+                int32_t* d_status, float* d_delta);
+
 /* (a5) chi^2 only: d_chisq[u] = sum_b |V_b - g_i conj(g_j) V_alpha|^2 for
  * complex64 d_g [U][N], d_vm [U][K], d_vred [U][P] (complex64, any dtype
  * plan; int sums must be converted by the caller).  FP32 products, FP64 sum. */
@@ -304,6 +326,44 @@ int rrc_run(rrc_plan* plan, void* stream, int32_t mode, const rrc_io* io);
  * race on it and must be ordered by the caller. */
 #define RRC_STATIC_SCRATCH_BYTES (32u << 20)
 int rrc_run_static(rrc_plan* plan, void* stream, int32_t mode, const rrc_io* io);
+
+/* ---- low-cadence calibration (Sec. 4) -----------------------------------
+ * The calibrator correlates about p N log N baselines at a time (the budget
+ * of eq. lowcadcal_inttime) and cycles through every redundant group, whole
+ * groups per cycle, so N_cycle cycles of t_int = t_cal / N_cycle populate
+ * the full visibility matrix, which is then calibrated once over every
+ * type.  Groups are taken in V^unique's lag order; a cycle takes whole
+ * groups while its pair count stays within p N ln N (log_base as in
+ * rrc_select_subset).  The populated matrix is the all-type pair list: the
+ * types in lag order, each type's pairs in the raster order of the first
+ * antenna (the layout of V^reduced with every type selected), P = N(N-1)/2. */
+#define RRC_LOWCAD_MAX_GRID   32    /* n of the low-cadence entry points        */
+#define RRC_LOWCAD_MAX_CYCLES 256
+
+/* The round robin: cycle c correlates lag-order types
+ * [type_begin[c], type_begin[c+1]); type_begin gets n_cycles + 1 entries
+ * (room for `cap`).  Host only, pure. */
+int rrc_lowcad_schedule(int32_t n, double p, double log_base, int32_t* type_begin, int32_t cap,
+                        int32_t* n_cycles);
+
+/* The populated matrix: d_volt [U][T][N] complex64 voltages of one
+ * calibration interval; cycle c integrates samples
+ * [floor(c T / n_cycles), floor((c+1) T / n_cycles)), and each pair's entry
+ * is the mean of v_i conj(v_j) over its cycle's samples (FP32).
+ * d_vfull: [U][N(N-1)/2] complex64.  n <= RRC_LOWCAD_MAX_GRID,
+ * n_cycles <= RRC_LOWCAD_MAX_CYCLES <= T. */
+int rrc_lowcad_xengine(int32_t n, int32_t n_units, int32_t n_time, const int32_t* type_begin,
+                       int32_t n_cycles, void* stream, const void* d_volt, void* d_vfull);
+
+/* Redundant calibration of the populated matrix over every type by
+ * omnical's damped updates (as rrc_omnical, finished: degeneracies fixed
+ * like RRC_DEGEN_REFANT, chi^2 in FP64), starting from d_gains_in (the
+ * previous interval's solution) with V_alpha from the group means.
+ * d_gains [U][N], d_vmodel [U][2n(n-1)] complex64 (lag order); d_chisq,
+ * d_niter, d_status [U].  3 <= n <= RRC_LOWCAD_MAX_GRID. */
+int rrc_lowcad_solve(int32_t n, int32_t n_units, void* stream, const void* d_vfull, const void* d_gains_in,
+                     int32_t max_iter, float tol, void* d_gains, void* d_vmodel, float* d_chisq,
+                     int32_t* d_niter, int32_t* d_status);
 
 /* A batch of plans (one per array; grids, channels and sample counts may
  * differ) whose hot paths run together: the uneven-batch case of several

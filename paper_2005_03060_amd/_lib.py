@@ -35,13 +35,16 @@ RRC_XENG_MFMA = 2
 RRC_MAX_TYPES = 16
 RRC_MAX_GRID = 64
 RRC_STATIC_SCRATCH_BYTES = 32 << 20
+RRC_LOWCAD_MAX_GRID = 32
+RRC_LOWCAD_MAX_CYCLES = 256
 
 EXPORTS = ("rrc_default_opts", "rrc_select_subset", "rrc_degeneracy_count", "rrc_plan_create",
            "rrc_plan_destroy", "rrc_plan_get_info", "rrc_workspace_size", "rrc_fftcorr",
            "rrc_xengine", "rrc_solve", "rrc_chisq_fwd", "rrc_chisq_adj", "rrc_run", "rrc_strerror",
            "rrc_batch_create", "rrc_batch_destroy", "rrc_batch_run", "rrc_plan_prepare",
            "rrc_plan_set_order", "rrc_wall_clock_hz", "rrc_run_static", "rrc_plan_set_xengine",
-           "rrc_gain_variance")
+           "rrc_gain_variance", "rrc_omnical", "rrc_lowcad_schedule", "rrc_lowcad_xengine",
+           "rrc_lowcad_solve")
 
 
 class SolverOpts(C.Structure):
@@ -109,6 +112,10 @@ def load_library() -> C.CDLL:
         "rrc_run_static": (C.c_int, [vp, vp, i32, C.POINTER(RunIO)]),
         "rrc_plan_set_xengine": (C.c_int, [vp, i32]),
         "rrc_gain_variance": (C.c_int, [i32, pi32, i32, C.c_double, C.POINTER(C.c_double)]),
+        "rrc_omnical": (C.c_int, [vp, vp, vp, vp, i32, C.c_float, i32, vp, vp, pf, vp, vp, pf]),
+        "rrc_lowcad_schedule": (C.c_int, [i32, C.c_double, C.c_double, pi32, i32, pi32]),
+        "rrc_lowcad_xengine": (C.c_int, [i32, i32, i32, pi32, i32, vp, vp, vp]),
+        "rrc_lowcad_solve": (C.c_int, [i32, i32, vp, vp, vp, i32, C.c_float, vp, vp, pf, vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

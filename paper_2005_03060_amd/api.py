@@ -56,6 +56,59 @@ def gain_variance(n: int, types: Sequence[Tuple[int, int]], snr: float):
     return out
 
 
+def lowcad_schedule(n: int, p: float = 1.0, log_base: float = 0.0):
+    """Low-cadence round robin (host only): list of cycles as lag-order type
+    ranges (t0, t1)."""
+    lib = L.load_library()
+    buf = (C.c_int32 * (L.RRC_LOWCAD_MAX_CYCLES + 1))()
+    nc = C.c_int32()
+    L.check(lib.rrc_lowcad_schedule(n, p, log_base, buf, L.RRC_LOWCAD_MAX_CYCLES + 1, C.byref(nc)),
+            "rrc_lowcad_schedule")
+    return [(buf[c], buf[c + 1]) for c in range(nc.value)]
+
+
+class LowCadence:
+    """Low-cadence calibration of U units of an n x n grid (Sec. 4): the
+    round-robin X-engine over each cycle's samples, then the omnical solve
+    over every type (rrc_lowcad_*)."""
+
+    def __init__(self, n: int, n_units: int, n_time: int, p: float = 1.0, log_base: float = 0.0):
+        self._lib = L.load_library()
+        self.n, self.n_units, self.n_time = n, n_units, n_time
+        self.cycles = lowcad_schedule(n, p, log_base)
+        flat = [c[0] for c in self.cycles] + [self.cycles[-1][1]]
+        self._tb = (C.c_int32 * len(flat))(*flat)
+        self.n_pairs = n * n * (n * n - 1) // 2
+        self.n_types = 2 * n * (n - 1)
+
+    def xengine(self, volt: torch.Tensor) -> torch.Tensor:
+        shape = (self.n_units, self.n_time, self.n * self.n)
+        if tuple(volt.shape) != shape or volt.dtype != torch.complex64 or not volt.is_cuda or not volt.is_contiguous():
+            raise ValueError(f"volt must be a contiguous complex64 CUDA tensor of shape {shape}")
+        out = torch.empty((self.n_units, self.n_pairs), dtype=torch.complex64, device=volt.device)
+        L.check(self._lib.rrc_lowcad_xengine(self.n, self.n_units, self.n_time, self._tb, len(self.cycles),
+                                             _stream(), _ptr(volt), _ptr(out)), "rrc_lowcad_xengine")
+        return out
+
+    def solve(self, vfull: torch.Tensor, gains_in: torch.Tensor, max_iter: int = 20000, tol: float = 1e-7):
+        dev = vfull.device
+        U = self.n_units
+        if tuple(vfull.shape) != (U, self.n_pairs) or vfull.dtype != torch.complex64 or not vfull.is_contiguous():
+            raise ValueError("vfull must be contiguous complex64 [U, N(N-1)/2]")
+        if tuple(gains_in.shape) != (U, self.n * self.n) or gains_in.dtype != torch.complex64 \
+                or not gains_in.is_contiguous():
+            raise ValueError("gains_in must be contiguous complex64 [U, N]")
+        out = dict(gains=torch.empty((U, self.n * self.n), dtype=torch.complex64, device=dev),
+                   vmodel=torch.empty((U, self.n_types), dtype=torch.complex64, device=dev),
+                   chisq=torch.empty((U,), dtype=torch.float32, device=dev),
+                   niter=torch.zeros((U,), dtype=torch.int32, device=dev),
+                   status=torch.empty((U,), dtype=torch.int32, device=dev))
+        L.check(self._lib.rrc_lowcad_solve(self.n, U, _stream(), _ptr(vfull), _ptr(gains_in), int(max_iter),
+                                           float(tol), _ptr(out["gains"]), _ptr(out["vmodel"]), _ptr(out["chisq"]),
+                                           _ptr(out["niter"]), _ptr(out["status"])), "rrc_lowcad_solve")
+        return out
+
+
 def default_opts() -> Dict[str, float]:
     lib = L.load_library()
     o = L.SolverOpts()
@@ -165,6 +218,32 @@ class Plan:
                                     _ptr(out["niter"]), _ptr(out["status"]), _ptr(self.workspace(dev))),
                 "rrc_solve")
         return out
+
+    def omnical(self, vred: torch.Tensor, gains_in: Optional[torch.Tensor] = None, max_iter: int = 100000,
+                tol: float = 1e-6, finish: bool = True, state: Optional[Dict[str, torch.Tensor]] = None):
+        """(a5) omnical's damped updates (rrc_omnical): one call of up to
+        max_iter iterations.  `state` (gains, vmodel, chisq, niter, status,
+        delta) is created when None and carried between calls."""
+        dev = vred.device
+        want = self.vred_like(dev)
+        if tuple(vred.shape) != tuple(want.shape) or vred.dtype != want.dtype or not vred.is_contiguous():
+            raise ValueError(f"vred must be contiguous {want.dtype} of shape {tuple(want.shape)}")
+        self._check_c64(gains_in, (self.n_units, self.n_ant), "gains_in")
+        if state is None:
+            if gains_in is None:
+                raise ValueError("the first call needs gains_in")
+            U = self.n_units
+            state = dict(gains=torch.empty((U, self.n_ant), dtype=torch.complex64, device=dev),
+                         vmodel=torch.empty((U, len(self.types)), dtype=torch.complex64, device=dev),
+                         chisq=torch.zeros((U,), dtype=torch.float32, device=dev),
+                         niter=torch.zeros((U,), dtype=torch.int32, device=dev),
+                         status=torch.zeros((U,), dtype=torch.int32, device=dev),
+                         delta=torch.zeros((U,), dtype=torch.float32, device=dev))
+        L.check(self._lib.rrc_omnical(self._h, _stream(), _ptr(vred), _ptr(gains_in), int(max_iter), float(tol),
+                                      1 if finish else 0, _ptr(state["gains"]), _ptr(state["vmodel"]),
+                                      _ptr(state["chisq"]), _ptr(state["niter"]), _ptr(state["status"]),
+                                      _ptr(state["delta"])), "rrc_omnical")
+        return state
 
     def chisq_fwd(self, g, vm, vred) -> torch.Tensor:
         self._check_c64(g, (self.n_units, self.n_ant), "g")

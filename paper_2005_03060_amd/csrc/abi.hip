@@ -599,6 +599,36 @@ int rrc_solve(rrc_plan* p, void* stream, const void* d_vred, const void* d_gains
                       d_niter, d_status, nullptr);
 }
 
+int rrc_omnical(rrc_plan* p, void* stream, const void* d_vred, const void* d_gains_in, int32_t max_iter,
+                float tol, int32_t finish, void* d_gains, void* d_vmodel, float* d_chisq, int32_t* d_niter,
+                int32_t* d_status, float* d_delta) {
+    if (!p || !d_vred || !d_gains || !d_vmodel || !d_niter || !d_status || max_iter < 0 || !(tol >= 0.f))
+        return RRC_EINVAL;
+    if (finish && !d_chisq) return RRC_EINVAL;
+    rrc::OmniLaunch L{};
+    L.n = p->sel.n;
+    L.K = p->sel.K;
+    L.P = p->sel.P;
+    L.n_units = p->U;
+    L.all = false;
+    L.ci4 = p->dtype == RRC_CI4;
+    L.sel = p->sel;
+    L.lds_types = 0;
+    L.max_iter = max_iter;
+    L.tol = tol;
+    L.damping = 0.3f;
+    L.finish = finish != 0;
+    L.gains_in = reinterpret_cast<const float2*>(d_gains_in);
+    L.vred = d_vred;
+    L.gains = d_gains;
+    L.vmodel = d_vmodel;
+    L.chisq = d_chisq;
+    L.niter = d_niter;
+    L.status = d_status;
+    L.delta = d_delta;
+    return rrc::launch_omnical(L, as_stream(stream)) == hipSuccess ? RRC_OK : RRC_EDEVICE;
+}
+
 static int chisq_common(rrc_plan* p, void* stream, const void* d_g, const void* d_vm,
                         const void* d_vred, float* d_chisq, void* d_grad_g, void* d_grad_v,
                         float* d_diag_g, float* d_diag_v, bool adj) {

@@ -65,6 +65,37 @@ struct SolveLaunch {
     unsigned long long* stamps;   // optional [1 + U] run stamps (see unit_done_stamp)
 };
 
+// Damped per-parameter updates (omnical.hip) over the plan's selection or,
+// with `all`, every canonical type of the grid in lag order.
+struct OmniLaunch {
+    int n, K, P, n_units;
+    bool all;              // every canonical type (K = 2 n (n - 1)), lag order
+    bool ci4;              // V^reduced as raw int32 sums
+    Sel sel;               // the selection when !all
+    size_t lds_types;      // LDS bytes of the every-type table (0 when !all)
+    int max_iter;
+    float tol, damping;
+    bool finish;           // fix the degeneracies and compute chi^2 at exit
+    const float2* gains_in;    // start (V from the group means), or null: continue
+    const void* vred;
+    void* gains;           // [U][N] state and output
+    void* vmodel;          // [U][K] state and output
+    float* chisq;
+    int* niter;
+    int* status;
+    float* delta;          // optional [U]: the last relative change
+};
+
+// Low-cadence X-engine (lowcad.hip): every pair of an n x n grid, each
+// integrated over the samples of its cycle.
+constexpr int kLowcadMaxCycles = 256;
+struct LowcadLaunch {
+    int n, n_units, T, n_cycles;
+    int type_begin[kLowcadMaxCycles + 1];   // cycle c = lag-order types [type_begin[c], type_begin[c+1])
+    const void* volt;      // [U][T][N] complex64
+    void* vfull;           // [U][N (N - 1) / 2] complex64, the all-type pair list
+};
+
 struct ChisqLaunch {
     Sel sel;
     int n_units;
@@ -92,6 +123,10 @@ size_t solve_lds_bytes(const Sel& s, bool vcache);
 hipError_t prepare_solve(const SolveLaunch& L);
 hipError_t launch_solve(const SolveLaunch& L, hipStream_t st);
 hipError_t launch_chisq(const ChisqLaunch& L, hipStream_t st, bool adjoint);
+hipError_t launch_omnical(const OmniLaunch& L, hipStream_t st);
+hipError_t launch_xlowcad(const LowcadLaunch& L, hipStream_t st);
+size_t omnical_lds_bytes(int n, int K, bool all);
+int omnical_max_all_grid();
 hipError_t launch_stamp_start(unsigned long long* stamps, int n_units, hipStream_t st);
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st);
 #endif

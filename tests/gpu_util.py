@@ -22,6 +22,13 @@ TOL_GAINS = 1e-6
 # SNR: measured 2e-7 .. 6e-7 at 16x16 (SNR 10) and 1.4e-5 at 32x32 (SNR 5).
 # 1e-4 bounds it with margin; the solver alone is held to TOL_GAINS.
 TOL_GAINS_E2E = 1e-4
+# omnical's FP32 iteration (no FP64 refinement) stopped at a relative change
+# Delta = 1e-7: the distance left to the minimum is about Delta / (eta (1 -
+# rho)) with eta = 0.3 the damping and rho the contraction of the slowest
+# (long-wavelength phase) mode, which approaches 1 as the grid grows:
+# measured 5.7e-6 at 8x8 and 2.3e-5 at 16x16 (chi^2 within 3e-8 of the
+# minimum's).  The bar is 1e-4.
+TOL_OMNICAL = 1e-4
 # FP32 X-engine: |dV_b| relative to the unit's mean voltage power.  T
 # products of |v|^2 ~ 1 summed in FP32 in runs of at most a few hundred
 # samples: a random-walk rounding error of ~sqrt(T) * 6e-8 < 4e-6 for

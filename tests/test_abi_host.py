@@ -150,3 +150,12 @@ def test_gain_variance_refuses_degenerate_selection():
     with pytest.raises(rrc.RRCError) as e:
         rrc.gain_variance(6, [(1, 0), (0, 1)], 10.0)
     assert e.value.code == _lib.RRC_EDEGEN
+
+
+@pytest.mark.parametrize("n,p,base", [(4, 1.0, 0.0), (8, 1.0, 0.0), (8, 0.5, 2.0), (16, 1.0, 0.0), (32, 1.0, 0.0)])
+def test_lowcad_schedule_matches_oracle(n, p, base):
+    # Sec. 4 round robin: whole groups in lag order within p N log N per cycle
+    from oracle import lowcad as LC
+    import math
+    got = rrc.lowcad_schedule(n, p, base)
+    assert got == LC.schedule(n, p, base if base > 1 else math.e)

@@ -6,7 +6,8 @@ import torch
 from oracle import correlator as OC
 from oracle import geometry as OG
 from oracle import redcal as OR
-from tests.gpu_util import (TOL_GAINS, TOL_GAINS_E2E, TOL_VUNIQUE, TOL_XENG, as_c64, ci4_sums_int32, gain_err,
+from tests.gpu_util import (TOL_GAINS, TOL_GAINS_E2E, TOL_OMNICAL, TOL_VUNIQUE, TOL_XENG, as_c64, ci4_sums_int32,
+                            gain_err,
                             make_ci4_units, make_units, oracle_solve, oracle_vred, oracle_vunique, pairs_of,
                             rel_l2)
 
@@ -228,6 +229,47 @@ def test_solve_from_gains_and_match_mode(rrc):
                            init=(gref, OR.group_mean(vr64[u], gref, pairs, tix, len(types))))
         assert gain_err(out["gains"][u].cpu().numpy(), ref["g"]) <= TOL_GAINS
         assert int(out["status"][u]) == 0
+
+
+@pytest.mark.parametrize("n,U,T", [(8, 2, 256), (16, 2, 1024)])
+def test_omnical_reaches_the_oracle_minimum(rrc, n, U, T):
+    # omnical's damped updates (FP32, from the true gains) and the oracle's
+    # Gauss-Newton (FP64, from its FIRSTCAL start) reach the same minimum of
+    # eq. redchi; FP32 stops at a relative change of 1e-7, so the gains agree
+    # to FP32 rounding times the iteration's condition
+    plan, types, vr32, vr64 = _solve_case(rrc, n, U, T, 10.0)
+    _, g = make_units(n, U, T, snr=10.0, wid=90)
+    st = plan.omnical(torch.from_numpy(vr32).to(DEV), gains_in=torch.from_numpy(g.astype(np.complex64)).to(DEV),
+                      max_iter=20000, tol=1e-7)
+    torch.cuda.synchronize()
+    for u in range(U):
+        ref = oracle_solve(vr64[u], n, types)
+        gerr = gain_err(st["gains"][u].cpu().numpy(), ref["g"])
+        cerr = abs(float(st["chisq"][u]) - ref["chisq"]) / ref["chisq"]
+        print(f"n={n} unit {u}: omnical gains {gerr:.2e} chi2 {cerr:.2e} niter {int(st['niter'][u])} "
+              f"status {int(st['status'][u])}")
+        assert int(st["status"][u]) == 0
+        assert gerr <= TOL_OMNICAL
+        assert cerr <= 1e-5
+
+
+def test_omnical_host_stepped_equals_one_call(rrc):
+    # the plain form (one iteration per call, state carried) is the same
+    # arithmetic as one call of many iterations
+    n, U, T = 8, 2, 256
+    plan, types, vr32, _ = _solve_case(rrc, n, U, T, 10.0)
+    _, g = make_units(n, U, T, snr=10.0, wid=90)
+    vr = torch.from_numpy(vr32).to(DEV)
+    gin = torch.from_numpy(g.astype(np.complex64)).to(DEV)
+    a = plan.omnical(vr, gains_in=gin, max_iter=7, tol=0.0, finish=True)
+    b = plan.omnical(vr, gains_in=gin, max_iter=1, tol=0.0, finish=False)
+    for _ in range(5):
+        b = plan.omnical(vr, max_iter=1, tol=0.0, finish=False, state=b)
+    b = plan.omnical(vr, max_iter=1, tol=0.0, finish=True, state=b)
+    torch.cuda.synchronize()
+    assert torch.equal(b["niter"], a["niter"]) and int(a["niter"][0]) == 7
+    for k in ("gains", "vmodel", "chisq"):
+        assert torch.equal(a[k], b[k]), k
 
 
 def test_solve_nonfinite_unit_is_flagged(rrc):
