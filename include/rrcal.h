@@ -365,6 +365,30 @@ int rrc_lowcad_solve(int32_t n, int32_t n_units, void* stream, const void* d_vfu
                      int32_t max_iter, float tol, void* d_gains, void* d_vmodel, float* d_chisq,
                      int32_t* d_niter, int32_t* d_status);
 
+/* Autotuner of a plan's launch parameters for the pipelined run on this
+ * device: the FFT-correlator's time chunk (1, 2 or 4 times the default
+ * length, i.e. fewer workgroups each integrating more samples and fewer
+ * partial grids for the finish), the branch order (rrc_plan_set_order) and,
+ * for 4-bit plans whose cover fits, the X-engine kernel
+ * (rrc_plan_set_xengine).  Each candidate runs the whole path (rrc_run,
+ * PIPELINED, on `io`, whose contents it overwrites) once to warm up and
+ * three times under HIP events on `stream`; the fastest is applied to the
+ * plan.  cache_path (may be NULL): a text file of past choices, one line
+ * per device (architecture, CU count) and plan shape (grid, types, U, T,
+ * dtype); a matching line is applied without timing, a new choice is
+ * appended.  Synchronises `stream`; not for use under graph capture.
+ * V^reduced and the solve's outputs are identical for every candidate;
+ * V^unique differs only by the order in which the time chunks' partial
+ * power grids are added (FP32 rounding). */
+typedef struct {
+    int32_t fft_chunk_factor;
+    int32_t order;      /* RRC_ORDER_*                              */
+    int32_t xengine;    /* RRC_XENG_*                               */
+    float   ms_per_run; /* the chosen candidate's time per rrc_run */
+    int32_t from_cache;
+} rrc_tune;
+int rrc_plan_tune(rrc_plan* plan, void* stream, const rrc_io* io, const char* cache_path, rrc_tune* out);
+
 /* A batch of plans (one per array; grids, channels and sample counts may
  * differ) whose hot paths run together: the uneven-batch case of several
  * arrays calibrated at once (Fig. 1 real-time loop over every channel of

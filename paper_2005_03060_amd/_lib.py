@@ -44,7 +44,7 @@ EXPORTS = ("rrc_default_opts", "rrc_select_subset", "rrc_degeneracy_count", "rrc
            "rrc_batch_create", "rrc_batch_destroy", "rrc_batch_run", "rrc_plan_prepare",
            "rrc_plan_set_order", "rrc_wall_clock_hz", "rrc_run_static", "rrc_plan_set_xengine",
            "rrc_gain_variance", "rrc_omnical", "rrc_lowcad_schedule", "rrc_lowcad_xengine",
-           "rrc_lowcad_solve")
+           "rrc_lowcad_solve", "rrc_plan_tune")
 
 
 class SolverOpts(C.Structure):
@@ -66,6 +66,11 @@ class RunIO(C.Structure):
                 ("d_gains_out", C.c_void_p), ("d_vmodel", C.c_void_p), ("d_chisq", C.c_void_p),
                 ("d_niter", C.c_void_p), ("d_status", C.c_void_p), ("d_work", C.c_void_p),
                 ("d_stamps", C.c_void_p)]
+
+
+class Tune(C.Structure):
+    _fields_ = [("fft_chunk_factor", C.c_int32), ("order", C.c_int32), ("xengine", C.c_int32),
+                ("ms_per_run", C.c_float), ("from_cache", C.c_int32)]
 
 
 class RRCError(RuntimeError):
@@ -114,6 +119,7 @@ def load_library() -> C.CDLL:
         "rrc_gain_variance": (C.c_int, [i32, pi32, i32, C.c_double, C.POINTER(C.c_double)]),
         "rrc_omnical": (C.c_int, [vp, vp, vp, vp, i32, C.c_float, i32, vp, vp, pf, vp, vp, pf]),
         "rrc_lowcad_schedule": (C.c_int, [i32, C.c_double, C.c_double, pi32, i32, pi32]),
+        "rrc_plan_tune": (C.c_int, [vp, vp, C.POINTER(RunIO), C.c_char_p, C.POINTER(Tune)]),
         "rrc_lowcad_xengine": (C.c_int, [i32, i32, i32, pi32, i32, vp, vp, vp]),
         "rrc_lowcad_solve": (C.c_int, [i32, i32, vp, vp, vp, i32, C.c_float, vp, vp, pf, vp, vp]),
     }

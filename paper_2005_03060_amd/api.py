@@ -307,6 +307,19 @@ class Plan:
         L.check(self._lib.rrc_run_static(self._h, _stream(), _MODES[mode], C.byref(io)), "rrc_run_static")
         return out
 
+    def tune(self, volt: torch.Tensor, gains_in: torch.Tensor, out: Optional[Dict[str, torch.Tensor]] = None,
+             cache_path: Optional[str] = None) -> Dict[str, float]:
+        """rrc_plan_tune: pick the fastest launch parameters of the pipelined
+        run (FFT time chunk, branch order, 4-bit X-engine kernel); `out` is
+        overwritten.  Returns the choice."""
+        if out is None:
+            out = self.alloc_outputs(volt.device)
+        io = self.run_io(volt, gains_in, None, out)
+        t = L.Tune()
+        L.check(self._lib.rrc_plan_tune(self._h, _stream(), C.byref(io),
+                                        cache_path.encode() if cache_path else None, C.byref(t)), "rrc_plan_tune")
+        return {f: getattr(t, f) for f, _ in L.Tune._fields_}
+
     def set_order(self, order: str) -> None:
         """Branch order of the pipelined run: "xeng_first" or "fft_first"."""
         code = {"xeng_first": L.RRC_ORDER_XENG_FIRST, "fft_first": L.RRC_ORDER_FFT_FIRST}[order]

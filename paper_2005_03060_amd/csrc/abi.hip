@@ -7,6 +7,8 @@
 #include <cstdlib>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
+#include <string>
 #include <mutex>
 #include <new>
 #include <vector>
@@ -24,6 +26,7 @@ struct rrc_plan {
     rrc_solver_opts opts;
     // FFT-correlator
     int fft_tchunk, fft_nchunk;
+    int fft_tchunk0;                 // the default chunk (the workspace is sized for it)
     // X-engine; 4-bit plans whose window cover an int8 matrix-core
     // instantiation holds use it (x_mf: its launch fields) unless the
     // caller selects the dot-product kernel
@@ -366,6 +369,7 @@ int rrc_plan_create(rrc_plan** out, int32_t n, const int32_t* types_xy, int32_t 
     int tch = ceil_div(ceil_div(n_time, nch), S) * S;
     p->fft_tchunk = tch;
     p->fft_nchunk = ceil_div(n_time, tch);
+    p->fft_tchunk0 = tch;
 
     // X-engine: blocks of 256 antennas, S samples staged per step, time
     // chunks (whole steps) so that the launch has >= 2048 workgroups while
@@ -750,6 +754,99 @@ int rrc_run_static(rrc_plan* p, void* stream, int32_t mode, const rrc_io* io) {
     rrc_io io2 = *io;
     io2.d_work = p->scratch;
     return rrc_run(p, stream, mode, &io2);
+}
+
+// ------------------------------------------------------------------ tuner
+
+// Chunk of `f` times the default chunk length, whole samples-per-step
+// multiples: fewer partial grids, so the workspace still holds them.
+static void set_fft_chunk_factor(rrc_plan* p, int f) {
+    const int S = rrc::fft_samples_per_step_for(p->M);
+    const int tch = std::min(ceil_div(p->T, S) * S, p->fft_tchunk0 * f);
+    p->fft_tchunk = tch;
+    p->fft_nchunk = ceil_div(p->T, tch);
+}
+
+static std::string tune_key(const rrc_plan* p) {
+    hipDeviceProp_t prop{};
+    std::string dev = "unknown";
+    if (hipGetDeviceProperties(&prop, p->device) == hipSuccess) dev = std::string(prop.gcnArchName) + "/" +
+                                                                        std::to_string(prop.multiProcessorCount);
+    std::string key = dev + " n=" + std::to_string(p->sel.n) + " types=";
+    for (int t = 0; t < p->sel.K; ++t)
+        key += std::to_string(p->sel.dx[t]) + ":" + std::to_string(p->sel.dy[t]) + (t + 1 < p->sel.K ? "," : "");
+    key += " U=" + std::to_string(p->U) + " T=" + std::to_string(p->T) + " dtype=" + std::to_string(p->dtype);
+    return key;
+}
+
+int rrc_plan_tune(rrc_plan* p, void* stream, const rrc_io* io, const char* cache_path, rrc_tune* out) {
+    if (!p || !io || !out || !io->d_gains_in) return RRC_EINVAL;
+    int rc = prepare(p);
+    if (rc != RRC_OK) return rc;
+    const std::string key = tune_key(p);
+    // cached choice
+    if (cache_path) {
+        std::ifstream f(cache_path);
+        std::string line;
+        while (std::getline(f, line)) {
+            const size_t bar = line.find(" | ");
+            if (bar == std::string::npos || line.substr(0, bar) != key) continue;
+            int fa = 0, ord = 0, xk = 0;
+            float ms = 0.f;
+            if (std::sscanf(line.c_str() + bar + 3, "chunk_factor=%d order=%d xengine=%d ms=%f", &fa, &ord, &xk,
+                            &ms) == 4 && fa >= 1) {
+                set_fft_chunk_factor(p, fa);
+                p->order = ord;
+                p->x_kind = xk;
+                *out = rrc_tune{fa, ord, xk, ms, 1};
+                return RRC_OK;
+            }
+        }
+    }
+    hipStream_t st = as_stream(stream);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return RRC_EDEVICE;
+    }
+    const int xkinds[2] = {RRC_XENG_DOT, RRC_XENG_MFMA};
+    const int nx = (p->dtype == RRC_CI4 && p->x_mf_ok) ? 2 : 1;
+    rrc_tune best{1, RRC_ORDER_XENG_FIRST, RRC_XENG_AUTO, 1e30f, 0};
+    for (int fa = 1; fa <= 4 && rc == RRC_OK; fa *= 2) {
+        if (fa > 1 && p->fft_tchunk0 * (fa / 2) >= p->T) break;       // no fewer chunks left
+        for (int ord = RRC_ORDER_XENG_FIRST; ord <= RRC_ORDER_FFT_FIRST && rc == RRC_OK; ++ord)
+            for (int xi = 0; xi < nx && rc == RRC_OK; ++xi) {
+                set_fft_chunk_factor(p, fa);
+                p->order = ord;
+                p->x_kind = nx > 1 ? xkinds[xi] : RRC_XENG_AUTO;
+                rc = rrc_run(p, stream, RRC_RUN_PIPELINED, io);           // warm-up
+                for (int r = 0; r < 3 && rc == RRC_OK; ++r) rc = rrc_run(p, stream, RRC_RUN_PIPELINED, io);
+                if (rc != RRC_OK) break;
+                if (hipEventRecord(e0, st) != hipSuccess) rc = RRC_EDEVICE;
+                for (int r = 0; r < 3 && rc == RRC_OK; ++r) rc = rrc_run(p, stream, RRC_RUN_PIPELINED, io);
+                float ms = 0.f;
+                if (rc == RRC_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                                     hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                    rc = RRC_EDEVICE;
+                ms /= 3.f;
+                if (rc == RRC_OK && ms < best.ms_per_run) best = rrc_tune{fa, ord, p->x_kind, ms, 0};
+            }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    set_fft_chunk_factor(p, best.fft_chunk_factor);
+    p->order = best.order;
+    p->x_kind = best.xengine;
+    if (rc != RRC_OK) return rc;
+    *out = best;
+    if (cache_path) {
+        std::ofstream f(cache_path, std::ios::app);
+        char buf[160];
+        std::snprintf(buf, sizeof(buf), " | chunk_factor=%d order=%d xengine=%d ms=%.4f", best.fft_chunk_factor,
+                      best.order, best.xengine, best.ms_per_run);
+        f << key << buf << "\n";
+    }
+    return RRC_OK;
 }
 
 // ------------------------------------------------------------------ batches

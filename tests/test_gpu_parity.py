@@ -585,3 +585,37 @@ def test_branch_orders_give_identical_results(rrc, dtype):
     torch.cuda.synchronize()
     for key in ("vunique", "vauto", "vred", "gains", "vmodel", "chisq", "niter", "status"):
         assert torch.equal(a[key], b2[key]), key
+
+
+@pytest.mark.parametrize("dtype", ["c64", "ci4"])
+def test_tuner_choice_cached_and_results_unchanged(rrc, dtype, tmp_path):
+    n, U, T = 16, 8, 1024
+    if dtype == "ci4":
+        b, re, im, g = make_ci4_units(n, U, T)
+        vd = torch.from_numpy(b).to(DEV)
+        v = re.astype(np.complex128) + 1j * im.astype(np.complex128)
+    else:
+        v, g = make_units(n, U, T)
+        vd = torch.from_numpy(v).to(DEV)
+    gin = torch.from_numpy(g.astype(np.complex64)).to(DEV)
+    plan, _ = _plan(rrc, n, U, T, dtype=dtype)
+    ref = plan.run(vd, gains_in=gin, mode="pipelined")
+    cache = str(tmp_path / "tune.txt")
+    t1 = plan.tune(vd, gin, cache_path=cache)
+    assert t1["from_cache"] == 0 and t1["ms_per_run"] > 0
+    got = plan.run(vd, gains_in=gin, mode="pipelined", out=plan.alloc_outputs(DEV))
+    torch.cuda.synchronize()
+    for key in ("vred", "gains", "vmodel", "chisq", "niter", "status"):
+        assert torch.equal(got[key], ref[key]), key
+    # another time chunking sums V^unique's partial grids in another order:
+    # the tuned result is held to the oracle at the V^unique tolerance
+    vu = got["vunique"].cpu().numpy()
+    for u in range(U):
+        want, _ = oracle_vunique(v[u], g[u].astype(np.complex64).astype(np.complex128), n)
+        assert rel_l2(vu[u], want) <= TOL_VUNIQUE
+    plan2, _ = _plan(rrc, n, U, T, dtype=dtype)
+    t2 = plan2.tune(vd, gin, cache_path=cache)
+    assert t2["from_cache"] == 1
+    for k in ("fft_chunk_factor", "order", "xengine"):
+        assert t2[k] == t1[k], k
+    print(f"{dtype}: tuned {t1}")

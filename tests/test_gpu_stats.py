@@ -47,3 +47,35 @@ def test_gain_spread_matches_predicted_covariance(rrc, n, seed):
     assert np.all(np.abs(ratio - 1.0) <= 0.12)
     # chi^2 has 2 DoF real degrees of freedom: spread sqrt(1 / DoF) per unit
     assert abs(chir.mean() - 1.0) <= 4.0 / np.sqrt(U * dof)
+
+
+def test_gain_variance_falls_with_subset_size(rrc):
+    # Fig. 5 (Sec. 5.3): more redundant groups in the subset, lower gain
+    # variance.  For each prefix of the length-sorted types, the GPU solve
+    # over 1024 realisations against the predicted covariance of that
+    # selection (eq. gaincov, the library's rrc_gain_variance, which is
+    # pinned to the oracle on the CPU), and the trend itself
+    n, U, snr = 8, 1024, 100.0
+    allt = OG.square_types(n)[0]
+    pos = OG.square_positions(n)
+    N = len(pos)
+    means = []
+    for k, K in enumerate((5, 7, 9, 12, 16)):
+        types = [tuple(t) for t in allt[:K]]
+        assert sum(OG.nullity(pos, types)) == 4
+        pairs, tix = OG.group_pairs(pos, types)
+        vred, g, vm = simulate_reduced_visibilities(40 + k, pairs, tix, N, K, U, snr)
+        plan = rrc.Plan(n, types, U, 256, init_mode="gains", degen_mode="match")
+        g32 = torch.from_numpy(np.broadcast_to(g.astype(np.complex64), (U, N)).copy()).to(DEV)
+        out = plan.solve(torch.from_numpy(vred.astype(np.complex64)).to(DEV), gains_in=g32, gains_ref=g32)
+        torch.cuda.synchronize()
+        assert int((out["status"] != 0).sum()) == 0
+        gg = out["gains"].cpu().numpy().astype(np.complex128)
+        emp = np.mean(np.abs(gg / g.astype(np.complex64).astype(np.complex128) - 1.0) ** 2, axis=0)
+        pred = rrc.gain_variance(n, types, snr)
+        ratio = emp.mean() / pred.mean()
+        print(f"K={K} ({len(pairs)} pairs): mean gain variance {emp.mean():.3e}, predicted {pred.mean():.3e}, "
+              f"ratio {ratio:.4f}")
+        assert abs(ratio - 1.0) <= 0.03
+        means.append(emp.mean())
+    assert all(b < a for a, b in zip(means, means[1:]))
