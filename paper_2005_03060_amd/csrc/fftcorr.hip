@@ -351,11 +351,16 @@ __global__ __launch_bounds__(kFftThreads) void k_fftcorr(const void* __restrict_
 // "quarter" q): with j' < 32,
 //     E(4m + q) = sum_j' w_32^{j'm} w_128^{j'q} [x_j' + (-i)^q x_{j'+32}],
 // a 32-point FFT after a fold of the 64 inputs.  512 work-items process two
-// samples per step: in the row stage wave (s, q) takes quarter q of the
-// rows of sample s (one row per lane); in the column stage wave (q, h)
-// takes quarter q of columns 64h .. 64h + 63 of both samples, so each
-// work-item owns 32 grid points of |E|^2 outright and writes them with no
-// reduction.
+// samples per step, one row or column per lane.  Row stage, in two halves:
+// wave (s, R) loads input group R (eight pairs j, j + 32) of every row of
+// sample s, divides by the gains and writes all four quarters' folded,
+// twiddled inputs into that row of the row buffer; after a barrier wave
+// (s, q) reads quarter q's 32 inputs back, transforms them, and after a
+// second barrier writes E(4m + q) over them.  So every voltage is unpacked
+// and divided by its gain once, not once per quarter.  Column stage: wave
+// (q, h) takes quarter q of columns 64h .. 64h + 63 of both samples, so
+// each work-item owns 32 grid points of |E|^2 outright and writes them with
+// no reduction.
 //
 // LDS: the two row buffers (128 KB) and the 1/g table (32 KB) fill the
 // 160 KB, so nothing is padded.  The table is stored transposed ([k][y]),
@@ -399,45 +404,56 @@ __device__ __forceinline__ const float2& lds_at(const float2* lds, uint32_t byte
     return *reinterpret_cast<const float2*>(reinterpret_cast<const char*>(lds) + byte_off);
 }
 
-// Quarter Q of one row: inputs x_j = v_j / g_j (zero for j >= n through the
-// table), outputs E(4m + Q) to the swizzled LDS row.  hcol = table + y;
-// wbase = byte offset of the row | (y mod 32) << 3.
-template <int Q, bool CI4, int W>
-__device__ __forceinline__ void row_quarter(const void* __restrict__ volt, size_t rowbase, int n,
-                                            const float2* hcol, float2* rbuf, uint32_t wbase) {
-    float2 u[32];
+// Row stage, first half: input group R of one row, the eight pairs
+// (j, j + 32) with j in [8R, 8R + 8).  x = v / g for both inputs (zero for
+// j + 32 >= n through the table), then every quarter's folded, twiddled
+// input u_q(j) = w_128^{jq} [x_j + (-i)^q x_{j+32}] goes to the row's own
+// LDS row at column 32 q + j (swizzled).  Each input is loaded and divided
+// by its gain once; the quarter waves that transform the row read u_q back.
+// hcol = table + y; wbase = byte offset of the row | (y mod 32) << 3.
+template <int R, bool CI4, int W>
+__device__ __forceinline__ void row_fold(const void* __restrict__ volt, size_t rowbase, int n,
+                                         const float2* hcol, float2* rbuf, uint32_t wbase) {
     // inputs 32 .. 63 may lie past the row (n >= 33 keeps 0 .. 31 inside):
-    // clamp their groups to the last one; the table zeroes them.  nw is
-    // re-read here so the 32 clamped offsets are not kept for the whole loop.
-    int nw = n - W;
-    asm volatile("" : "+s"(nw));
+    // clamp their groups to the last one; the table zeroes them
+    const int nw = n - W;
+    float2 a[8], b[8];
 #pragma unroll
-    for (int j = 0; j < 32; j += W) {
-        float2 a[W], b[W];
-        load_group<CI4, W>(volt, rowbase + j, a);
-        load_group<CI4, W>(volt, rowbase + min(j + 32, nw), b);
+    for (int e = 0; e < 8; e += W) {
+        float2 ga[W], gb[W];
+        load_group<CI4, W>(volt, rowbase + 8 * R + e, ga);
+        load_group<CI4, W>(volt, rowbase + min(8 * R + 32 + e, nw), gb);
 #pragma unroll
-        for (int e = 0; e < W; ++e) {
-            const float2 xa = cmul(a[e], hcol[(j + e) * 64]);
-            const float2 xb = cmul(b[e], hcol[(j + 32 + e) * 64]);
-            u[j + e] = twmul<128>(cadd(xa, twmul<4>(xb, Q)), (j + e) * Q);
-        }
-        // complex64 rows: finish each 8 inputs before the next loads issue.
-        // Issuing all 64 at once (what the scheduler prefers) holds 128
-        // registers of voltages plus 128 of 1/g and spills.  The empty asm
-        // consumes the 8 results and orders memory, so it is a fence for both.
-        if constexpr (!CI4) {
-            if ((j + W) % 8 == 0) {
-                const int b = (j + W) - 8;
-                asm volatile("" : "+v"(u[b].x), "+v"(u[b].y), "+v"(u[b + 1].x), "+v"(u[b + 1].y),
-                             "+v"(u[b + 2].x), "+v"(u[b + 2].y), "+v"(u[b + 3].x), "+v"(u[b + 3].y),
-                             "+v"(u[b + 4].x), "+v"(u[b + 4].y), "+v"(u[b + 5].x), "+v"(u[b + 5].y),
-                             "+v"(u[b + 6].x), "+v"(u[b + 6].y), "+v"(u[b + 7].x), "+v"(u[b + 7].y)
-                             :: "memory");
-            }
+        for (int f = 0; f < W; ++f) {
+            a[e + f] = ga[f];
+            b[e + f] = gb[f];
         }
     }
+    char* rb = reinterpret_cast<char*>(rbuf);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int j = 8 * R + e;
+        const float2 xa = cmul(a[e], hcol[j * 64]);
+        const float2 xb = cmul(b[e], hcol[(j + 32) * 64]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            *reinterpret_cast<float2*>(rb + (wbase ^ ((32 * q + j) << 3))) =
+                twmul<128>(cadd(xa, twmul<4>(xb, q)), j * q);
+    }
+}
+
+// Row stage, second half: quarter Q of one row, the 32-point transform of
+// u_Q read back from the row; outputs E(4m + Q) stay in registers until
+// every wave has read its inputs.
+template <int Q>
+__device__ __forceinline__ void row_fft(const float2* rbuf, uint32_t wbase, float2 (&u)[32]) {
+#pragma unroll
+    for (int j = 0; j < 32; ++j) u[j] = lds_at(rbuf, wbase ^ ((32 * Q + j) << 3));
     fft_dif<32>(u);
+}
+
+template <int Q>
+__device__ __forceinline__ void row_store(float2* rbuf, uint32_t wbase, const float2 (&u)[32]) {
     char* rb = reinterpret_cast<char*>(rbuf);
 #pragma unroll
     for (int r = 0; r < 32; ++r)
@@ -508,17 +524,38 @@ __global__ __launch_bounds__(kQThreads) void k_fftcorr_q(const void* __restrict_
 
     for (int t0 = tb; t0 < te; t0 += S) {
         const int t = t0 + rs;
-        if (t < te && y < n) {
+        const bool row_lane = t < te && y < n;
+        // byte offset of row y of sample rs | (y mod 32) << 3, recomputed per
+        // step so the swizzled addresses are not hoisted into registers for
+        // the whole loop
+        uint32_t wbase = (uint32_t)((rs * H + y) * M * 8) | (uint32_t)((y & 31) << 3);
+        asm volatile("" : "+v"(wbase));
+        if (row_lane) {
             const size_t rowbase = ((size_t)unit * T + t) * N + (size_t)y * n;
-            uint32_t wbase = (uint32_t)((rs * H + y) * M * 8) | (uint32_t)((y & 31) << 3);
-            // recomputed per step, so the 32 swizzled addresses are not
-            // hoisted into registers for the whole loop
-            asm volatile("" : "+v"(wbase));
             switch (rq) {
-                case 0: row_quarter<0, CI4, W>(volt, rowbase, n, hinv + y, rbuf, wbase); break;
-                case 1: row_quarter<1, CI4, W>(volt, rowbase, n, hinv + y, rbuf, wbase); break;
-                case 2: row_quarter<2, CI4, W>(volt, rowbase, n, hinv + y, rbuf, wbase); break;
-                default: row_quarter<3, CI4, W>(volt, rowbase, n, hinv + y, rbuf, wbase); break;
+                case 0: row_fold<0, CI4, W>(volt, rowbase, n, hinv + y, rbuf, wbase); break;
+                case 1: row_fold<1, CI4, W>(volt, rowbase, n, hinv + y, rbuf, wbase); break;
+                case 2: row_fold<2, CI4, W>(volt, rowbase, n, hinv + y, rbuf, wbase); break;
+                default: row_fold<3, CI4, W>(volt, rowbase, n, hinv + y, rbuf, wbase); break;
+            }
+        }
+        __syncthreads();
+        float2 u[32];
+        if (row_lane) {
+            switch (rq) {
+                case 0: row_fft<0>(rbuf, wbase, u); break;
+                case 1: row_fft<1>(rbuf, wbase, u); break;
+                case 2: row_fft<2>(rbuf, wbase, u); break;
+                default: row_fft<3>(rbuf, wbase, u); break;
+            }
+        }
+        __syncthreads();   // every quarter has read its inputs: the row may be overwritten
+        if (row_lane) {
+            switch (rq) {
+                case 0: row_store<0>(rbuf, wbase, u); break;
+                case 1: row_store<1>(rbuf, wbase, u); break;
+                case 2: row_store<2>(rbuf, wbase, u); break;
+                default: row_store<3>(rbuf, wbase, u); break;
             }
         }
         __syncthreads();

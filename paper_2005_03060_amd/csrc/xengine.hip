@@ -137,37 +137,66 @@ __global__ __launch_bounds__(kXThreads, 2) void k_xant(XengLaunch L) {
 
     // Staging: every work-item loads its share of the next S rows into
     // registers (all loads in flight together), then writes them to LDS.
-    // Indices are clamped instead of predicated (a row past the chunk's end
-    // repeats the last one, a unit past the row's end repeats the last unit;
-    // neither is read), so the copy has no branches.  4-bit rows past the
-    // end are zeroed instead, since they are summed in groups of four, and
-    // stored transposed: LDS word (g, a) holds samples 4g .. 4g + 3 of
-    // antenna a.
+    // Complex64: work-item i copies unit i of every row.  Indices are clamped
+    // instead of predicated (a row past the chunk's end repeats the last
+    // one, a unit past the row's end repeats the last unit; neither is read),
+    // so the copy has no branches.  4-bit: the S rows are S/4 groups of four,
+    // and a staging unit is (group g, word column c), four words that are
+    // transposed and stored as one 16-byte LDS write: LDS word (g, a) holds
+    // samples 4g .. 4g + 3 of antenna a.  Wave w takes groups w, w + 4, ...
+    // (row addresses uniform over the wave) and lane l columns l and l + 64,
+    // so no word is loaded twice; rows past the chunk's end are zeroed, since
+    // they are summed in groups of four.
     const RT* vol = reinterpret_cast<const RT*>(L.volt);
     const size_t rowstride = (size_t)N / W;
-    RT r[S][KPT];
+    constexpr int GW = S / 4 / (NT / 64);          // 4-bit groups per wave
+    constexpr int RU = CI4 ? 2 * GW : S;           // register rows of staged data
+    constexpr int RK = CI4 ? 4 : KPT;
+    static_assert(!CI4 || (kXThreads + kXHaloMax + 6) / 4 <= 128, "two word columns per lane");
+    RT r[RU][RK];
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6), ln = tid & 63;
     auto load = [&](int t0) {
         const int last = min(S, te - t0) - 1;
         const RT* base = vol + (((size_t)unit * T + t0) * N + lo) / W;
+        if constexpr (CI4) {
 #pragma unroll
-        for (int q = 0; q < S; ++q) {
+            for (int gi = 0; gi < GW; ++gi) {
+                const int g4 = 4 * (wv + 4 * gi);
 #pragma unroll
-            for (int u = 0; u < KPT; ++u) {
-                r[q][u] = base[(size_t)min(q, last) * rowstride + min(tid + u * NT, upr - 1)];
-                if constexpr (CI4) r[q][u] = q <= last ? r[q][u] : 0u;
+                for (int m = 0; m < 2; ++m) {
+                    const int c = ln + 64 * m;
+                    if (c >= upr) continue;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const uint32_t w = base[(size_t)min(g4 + i, last) * rowstride + c];
+                        r[2 * gi + m][i] = g4 + i <= last ? w : 0u;
+                    }
+                }
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < S; ++q) {
+#pragma unroll
+                for (int u = 0; u < KPT; ++u)
+                    r[q][u] = base[(size_t)min(q, last) * rowstride + min(tid + u * NT, upr - 1)];
             }
         }
     };
     auto store = [&]() {
         if constexpr (CI4) {
             uint4* st = reinterpret_cast<uint4*>(xsm);
-            const int col = min(tid, upr - 1);
 #pragma unroll
-            for (int g = 0; g < S / 4; ++g) {
-                const uint32_t w[4] = {r[4 * g][0], r[4 * g + 1][0], r[4 * g + 2][0], r[4 * g + 3][0]};
-                uint32_t o[4];
-                transpose4x4(w, o);
-                st[g * upr + col] = make_uint4(o[0], o[1], o[2], o[3]);
+            for (int gi = 0; gi < GW; ++gi) {
+                const int g = wv + 4 * gi;
+#pragma unroll
+                for (int m = 0; m < 2; ++m) {
+                    const int c = ln + 64 * m;
+                    if (c >= upr) continue;
+                    const uint32_t w[4] = {r[2 * gi + m][0], r[2 * gi + m][1], r[2 * gi + m][2], r[2 * gi + m][3]};
+                    uint32_t o[4];
+                    transpose4x4(w, o);
+                    st[g * upr + c] = make_uint4(o[0], o[1], o[2], o[3]);
+                }
             }
         } else {
             RT* st = reinterpret_cast<RT*>(xsm);
