@@ -23,11 +23,14 @@
 // the signed 4-bit dot product (eight nibble products per instruction).  The
 // staging transposes 4 x 4 byte blocks so that one LDS word holds four
 // consecutive samples of one antenna.  With A the own word and B a
-// partner's, dot(A, B) sums ar br + ai bi (the real part), and moving the
-// own nibbles to the other half of each byte (A << 4 keeps ai against br,
-// A >> 4 keeps ar against bi, the other nibbles zeroed) gives the two terms
-// of the imaginary part ai br - ar bi: three instructions for four samples
-// of one pair, where the unpacked form takes four multiply-adds per sample.
+// partner's, dot(A, B) sums ar br + ai bi (the real part).  For the
+// imaginary part ai br - ar bi, -ar cannot be formed in 4 bits (-(-8)), but
+// -ar = ~ar + 1 and ~ar stays in [-8, 7]: with A' = (ai, ~ar) per byte,
+// dot(A', B) = sum ai br + ~ar bi, and adding the partner's own imaginary
+// sum (one dot product per antenna, not per pair, exchanged through LDS at
+// the end) gives the exact imaginary sum.  Two instructions for four
+// samples of one pair, where the unpacked form takes four multiply-adds
+// per sample.
 // (The int8 matrix-core form for 4-bit voltages is in xmfma.hip; this
 // kernel serves complex64 voltages, and 4-bit selections whose window
 // cover no matrix-core instantiation holds.)
@@ -44,6 +47,10 @@ constexpr int kXHaloMax = 248;   // largest raster offset d_t the staging covers
 // largest halo: a compile-time stride turns the sample offset of every LDS
 // read into an immediate, so the products need no address arithmetic
 constexpr int kXRowF = kXThreads + kXHaloMax + 2;
+// LDS stride of a staged group of four 4-bit samples (words, one per
+// antenna), fixed for the same reason: a group's offset is an immediate
+constexpr int kXRowW4 = 512;
+static_assert(kXRowW4 >= kXThreads + kXHaloMax + 6, "a 4-bit group row holds every staged antenna");
 
 // Transpose a 4 x 4 block of bytes: out[k] byte q = in[q] byte k.
 __device__ __forceinline__ void transpose4x4(const uint32_t (&w)[4], uint32_t (&o)[4]) {
@@ -125,12 +132,16 @@ __global__ __launch_bounds__(kXThreads, 2) void k_xant(XengLaunch L) {
     }
     const int own = live ? a - lo : 0;
 
-    // float: real and imaginary sums; 4-bit: the real sum and the two terms
-    // of the imaginary one (acci - accn)
+    // float: real and imaginary sums; 4-bit: the real sum and the imaginary
+    // one less the partner's own imaginary sum (added at the end)
     using AT = typename std::conditional<CI4, int, float>::type;
-    AT accr[KMAX], acci[KMAX], accn[KMAX];
+    AT accr[KMAX], acci[KMAX];
 #pragma unroll
-    for (int t = 0; t < KMAX; ++t) accr[t] = acci[t] = accn[t] = 0;
+    for (int t = 0; t < KMAX; ++t) accr[t] = acci[t] = 0;
+    // 4-bit: sum over the chunk of the imaginary part of antenna a (own) and
+    // of halo antenna lo + tid (tid < a0 - lo)
+    int sim_own = 0, sim_halo = 0;
+    const int hc = a0 - lo;
 
     const int tb = chunk * L.tchunk;
     const int te = min(T, tb + L.tchunk);
@@ -195,7 +206,7 @@ __global__ __launch_bounds__(kXThreads, 2) void k_xant(XengLaunch L) {
                     const uint32_t w[4] = {r[2 * gi + m][0], r[2 * gi + m][1], r[2 * gi + m][2], r[2 * gi + m][3]};
                     uint32_t o[4];
                     transpose4x4(w, o);
-                    st[g * upr + c] = make_uint4(o[0], o[1], o[2], o[3]);
+                    st[g * (kXRowW4 / 4) + c] = make_uint4(o[0], o[1], o[2], o[3]);
                 }
             }
         } else {
@@ -217,20 +228,32 @@ __global__ __launch_bounds__(kXThreads, 2) void k_xant(XengLaunch L) {
         // KMAX is the selection's K (or above it, the extra pairs being the
         // antenna with itself, never written): no branch per type
         if constexpr (CI4) {
-            const int ng = (ns + 3) >> 2;
-#pragma unroll 2
-            for (int g = 0; g < ng; ++g) {
-                const uint32_t* srow = reinterpret_cast<const uint32_t*>(xsm) + g * cnt;
+            // one group: own word and the K partners' words (all reads issued
+            // before the products), two dot products per pair
+            auto group = [&](const uint32_t* srow) {
+                uint32_t vb[KMAX];
                 const uint32_t va = srow[own];
-                const uint32_t vi = (va << 4) & 0xF0F0F0F0u;   // ai in the real slots
-                const uint32_t vr = (va >> 4) & 0x0F0F0F0Fu;   // ar in the imaginary slots
+                const uint32_t vh = srow[tid];
+#pragma unroll
+                for (int t = 0; t < KMAX; ++t) vb[t] = srow[poff[t]];
+                // (ai, ~ar) per byte: ~ar = -ar - 1 stays in [-8, 7]
+                const uint32_t vq = ((va << 4) & 0xF0F0F0F0u) | ((~va >> 4) & 0x0F0F0F0Fu);
+                sim_own = dot8(va, 0x01010101u, sim_own);
+                sim_halo = dot8(vh, 0x01010101u, sim_halo);
 #pragma unroll
                 for (int t = 0; t < KMAX; ++t) {
-                    const uint32_t vb = srow[poff[t]];
-                    accr[t] = dot8(va, vb, accr[t]);
-                    acci[t] = dot8(vi, vb, acci[t]);
-                    accn[t] = dot8(vr, vb, accn[t]);
+                    accr[t] = dot8(va, vb[t], accr[t]);
+                    acci[t] = dot8(vq, vb[t], acci[t]);
                 }
+            };
+            const uint32_t* sw = reinterpret_cast<const uint32_t*>(xsm);
+            if (ns == S) {
+                // full step: every group's offset is an immediate
+#pragma unroll
+                for (int g = 0; g < S / 4; ++g) group(sw + g * kXRowW4);
+            } else {
+                const int ng = (ns + 3) >> 2;
+                for (int g = 0; g < ng; ++g) group(sw + g * kXRowW4);
             }
         } else {
             auto products = [&](const float2* srow) {
@@ -259,12 +282,24 @@ __global__ __launch_bounds__(kXThreads, 2) void k_xant(XengLaunch L) {
         __syncthreads();
     }
 
+    if constexpr (CI4) {
+        // Im(q_i conj q_j) = ai bj_r - ar bj_i and -ar = ~ar + 1, so the
+        // imaginary sum is acci plus the partner's own imaginary sum.  The
+        // staging buffer is free after the loop's last barrier.
+        int* sim = reinterpret_cast<int*>(xsm);
+        if (live) sim[own] = sim_own;
+        if (tid < hc) sim[tid] = sim_halo;
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < KMAX; ++t) acci[t] += sim[poff[t]];
+    }
+
     if (L.nchunk == 1) {
 #pragma unroll
         for (int t = 0; t < KMAX; ++t) {
             if (t >= K || pidx[t] < 0) continue;
             const size_t o = (size_t)unit * s.P + pidx[t];
-            if constexpr (CI4) reinterpret_cast<int2*>(L.vred)[o] = make_int2(accr[t], acci[t] - accn[t]);
+            if constexpr (CI4) reinterpret_cast<int2*>(L.vred)[o] = make_int2(accr[t], acci[t]);
             else reinterpret_cast<float2*>(L.vred)[o] = make_float2(accr[t] * L.inv_t, acci[t] * L.inv_t);
         }
     } else {
@@ -272,16 +307,17 @@ __global__ __launch_bounds__(kXThreads, 2) void k_xant(XengLaunch L) {
 #pragma unroll
         for (int t = 0; t < KMAX; ++t) {
             if (t >= K || pidx[t] < 0) continue;
-            if constexpr (CI4) reinterpret_cast<int2*>(L.vpart)[base + pidx[t]] = make_int2(accr[t], acci[t] - accn[t]);
+            if constexpr (CI4) reinterpret_cast<int2*>(L.vpart)[base + pidx[t]] = make_int2(accr[t], acci[t]);
             else reinterpret_cast<float2*>(L.vpart)[base + pidx[t]] = make_float2(accr[t], acci[t]);
         }
     }
 }
 
-// LDS of one workgroup: S staged rows of (256 + halo) antennas, 4-bit rows
-// widened by up to 6 bytes to whole words (stored as S/4 rows of words).
+// LDS of one workgroup: complex64, S staged rows of kXRowF values; 4-bit,
+// S/4 group rows of kXRowW4 words (up to 256 + halo + 6 antennas, whole
+// words, four samples each).
 size_t xengine_lds_bytes(int halo, bool ci4) {
-    return ci4 ? (size_t)xeng_samples<true>() * (kXThreads + halo + 6)
+    return ci4 ? (size_t)xeng_samples<true>() / 4 * kXRowW4 * 4
                : (size_t)xeng_samples<false>() * kXRowF * 8;
 }
 
