@@ -404,29 +404,66 @@ __device__ __forceinline__ const float2& lds_at(const float2* lds, uint32_t byte
     return *reinterpret_cast<const float2*>(reinterpret_cast<const char*>(lds) + byte_off);
 }
 
-// Row stage, first half: input group R of one row, the eight pairs
-// (j, j + 32) with j in [8R, 8R + 8).  x = v / g for both inputs (zero for
-// j + 32 >= n through the table), then every quarter's folded, twiddled
-// input u_q(j) = w_128^{jq} [x_j + (-i)^q x_{j+32}] goes to the row's own
-// LDS row at column 32 q + j (swizzled).  Each input is loaded and divided
-// by its gain once; the quarter waves that transform the row read u_q back.
-// hcol = table + y; wbase = byte offset of the row | (y mod 32) << 3.
-template <int R, bool CI4, int W>
-__device__ __forceinline__ void row_fold(const void* __restrict__ volt, size_t rowbase, int n,
-                                         const float2* hcol, float2* rbuf, uint32_t wbase) {
-    // inputs 32 .. 63 may lie past the row (n >= 33 keeps 0 .. 31 inside):
-    // clamp their groups to the last one; the table zeroes them
+// Raw inputs of one row group (the eight pairs j, j + 32 with j in
+// [8R, 8R + 8)): 4-bit as the loaded words (or half-words), complex64 as
+// values.  Loaded one step ahead, so the loads are in flight during the
+// column stage.
+template <bool CI4, int W> struct RowRaw;
+template <int W> struct RowRaw<true, W> { uint32_t w[16 / W]; };
+template <int W> struct RowRaw<false, W> { float2 v[16]; };
+
+// Inputs 32 .. 63 may lie past the row (n >= 33 keeps 0 .. 31 inside):
+// their groups are clamped to the last one, and the table zeroes them.
+template <bool CI4, int W>
+__device__ __forceinline__ void row_load(const void* __restrict__ volt, size_t rowbase, int R, int n,
+                                         RowRaw<CI4, W>& raw) {
     const int nw = n - W;
-    float2 a[8], b[8];
 #pragma unroll
     for (int e = 0; e < 8; e += W) {
-        float2 ga[W], gb[W];
-        load_group<CI4, W>(volt, rowbase + 8 * R + e, ga);
-        load_group<CI4, W>(volt, rowbase + min(8 * R + 32 + e, nw), gb);
+        const size_t ia = rowbase + 8 * R + e, ib = rowbase + min(8 * R + 32 + e, nw);
+        if constexpr (CI4) {
+            const uint8_t* b = reinterpret_cast<const uint8_t*>(volt);
+            if constexpr (W == 4) {
+                raw.w[e / W] = *reinterpret_cast<const uint32_t*>(b + ia);
+                raw.w[8 / W + e / W] = *reinterpret_cast<const uint32_t*>(b + ib);
+            } else {
+                static_assert(W == 2, "4-bit groups of two or four");
+                raw.w[e / W] = *reinterpret_cast<const uint16_t*>(b + ia);
+                raw.w[8 / W + e / W] = *reinterpret_cast<const uint16_t*>(b + ib);
+            }
+        } else {
+            float2 ga[W], gb[W];
+            load_group<false, W>(volt, ia, ga);
+            load_group<false, W>(volt, ib, gb);
 #pragma unroll
-        for (int f = 0; f < W; ++f) {
-            a[e + f] = ga[f];
-            b[e + f] = gb[f];
+            for (int f = 0; f < W; ++f) {
+                raw.v[e + f] = ga[f];
+                raw.v[8 + e + f] = gb[f];
+            }
+        }
+    }
+}
+
+// Row stage, first half: group R of one row.  x = v / g for both inputs of
+// each pair, then every quarter's folded, twiddled input
+// u_q(j) = w_128^{jq} [x_j + (-i)^q x_{j+32}] goes to the row's own LDS row
+// at column 32 q + j (swizzled).  Each input is divided by its gain once;
+// the quarter waves that transform the row read u_q back.
+// hcol = table + y; wbase = byte offset of the row | (y mod 32) << 3.
+template <int R, bool CI4, int W>
+__device__ __forceinline__ void row_fold(const RowRaw<CI4, W>& raw, const float2* hcol, float2* rbuf,
+                                         uint32_t wbase) {
+    float2 a[8], b[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        if constexpr (CI4) {
+            const int wa = (int)((raw.w[e / W] >> (8 * (e % W))) & 0xFFu);
+            const int wb = (int)((raw.w[8 / W + e / W] >> (8 * (e % W))) & 0xFFu);
+            a[e] = make_float2((float)((wa << 24) >> 28), (float)((wa << 28) >> 28));
+            b[e] = make_float2((float)((wb << 24) >> 28), (float)((wb << 28) >> 28));
+        } else {
+            a[e] = raw.v[e];
+            b[e] = raw.v[8 + e];
         }
     }
     char* rb = reinterpret_cast<char*>(rbuf);
@@ -522,6 +559,12 @@ __global__ __launch_bounds__(kQThreads) void k_fftcorr_q(const void* __restrict_
     const int y = lane;
     __syncthreads();
 
+    // 4-bit inputs (four or eight registers) are loaded one step ahead;
+    // complex64 ones (32 registers) would spill, so they are loaded in step
+    constexpr bool PF = CI4;
+    RowRaw<CI4, W> raw;
+    auto rowbase_of = [&](int t) { return ((size_t)unit * T + t) * N + (size_t)y * n; };
+    if (PF && tb + rs < te && y < n) row_load<CI4, W>(volt, rowbase_of(tb + rs), rq, n, raw);
     for (int t0 = tb; t0 < te; t0 += S) {
         const int t = t0 + rs;
         const bool row_lane = t < te && y < n;
@@ -531,12 +574,12 @@ __global__ __launch_bounds__(kQThreads) void k_fftcorr_q(const void* __restrict_
         uint32_t wbase = (uint32_t)((rs * H + y) * M * 8) | (uint32_t)((y & 31) << 3);
         asm volatile("" : "+v"(wbase));
         if (row_lane) {
-            const size_t rowbase = ((size_t)unit * T + t) * N + (size_t)y * n;
+            if constexpr (!PF) row_load<CI4, W>(volt, rowbase_of(t), rq, n, raw);
             switch (rq) {
-                case 0: row_fold<0, CI4, W>(volt, rowbase, n, hinv + y, rbuf, wbase); break;
-                case 1: row_fold<1, CI4, W>(volt, rowbase, n, hinv + y, rbuf, wbase); break;
-                case 2: row_fold<2, CI4, W>(volt, rowbase, n, hinv + y, rbuf, wbase); break;
-                default: row_fold<3, CI4, W>(volt, rowbase, n, hinv + y, rbuf, wbase); break;
+                case 0: row_fold<0, CI4, W>(raw, hinv + y, rbuf, wbase); break;
+                case 1: row_fold<1, CI4, W>(raw, hinv + y, rbuf, wbase); break;
+                case 2: row_fold<2, CI4, W>(raw, hinv + y, rbuf, wbase); break;
+                default: row_fold<3, CI4, W>(raw, hinv + y, rbuf, wbase); break;
             }
         }
         __syncthreads();
@@ -559,6 +602,8 @@ __global__ __launch_bounds__(kQThreads) void k_fftcorr_q(const void* __restrict_
             }
         }
         __syncthreads();
+        // the next step's inputs, in flight during the column stage
+        if (PF && t + S < te && y < n) row_load<CI4, W>(volt, rowbase_of(t + S), rq, n, raw);
         const int ns = min(S, te - t0);
         for (int s = 0; s < ns; ++s) {
             uint32_t rbase = (uint32_t)(s * H * M * 8) | (uint32_t)(cu << 3);
