@@ -119,6 +119,8 @@ typedef struct {
     int32_t n_time;       /* T, samples per integration                  */
     int32_t dtype;        /* RRC_C64 or RRC_CI4                          */
     uint64_t workspace_bytes;
+    int32_t n_live;       /* antennas (N, or the mask's count)           */
+    int32_t masked;       /* plan made by rrc_plan_create_masked         */
 } rrc_plan_info;
 
 /* Default solver options (FIRSTCAL, REFANT, at most 12 main steps, tol32
@@ -168,6 +170,54 @@ int rrc_gain_variance(int32_t n, const int32_t* types_xy, int32_t k, double snr,
 int rrc_plan_create(rrc_plan** out, int32_t n, const int32_t* types_xy, int32_t k,
                     int32_t n_units, int32_t n_time, int32_t dtype,
                     const rrc_solver_opts* opts);
+/* ---- masked lattices: hexagonal arrays (Sec. 3, Fig. 2) ------------------
+ * An array whose antennas sit on a subset of an n x n lattice index grid:
+ * mask[y*n + x] != 0 marks an antenna.  Positions stay integer lattice
+ * coordinates, so redundant groups are again equal displacements d and the
+ * spatial FFT of the grid (zero where there is no antenna) still gives
+ * every lag; only the group sizes N_d change (the mask's autocorrelation).
+ * A hexagonal array is the lattice with basis (1, 0), (1/2, sqrt3/2): its
+ * axial coordinates (a, b), |a|, |b|, |a + b| < side, sit on the
+ * (2 side - 1)^2 grid at (x, y) = (a + side - 1, b + side - 1).
+ * Layouts follow the grid: voltages [U][T][n*n] and gains [U][n*n] (values
+ * where mask == 0 are never read), V^unique [U][2n(n-1)] with every grid
+ * lag (zero at a lag no pair realises), V_auto the mean over the N_live
+ * antennas.  V^reduced holds only pairs of two antennas: type-major in the
+ * given order, within a type by the raster index of the first antenna.
+ * The degeneracy criterion and RRC_DEGEN_REFANT use the first antenna in
+ * raster order and its +x and +y neighbours as references (for a full
+ * square grid (0,0), (1,0), (0,1)). */
+#define RRC_METRIC_SQUARE 0   /* |d|^2 = dx^2 + dy^2                        */
+#define RRC_METRIC_HEX    1   /* |d|^2 = dx^2 + dx dy + dy^2 (hex lattice)  */
+
+/* The hexagon of `side` antennas per edge on its (2 side - 1)^2 grid:
+ * writes n*n mask bytes (room for `cap`), n and the antenna count
+ * (3 side (side - 1) + 1).  Host only, pure. */
+int rrc_hex_mask(int32_t side, uint8_t* mask, int32_t cap, int32_t* n_out, int32_t* n_live_out);
+
+/* rrc_select_subset for a masked lattice: types realised by at least one
+ * pair, in ascending |d| under `metric` (ties: dy, then dx); group sizes
+ * counted over the mask.  Host only, pure. */
+int rrc_select_subset_masked(int32_t n, const uint8_t* mask, int32_t metric, double p, double log_base,
+                             int32_t* types_xy, int32_t cap, int32_t* k_out, int32_t* n_pairs_out);
+
+/* rrc_degeneracy_count over the mask's antennas and pairs.  Host only. */
+int rrc_degeneracy_count_masked(int32_t n, const uint8_t* mask, const int32_t* types_xy, int32_t k,
+                                int32_t* n_null_amp, int32_t* n_null_phase);
+
+/* A plan over a masked lattice.  The plan keeps a copy of the mask; every
+ * selected type must be realised by a pair, the selection must have the
+ * four degeneracies only (else RRC_EDEGEN), and the reference antennas must
+ * exist.  Supported calls: rrc_fftcorr, rrc_xengine (dot-product kernel),
+ * rrc_omnical (the solve of a masked plan) and the info/workspace queries;
+ * rrc_solve, rrc_run, rrc_run_static, rrc_chisq_* and rrc_plan_tune return
+ * RRC_ENOTIMPL.  Device calls first rebuild the plan's mask, pair and lag
+ * tables in d_work from the mask bits the plan passes by value (two small
+ * kernels), so the plan still owns no device memory.  Limits as for
+ * rrc_plan_create (4-bit plans: n*n a multiple of 4). */
+int rrc_plan_create_masked(rrc_plan** out, int32_t n, const uint8_t* mask, const int32_t* types_xy,
+                           int32_t k, int32_t n_units, int32_t n_time, int32_t dtype,
+                           const rrc_solver_opts* opts);
 void rrc_plan_destroy(rrc_plan* plan);
 int rrc_plan_get_info(const rrc_plan* plan, rrc_plan_info* info);
 int rrc_workspace_size(const rrc_plan* plan, size_t* bytes);
@@ -247,10 +297,13 @@ int rrc_solve(rrc_plan* plan, void* stream, const void* d_vred, const void* d_ga
  * d_gains [U][N], d_vmodel [U][K]: complex64 state in, result out;
  * d_niter [U]: iterations so far (set by a call with d_gains_in, else
  * increased); d_status [U]: RRC_UNIT_*; d_delta [U] (optional): the last
- * relative change; d_chisq [U] (finish only). */
+ * relative change; d_chisq [U] (finish only).
+ * d_work: the plan's workspace, required for a masked plan (its pair
+ * tables), may be NULL otherwise.  A masked plan's grid points without an
+ * antenna keep gain 0 and take no part. */
 int rrc_omnical(rrc_plan* plan, void* stream, const void* d_vred, const void* d_gains_in, int32_t max_iter,
                 float tol, int32_t finish, void* d_gains, void* d_vmodel, float* d_chisq, int32_t* d_niter,
-                int32_t* d_status, float* d_delta);
+                int32_t* d_status, float* d_delta, void* d_work);
 
 /* (a5) chi^2 only: d_chisq[u] = sum_b |V_b - g_i conj(g_j) V_alpha|^2 for
  * complex64 d_g [U][N], d_vm [U][K], d_vred [U][P] (complex64, any dtype

@@ -32,13 +32,17 @@ def redundant_average(vfull: np.ndarray, gains: np.ndarray, pos: np.ndarray,
     with the pairs of type alpha being those with r_i - r_j = d_alpha.
     This is what the FFT-correlator outputs when the voltages are divided
     by the gains before the spatial transform (Sec. 2, Fig. 1).
+    A lag that no pair of antennas realises (possible on a masked lattice,
+    e.g. a hexagonal array inside its bounding grid) has no visibility; it
+    is reported as zero.
     """
     g = np.asarray(gains, dtype=np.complex128)
     idx = PositionIndex(pos)
     out = np.zeros(len(types), dtype=np.complex128)
     for t, (dx, dy) in enumerate(types):
         i, j = idx.pairs_of(dx, dy)
-        out[t] = np.sum(vfull[i, j] / (g[i] * np.conj(g[j]))) / len(i)
+        if len(i):
+            out[t] = np.sum(vfull[i, j] / (g[i] * np.conj(g[j]))) / len(i)
     return out
 
 

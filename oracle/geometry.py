@@ -43,6 +43,22 @@ def hex_positions(side: int) -> np.ndarray:
     return np.array(pts, dtype=np.int64)
 
 
+def hex_grid(side: int):
+    """A hexagonal array laid on its bounding lattice grid.
+
+    In lattice coordinates the hexagon of `side` antennas per edge fits an
+    n x n index grid, n = 2 side - 1, with (x, y) = (a + side - 1,
+    b + side - 1).  Returns (n, mask, pos): mask [n*n] bool marks the
+    antennas (raster index y n + x), pos [N, 2] their (x, y) in raster
+    order, i.e. `hex_positions(side)` shifted onto the grid.
+    """
+    n = 2 * side - 1
+    pos = hex_positions(side) + (side - 1)
+    mask = np.zeros(n * n, dtype=bool)
+    mask[pos[:, 1] * n + pos[:, 0]] = True
+    return n, mask, pos
+
+
 def is_canonical(dx: int, dy: int) -> bool:
     return dy > 0 or (dy == 0 and dx > 0)
 

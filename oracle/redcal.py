@@ -309,21 +309,27 @@ def omnical(vred, pairs, tix, g0, v0, gain: float = 0.3, tol: float = 1e-10,
 
 
 def _ref_antennas(pos):
+    # Sec. 5.2 fixes the phase and the two phase slopes against reference
+    # antennas without naming them: the first antenna in raster order (least
+    # y, then least x) and its neighbours one step along x and along y.  On a
+    # square grid these are (0,0), (1,0), (0,1).
+    pos = np.asarray(pos, dtype=np.int64)
+    a0 = int(np.lexsort((pos[:, 0], pos[:, 1]))[0])
     idx = PositionIndex(pos)
-    lo = idx.lo
-    a0 = idx.lut[0, 0]
-    ax = idx.lut[1, 0]
-    ay = idx.lut[0, 1]
-    if min(a0, ax, ay) < 0:
-        raise ValueError("reference antennas (0,0), (1,0), (0,1) must exist")
-    return int(a0), int(ax), int(ay), pos - pos[a0]
+    r = pos[a0] - idx.lo
+    ax = idx.lut[r[0] + 1, r[1]] if r[0] + 1 < idx.lut.shape[0] else -1
+    ay = idx.lut[r[0], r[1] + 1] if r[1] + 1 < idx.lut.shape[1] else -1
+    if min(ax, ay) < 0:
+        raise ValueError("the first antenna's +x and +y neighbours must exist")
+    return a0, int(ax), int(ay), pos - pos[a0]
 
 
 def fix_refant(g, vm, pos, types):
     """Fix the four degeneracies against reference antennas.
 
     Amplitude: sum_i ln|g_i| = 0.  Phase and both phase slopes: the gains of
-    the antennas at (0,0), (1,0) and (0,1) become real and positive.  Because
+    the first antenna in raster order and of its +x and +y neighbours
+    ((0,0), (1,0) and (0,1) on a square grid) become real and positive.  Because
     positions are integers the slope transform is 2 pi periodic, so no phase
     unwrapping is involved.  V_alpha absorbs the compensating transform.
     """

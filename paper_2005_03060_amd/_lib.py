@@ -37,6 +37,8 @@ RRC_MAX_GRID = 64
 RRC_STATIC_SCRATCH_BYTES = 32 << 20
 RRC_LOWCAD_MAX_GRID = 32
 RRC_LOWCAD_MAX_CYCLES = 256
+RRC_METRIC_SQUARE = 0
+RRC_METRIC_HEX = 1
 
 EXPORTS = ("rrc_default_opts", "rrc_select_subset", "rrc_degeneracy_count", "rrc_plan_create",
            "rrc_plan_destroy", "rrc_plan_get_info", "rrc_workspace_size", "rrc_fftcorr",
@@ -44,7 +46,8 @@ EXPORTS = ("rrc_default_opts", "rrc_select_subset", "rrc_degeneracy_count", "rrc
            "rrc_batch_create", "rrc_batch_destroy", "rrc_batch_run", "rrc_plan_prepare",
            "rrc_plan_set_order", "rrc_wall_clock_hz", "rrc_run_static", "rrc_plan_set_xengine",
            "rrc_gain_variance", "rrc_omnical", "rrc_lowcad_schedule", "rrc_lowcad_xengine",
-           "rrc_lowcad_solve", "rrc_plan_tune")
+           "rrc_lowcad_solve", "rrc_plan_tune", "rrc_hex_mask", "rrc_select_subset_masked",
+           "rrc_degeneracy_count_masked", "rrc_plan_create_masked")
 
 
 class SolverOpts(C.Structure):
@@ -57,7 +60,8 @@ class PlanInfo(C.Structure):
     _fields_ = [("n", C.c_int32), ("n_ant", C.c_int32), ("fft_size", C.c_int32),
                 ("n_lags", C.c_int32), ("n_types", C.c_int32), ("n_pairs", C.c_int32),
                 ("dof", C.c_int32), ("n_units", C.c_int32), ("n_time", C.c_int32),
-                ("dtype", C.c_int32), ("workspace_bytes", C.c_uint64)]
+                ("dtype", C.c_int32), ("workspace_bytes", C.c_uint64), ("n_live", C.c_int32),
+                ("masked", C.c_int32)]
 
 
 class RunIO(C.Structure):
@@ -117,7 +121,12 @@ def load_library() -> C.CDLL:
         "rrc_run_static": (C.c_int, [vp, vp, i32, C.POINTER(RunIO)]),
         "rrc_plan_set_xengine": (C.c_int, [vp, i32]),
         "rrc_gain_variance": (C.c_int, [i32, pi32, i32, C.c_double, C.POINTER(C.c_double)]),
-        "rrc_omnical": (C.c_int, [vp, vp, vp, vp, i32, C.c_float, i32, vp, vp, pf, vp, vp, pf]),
+        "rrc_omnical": (C.c_int, [vp, vp, vp, vp, i32, C.c_float, i32, vp, vp, pf, vp, vp, pf, vp]),
+        "rrc_hex_mask": (C.c_int, [i32, vp, i32, pi32, pi32]),
+        "rrc_select_subset_masked": (C.c_int, [i32, vp, i32, C.c_double, C.c_double, pi32, i32, pi32, pi32]),
+        "rrc_degeneracy_count_masked": (C.c_int, [i32, vp, pi32, i32, pi32, pi32]),
+        "rrc_plan_create_masked": (C.c_int, [C.POINTER(vp), i32, vp, pi32, i32, i32, i32, i32,
+                                             C.POINTER(SolverOpts)]),
         "rrc_lowcad_schedule": (C.c_int, [i32, C.c_double, C.c_double, pi32, i32, pi32]),
         "rrc_plan_tune": (C.c_int, [vp, vp, C.POINTER(RunIO), C.c_char_p, C.POINTER(Tune)]),
         "rrc_lowcad_xengine": (C.c_int, [i32, i32, i32, pi32, i32, vp, vp, vp]),

@@ -46,6 +46,48 @@ def degeneracy_count(n: int, types: Sequence[Tuple[int, int]]):
     return na.value, nph.value
 
 
+def hex_mask(side: int):
+    """The hexagon of `side` antennas per edge on its (2 side - 1)^2 lattice
+    grid (host only): returns (n, mask uint8 [n*n] numpy array)."""
+    import numpy as np
+    lib = L.load_library()
+    n_max = 2 * side - 1
+    mask = np.zeros(max(1, n_max * n_max), dtype=np.uint8)
+    n, live = C.c_int32(), C.c_int32()
+    L.check(lib.rrc_hex_mask(int(side), mask.ctypes.data, mask.size, C.byref(n), C.byref(live)), "rrc_hex_mask")
+    return n.value, mask[: n.value * n.value]
+
+
+def _mask_arg(n: int, mask):
+    import numpy as np
+    m = np.ascontiguousarray(np.asarray(mask, dtype=np.uint8).reshape(-1))
+    if m.size != n * n:
+        raise ValueError(f"mask must hold n*n = {n * n} entries")
+    return m
+
+
+def select_subset_masked(n: int, mask, metric: str = "hex", p: float = 1.0, log_base: float = 0.0):
+    """Subset selection on a masked lattice (host only): (types, n_pairs)."""
+    lib = L.load_library()
+    m = _mask_arg(n, mask)
+    buf = (C.c_int32 * (2 * L.RRC_MAX_TYPES))()
+    k, npairs = C.c_int32(), C.c_int32()
+    met = {"square": L.RRC_METRIC_SQUARE, "hex": L.RRC_METRIC_HEX}[metric]
+    L.check(lib.rrc_select_subset_masked(n, m.ctypes.data, met, p, log_base, buf, L.RRC_MAX_TYPES, C.byref(k),
+                                         C.byref(npairs)), "rrc_select_subset_masked")
+    return [(buf[2 * t], buf[2 * t + 1]) for t in range(k.value)], npairs.value
+
+
+def degeneracy_count_masked(n: int, mask, types: Sequence[Tuple[int, int]]):
+    """(amplitude, phase) null-space dimensions on a masked lattice (host only)."""
+    lib = L.load_library()
+    m = _mask_arg(n, mask)
+    na, nph = C.c_int32(), C.c_int32()
+    L.check(lib.rrc_degeneracy_count_masked(n, m.ctypes.data, _types_array(types), len(types), C.byref(na),
+                                            C.byref(nph)), "rrc_degeneracy_count_masked")
+    return na.value, nph.value
+
+
 def gain_variance(n: int, types: Sequence[Tuple[int, int]], snr: float):
     """Predicted per-antenna E|g_est/g_true - 1|^2 of a selection (host only)."""
     import numpy as np
@@ -117,10 +159,12 @@ def default_opts() -> Dict[str, float]:
 
 
 class Plan:
-    """A plan for U units (channels) of an n x n grid with T samples each."""
+    """A plan for U units (channels) of an n x n grid with T samples each;
+    with `mask` (n*n bytes), of the antennas of a masked lattice such as a
+    hexagonal array on its grid (rrc_plan_create_masked)."""
 
     def __init__(self, n: int, types: Sequence[Tuple[int, int]], n_units: int, n_time: int,
-                 dtype: str = "c64", **opts):
+                 dtype: str = "c64", mask=None, **opts):
         self._lib = L.load_library()
         self.n = n
         self.types = [tuple(int(v) for v in t) for t in types]
@@ -135,8 +179,14 @@ class Plan:
             setattr(o, key, val)
         self.opts = o
         h = C.c_void_p()
-        L.check(self._lib.rrc_plan_create(C.byref(h), n, _types_array(self.types), len(self.types),
-                                          n_units, n_time, self.dtype, C.byref(o)), "rrc_plan_create")
+        if mask is None:
+            L.check(self._lib.rrc_plan_create(C.byref(h), n, _types_array(self.types), len(self.types),
+                                              n_units, n_time, self.dtype, C.byref(o)), "rrc_plan_create")
+        else:
+            m = _mask_arg(n, mask)
+            L.check(self._lib.rrc_plan_create_masked(C.byref(h), n, m.ctypes.data, _types_array(self.types),
+                                                     len(self.types), n_units, n_time, self.dtype, C.byref(o)),
+                    "rrc_plan_create_masked")
         self._h = h
         info = L.PlanInfo()
         L.check(self._lib.rrc_plan_get_info(h, C.byref(info)), "rrc_plan_get_info")
@@ -242,7 +292,7 @@ class Plan:
         L.check(self._lib.rrc_omnical(self._h, _stream(), _ptr(vred), _ptr(gains_in), int(max_iter), float(tol),
                                       1 if finish else 0, _ptr(state["gains"]), _ptr(state["vmodel"]),
                                       _ptr(state["chisq"]), _ptr(state["niter"]), _ptr(state["status"]),
-                                      _ptr(state["delta"])), "rrc_omnical")
+                                      _ptr(state["delta"]), _ptr(self.workspace(dev))), "rrc_omnical")
         return state
 
     def chisq_fwd(self, g, vm, vred) -> torch.Tensor:

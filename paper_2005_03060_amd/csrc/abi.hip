@@ -55,6 +55,13 @@ struct rrc_plan {
     // units launched concurrently with this plan's (a batch sets the sum of
     // its plans'); the solve claims whole CUs only when they all fit
     long concurrent_units = 0;
+    // masked lattice (rrc_plan_create_masked): the mask as bits, the antenna
+    // count, the first antenna in raster order, and the workspace offsets of
+    // the tables rebuilt from the mask by each device call
+    bool masked = false;
+    uint32_t mask_bits[rrc::kMaskWords] = {0};
+    int n_live = 0, ref0 = 0;
+    size_t off_live = 0, off_pidx = 0, off_pfirst = 0, off_nd = 0;
 };
 
 struct rrc_batch {
@@ -74,19 +81,43 @@ struct Type {
     int dx, dy;
 };
 
+// |d|^2 of a lattice displacement: square basis, or the hexagonal lattice's
+// (1, 0), (1/2, sqrt3/2) basis (|d|^2 = dx^2 + dx dy + dy^2)
+int metric_len2(int dx, int dy, int metric) {
+    return metric == RRC_METRIC_HEX ? dx * dx + dx * dy + dy * dy : dx * dx + dy * dy;
+}
+
 // Canonical types of an n x n grid sorted by (|d|^2, dy, dx).
-std::vector<Type> sorted_types(int n) {
+std::vector<Type> sorted_types(int n, int metric = RRC_METRIC_SQUARE) {
     std::vector<Type> t;
     for (int dy = 0; dy < n; ++dy)
         for (int dx = -(n - 1); dx < n; ++dx)
             if (dy > 0 || dx > 0) t.push_back({dx, dy});
-    std::sort(t.begin(), t.end(), [](const Type& a, const Type& b) {
-        const int la = a.dx * a.dx + a.dy * a.dy, lb = b.dx * b.dx + b.dy * b.dy;
+    std::sort(t.begin(), t.end(), [metric](const Type& a, const Type& b) {
+        const int la = metric_len2(a.dx, a.dy, metric), lb = metric_len2(b.dx, b.dy, metric);
         if (la != lb) return la < lb;
         if (a.dy != b.dy) return a.dy < b.dy;
         return a.dx < b.dx;
     });
     return t;
+}
+
+bool bit_of(const uint32_t* bits, int a) { return bits == nullptr || ((bits[a >> 5] >> (a & 31)) & 1u); }
+
+// Pairs of type (dx, dy) whose antennas both exist (bits == nullptr: all).
+long group_size_masked(int n, const uint32_t* bits, int dx, int dy) {
+    if (!bits) return (long)(n - std::abs(dx)) * (n - std::abs(dy));
+    long c = 0;
+    for (int y = std::max(0, dy); y < n; ++y)
+        for (int x = std::max(0, dx); x < n + std::min(0, dx); ++x)
+            c += bit_of(bits, y * n + x) && bit_of(bits, (y - dy) * n + (x - dx));
+    return c;
+}
+
+void pack_mask(int n, const uint8_t* mask, uint32_t* bits) {
+    std::memset(bits, 0, sizeof(uint32_t) * rrc::kMaskWords);
+    for (int a = 0; a < n * n; ++a)
+        if (mask[a]) bits[a >> 5] |= 1u << (a & 31);
 }
 
 int group_size(int n, int dx, int dy) { return (n - std::abs(dx)) * (n - std::abs(dy)); }
@@ -103,7 +134,7 @@ bool valid_type(int n, int dx, int dy) {
 // L D L^T without pivoting; a positive semi-definite matrix meets a zero
 // pivot exactly on each null direction, counted against a relative
 // tolerance.
-int normal_nullity(int n, const std::vector<Type>& sel, int sign) {
+int normal_nullity(int n, const std::vector<Type>& sel, int sign, const uint32_t* bits = nullptr) {
     const int N = n * n, K = (int)sel.size(), V = N + K;
     int bw = 0;
     for (const Type& t : sel) bw = std::max(bw, t.dy * n + std::abs(t.dx));
@@ -122,6 +153,7 @@ int normal_nullity(int n, const std::vector<Type>& sel, int sign) {
                 const int jx = x - dx, jy = y - dy;
                 if (jx < 0 || jx >= n || jy < 0 || jy >= n) continue;
                 const int i = y * n + x, j = jy * n + jx;
+                if (!bit_of(bits, i) || !bit_of(bits, j)) continue;
                 const int idx[3] = {i, j, N + t};
                 const double cf[3] = {1.0, (double)sign, 1.0};
                 for (int p = 0; p < 3; ++p)
@@ -134,6 +166,10 @@ int normal_nullity(int n, const std::vector<Type>& sel, int sign) {
     }
     // the loop above adds the off-diagonal once per unordered (p, q); the
     // diagonal terms (p == q) once as well -- which is A^T A exactly.
+    // A grid point with no antenna is not an unknown: its (empty) row gets a
+    // unit diagonal, so it adds no null direction.
+    for (int a = 0; a < N; ++a)
+        if (!bit_of(bits, a)) at(a, a) = 1.0;
     std::vector<double> D(V, 0.0), diag0(V);
     for (int r = 0; r < V; ++r) diag0[r] = at(r, r);
     int null = 0;
@@ -157,7 +193,7 @@ int normal_nullity(int n, const std::vector<Type>& sel, int sign) {
     return null;
 }
 
-int build_sel(int n, const int32_t* types_xy, int k, Sel& s) {
+int build_sel(int n, const int32_t* types_xy, int k, Sel& s, const uint32_t* bits = nullptr) {
     if (n < 2 || n > RRC_MAX_GRID || k < 1 || k > RRC_MAX_TYPES || !types_xy) return RRC_EINVAL;
     std::memset(&s, 0, sizeof(s));
     s.n = n;
@@ -172,7 +208,9 @@ int build_sel(int n, const int32_t* types_xy, int k, Sel& s) {
         s.dx[t] = dx;
         s.dy[t] = dy;
         s.off[t] = off;
-        off += group_size(n, dx, dy);
+        const long m = group_size_masked(n, bits, dx, dy);
+        if (m == 0) return RRC_EINVAL;    // a type no pair realises
+        off += (int)m;
     }
     s.off[k] = off;
     s.P = off;
@@ -324,12 +362,31 @@ int rrc_select_subset(int32_t n, double p, double log_base, int32_t* types_xy, i
     return RRC_OK;
 }
 
-int rrc_plan_create(rrc_plan** out, int32_t n, const int32_t* types_xy, int32_t k,
-                    int32_t n_units, int32_t n_time, int32_t dtype, const rrc_solver_opts* opts) {
+static int plan_create(rrc_plan** out, int32_t n, const int32_t* types_xy, int32_t k, int32_t n_units,
+                       int32_t n_time, int32_t dtype, const rrc_solver_opts* opts, const uint8_t* mask) {
     if (!out) return RRC_EINVAL;
     *out = nullptr;
+    uint32_t bits_store[rrc::kMaskWords];
+    const uint32_t* bits = nullptr;
+    int n_live = n * n, ref0 = 0;
+    if (mask) {
+        if (n < 2 || n > RRC_MAX_GRID) return RRC_EINVAL;
+        pack_mask(n, mask, bits_store);
+        bits = bits_store;
+        n_live = 0;
+        ref0 = -1;
+        for (int a = 0; a < n * n; ++a)
+            if (mask[a]) {
+                ++n_live;
+                if (ref0 < 0) ref0 = a;
+            }
+        // the references of the degeneracy fix: the first antenna and its
+        // +x and +y neighbours
+        if (ref0 < 0 || ref0 % n + 1 >= n || ref0 / n + 1 >= n || !mask[ref0 + 1] || !mask[ref0 + n])
+            return RRC_EINVAL;
+    }
     Sel s;
-    int rc = build_sel(n, types_xy, k, s);
+    int rc = build_sel(n, types_xy, k, s, bits);
     if (rc != RRC_OK) return rc;
     if (n_units < 1 || n_time < 1 || (dtype != RRC_C64 && dtype != RRC_CI4)) return RRC_EINVAL;
     if (dtype == RRC_CI4 && (long)n_time * 98L > 2147483647L) return RRC_ERANGE;
@@ -345,15 +402,22 @@ int rrc_plan_create(rrc_plan** out, int32_t n, const int32_t* types_xy, int32_t 
         has10 |= (s.dx[t] == 1 && s.dy[t] == 0);
         has01 |= (s.dx[t] == 0 && s.dy[t] == 1);
     }
-    if (o.init_mode == RRC_INIT_FIRSTCAL && !(has10 && has01)) return RRC_EINVAL;
-    int32_t na = 0, np = 0;
-    rc = rrc_degeneracy_count(n, types_xy, k, &na, &np);
-    if (rc != RRC_OK) return rc;
-    if (na + np != 4) return RRC_EDEGEN;
+    if (!mask && o.init_mode == RRC_INIT_FIRSTCAL && !(has10 && has01)) return RRC_EINVAL;
+    {
+        std::vector<Type> sv(k);
+        for (int t = 0; t < k; ++t) sv[t] = {s.dx[t], s.dy[t]};
+        if (normal_nullity(n, sv, +1, bits) + normal_nullity(n, sv, -1, bits) != 4) return RRC_EDEGEN;
+    }
 
     rrc_plan* p = new (std::nothrow) rrc_plan();
     if (!p) return RRC_ERANGE;
     p->sel = s;
+    if (mask) {
+        p->masked = true;
+        std::memcpy(p->mask_bits, bits_store, sizeof(bits_store));
+    }
+    p->n_live = n_live;
+    p->ref0 = ref0;
     int M = 16;                      // smallest transform the kernels instantiate
     while (M < 2 * n) M *= 2;
     p->M = M;
@@ -394,7 +458,7 @@ int rrc_plan_create(rrc_plan** out, int32_t n, const int32_t* types_xy, int32_t 
         const int xt = ceil_div(ceil_div(n_time, xn), p->x_S) * p->x_S;
         p->x_tchunk = xt;
         p->x_nchunk = ceil_div(n_time, xt);
-        if (dtype == RRC_CI4) {
+        if (dtype == RRC_CI4 && !mask) {
             p->x_mf.sel = s;
             p->x_mf_ok = rrc::xmfma_plan(s, p->x_mf) && xt % 32 == 0 && xt <= (1 << 17);
         }
@@ -414,8 +478,116 @@ int rrc_plan_create(rrc_plan** out, int32_t n, const int32_t* types_xy, int32_t 
     off = align256(off + (p->x_nchunk > 1 ? (size_t)n_units * p->x_nchunk * s.P * 8 : 0));
     p->off_gcopy = off;                      // copy of gains_in when it aliases gains_out
     off = align256(off + (size_t)n_units * s.N * 8);
+    if (mask) {                              // the masked lattice's tables
+        p->off_live = off;
+        off = align256(off + (size_t)s.N);
+        p->off_pidx = off;
+        off = align256(off + (size_t)s.K * s.N * 4);
+        p->off_pfirst = off;
+        off = align256(off + (size_t)s.P * 4);
+        p->off_nd = off;
+        off = align256(off + (size_t)p->nlag * 4);
+    }
     p->ws_bytes = off;
     *out = p;
+    return RRC_OK;
+}
+
+int rrc_plan_create(rrc_plan** out, int32_t n, const int32_t* types_xy, int32_t k, int32_t n_units,
+                    int32_t n_time, int32_t dtype, const rrc_solver_opts* opts) {
+    return plan_create(out, n, types_xy, k, n_units, n_time, dtype, opts, nullptr);
+}
+
+int rrc_plan_create_masked(rrc_plan** out, int32_t n, const uint8_t* mask, const int32_t* types_xy, int32_t k,
+                           int32_t n_units, int32_t n_time, int32_t dtype, const rrc_solver_opts* opts) {
+    if (!mask) return RRC_EINVAL;
+    return plan_create(out, n, types_xy, k, n_units, n_time, dtype, opts, mask);
+}
+
+int rrc_hex_mask(int32_t side, uint8_t* mask, int32_t cap, int32_t* n_out, int32_t* n_live_out) {
+    if (side < 2 || !mask || !n_out || !n_live_out) return RRC_EINVAL;
+    const int n = 2 * side - 1, r = side - 1;
+    if (n > RRC_MAX_GRID) return RRC_ERANGE;
+    if (cap < n * n) return RRC_ERANGE;
+    int live = 0;
+    for (int y = 0; y < n; ++y)
+        for (int x = 0; x < n; ++x) {
+            const int a = x - r, b = y - r;      // axial coordinates
+            const bool on = std::abs(a + b) <= r;
+            mask[y * n + x] = on ? 1 : 0;
+            live += on;
+        }
+    *n_out = n;
+    *n_live_out = live;
+    return RRC_OK;
+}
+
+int rrc_degeneracy_count_masked(int32_t n, const uint8_t* mask, const int32_t* types_xy, int32_t k,
+                                int32_t* n_null_amp, int32_t* n_null_phase) {
+    if (!mask || !n_null_amp || !n_null_phase || n < 2 || n > RRC_MAX_GRID) return RRC_EINVAL;
+    uint32_t bits[rrc::kMaskWords];
+    pack_mask(n, mask, bits);
+    Sel s;
+    const int rc = build_sel(n, types_xy, k, s, bits);
+    if (rc != RRC_OK) return rc;
+    std::vector<Type> sel(k);
+    for (int t = 0; t < k; ++t) sel[t] = {s.dx[t], s.dy[t]};
+    *n_null_amp = normal_nullity(n, sel, +1, bits);
+    *n_null_phase = normal_nullity(n, sel, -1, bits);
+    return RRC_OK;
+}
+
+int rrc_select_subset_masked(int32_t n, const uint8_t* mask, int32_t metric, double p, double log_base,
+                             int32_t* types_xy, int32_t cap, int32_t* k_out, int32_t* n_pairs_out) {
+    if (n < 2 || n > RRC_MAX_GRID || !mask || !(p > 0.0) || !types_xy || !k_out || !n_pairs_out ||
+        (metric != RRC_METRIC_SQUARE && metric != RRC_METRIC_HEX))
+        return RRC_EINVAL;
+    uint32_t bits[rrc::kMaskWords];
+    pack_mask(n, mask, bits);
+    int live = 0;
+    for (int a = 0; a < n * n; ++a) live += mask[a] != 0;
+    if (live < 2) return RRC_EINVAL;
+    // types some pair realises, in ascending length under the metric
+    std::vector<Type> all;
+    std::vector<long> size;
+    for (const Type& t : sorted_types(n, metric)) {
+        const long m = group_size_masked(n, bits, t.dx, t.dy);
+        if (m > 0) {
+            all.push_back(t);
+            size.push_back(m);
+        }
+    }
+    const double N = (double)live;
+    const double lg = (log_base > 1.0) ? std::log(N) / std::log(log_base) : std::log(N);
+    const double budget = p * N * lg;
+    long cum = 0;
+    int best = 1;
+    double best_d = 1e300;
+    for (size_t t = 0; t < all.size(); ++t) {
+        cum += size[t];
+        const double d = std::fabs((double)cum - budget);
+        if (d < best_d) {
+            best_d = d;
+            best = (int)t + 1;
+        }
+    }
+    int k = best;
+    while (true) {
+        if (k > RRC_MAX_TYPES) return RRC_ERANGE;
+        std::vector<Type> sel(all.begin(), all.begin() + k);
+        if (normal_nullity(n, sel, +1, bits) + normal_nullity(n, sel, -1, bits) == 4) break;
+        if (k >= (int)all.size()) return RRC_EDEGEN;
+        ++k;
+    }
+    if (k > cap) return RRC_ERANGE;
+    long pairs = 0;
+    for (int t = 0; t < k; ++t) {
+        types_xy[2 * t] = all[t].dx;
+        types_xy[2 * t + 1] = all[t].dy;
+        pairs += size[t];
+    }
+    *k_out = k;
+    *n_pairs_out = (int32_t)pairs;
     return RRC_OK;
 }
 
@@ -494,12 +666,38 @@ int rrc_plan_get_info(const rrc_plan* p, rrc_plan_info* info) {
     info->n_time = p->T;
     info->dtype = p->dtype;
     info->workspace_bytes = p->ws_bytes;
+    info->n_live = p->n_live;
+    info->masked = p->masked ? 1 : 0;
+    if (p->masked) info->dof = p->sel.P - p->n_live - p->sel.K + 2;
     return RRC_OK;
 }
 
 int rrc_workspace_size(const rrc_plan* p, size_t* bytes) {
     if (!p || !bytes) return RRC_EINVAL;
     *bytes = p->ws_bytes;
+    return RRC_OK;
+}
+
+// A masked plan's tables, rebuilt in the workspace from the mask bits;
+// returns the pointers the kernels read (all null for a full grid).
+static int mask_tables(const rrc_plan* p, void* stream, void* d_work, rrc::MaskTables& mt) {
+    mt = rrc::MaskTables{};
+    mt.n_live = p->n_live;
+    mt.ref0 = p->ref0;
+    if (!p->masked) return RRC_OK;
+    char* w = static_cast<char*>(d_work);
+    rrc::MaskLaunch L;
+    L.sel = p->sel;
+    std::memcpy(L.bits, p->mask_bits, sizeof(L.bits));
+    L.live = reinterpret_cast<uint8_t*>(w + p->off_live);
+    L.pidx = reinterpret_cast<int*>(w + p->off_pidx);
+    L.pfirst = reinterpret_cast<int*>(w + p->off_pfirst);
+    L.nd = reinterpret_cast<float*>(w + p->off_nd);
+    if (rrc::launch_mask_tables(L, as_stream(stream)) != hipSuccess) return RRC_EDEVICE;
+    mt.live = L.live;
+    mt.pidx = L.pidx;
+    mt.pfirst = L.pfirst;
+    mt.nd = L.nd;
     return RRC_OK;
 }
 
@@ -520,6 +718,8 @@ static int fftcorr_impl(rrc_plan* p, void* stream, const void* d_volt, const voi
     L.ppart = reinterpret_cast<float*>(static_cast<char*>(d_work) + p->off_fft);
     L.vunique = reinterpret_cast<float2*>(d_vunique);
     L.vauto = d_vauto;
+    const int rc = mask_tables(p, stream, d_work, L.mt);
+    if (rc != RRC_OK) return rc;
     return rrc::launch_fftcorr(L, as_stream(stream)) == hipSuccess ? RRC_OK : RRC_EDEVICE;
 }
 
@@ -557,6 +757,8 @@ int rrc_xengine(rrc_plan* p, void* stream, const void* d_volt, void* d_vred, voi
         L.mf_lo = p->x_mf.mf_lo;
         L.mf_cnt = p->x_mf.mf_cnt;
     }
+    const int rc = mask_tables(p, stream, d_work, L.mt);
+    if (rc != RRC_OK) return rc;
     return rrc::launch_xengine(L, as_stream(stream)) == hipSuccess ? RRC_OK : RRC_EDEVICE;
 }
 
@@ -577,6 +779,7 @@ static int solve_impl(rrc_plan* p, void* stream, const void* d_vred, const void*
                       int32_t* d_niter, int32_t* d_status, uint64_t* d_stamps) {
     if (!p || !d_vred || !d_gains_out || !d_vmodel || !d_chisq || !d_niter || !d_status)
         return RRC_EINVAL;
+    if (p->masked) return RRC_ENOTIMPL;   // a masked plan solves with rrc_omnical
     if (p->opts.init_mode == RRC_INIT_GAINS && !d_gains_in) return RRC_EINVAL;
     if (p->opts.degen_mode == RRC_DEGEN_MATCH && !d_gains_ref) return RRC_EINVAL;
     const int rc = prepare(p);
@@ -605,10 +808,11 @@ int rrc_solve(rrc_plan* p, void* stream, const void* d_vred, const void* d_gains
 
 int rrc_omnical(rrc_plan* p, void* stream, const void* d_vred, const void* d_gains_in, int32_t max_iter,
                 float tol, int32_t finish, void* d_gains, void* d_vmodel, float* d_chisq, int32_t* d_niter,
-                int32_t* d_status, float* d_delta) {
+                int32_t* d_status, float* d_delta, void* d_work) {
     if (!p || !d_vred || !d_gains || !d_vmodel || !d_niter || !d_status || max_iter < 0 || !(tol >= 0.f))
         return RRC_EINVAL;
     if (finish && !d_chisq) return RRC_EINVAL;
+    if (p->masked && !d_work) return RRC_EINVAL;
     rrc::OmniLaunch L{};
     L.n = p->sel.n;
     L.K = p->sel.K;
@@ -630,6 +834,8 @@ int rrc_omnical(rrc_plan* p, void* stream, const void* d_vred, const void* d_gai
     L.niter = d_niter;
     L.status = d_status;
     L.delta = d_delta;
+    const int rc = mask_tables(p, stream, d_work, L.mt);
+    if (rc != RRC_OK) return rc;
     return rrc::launch_omnical(L, as_stream(stream)) == hipSuccess ? RRC_OK : RRC_EDEVICE;
 }
 
@@ -638,6 +844,7 @@ static int chisq_common(rrc_plan* p, void* stream, const void* d_g, const void* 
                         float* d_diag_g, float* d_diag_v, bool adj) {
     if (!p || !d_g || !d_vm || !d_vred) return RRC_EINVAL;
     if (!adj && !d_chisq) return RRC_EINVAL;
+    if (p->masked) return RRC_ENOTIMPL;
     rrc::ChisqLaunch L;
     L.sel = p->sel;
     L.n_units = p->U;
@@ -666,6 +873,7 @@ int rrc_chisq_adj(rrc_plan* p, void* stream, const void* d_g, const void* d_vm, 
 
 int rrc_run(rrc_plan* p, void* stream, int32_t mode, const rrc_io* io) {
     if (!p || !io) return RRC_EINVAL;
+    if (p->masked) return RRC_ENOTIMPL;
     if (mode != RRC_RUN_PIPELINED && mode != RRC_RUN_SELFCAL) return RRC_EINVAL;
     if (mode == RRC_RUN_PIPELINED && !io->d_gains_in) return RRC_EINVAL;
     if (!io->d_volt || !io->d_vunique || !io->d_vauto || !io->d_vred || !io->d_gains_out ||
@@ -745,6 +953,7 @@ int rrc_run(rrc_plan* p, void* stream, int32_t mode, const rrc_io* io) {
 
 int rrc_run_static(rrc_plan* p, void* stream, int32_t mode, const rrc_io* io) {
     if (!p || !io) return RRC_EINVAL;
+    if (p->masked) return RRC_ENOTIMPL;
     if (io->d_work) return RRC_EINVAL;            // the scratch replaces the workspace
     if (p->ws_bytes > (size_t)RRC_STATIC_SCRATCH_BYTES) return RRC_ERANGE;
     // set-up (streams, events, the scratch address) belongs to
@@ -781,6 +990,7 @@ static std::string tune_key(const rrc_plan* p) {
 
 int rrc_plan_tune(rrc_plan* p, void* stream, const rrc_io* io, const char* cache_path, rrc_tune* out) {
     if (!p || !io || !out || !io->d_gains_in) return RRC_EINVAL;
+    if (p->masked) return RRC_ENOTIMPL;
     int rc = prepare(p);
     if (rc != RRC_OK) return rc;
     const std::string key = tune_key(p);
@@ -874,6 +1084,7 @@ int rrc_batch_create(rrc_batch** out, int32_t n_plans, rrc_plan* const* plans, u
     if (flags & RRC_BATCH_GRAPH) return RRC_ENOTIMPL;
     for (int i = 0; i < n_plans; ++i) {
         if (!plans[i]) return RRC_EINVAL;
+        if (plans[i]->masked) return RRC_ENOTIMPL;   // batches run rrc_run
         for (int j = 0; j < i; ++j)
             if (plans[j] == plans[i]) return RRC_EINVAL;   // each plan owns its streams and events
     }

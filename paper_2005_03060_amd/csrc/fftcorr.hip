@@ -60,6 +60,15 @@ __device__ __forceinline__ int lag_index(int n, int dx, int dy) {
     return dy == 0 ? dx - 1 : (n - 1) + (dy - 1) * (2 * n - 1) + (dx + n - 1);
 }
 
+// V(d) = C(d) / N_d (C already divided by M^2 T): N_d = (n - |dx|)(n - dy)
+// on a full grid, else the masked lattice's table, and zero at a lag no
+// pair of antennas realises.
+__device__ __forceinline__ float2 lag_value(float2 c, int n, int dx, int dy, const float* __restrict__ ndt, int l) {
+    const int adx = dx < 0 ? -dx : dx;
+    const float nd = ndt ? ndt[l] : (float)((n - adx) * (n - dy));
+    return nd > 0.0f ? make_float2(c.x / nd, c.y / nd) : make_float2(0.0f, 0.0f);
+}
+
 // Inverse transform of one unit's integrated power grid and redundant
 // normalisation, by one workgroup, for M <= 64: C = conj(FFT2(P)) / M^2
 // (P is real).  Only M/2-point FFTs are used, so the registers needed match
@@ -112,7 +121,8 @@ __device__ __forceinline__ void sum_partials(const float* __restrict__ src, int 
 template <int M>
 __device__ __forceinline__ void inverse_to_lags(float2* lds, const float* __restrict__ src, int nchunk,
                                                 int n, int T, float2* __restrict__ vunique,
-                                                float* __restrict__ vauto, int unit) {
+                                                float* __restrict__ vauto, int unit,
+                                                const float* __restrict__ ndt, int n_live) {
     constexpr int H = M / 2, RS = M + 1, NT = kFftThreads;
     float2* A = lds;                                       // [M][RS] row transforms
     float* psum = reinterpret_cast<float*>(lds + M * RS);  // [M][RS] integrated power
@@ -150,7 +160,6 @@ __device__ __forceinline__ void inverse_to_lags(float2* lds, const float* __rest
         }
     }
     __syncthreads();
-    const int N = n * n;
     const int nlag = 2 * n * (n - 1);
     const float norm = 1.0f / ((float)M * (float)M * (float)T);
     for (int q = tid; q < M * n; q += NT) {
@@ -160,11 +169,10 @@ __device__ __forceinline__ void inverse_to_lags(float2* lds, const float* __rest
         const float2 xv = cadd(eo[f * H + dy], twmul<M>(eo[(M + f) * H + dy], dy));
         const float2 c = make_float2(xv.x * norm, -xv.y * norm);
         if (dx == 0 && dy == 0) {
-            vauto[unit] = c.x / (float)N;
+            vauto[unit] = c.x / (float)n_live;
         } else {
-            const int adx = dx < 0 ? -dx : dx;
-            const float nd = (float)((n - adx) * (n - dy));
-            vunique[(size_t)unit * nlag + lag_index(n, dx, dy)] = make_float2(c.x / nd, c.y / nd);
+            const int l = lag_index(n, dx, dy);
+            vunique[(size_t)unit * nlag + l] = lag_value(c, n, dx, dy, ndt, l);
         }
     }
 }
@@ -211,7 +219,8 @@ template <int M, bool CI4, bool W2 = false>
 __global__ __launch_bounds__(kFftThreads) void k_fftcorr(const void* __restrict__ volt,
                                                          const float2* __restrict__ gains,
                                                          float* __restrict__ ppart, int n, int T,
-                                                         int tchunk, int nchunk) {
+                                                         int tchunk, int nchunk,
+                                                         const uint8_t* __restrict__ live) {
     constexpr int H = M / 2;
     constexpr int S = FftCfg<M>::S;
     constexpr int NT = kFftThreads;
@@ -234,13 +243,14 @@ __global__ __launch_bounds__(kFftThreads) void k_fftcorr(const void* __restrict_
     const int tb = chunk * tchunk;
     const int te = min(T, tb + tchunk);
 
-    // 1/g on an (H+1) x (H+1) table, zero outside the n x n grid: the
-    // padded inputs of a row then come out zero without a branch per
-    // element, and row H (all zero) serves the samples past the chunk end.
+    // 1/g on an (H+1) x (H+1) table, zero outside the n x n grid (and at
+    // grid points of a masked lattice with no antenna): the padded inputs
+    // of a row then come out zero without a branch per element, and row H
+    // (all zero) serves the samples past the chunk end.
     for (int q = tid; q < (H + 1) * (H + 1); q += NT) {
         const int y = q / (H + 1), k = q % (H + 1);
         float2 h = make_float2(0.0f, 0.0f);
-        if (y < n && k < n) {
+        if (y < n && k < n && (!live || live[y * n + k])) {
             const float2 g = gains[(size_t)unit * N + y * n + k];
             const float d = 1.0f / cabs2(g);
             h = make_float2(g.x * d, -g.y * d);
@@ -518,7 +528,8 @@ template <bool CI4, int W>
 __global__ __launch_bounds__(kQThreads) void k_fftcorr_q(const void* __restrict__ volt,
                                                          const float2* __restrict__ gains,
                                                          float* __restrict__ ppart, int n, int T,
-                                                         int tchunk, int nchunk) {
+                                                         int tchunk, int nchunk,
+                                                         const uint8_t* __restrict__ live) {
     constexpr int M = 128, H = 64, S = FftCfg<128>::S, NT = kQThreads;
     static_assert(NT == 4 * 64 * S, "one row quarter per wave and sample");
     static_assert(M * 8 == 1024, "row stride of 1 KiB: the swizzle stays below bit 10");
@@ -538,7 +549,7 @@ __global__ __launch_bounds__(kQThreads) void k_fftcorr_q(const void* __restrict_
     for (int q = tid; q < H * H; q += NT) {
         const int k = q / H, y = q % H;
         float2 h = make_float2(0.0f, 0.0f);
-        if (y < n && k < n) {
+        if (y < n && k < n && (!live || live[y * n + k])) {
             const float2 g = gains[(size_t)unit * N + y * n + k];
             const float d = 1.0f / cabs2(g);
             h = make_float2(g.x * d, -g.y * d);
@@ -631,7 +642,8 @@ template <int M>
 __global__ __launch_bounds__(kFinThreads) void k_fftfin(const float* __restrict__ ppart, int nchunk,
                                                         int n, int T, float2* __restrict__ vunique,
                                                         float* __restrict__ vauto,
-                                                        unsigned long long* __restrict__ stamps) {
+                                                        unsigned long long* __restrict__ stamps,
+                                                        const float* __restrict__ ndt, int n_live) {
     constexpr int NT = kFinThreads;
     constexpr int DB = kFinDxBlock;
     __shared__ float pw[M * M];
@@ -640,7 +652,6 @@ __global__ __launch_bounds__(kFinThreads) void k_fftfin(const float* __restrict_
 
     const int tid = threadIdx.x;
     const int unit = blockIdx.x;
-    const int N = n * n;
     const int nlag = 2 * n * (n - 1);
     const float* src = ppart + (size_t)unit * nchunk * (M * M);
     sum_partials<M, NT, M>(src, nchunk, pw);
@@ -675,12 +686,10 @@ __global__ __launch_bounds__(kFinThreads) void k_fftfin(const float* __restrict_
                 c = cadd(c, cmul(abuf[uy * DB + di], twp[(uy * dy) & (M - 1)]));
             }
             if (dx == 0 && dy == 0) {
-                vauto[unit] = c.x * norm / (float)N;
+                vauto[unit] = c.x * norm / (float)n_live;
             } else {
-                const int adx = dx < 0 ? -dx : dx;
-                const float nd = (float)((n - adx) * (n - dy));
-                vunique[(size_t)unit * nlag + lag_index(n, dx, dy)] =
-                    make_float2(c.x * norm / nd, c.y * norm / nd);
+                const int l = lag_index(n, dx, dy);
+                vunique[(size_t)unit * nlag + l] = lag_value(make_float2(c.x * norm, c.y * norm), n, dx, dy, ndt, l);
             }
         }
         __syncthreads();
@@ -694,10 +703,12 @@ template <int M>
 __global__ __launch_bounds__(kFftThreads) void k_fftfin_fft(const float* __restrict__ ppart, int nchunk,
                                                             int n, int T, float2* __restrict__ vunique,
                                                             float* __restrict__ vauto,
-                                                            unsigned long long* __restrict__ stamps) {
+                                                            unsigned long long* __restrict__ stamps,
+                                                            const float* __restrict__ ndt, int n_live) {
     __shared__ float2 lds[M * (M + 1) + M * M];
     const int unit = blockIdx.x;
-    inverse_to_lags<M>(lds, ppart + (size_t)unit * nchunk * (M * M), nchunk, n, T, vunique, vauto, unit);
+    inverse_to_lags<M>(lds, ppart + (size_t)unit * nchunk * (M * M), nchunk, n, T, vunique, vauto, unit, ndt,
+                       n_live);
     if (stamps) {
         __syncthreads();
         if (threadIdx.x == 0) unit_done_stamp(stamps, unit);
@@ -707,7 +718,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fftfin_fft(const float* __restr
 template <bool CI4, int W>
 static void launch_q(const FftLaunch& L, hipStream_t st) {
     hipLaunchKernelGGL((k_fftcorr_q<CI4, W>), dim3(L.nchunk, L.n_units), dim3(kQThreads), 0, st, L.volt,
-                       L.gains, L.ppart, L.n, L.T, L.tchunk, L.nchunk);
+                       L.gains, L.ppart, L.n, L.T, L.tchunk, L.nchunk, L.mt.live);
 }
 
 template <int M, bool CI4>
@@ -726,19 +737,19 @@ static hipError_t launch_fft_m(const FftLaunch& L, hipStream_t st) {
         dim3 grid1(L.nchunk, L.n_units);
         if (!CI4 && L.n % 2 == 0)
             hipLaunchKernelGGL((k_fftcorr<M, CI4, !CI4>), grid1, dim3(kFftThreads), 0, st, L.volt, L.gains,
-                               L.ppart, L.n, L.T, L.tchunk, L.nchunk);
+                               L.ppart, L.n, L.T, L.tchunk, L.nchunk, L.mt.live);
         else
             hipLaunchKernelGGL((k_fftcorr<M, CI4, false>), grid1, dim3(kFftThreads), 0, st, L.volt, L.gains,
-                               L.ppart, L.n, L.T, L.tchunk, L.nchunk);
+                               L.ppart, L.n, L.T, L.tchunk, L.nchunk, L.mt.live);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if constexpr (M <= 64) {
         hipLaunchKernelGGL((k_fftfin_fft<M>), dim3(L.n_units), dim3(kFftThreads), 0, st, L.ppart,
-                           L.nchunk, L.n, L.T, L.vunique, L.vauto, L.stamps);
+                           L.nchunk, L.n, L.T, L.vunique, L.vauto, L.stamps, L.mt.nd, L.mt.n_live);
     } else {
         hipLaunchKernelGGL((k_fftfin<M>), dim3(L.n_units), dim3(kFinThreads), 0, st, L.ppart,
-                           L.nchunk, L.n, L.T, L.vunique, L.vauto, L.stamps);
+                           L.nchunk, L.n, L.T, L.vunique, L.vauto, L.stamps, L.mt.nd, L.mt.n_live);
     }
     return hipGetLastError();
 }

@@ -109,6 +109,21 @@ __global__ __launch_bounds__(kOThreads) void k_omnical(OmniLaunch L) {
             cnt = L.sel.off[t + 1] - off;
         }
     };
+    // A masked lattice (a hexagonal array on its grid): pairs come from the
+    // tables, grid points without an antenna keep gain 0 and take no part,
+    // and the references of the degeneracy fix are the first antenna and
+    // its +x and +y neighbours.
+    const bool masked = L.mt.pidx != nullptr;
+    const int n_live = masked ? L.mt.n_live : N, ref0 = masked ? L.mt.ref0 : 0;
+    auto alive = [&](int a) { return !masked || L.mt.live[a] != 0; };
+    // first antenna of pair b of a type
+    auto first_of = [&](int off, int b, int dx, int dy, int w) {
+        return masked ? L.mt.pfirst[off + b] : (b / w + dy) * n + b % w + (dx > 0 ? dx : 0);
+    };
+    // V^reduced index of pair (a, a - d_t) (both on the grid), or -1
+    auto pair_at = [&](int t, int off, int a, int jx, int jy, int w, int dx) {
+        return masked ? L.mt.pidx[(size_t)t * N + a] : off + jy * w + (a % n) - (dx > 0 ? dx : 0);
+    };
     // V^reduced: complex64, or raw int32 sums (4-bit plans) read as floats
     const float2* vrf = reinterpret_cast<const float2*>(L.vred) + (size_t)unit * L.P;
     const int2* vri = reinterpret_cast<const int2*>(L.vred) + (size_t)unit * L.P;
@@ -124,7 +139,8 @@ __global__ __launch_bounds__(kOThreads) void k_omnical(OmniLaunch L) {
 
     // ---- state: from gains_in (V from the group means), or continued
     if (L.gains_in) {
-        for (int a = tid; a < N; a += kOThreads) g[a] = L.gains_in[(size_t)unit * N + a];
+        for (int a = tid; a < N; a += kOThreads)
+            g[a] = alive(a) ? L.gains_in[(size_t)unit * N + a] : make_float2(0.f, 0.f);
         __syncthreads();
         for (int t = wave; t < K; t += kOThreads / 64) {
             int dx, dy, off, cnt;
@@ -132,7 +148,7 @@ __global__ __launch_bounds__(kOThreads) void k_omnical(OmniLaunch L) {
             const int w = n - (dx < 0 ? -dx : dx);
             float sr = 0.f, si = 0.f;
             for (int b = lane; b < cnt; b += 64) {
-                const int i = (b / w + dy) * n + b % w + (dx > 0 ? dx : 0), j = i - (dy * n + dx);
+                const int i = first_of(off, b, dx, dy, w), j = i - (dy * n + dx);
                 const float2 gg = cmulc(g[i], g[j]);            // g_i conj(g_j)
                 const float2 q = cmulc(vr_at(off + b), gg);        // V_b conj(g_i conj(g_j))
                 const float d = cabs2(gg);
@@ -163,18 +179,25 @@ __global__ __launch_bounds__(kOThreads) void k_omnical(OmniLaunch L) {
                 const int w = n - (dx < 0 ? -dx : dx);
                 const int jx = ax - dx, jy = ay - dy;
                 if (jx >= 0 && jx < n && jy >= 0) {          // (a, j): V_b g_j conj(V_t)
-                    const float2 c = cmulc(g[jy * n + jx], vm[t]);
-                    num = cadd(num, cmul(vr_at(off + jy * w + ax - (dx > 0 ? dx : 0)), c));
-                    den += cabs2(c);
+                    const int b = pair_at(t, off, a, jx, jy, w, dx);
+                    if (b >= 0) {
+                        const float2 c = cmulc(g[jy * n + jx], vm[t]);
+                        num = cadd(num, cmul(vr_at(b), c));
+                        den += cabs2(c);
+                    }
                 }
                 const int ix = ax + dx, iy = ay + dy;
                 if (ix >= 0 && ix < n && iy < n) {           // (i, a): conj(V_b) g_i V_t
-                    const float2 c = cmul(g[iy * n + ix], vm[t]);
-                    num = cadd(num, cmul(cconj(vr_at(off + ay * w + ix - (dx > 0 ? dx : 0))), c));
-                    den += cabs2(c);
+                    const int b = pair_at(t, off, iy * n + ix, ax, ay, w, dx);
+                    if (b >= 0) {
+                        const float2 c = cmul(g[iy * n + ix], vm[t]);
+                        num = cadd(num, cmul(cconj(vr_at(b)), c));
+                        den += cabs2(c);
+                    }
                 }
             }
-            gn[a] = make_float2(num.x / den, num.y / den);
+            // a grid point with no antenna has no pair: it keeps its gain (0)
+            gn[a] = den > 0.f ? make_float2(num.x / den, num.y / den) : g[a];
         }
         // types: the minimiser of each single V_alpha
         for (int t = wave; t < K; t += kOThreads / 64) {
@@ -183,7 +206,7 @@ __global__ __launch_bounds__(kOThreads) void k_omnical(OmniLaunch L) {
             const int w = n - (dx < 0 ? -dx : dx);
             float sr = 0.f, si = 0.f, sd = 0.f;
             for (int b = lane; b < cnt; b += 64) {
-                const int i = (b / w + dy) * n + b % w + (dx > 0 ? dx : 0), j = i - (dy * n + dx);
+                const int i = first_of(off, b, dx, dy, w), j = i - (dy * n + dx);
                 const float2 gg = cmulc(g[j], g[i]);            // conj(g_i) g_j
                 const float2 q = cmul(vr_at(off + b), gg);
                 sr += q.x;
@@ -225,18 +248,22 @@ __global__ __launch_bounds__(kOThreads) void k_omnical(OmniLaunch L) {
     __syncthreads();
 
     if (L.finish) {
-        // degeneracies (FP64): sum ln|g| = 0; antennas (0,0), (1,0), (0,1) real
+        // degeneracies (FP64): sum ln|g| = 0 over the antennas; the first
+        // antenna and its +x, +y neighbours real ((0,0), (1,0), (0,1) on a
+        // full grid)
         double ls = 0.0;
-        for (int a = tid; a < N; a += kOThreads) ls += 0.5 * log((double)cabs2(g[a]));
+        for (int a = tid; a < N; a += kOThreads)
+            if (alive(a)) ls += 0.5 * log((double)cabs2(g[a]));
         ls = o_block_sum(ls, dred);
-        const double lam = exp(ls / N);
-        const double2 g0 = to_d(g[0]), g1 = to_d(g[1]), gy = to_d(g[n]);
+        const double lam = exp(ls / n_live);
+        const double2 g0 = to_d(g[ref0]), g1 = to_d(g[ref0 + 1]), gy = to_d(g[ref0 + n]);
         const double2 qx = dmulc(g1, g0), qy = dmulc(gy, g0);
         const double c0 = atan2(g0.y, g0.x), kx = atan2(qx.y, qx.x), ky = atan2(qy.y, qy.x);
+        const int x0 = ref0 % n, y0 = ref0 / n;
         __syncthreads();
         for (int a = tid; a < N; a += kOThreads) {
             double sn, cs;
-            sincos(-(c0 + kx * (a % n) + ky * (a / n)), &sn, &cs);
+            sincos(-(c0 + kx * (a % n - x0) + ky * (a / n - y0)), &sn, &cs);
             const double2 x = to_d(g[a]);
             g[a] = to_f(make_double2((x.x * cs - x.y * sn) / lam, (x.x * sn + x.y * cs) / lam));
         }
@@ -256,7 +283,7 @@ __global__ __launch_bounds__(kOThreads) void k_omnical(OmniLaunch L) {
             typ(t, dx, dy, off, cnt);
             const int w = n - (dx < 0 ? -dx : dx);
             for (int b = lane; b < cnt; b += 64) {
-                const int i = (b / w + dy) * n + b % w + (dx > 0 ? dx : 0), j = i - (dy * n + dx);
+                const int i = first_of(off, b, dx, dy, w), j = i - (dy * n + dx);
                 const double2 m = dmul(dmulc(to_d(g[i]), to_d(g[j])), to_d(vm[t]));
                 c2 += dabs2(dsub(to_d(vr_at(off + b)), m));
             }

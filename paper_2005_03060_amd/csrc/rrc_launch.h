@@ -9,6 +9,30 @@
 
 namespace rrc {
 
+// Geometry tables of a masked lattice (a hexagonal array on its grid),
+// rebuilt in the workspace by launch_mask_tables before the kernels that
+// read them; every pointer is null for a full square grid.
+struct MaskTables {
+    const uint8_t* live = nullptr;   // [N] 1 where an antenna sits
+    const int* pidx = nullptr;       // [K][N] index of pair (a, a - d_t) in V^reduced, or -1
+    const int* pfirst = nullptr;     // [P] first antenna of each pair
+    const float* nd = nullptr;       // [2n(n-1)] pairs per lag, V^unique order
+    int n_live = 0;                  // antennas
+    int ref0 = 0;                    // the first antenna in raster order
+};
+
+constexpr int kMaskGridMax = 64;
+constexpr int kMaskWords = kMaskGridMax * kMaskGridMax / 32;
+
+struct MaskLaunch {
+    Sel sel;                         // the selection, offsets over the mask's pairs
+    uint32_t bits[kMaskWords];       // antenna a present: bit a % 32 of word a / 32
+    uint8_t* live;
+    int* pidx;
+    int* pfirst;
+    float* nd;
+};
+
 struct FftLaunch {
     int M, n, T, n_units;
     int tchunk, nchunk;
@@ -19,6 +43,7 @@ struct FftLaunch {
     float2* vunique;
     float* vauto;
     unsigned long long* stamps;   // optional [1 + U] run stamps (see unit_done_stamp)
+    MaskTables mt;
 };
 
 constexpr int kXMaxRuns = 4;   // window runs of the int8-MFMA X-engine's cover
@@ -39,6 +64,7 @@ struct XengLaunch {
     // antenna), and the staged antennas of a workgroup [a0 + mf_lo, + mf_cnt)
     bool mfma;
     int mf_inst, mf_nrun, mf_start[kXMaxRuns], mf_len[kXMaxRuns], mf_lo, mf_cnt;
+    MaskTables mt;
 };
 
 struct SolveOpts {
@@ -84,6 +110,7 @@ struct OmniLaunch {
     int* niter;
     int* status;
     float* delta;          // optional [U]: the last relative change
+    MaskTables mt;         // a masked lattice's tables (selection only)
 };
 
 // Low-cadence X-engine (lowcad.hip): every pair of an n x n grid, each
@@ -129,6 +156,7 @@ size_t omnical_lds_bytes(int n, int K, bool all);
 int omnical_max_all_grid();
 hipError_t launch_stamp_start(unsigned long long* stamps, int n_units, hipStream_t st);
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st);
+hipError_t launch_mask_tables(const MaskLaunch& L, hipStream_t st);
 #endif
 
 }  // namespace rrc

@@ -127,7 +127,8 @@ __global__ __launch_bounds__(kXThreads, 2) void k_xant(XengLaunch L) {
         if (jx >= 0 && jx < n && jy >= 0) {
             const int w = n - (dx < 0 ? -dx : dx);
             poff[t] = a - (dy * n + dx) - lo;
-            pidx[t] = s.off[t] + jy * w + (ax - (dx > 0 ? dx : 0));
+            // a masked lattice's table holds -1 where either antenna is absent
+            pidx[t] = L.mt.pidx ? L.mt.pidx[(size_t)t * N + a] : s.off[t] + jy * w + (ax - (dx > 0 ? dx : 0));
         }
     }
     const int own = live ? a - lo : 0;

@@ -159,3 +159,106 @@ def test_lowcad_schedule_matches_oracle(n, p, base):
     import math
     got = rrc.lowcad_schedule(n, p, base)
     assert got == LC.schedule(n, p, base if base > 1 else math.e)
+
+
+# ----------------------------------------------------------- masked lattices
+
+@pytest.mark.parametrize("side", [2, 3, 4, 5, 11, 32])
+def test_hex_mask_matches_oracle(side):
+    # the hexagon on its lattice grid: 3 side (side - 1) + 1 antennas (37 at
+    # side 4, 331 at side 11)
+    n, m = rrc.hex_mask(side)
+    n2, m2, pos = G.hex_grid(side)
+    assert n == n2 and np.array_equal(m.astype(bool), m2)
+    assert int(m.sum()) == 3 * side * (side - 1) + 1 == len(pos)
+
+
+def test_hex_mask_refuses_grids_past_the_limit():
+    with pytest.raises(rrc.RRCError) as e:
+        rrc.hex_mask(33)
+    assert e.value.code == _lib.RRC_ERANGE
+
+
+@pytest.mark.parametrize("side,p,base", [(3, 1.0, 0.0), (4, 1.0, 0.0), (4, 0.5, 2.0), (5, 1.0, 0.0),
+                                         (8, 1.0, 0.0), (11, 1.0, 0.0)])
+def test_masked_selection_matches_oracle(side, p, base):
+    # Sec. 5 rule on the hexagonal lattice: groups by length under the hex
+    # metric, pair counts over the antennas
+    import math
+    n, m = rrc.hex_mask(side)
+    _, _, pos = G.hex_grid(side)
+    types, npairs = rrc.select_subset_masked(n, m, "hex", p, base)
+    want = G.select_subset(pos, G.HEX_METRIC, p, base if base > 1 else math.e)
+    assert types == [tuple(t) for t in want]
+    assert npairs == len(G.group_pairs(pos, want)[0])
+
+
+@pytest.mark.parametrize("side", [3, 4, 6])
+def test_masked_degeneracy_count_matches_oracle(side):
+    # the three nearest-neighbour directions are the minimum (Sec. 5.2),
+    # two of them leave the lattice split (more null directions)
+    n, m = rrc.hex_mask(side)
+    _, _, pos = G.hex_grid(side)
+    for types in ([(1, 0), (0, 1)], [(1, 0), (-1, 1), (0, 1)], [(1, 0), (-1, 1), (0, 1), (1, 1)],
+                  [(1, 0), (-2, 1)]):
+        assert rrc.degeneracy_count_masked(n, m, types) == G.nullity(pos, types), types
+    assert rrc.degeneracy_count_masked(n, m, [(1, 0), (-1, 1), (0, 1)]) == (1, 3)
+
+
+def test_full_mask_equals_square_grid():
+    # every grid point an antenna: the square grid's selection and counts
+    for n in (4, 8, 16):
+        full = np.ones(n * n, dtype=np.uint8)
+        assert rrc.select_subset_masked(n, full, "square") == rrc.select_subset(n)
+        types, _ = rrc.select_subset(n)
+        assert rrc.degeneracy_count_masked(n, full, types) == rrc.degeneracy_count(n, types)
+
+
+def test_masked_plan_info_and_refusals():
+    side = 4
+    n, m = rrc.hex_mask(side)
+    _, _, pos = G.hex_grid(side)
+    types, npairs = rrc.select_subset_masked(n, m, "hex")
+    plan = rrc.Plan(n, types, 3, 64, mask=m)
+    assert plan.info["masked"] == 1 and plan.info["n_live"] == 37
+    assert plan.n_pairs == npairs and plan.n_ant == n * n and plan.n_lags == 2 * n * (n - 1)
+    assert plan.dof == npairs - 37 - len(types) + 2
+    lib = rrc.load_library()
+    io = _lib.RunIO()
+    # the whole-path calls refuse a masked plan before touching any pointer
+    assert lib.rrc_run(plan._h, None, 0, ctypes.byref(io)) == _lib.RRC_ENOTIMPL
+    assert lib.rrc_run_static(plan._h, None, 0, ctypes.byref(io)) == _lib.RRC_ENOTIMPL
+    tune = _lib.Tune()
+    io.d_gains_in = 1
+    assert lib.rrc_plan_tune(plan._h, None, ctypes.byref(io), None, ctypes.byref(tune)) == _lib.RRC_ENOTIMPL
+    one = ctypes.c_void_p(8)
+    assert lib.rrc_solve(plan._h, None, one, None, None, one, one, one, one, one, None) == _lib.RRC_ENOTIMPL
+    assert lib.rrc_chisq_fwd(plan._h, None, one, one, one, one) == _lib.RRC_ENOTIMPL
+    # omnical on a masked plan needs the workspace (its pair tables)
+    assert lib.rrc_omnical(plan._h, None, one, one, 1, 0.0, 1, one, one, one, one, one, None, None) == _lib.RRC_EINVAL
+    hs = (ctypes.c_void_p * 1)(plan._h)
+    b = ctypes.c_void_p()
+    assert lib.rrc_batch_create(ctypes.byref(b), 1, hs, 0) == _lib.RRC_ENOTIMPL
+
+
+def test_masked_plan_errors():
+    n, m = rrc.hex_mask(4)
+    # a type no pair of the hexagon realises
+    with pytest.raises(rrc.RRCError) as e:
+        rrc.Plan(n, [(1, 0), (-1, 1), (0, 1), (6, 6)], 1, 16, mask=m)
+    assert e.value.code == _lib.RRC_EINVAL
+    # too few types: more than the four degeneracies
+    with pytest.raises(rrc.RRCError) as e:
+        rrc.Plan(n, [(1, 0), (0, 1)], 1, 16, mask=m)
+    assert e.value.code == _lib.RRC_EDEGEN
+    # no +y neighbour of the first antenna: the references are missing
+    bad = m.copy()
+    first = int(np.nonzero(bad)[0][0])
+    bad[first + n] = 0
+    with pytest.raises(rrc.RRCError) as e:
+        rrc.Plan(n, [(1, 0), (-1, 1), (0, 1)], 1, 16, mask=bad)
+    assert e.value.code == _lib.RRC_EINVAL
+    # 4-bit plans on an odd grid (whole 32-bit words of samples)
+    with pytest.raises(rrc.RRCError) as e:
+        rrc.Plan(n, [(1, 0), (-1, 1), (0, 1)], 1, 16, dtype="ci4", mask=m)
+    assert e.value.code == _lib.RRC_ENOTIMPL

@@ -1,0 +1,166 @@
+"""Masked lattices on the GPU: hexagonal arrays (Sec. 3, Fig. 2) laid on
+their lattice index grid, against the FP64 oracle fed the same antennas.
+
+The voltages are the seeded sky on the whole grid; only the hexagon's grid
+points are antennas, and the oracle sees exactly those (in raster order,
+its positions `oracle.geometry.hex_grid`).  V^unique keeps every lag of the
+grid (zero where no pair realises it); V^reduced and the solve cover the
+mask's pairs only."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import correlator as OC
+from oracle import geometry as OG
+from oracle import redcal as OR
+from tests.gpu_util import TOL_OMNICAL, TOL_VUNIQUE, TOL_XENG, as_c64, gain_err, make_ci4_units, make_units, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+def _hex(rrc, side):
+    n, mask = rrc.hex_mask(side)
+    n2, m2, pos = OG.hex_grid(side)
+    assert n == n2 and np.array_equal(mask.astype(bool), m2)
+    return n, mask, pos, pos[:, 1] * n + pos[:, 0]
+
+
+def _embedded(side, n):
+    # the hexagon in the lower-left corner of a larger n x n grid (4-bit
+    # plans need n*n a multiple of 4 and an even n)
+    _, _, hp = OG.hex_grid(side)
+    mask = np.zeros(n * n, dtype=np.uint8)
+    mask[hp[:, 1] * n + hp[:, 0]] = 1
+    return mask, hp, hp[:, 1] * n + hp[:, 0]
+
+
+@pytest.mark.parametrize("side,U,T", [(2, 2, 64), (3, 2, 200), (4, 2, 256), (6, 1, 333), (11, 2, 512),
+                                      (17, 1, 64), (4, 1, 1)])
+def test_hex_fftcorr_matches_oracle(rrc, side, U, T):
+    n, mask, pos, idx = _hex(rrc, side)
+    types, _ = rrc.select_subset_masked(n, mask, "hex")
+    plan = rrc.Plan(n, types, U, T, mask=mask)
+    assert plan.info["masked"] == 1 and plan.info["n_live"] == len(pos)
+    v, g = make_units(n, U, T)
+    g64 = g.astype(np.complex64)
+    vu, va = plan.fftcorr(torch.from_numpy(v).to(DEV), torch.from_numpy(g64).to(DEV))
+    vu, va = vu.cpu().numpy(), va.cpu().numpy()
+    lags = OC.canonical_lags(n)
+    for u in range(U):
+        vf = OC.fx_correlate(v[u][:, idx].astype(np.complex128))
+        gl = g64[u][idx].astype(np.complex128)
+        ref = OC.redundant_average(vf, gl, pos, lags)
+        aref = OC.calibrated_auto(vf, gl)
+        empty = np.array([len(OG.PositionIndex(pos).pairs_of(dx, dy)[0]) == 0 for dx, dy in lags])
+        err = rel_l2(vu[u], ref)
+        print(f"hex side {side} (n={n}, N={len(pos)}) T={T} unit {u}: V^unique rel L2 {err:.2e}, "
+              f"{int(empty.sum())} empty lags")
+        assert err <= TOL_VUNIQUE
+        assert np.all(vu[u][empty] == 0)
+        assert abs(va[u] - aref) <= 1e-5 * aref
+
+
+@pytest.mark.parametrize("side,U,T", [(3, 2, 300), (4, 2, 1024), (11, 1, 512)])
+def test_hex_xengine_float_matches_oracle(rrc, side, U, T):
+    n, mask, pos, idx = _hex(rrc, side)
+    types, npairs = rrc.select_subset_masked(n, mask, "hex")
+    pairs, tix = OG.group_pairs(pos, types)
+    assert len(pairs) == npairs
+    plan = rrc.Plan(n, types, U, T, mask=mask)
+    assert plan.n_pairs == npairs
+    v, _ = make_units(n, U, T)
+    vr = plan.xengine(torch.from_numpy(v).to(DEV)).cpu().numpy()
+    for u in range(U):
+        ref = OC.xengine(OC.fx_correlate(v[u][:, idx].astype(np.complex128)), pairs)
+        scale = np.mean(np.abs(v[u][:, idx]) ** 2)
+        err = float(np.max(np.abs(vr[u] - ref)) / scale)
+        print(f"hex side {side} unit {u}: V^reduced max |dV| / <|v|^2> {err:.2e} ({npairs} pairs)")
+        assert err <= TOL_XENG
+
+
+@pytest.mark.parametrize("side,n,U,T", [(4, 8, 2, 256), (6, 12, 1, 130), (11, 24, 1, 64)])
+def test_hex_xengine_ci4_bit_exact(rrc, side, n, U, T):
+    mask, pos, idx = _embedded(side, n)
+    types, npairs = rrc.select_subset_masked(n, mask, "hex")
+    pairs, _ = OG.group_pairs(pos, types)
+    plan = rrc.Plan(n, types, U, T, dtype="ci4", mask=mask)
+    b, re, im, _ = make_ci4_units(n, U, T)
+    vr = plan.xengine(torch.from_numpy(b).to(DEV)).cpu().numpy()
+    for u in range(U):
+        ref = OC.xengine_int(re[u][:, idx].astype(np.int64), im[u][:, idx].astype(np.int64), pairs)
+        assert np.array_equal(vr[u].astype(np.int64), ref), f"unit {u}"
+    print(f"hex side {side} on {n}x{n}: {npairs} pairs bit-exact")
+
+
+@pytest.mark.parametrize("side,n", [(4, 8), (11, 24), (17, 34), (17, 36)])
+def test_hex_fftcorr_ci4_matches_oracle(rrc, side, n):
+    U, T = 1, 128
+    mask, pos, idx = _embedded(side, n)
+    types, _ = rrc.select_subset_masked(n, mask, "hex")
+    plan = rrc.Plan(n, types, U, T, dtype="ci4", mask=mask)
+    b, re, im, g = make_ci4_units(n, U, T)
+    g64 = g.astype(np.complex64)
+    vu, va = plan.fftcorr(torch.from_numpy(b).to(DEV), torch.from_numpy(g64).to(DEV))
+    v = re[0][:, idx].astype(np.complex128) + 1j * im[0][:, idx].astype(np.complex128)
+    vf = OC.fx_correlate(v)
+    gl = g64[0][idx].astype(np.complex128)
+    ref = OC.redundant_average(vf, gl, pos, OC.canonical_lags(n))
+    err = rel_l2(vu.cpu().numpy()[0], ref)
+    print(f"ci4 hex side {side} on {n}x{n}: V^unique rel L2 {err:.2e}")
+    assert err <= TOL_VUNIQUE
+    assert abs(float(va[0]) - OC.calibrated_auto(vf, gl)) <= 1e-5 * OC.calibrated_auto(vf, gl)
+
+
+@pytest.mark.parametrize("side,U,T", [(3, 2, 512), (4, 2, 1024), (6, 1, 1024)])
+def test_hex_omnical_reaches_the_oracle_minimum(rrc, side, U, T):
+    # the masked omnical (from the true gains) and the oracle's Gauss-Newton
+    # (FP64, from the same start) reach the same minimum of eq. redchi, with
+    # the degeneracies fixed against the first antenna in raster order and
+    # its +x, +y neighbours on both sides
+    n, mask, pos, idx = _hex(rrc, side)
+    types, _ = rrc.select_subset_masked(n, mask, "hex")
+    pairs, tix = OG.group_pairs(pos, types)
+    plan = rrc.Plan(n, types, U, T, mask=mask)
+    v, g = make_units(n, U, T, snr=10.0)
+    vr32 = np.empty((U, len(pairs)), dtype=np.complex64)
+    vr64 = np.empty((U, len(pairs)), dtype=np.complex128)
+    for u in range(U):
+        vr32[u], vr64[u] = as_c64(OC.xengine(OC.fx_correlate(v[u][:, idx].astype(np.complex128)), pairs))
+    st = plan.omnical(torch.from_numpy(vr32).to(DEV), gains_in=torch.from_numpy(g.astype(np.complex64)).to(DEV),
+                      max_iter=20000, tol=1e-7)
+    torch.cuda.synchronize()
+    gg = st["gains"].cpu().numpy()
+    dead = np.ones(n * n, dtype=bool)
+    dead[idx] = False
+    for u in range(U):
+        gl = g[u][idx]
+        ref = OR.calibrate(vr64[u], pos, types, pairs, tix, init=(gl, OR.group_mean(vr64[u], gl, pairs, tix, len(types))))
+        gerr = gain_err(gg[u][idx], ref["g"])
+        cerr = abs(float(st["chisq"][u]) - ref["chisq"]) / ref["chisq"]
+        print(f"hex side {side} unit {u}: omnical gains {gerr:.2e} chi2 {cerr:.2e} niter {int(st['niter'][u])}")
+        assert int(st["status"][u]) == 0
+        assert gerr <= TOL_OMNICAL
+        assert cerr <= 1e-5
+        assert np.all(gg[u][dead] == 0)
+
+
+def test_masked_full_grid_equals_plain_plan(rrc):
+    # a mask with every grid point set is the square grid: the same
+    # V^unique, V^reduced and omnical result as the plain plan
+    n, U, T = 8, 2, 256
+    types, _ = rrc.select_subset(n)
+    v, g = make_units(n, U, T)
+    vd, gd = torch.from_numpy(v).to(DEV), torch.from_numpy(g.astype(np.complex64)).to(DEV)
+    a = rrc.Plan(n, types, U, T)
+    b = rrc.Plan(n, types, U, T, mask=np.ones(n * n, dtype=np.uint8))
+    assert a.n_pairs == b.n_pairs
+    for x, y in zip(a.fftcorr(vd, gd), b.fftcorr(vd, gd)):
+        assert torch.equal(x, y)
+    va, vb = a.xengine(vd), b.xengine(vd)
+    assert torch.equal(va, vb)
+    sa = a.omnical(va, gains_in=gd, max_iter=300, tol=0.0)
+    sb = b.omnical(vb, gains_in=gd, max_iter=300, tol=0.0)
+    for k in ("gains", "vmodel", "chisq", "niter"):
+        assert torch.equal(sa[k], sb[k]), k

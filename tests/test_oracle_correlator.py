@@ -154,3 +154,26 @@ def test_ci4_quantise_scale():
     assert re.min() >= -7 and re.max() <= 7 and im.min() >= -7 and im.max() <= 7
     rms = np.sqrt(np.mean(re.astype(float) ** 2 + im.astype(float) ** 2) / 2)
     assert abs(rms - 2.5) < 0.05
+
+
+def test_redundant_average_on_a_masked_lattice():
+    # a lag that no pair of the hexagon realises is reported as zero; the
+    # others are the brute-force group means
+    n, _, pos = G.hex_grid(3)
+    rng = np.random.default_rng(11)
+    v = rng.standard_normal((40, len(pos))) + 1j * rng.standard_normal((40, len(pos)))
+    g = np.exp(0.1 * rng.standard_normal(len(pos)) + 1j * rng.uniform(-1, 1, len(pos)))
+    vf = C.fx_correlate(v)
+    lags = C.canonical_lags(n)
+    out = C.redundant_average(vf, g, pos, lags)
+    empty = 0
+    for t, (dx, dy) in enumerate(lags):
+        members = [(i, j) for i in range(len(pos)) for j in range(len(pos))
+                   if pos[i, 0] - pos[j, 0] == dx and pos[i, 1] - pos[j, 1] == dy]
+        if not members:
+            assert out[t] == 0
+            empty += 1
+        else:
+            want = np.mean([vf[i, j] / (g[i] * np.conj(g[j])) for i, j in members])
+            assert abs(out[t] - want) <= 1e-12 * abs(want)
+    assert empty > 0

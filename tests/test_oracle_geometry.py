@@ -115,3 +115,17 @@ def test_selection_budget_closest_prefix():
         assert abs(cum[k - 1] - b) <= abs(cum[k] - b)
         if k >= 2:
             assert abs(cum[k - 1] - b) <= abs(cum[k - 2] - b)
+
+
+def test_hex_grid_lays_the_hexagon_on_its_lattice_grid():
+    # Sec. 3 / Fig. 2 layout in lattice coordinates: the side-4 hexagon fits
+    # a 7 x 7 index grid, 37 of whose 49 points are antennas
+    n, mask, pos = G.hex_grid(4)
+    assert n == 7 and mask.sum() == 37 and len(pos) == 37
+    assert np.array_equal(pos, G.hex_positions(4) + 3)
+    assert pos.min() == 0 and pos.max() == 6
+    # raster order (y major, x minor) and the mask agree
+    assert np.array_equal(np.nonzero(mask)[0], pos[:, 1] * n + pos[:, 0])
+    # the 30 pairs of each nearest-neighbour direction survive the shift
+    for d in [(1, 0), (0, 1), (-1, 1)]:
+        assert len(G.PositionIndex(pos).pairs_of(*d)[0]) == 30

@@ -251,3 +251,28 @@ def test_logcal_amplitude_is_the_minimum_norm_least_squares_fit():
     x = np.linalg.lstsq(a, np.log(np.abs(vred)), rcond=None)[0]
     assert np.max(np.abs(np.log(amp) - x[:n * n])) < 1e-12
     assert np.max(np.abs(np.log(vamp) - x[n * n:])) < 1e-12
+
+
+def test_refant_fix_on_a_hexagonal_array():
+    # Sec. 5.2 reference antennas on a lattice whose grid corner is empty:
+    # the first antenna in raster order and its +x, +y neighbours become
+    # real and positive, mean ln|g| becomes 0, and every model visibility
+    # g_i conj(g_j) V_alpha is unchanged (the fix moves along the
+    # degeneracies only)
+    _, _, pos = G.hex_grid(4)
+    types = [(1, 0), (-1, 1), (0, 1), (1, 1)]
+    pairs, tix = G.group_pairs(pos, types)
+    rng = np.random.default_rng(3)
+    g = (1 + 0.3 * rng.standard_normal(len(pos))) * np.exp(1j * rng.uniform(-3, 3, len(pos)))
+    vm = rng.standard_normal(len(types)) + 1j * rng.standard_normal(len(types))
+    g2, vm2 = R.fix_refant(g, vm, pos, types)
+    idx = G.PositionIndex(pos)
+    a0 = idx.lut[3 - idx.lo[0], 0 - idx.lo[1]]
+    ax = idx.lut[4 - idx.lo[0], 0 - idx.lo[1]]
+    ay = idx.lut[3 - idx.lo[0], 1 - idx.lo[1]]
+    assert (tuple(pos[a0]), tuple(pos[ax]), tuple(pos[ay])) == ((3, 0), (4, 0), (3, 1))
+    for a in (a0, ax, ay):
+        assert abs(g2[a].imag) < 1e-12 and g2[a].real > 0
+    assert abs(np.mean(np.log(np.abs(g2)))) < 1e-12
+    np.testing.assert_allclose(R.model_vis(g2, vm2, pairs, tix), R.model_vis(g, vm, pairs, tix),
+                               rtol=1e-12, atol=1e-12)
