@@ -418,6 +418,19 @@ int rrc_lowcad_solve(int32_t n, int32_t n_units, void* stream, const void* d_vfu
                      int32_t max_iter, float tol, void* d_gains, void* d_vmodel, float* d_chisq,
                      int32_t* d_niter, int32_t* d_status);
 
+/* Whole-array goodness of fit (Sec. 2: the reduced calibration's gains and
+ * the FFT-correlator's V^unique, eq. modelvis, against the full visibility
+ * matrix of an FX correlator; the metric of Sec. 6.4): for every pair of the
+ * all-type list, r_ij = V_ij - g_i conj(g_j) V^unique(d_ij), and per unit
+ * d_chisq[u] = sum |r_ij|^2 (eq. redchi with sigma_ij = 1) and, when
+ * d_chisq_cal is not NULL, d_chisq_cal[u] = sum |r_ij / (g_i conj(g_j))|^2
+ * (residuals of the calibrated visibilities, whose sample noise is the same
+ * for every pair).  Both FP64.  d_vfull: [U][N(N-1)/2] complex64, the
+ * all-type list (e.g. rrc_lowcad_xengine with one cycle); d_gains [U][N],
+ * d_vunique [U][2n(n-1)] complex64.  n <= RRC_LOWCAD_MAX_GRID. */
+int rrc_chisq_full(int32_t n, int32_t n_units, void* stream, const void* d_vfull, const void* d_gains,
+                   const void* d_vunique, double* d_chisq, double* d_chisq_cal);
+
 /* Autotuner of a plan's launch parameters for the pipelined run on this
  * device: the FFT-correlator's time chunk (1, 2 or 4 times the default
  * length, i.e. fewer workgroups each integrating more samples and fewer

@@ -92,3 +92,29 @@ def reduced_chisq(chisq: float, sigma2: float, n_obs: int, n_ant: int, n_ubl: in
     chi^2 / (sigma^2 DoF), DoF = N_obs - N - N_ubl + 2 (eq. dof)."""
     return chisq / (sigma2 * (n_obs - n_ant - n_ubl + 2))
 
+
+
+def whole_array_chisq(vfull: np.ndarray, g: np.ndarray, vunique: np.ndarray, pos: np.ndarray, lags) -> Tuple[float, float]:
+    """Goodness of fit of the FFT-correlator's model to the full visibility
+    matrix (Sec. 2 on the scatter of redundant visibilities, the metric of
+    Sec. 6.4): the numerator of eq. redchi over every pair of the array,
+    with the gains of the reduced calibration and V^unique (eq. modelvis) as
+    the model visibilities.
+
+    vfull: [N, N] visibility matrix of an FX correlator (V_ij, i and j in
+    `pos` order); g: [N] gains; vunique: [len(lags)] one value per lag.
+    Returns (sum |V_ij - g_i conj(g_j) V_d|^2, sum |V_ij / (g_i conj(g_j)) -
+    V_d|^2) over every pair (i, j) with r_i - r_j = d in `lags`.  The second
+    (calibrated residuals) has the same sample noise on every pair when the
+    voltages are Gaussian, so chi^2_r follows with one sigma^2."""
+    from .geometry import PositionIndex
+    g = np.asarray(g, dtype=np.complex128)
+    idx = PositionIndex(pos)
+    c2 = c2cal = 0.0
+    for t, (dx, dy) in enumerate(lags):
+        i, j = idx.pairs_of(dx, dy)
+        gg = g[i] * np.conj(g[j])
+        r = vfull[i, j] - gg * vunique[t]
+        c2 += float(np.sum(np.abs(r) ** 2))
+        c2cal += float(np.sum(np.abs(r / gg) ** 2))
+    return c2, c2cal

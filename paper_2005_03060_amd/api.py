@@ -114,10 +114,13 @@ class LowCadence:
     round-robin X-engine over each cycle's samples, then the omnical solve
     over every type (rrc_lowcad_*)."""
 
-    def __init__(self, n: int, n_units: int, n_time: int, p: float = 1.0, log_base: float = 0.0):
+    def __init__(self, n: int, n_units: int, n_time: int, p: float = 1.0, log_base: float = 0.0,
+                 one_cycle: bool = False):
         self._lib = L.load_library()
         self.n, self.n_units, self.n_time = n, n_units, n_time
-        self.cycles = lowcad_schedule(n, p, log_base)
+        # one_cycle: every type in one cycle over the whole interval, i.e. the
+        # full visibility matrix V^full of an FX correlator
+        self.cycles = [(0, 2 * n * (n - 1))] if one_cycle else lowcad_schedule(n, p, log_base)
         flat = [c[0] for c in self.cycles] + [self.cycles[-1][1]]
         self._tb = (C.c_int32 * len(flat))(*flat)
         self.n_pairs = n * n * (n * n - 1) // 2
@@ -149,6 +152,23 @@ class LowCadence:
                                            float(tol), _ptr(out["gains"]), _ptr(out["vmodel"]), _ptr(out["chisq"]),
                                            _ptr(out["niter"]), _ptr(out["status"])), "rrc_lowcad_solve")
         return out
+
+
+def chisq_full(n: int, vfull: torch.Tensor, gains: torch.Tensor, vunique: torch.Tensor):
+    """Whole-array fit of the FFT-correlator's model to the full visibility
+    matrix (rrc_chisq_full): returns (chisq [U], chisq_cal [U]) float64."""
+    lib = L.load_library()
+    U = vfull.shape[0]
+    N = n * n
+    for t, shape, name in ((vfull, (U, N * (N - 1) // 2), "vfull"), (gains, (U, N), "gains"),
+                           (vunique, (U, 2 * n * (n - 1)), "vunique")):
+        if tuple(t.shape) != shape or t.dtype != torch.complex64 or not t.is_cuda or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous complex64 CUDA tensor of shape {shape}")
+    c = torch.empty((U,), dtype=torch.float64, device=vfull.device)
+    cc = torch.empty((U,), dtype=torch.float64, device=vfull.device)
+    L.check(lib.rrc_chisq_full(n, U, _stream(), _ptr(vfull), _ptr(gains), _ptr(vunique), _ptr(c), _ptr(cc)),
+            "rrc_chisq_full")
+    return c, cc
 
 
 def default_opts() -> Dict[str, float]:

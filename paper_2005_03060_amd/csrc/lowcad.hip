@@ -90,6 +90,63 @@ __global__ __launch_bounds__(kLThreads) void k_xlowcad(LowcadLaunch L) {
     reinterpret_cast<float2*>(L.vfull)[(size_t)unit * P + b] = make_float2(acc.x * inv, acc.y * inv);
 }
 
+// Whole-array fit of the FFT-correlator's model (Sec. 2 scatter of
+// redundant visibilities; Sec. 6.4): for every pair of the all-type list,
+// r = V_ij - g_i conj(g_j) V^unique(d_ij), summed in FP64 as |r|^2 (eq. redchi
+// with sigma = 1) and as |r / (g_i conj(g_j))|^2 (the calibrated residual,
+// whose noise is the same for every pair).  One workgroup per unit, types in
+// lag order (the all-type list's order and V^unique's), a fixed reduction
+// order.
+__global__ __launch_bounds__(kLThreads) void k_chisq_full(int n, const float2* __restrict__ vfull,
+                                                          const float2* __restrict__ gains,
+                                                          const float2* __restrict__ vunique,
+                                                          double* __restrict__ chisq,
+                                                          double* __restrict__ chisq_cal) {
+    __shared__ double red[2][kLThreads / 64];
+    const int N = n * n, K = 2 * n * (n - 1), unit = blockIdx.x, tid = threadIdx.x;
+    const long P = (long)N * (N - 1) / 2;
+    const float2* vf = vfull + (size_t)unit * P;
+    const float2* g = gains + (size_t)unit * N;
+    const float2* vu = vunique + (size_t)unit * K;
+    double s = 0.0, sc = 0.0;
+    long off = 0;
+    for (int t = 0; t < K; ++t) {
+        int dx, dy;
+        l_lag(n, t, dx, dy);
+        const int w = n - (dx < 0 ? -dx : dx), cnt = w * (n - dy);
+        const double2 va = make_double2(vu[t].x, vu[t].y);
+        for (int b = tid; b < cnt; b += kLThreads) {
+            const int i = (b / w + dy) * n + b % w + (dx > 0 ? dx : 0), j = i - (dy * n + dx);
+            const double gr = (double)g[i].x * g[j].x + (double)g[i].y * g[j].y;   // g_i conj(g_j)
+            const double gim = (double)g[i].y * g[j].x - (double)g[i].x * g[j].y;
+            const double mr = gr * va.x - gim * va.y, mi = gr * va.y + gim * va.x;
+            const double rr = (double)vf[off + b].x - mr, ri = (double)vf[off + b].y - mi;
+            const double e2 = rr * rr + ri * ri;
+            s += e2;
+            sc += e2 / (gr * gr + gim * gim);
+        }
+        off += cnt;
+    }
+    for (int o = 1; o < 64; o <<= 1) {
+        s += __shfl_xor(s, o, 64);
+        sc += __shfl_xor(sc, o, 64);
+    }
+    if ((tid & 63) == 0) {
+        red[0][tid >> 6] = s;
+        red[1][tid >> 6] = sc;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double a = 0.0, c = 0.0;
+        for (int w = 0; w < kLThreads / 64; ++w) {
+            a += red[0][w];
+            c += red[1][w];
+        }
+        chisq[unit] = a;
+        if (chisq_cal) chisq_cal[unit] = c;
+    }
+}
+
 hipError_t launch_xlowcad(const LowcadLaunch& L, hipStream_t st) {
     const long P = (long)L.n * L.n * ((long)L.n * L.n - 1) / 2;
     hipLaunchKernelGGL(k_xlowcad, dim3((unsigned)((P + kLThreads - 1) / kLThreads), L.n_units), dim3(kLThreads),
@@ -151,6 +208,17 @@ int rrc_lowcad_xengine(int32_t n, int32_t n_units, int32_t n_time, const int32_t
     L.volt = d_volt;
     L.vfull = d_vfull;
     return rrc::launch_xlowcad(L, reinterpret_cast<hipStream_t>(stream)) == hipSuccess ? RRC_OK : RRC_EDEVICE;
+}
+
+int rrc_chisq_full(int32_t n, int32_t n_units, void* stream, const void* d_vfull, const void* d_gains,
+                   const void* d_vunique, double* d_chisq, double* d_chisq_cal) {
+    if (n < 2 || n > RRC_LOWCAD_MAX_GRID || n_units < 1 || !d_vfull || !d_gains || !d_vunique || !d_chisq)
+        return RRC_EINVAL;
+    hipLaunchKernelGGL(rrc::k_chisq_full, dim3(n_units), dim3(rrc::kLThreads), 0,
+                       reinterpret_cast<hipStream_t>(stream), n, static_cast<const float2*>(d_vfull),
+                       static_cast<const float2*>(d_gains), static_cast<const float2*>(d_vunique), d_chisq,
+                       d_chisq_cal);
+    return hipGetLastError() == hipSuccess ? RRC_OK : RRC_EDEVICE;
 }
 
 int rrc_lowcad_solve(int32_t n, int32_t n_units, void* stream, const void* d_vfull, const void* d_gains_in,

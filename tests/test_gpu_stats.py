@@ -79,3 +79,79 @@ def test_gain_variance_falls_with_subset_size(rrc):
         assert abs(ratio - 1.0) <= 0.03
         means.append(emp.mean())
     assert all(b < a for a, b in zip(means, means[1:]))
+
+
+@pytest.mark.parametrize("n,U,T", [(4, 2, 256), (8, 2, 512), (12, 1, 300)])
+def test_chisq_full_matches_oracle(rrc, n, U, T):
+    # the whole-array fit (Sec. 6.4 metric) on identical complex64 inputs:
+    # the oracle's V^full (FX correlator, FP64, all-type pair list), gains
+    # and V^unique (eq. modelvis with those gains), each rounded once
+    from oracle import correlator as OC
+    from tests.gpu_util import make_units
+    pos = OG.square_positions(n)
+    lags = OC.canonical_lags(n)
+    pairs, _ = OG.group_pairs(pos, lags)
+    v, g = make_units(n, U, T)
+    vf32 = np.empty((U, len(pairs)), dtype=np.complex64)
+    vu32 = np.empty((U, len(lags)), dtype=np.complex64)
+    g32 = (g * np.exp(0.02j)).astype(np.complex64)
+    want = []
+    for u in range(U):
+        vf = OC.fx_correlate(v[u].astype(np.complex128))
+        vf32[u] = vf[pairs[:, 0], pairs[:, 1]].astype(np.complex64)
+        vu32[u] = OC.redundant_average(vf, g32[u].astype(np.complex128), pos, lags).astype(np.complex64)
+        vfr = np.zeros_like(vf)
+        vfr[pairs[:, 0], pairs[:, 1]] = vf32[u].astype(np.complex128)
+        want.append(OS.whole_array_chisq(vfr, g32[u].astype(np.complex128), vu32[u].astype(np.complex128), pos, lags))
+    c, cc = rrc.chisq_full(n, torch.from_numpy(vf32).to(DEV), torch.from_numpy(g32).to(DEV),
+                           torch.from_numpy(vu32).to(DEV))
+    c, cc = c.cpu().numpy(), cc.cpu().numpy()
+    for u in range(U):
+        print(f"n={n} unit {u}: chi2 {c[u]:.6e} (oracle {want[u][0]:.6e}), calibrated {cc[u]:.6e}")
+        assert abs(c[u] - want[u][0]) <= 1e-10 * want[u][0]
+        assert abs(cc[u] - want[u][1]) <= 1e-10 * want[u][1]
+
+
+def test_whole_array_chisq_r_near_one(rrc):
+    # Sec. 6.4: the reduced calibration's gains with the FFT-correlator's
+    # V^unique fit the full visibility matrix with chi^2_r close to one.
+    # All on the GPU: the whole path (X-engine, solve, FFT-correlator with
+    # the solved gains), V^full from the all-type X-engine over the whole
+    # interval, the calibrated residuals summed in FP64.  For Gaussian
+    # voltages a calibrated visibility's sample noise is P_i P_j / T
+    # (Isserlis), P the calibrated power: V_auto^2 / T for every pair, and
+    # independent from pair to pair when the receiver noise dominates the
+    # sky (SNR 0.5 per sample; where the sky dominates, pairs sharing
+    # antennas carry correlated sample noise and the scatter is smaller).
+    # DoF = N_obs - N - N_ubl + 2 (eq. dof) over all N(N-1)/2 pairs.
+    from tests.gpu_util import make_units
+    n, U, T, snr = 8, 64, 2048, 0.5
+    N, K = n * n, 2 * n * (n - 1)
+    types, _ = rrc.select_subset(n)
+    v, g = make_units(n, U, T, snr=snr)
+    vd = torch.from_numpy(v).to(DEV)
+    gt = torch.from_numpy(g.astype(np.complex64)).to(DEV)
+    plan = rrc.Plan(n, types, U, T)
+    out = plan.run(vd, mode="selfcal")
+    truth = plan.fftcorr(vd, gt)
+    vfull = rrc.LowCadence(n, U, T, one_cycle=True).xengine(vd)
+    _, cc = rrc.chisq_full(n, vfull, out["gains"], out["vunique"])
+    _, ct = rrc.chisq_full(n, vfull, gt, truth[0])
+    torch.cuda.synchronize()
+    assert int((out["status"] != 0).sum()) == 0
+    n_obs = N * (N - 1) // 2
+    dof = n_obs - N - K + 2
+    chir = cc.cpu().numpy() / (out["vauto"].double().cpu().numpy() ** 2 / T * dof)
+    chit = ct.cpu().numpy() / (truth[1].double().cpu().numpy() ** 2 / T * dof)
+    print(f"chi^2_r against V^full: reduced calibration {chir.mean():.4f} (sd {chir.std():.4f}); "
+          f"true gains {chit.mean():.4f}; the groups' scatter alone {(n_obs - K) / dof:.4f}")
+    # true gains: only the groups' scatter about their means remains,
+    # (N_obs - N_ubl) / DoF on average; |r|^2 / sigma^2 has unit spread per
+    # pair, so the mean over U units is within 3 / sqrt(U (N_obs - N_ubl))
+    # up to the per-antenna spread of the calibrated power (0.5%)
+    assert abs(chit.mean() * dof / (n_obs - K) - 1.0) <= 0.005 + 3.0 / np.sqrt(U * (n_obs - K))
+    # the solved gains were fitted to a subset of the same visibilities, so
+    # they absorb part of its noise (chi^2 falls below the true gains'), and
+    # the fit to the whole array stays close to one
+    assert chir.mean() <= chit.mean()
+    assert abs(chir.mean() - 1.0) <= 0.05

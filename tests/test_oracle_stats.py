@@ -126,3 +126,37 @@ def test_subset_raises_the_predicted_variance():
         vs.append(OS.predicted_gain_variance(pos, pairs, tix, k, 1.0).mean())
     assert len(vs) >= 3
     assert all(a > b for a, b in zip(vs, vs[1:]))
+
+
+def test_whole_array_chisq_pins():
+    # (1) noise-free redundant data is fitted exactly; (2) with V_d the group
+    # mean of the calibrated visibilities, the calibrated sum is the groups'
+    # scatter about their means (N_d times the population variance); (3) any
+    # other model value raises it (the group mean is the least-squares fit)
+    from oracle import correlator as C
+    from oracle import stats as S
+    n = 4
+    pos = OG.square_positions(n)
+    lags = C.canonical_lags(n)
+    rng = np.random.default_rng(8)
+    g = (1 + 0.1 * rng.standard_normal(n * n)) * np.exp(1j * rng.uniform(-3, 3, n * n))
+    vd = rng.standard_normal(len(lags)) + 1j * rng.standard_normal(len(lags))
+    vf = np.zeros((n * n, n * n), dtype=np.complex128)
+    idx = OG.PositionIndex(pos)
+    for t, d in enumerate(lags):
+        i, j = idx.pairs_of(*d)
+        vf[i, j] = g[i] * np.conj(g[j]) * vd[t]
+    c2, c2cal = S.whole_array_chisq(vf, g, vd, pos, lags)
+    assert c2 < 1e-24 and c2cal < 1e-24
+    noisy = vf + 0.1 * (rng.standard_normal(vf.shape) + 1j * rng.standard_normal(vf.shape))
+    vmean = C.redundant_average(noisy, g, pos, lags)
+    _, c2cal = S.whole_array_chisq(noisy, g, vmean, pos, lags)
+    scatter = 0.0
+    for t, d in enumerate(lags):
+        i, j = idx.pairs_of(*d)
+        q = noisy[i, j] / (g[i] * np.conj(g[j]))
+        scatter += len(q) * (np.var(q.real) + np.var(q.imag))
+    assert abs(c2cal - scatter) <= 1e-10 * scatter
+    for _ in range(5):
+        bump = vmean + 0.01 * (rng.standard_normal(len(lags)) + 1j * rng.standard_normal(len(lags)))
+        assert S.whole_array_chisq(noisy, g, bump, pos, lags)[1] > c2cal
