@@ -238,9 +238,9 @@ int rrc_plan_set_order(rrc_plan* plan, int32_t order);
 
 /* X-engine kernel of a 4-bit plan (complex64 plans have one):
  * RRC_XENG_AUTO (default): the faster form, which on MI355X is the
- *   dot-product one (the matrix-core form reads each staged column
- *   window for only two products of the banded selection and is bound by
- *   LDS bandwidth: 27.7 against 10.7 ms at 64x64 x 1024 channels x 4096
+ *   dot-product one (the matrix-core form keeps one entry per selected
+ *   diagonal of each tile and is bound by LDS bank conflicts and its
+ *   operand expansion: 27.8 against 9.5 ms at 64x64 x 1024 channels x 4096
  *   samples);
  * RRC_XENG_DOT: signed 4-bit dot products on the vector ALUs;
  * RRC_XENG_MFMA: int8 matrix-core tiles over windows covering the selected
