@@ -209,8 +209,10 @@ int rrc_degeneracy_count_masked(int32_t n, const uint8_t* mask, const int32_t* t
  * selected type must be realised by a pair, the selection must have the
  * four degeneracies only (else RRC_EDEGEN), and the reference antennas must
  * exist.  Supported calls: rrc_fftcorr, rrc_xengine (dot-product kernel),
- * rrc_omnical (the solve of a masked plan) and the info/workspace queries;
- * rrc_solve, rrc_run, rrc_run_static, rrc_chisq_* and rrc_plan_tune return
+ * rrc_omnical, the info/workspace queries, and with RRC_INIT_GAINS (the
+ * solve starts from the caller's gains, e.g. the previous integration's)
+ * rrc_solve (its d_work is then required) and rrc_run; otherwise those two,
+ * and rrc_run_static, rrc_chisq_*, rrc_plan_tune and batches, return
  * RRC_ENOTIMPL.  Device calls first rebuild the plan's mask, pair and lag
  * tables in d_work from the mask bits the plan passes by value (two small
  * kernels), so the plan still owns no device memory.  Limits as for

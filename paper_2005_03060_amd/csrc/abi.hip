@@ -680,7 +680,7 @@ int rrc_workspace_size(const rrc_plan* p, size_t* bytes) {
 
 // A masked plan's tables, rebuilt in the workspace from the mask bits;
 // returns the pointers the kernels read (all null for a full grid).
-static int mask_tables(const rrc_plan* p, void* stream, void* d_work, rrc::MaskTables& mt) {
+static int mask_tables(const rrc_plan* p, void* stream, void* d_work, rrc::MaskTables& mt, bool build = true) {
     mt = rrc::MaskTables{};
     mt.n_live = p->n_live;
     mt.ref0 = p->ref0;
@@ -693,7 +693,7 @@ static int mask_tables(const rrc_plan* p, void* stream, void* d_work, rrc::MaskT
     L.pidx = reinterpret_cast<int*>(w + p->off_pidx);
     L.pfirst = reinterpret_cast<int*>(w + p->off_pfirst);
     L.nd = reinterpret_cast<float*>(w + p->off_nd);
-    if (rrc::launch_mask_tables(L, as_stream(stream)) != hipSuccess) return RRC_EDEVICE;
+    if (build && rrc::launch_mask_tables(L, as_stream(stream)) != hipSuccess) return RRC_EDEVICE;
     mt.live = L.live;
     mt.pidx = L.pidx;
     mt.pfirst = L.pfirst;
@@ -702,7 +702,7 @@ static int mask_tables(const rrc_plan* p, void* stream, void* d_work, rrc::MaskT
 }
 
 static int fftcorr_impl(rrc_plan* p, void* stream, const void* d_volt, const void* d_gains,
-                        void* d_vunique, float* d_vauto, void* d_work, uint64_t* d_stamps) {
+                        void* d_vunique, float* d_vauto, void* d_work, uint64_t* d_stamps, bool build = true) {
     if (!p || !d_volt || !d_gains || !d_vunique || !d_vauto || !d_work) return RRC_EINVAL;
     rrc::FftLaunch L{};
     L.stamps = reinterpret_cast<unsigned long long*>(d_stamps);
@@ -718,7 +718,7 @@ static int fftcorr_impl(rrc_plan* p, void* stream, const void* d_volt, const voi
     L.ppart = reinterpret_cast<float*>(static_cast<char*>(d_work) + p->off_fft);
     L.vunique = reinterpret_cast<float2*>(d_vunique);
     L.vauto = d_vauto;
-    const int rc = mask_tables(p, stream, d_work, L.mt);
+    const int rc = mask_tables(p, stream, d_work, L.mt, build);
     if (rc != RRC_OK) return rc;
     return rrc::launch_fftcorr(L, as_stream(stream)) == hipSuccess ? RRC_OK : RRC_EDEVICE;
 }
@@ -728,7 +728,7 @@ int rrc_fftcorr(rrc_plan* p, void* stream, const void* d_volt, const void* d_gai
     return fftcorr_impl(p, stream, d_volt, d_gains, d_vunique, d_vauto, d_work, nullptr);
 }
 
-int rrc_xengine(rrc_plan* p, void* stream, const void* d_volt, void* d_vred, void* d_work) {
+static int xengine_impl(rrc_plan* p, void* stream, const void* d_volt, void* d_vred, void* d_work, bool build) {
     if (!p || !d_volt || !d_vred || !d_work) return RRC_EINVAL;
     rrc::XengLaunch L;
     L.sel = p->sel;
@@ -757,9 +757,13 @@ int rrc_xengine(rrc_plan* p, void* stream, const void* d_volt, void* d_vred, voi
         L.mf_lo = p->x_mf.mf_lo;
         L.mf_cnt = p->x_mf.mf_cnt;
     }
-    const int rc = mask_tables(p, stream, d_work, L.mt);
+    const int rc = mask_tables(p, stream, d_work, L.mt, build);
     if (rc != RRC_OK) return rc;
     return rrc::launch_xengine(L, as_stream(stream)) == hipSuccess ? RRC_OK : RRC_EDEVICE;
+}
+
+int rrc_xengine(rrc_plan* p, void* stream, const void* d_volt, void* d_vred, void* d_work) {
+    return xengine_impl(p, stream, d_volt, d_vred, d_work, true);
 }
 
 static rrc::SolveLaunch solve_launch(const rrc_plan* p) {
@@ -776,10 +780,14 @@ static rrc::SolveLaunch solve_launch(const rrc_plan* p) {
 
 static int solve_impl(rrc_plan* p, void* stream, const void* d_vred, const void* d_gains_in,
                       const void* d_gains_ref, void* d_gains_out, void* d_vmodel, float* d_chisq,
-                      int32_t* d_niter, int32_t* d_status, uint64_t* d_stamps) {
+                      int32_t* d_niter, int32_t* d_status, uint64_t* d_stamps, void* d_work, bool build) {
     if (!p || !d_vred || !d_gains_out || !d_vmodel || !d_chisq || !d_niter || !d_status)
         return RRC_EINVAL;
-    if (p->masked) return RRC_ENOTIMPL;   // a masked plan solves with rrc_omnical
+    // a masked lattice starts from the caller's gains (FIRSTCAL chains
+    // phases along full grid rows and columns) and needs the workspace for
+    // its pair tables
+    if (p->masked && p->opts.init_mode != RRC_INIT_GAINS) return RRC_ENOTIMPL;
+    if (p->masked && !d_work) return RRC_EINVAL;
     if (p->opts.init_mode == RRC_INIT_GAINS && !d_gains_in) return RRC_EINVAL;
     if (p->opts.degen_mode == RRC_DEGEN_MATCH && !d_gains_ref) return RRC_EINVAL;
     const int rc = prepare(p);
@@ -795,15 +803,18 @@ static int solve_impl(rrc_plan* p, void* stream, const void* d_vred, const void*
     L.niter = d_niter;
     L.status = d_status;
     L.stamps = reinterpret_cast<unsigned long long*>(d_stamps);
+    const int rm = mask_tables(p, stream, d_work, L.mt, build);
+    if (rm != RRC_OK) return rm;
     return rrc::launch_solve(L, as_stream(stream)) == hipSuccess ? RRC_OK : RRC_EDEVICE;
 }
 
 int rrc_solve(rrc_plan* p, void* stream, const void* d_vred, const void* d_gains_in,
               const void* d_gains_ref, void* d_gains_out, void* d_vmodel, float* d_chisq,
               int32_t* d_niter, int32_t* d_status, void* d_work) {
-    (void)d_work;   // the solve keeps its whole state in LDS
+    // the solve keeps its whole state in LDS; d_work holds a masked
+    // lattice's pair tables
     return solve_impl(p, stream, d_vred, d_gains_in, d_gains_ref, d_gains_out, d_vmodel, d_chisq,
-                      d_niter, d_status, nullptr);
+                      d_niter, d_status, nullptr, d_work, true);
 }
 
 int rrc_omnical(rrc_plan* p, void* stream, const void* d_vred, const void* d_gains_in, int32_t max_iter,
@@ -873,7 +884,7 @@ int rrc_chisq_adj(rrc_plan* p, void* stream, const void* d_g, const void* d_vm, 
 
 int rrc_run(rrc_plan* p, void* stream, int32_t mode, const rrc_io* io) {
     if (!p || !io) return RRC_EINVAL;
-    if (p->masked) return RRC_ENOTIMPL;
+    if (p->masked && p->opts.init_mode != RRC_INIT_GAINS) return RRC_ENOTIMPL;
     if (mode != RRC_RUN_PIPELINED && mode != RRC_RUN_SELFCAL) return RRC_EINVAL;
     if (mode == RRC_RUN_PIPELINED && !io->d_gains_in) return RRC_EINVAL;
     if (!io->d_volt || !io->d_vunique || !io->d_vauto || !io->d_vred || !io->d_gains_out ||
@@ -888,15 +899,23 @@ int rrc_run(rrc_plan* p, void* stream, int32_t mode, const rrc_io* io) {
     if (io->d_stamps && rrc::launch_stamp_start(reinterpret_cast<unsigned long long*>(io->d_stamps),
                                                 p->U, st) != hipSuccess)
         return RRC_EDEVICE;
+    // a masked lattice's tables, built once on `stream` before anything
+    // forks; the stages below only read them
+    {
+        rrc::MaskTables mt;
+        rc = mask_tables(p, stream, io->d_work, mt, true);
+        if (rc != RRC_OK) return rc;
+    }
     if (mode == RRC_RUN_SELFCAL) {
         // X-engine, solve, then the FFT-correlator with the solved gains
-        rc = rrc_xengine(p, stream, io->d_volt, io->d_vred, io->d_work);
+        rc = xengine_impl(p, stream, io->d_volt, io->d_vred, io->d_work, false);
         if (rc == RRC_OK)
             rc = solve_impl(p, stream, io->d_vred, io->d_gains_in, io->d_gains_ref, io->d_gains_out,
-                            io->d_vmodel, io->d_chisq, io->d_niter, io->d_status, io->d_stamps);
+                            io->d_vmodel, io->d_chisq, io->d_niter, io->d_status, io->d_stamps, io->d_work,
+                            false);
         if (rc == RRC_OK)
             rc = fftcorr_impl(p, stream, io->d_volt, io->d_gains_out, io->d_vunique, io->d_vauto,
-                              io->d_work, io->d_stamps);
+                              io->d_work, io->d_stamps, false);
         return rc;
     }
     // PIPELINED.  The FFT-correlator applies the previous integration's gains
@@ -919,7 +938,7 @@ int rrc_run(rrc_plan* p, void* stream, int32_t mode, const rrc_io* io) {
         if (hipEventRecord(p->ev_fork, st) != hipSuccess) return RRC_EDEVICE;
         if (hipStreamWaitEvent(p->aux, p->ev_fork, 0) != hipSuccess) return RRC_EDEVICE;
         const int r = fftcorr_impl(p, p->aux, io->d_volt, gfft, io->d_vunique, io->d_vauto, io->d_work,
-                                   io->d_stamps);
+                                   io->d_stamps, false);
         if (r != RRC_OK) return r;
         return hipEventRecord(p->ev_join, p->aux) == hipSuccess ? RRC_OK : RRC_EDEVICE;
     };
@@ -927,24 +946,25 @@ int rrc_run(rrc_plan* p, void* stream, int32_t mode, const rrc_io* io) {
         // a VALU-bound FFT stage that dominates the step starts at once; the
         // X-engine and the solve follow on `stream` beside it
         rc = fork_fft();
-        if (rc == RRC_OK) rc = rrc_xengine(p, stream, io->d_volt, io->d_vred, io->d_work);
+        if (rc == RRC_OK) rc = xengine_impl(p, stream, io->d_volt, io->d_vred, io->d_work, false);
         if (rc == RRC_OK)
             rc = solve_impl(p, stream, io->d_vred, io->d_gains_in, io->d_gains_ref, io->d_gains_out,
-                            io->d_vmodel, io->d_chisq, io->d_niter, io->d_status, io->d_stamps);
+                            io->d_vmodel, io->d_chisq, io->d_niter, io->d_status, io->d_stamps, io->d_work,
+                            false);
     } else {
         // The X-engine heads the critical path; once it is done the FFT
         // runs beside the latency-bound solve.  The solve is queued first:
         // it follows the X-engine on its own stream and so takes its CUs
         // before the FFT's workgroups fill the device.
-        rc = rrc_xengine(p, stream, io->d_volt, io->d_vred, io->d_work);
+        rc = xengine_impl(p, stream, io->d_volt, io->d_vred, io->d_work, false);
         if (rc != RRC_OK) return rc;
         if (hipEventRecord(p->ev_fork, st) != hipSuccess) return RRC_EDEVICE;
         rc = solve_impl(p, stream, io->d_vred, io->d_gains_in, io->d_gains_ref, io->d_gains_out,
-                        io->d_vmodel, io->d_chisq, io->d_niter, io->d_status, io->d_stamps);
+                        io->d_vmodel, io->d_chisq, io->d_niter, io->d_status, io->d_stamps, io->d_work, false);
         if (rc != RRC_OK) return rc;
         if (hipStreamWaitEvent(p->aux, p->ev_fork, 0) != hipSuccess) return RRC_EDEVICE;
         rc = fftcorr_impl(p, p->aux, io->d_volt, gfft, io->d_vunique, io->d_vauto, io->d_work,
-                          io->d_stamps);
+                          io->d_stamps, false);
         if (rc == RRC_OK && hipEventRecord(p->ev_join, p->aux) != hipSuccess) rc = RRC_EDEVICE;
     }
     if (rc != RRC_OK) return rc;

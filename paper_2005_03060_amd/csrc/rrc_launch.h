@@ -89,6 +89,7 @@ struct SolveLaunch {
     int* niter;
     int* status;
     unsigned long long* stamps;   // optional [1 + U] run stamps (see unit_done_stamp)
+    MaskTables mt;                // a masked lattice's tables (start from the caller's gains)
 };
 
 // Damped per-parameter updates (omnical.hip) over the plan's selection or,

@@ -250,6 +250,10 @@ struct Solver {
     bool ci4;
     size_t vbase;
     const uint2* vl;   // the unit's V^reduced in LDS (raw 8-byte entries), or null
+    // masked lattice: pair index table ([K][N], -1 where a pair does not
+    // exist), antenna count and the first antenna (null / N / 0 otherwise)
+    const int* pt;
+    int n_live, ref0;
     // Only the one-antenna-per-work-item shapes (N <= 1024) take the LDS
     // copy: the larger grids' pairs do not fit beside the state, and their
     // register-bound kernels are left without the extra branches.
@@ -277,6 +281,10 @@ struct Solver {
         K = s.K;
         n = s.n;
         tid = threadIdx.x;
+        pt = L.mt.pidx;
+        n_live = pt ? L.mt.n_live : N;
+        ref0 = pt ? L.mt.ref0 : 0;
+        const uint8_t* lv = L.mt.live;
         const SolveLayout Ly = solve_layout(s, vcache);
         rec = reinterpret_cast<float4*>(lds + Ly.rec);
         gd = reinterpret_cast<double2*>(lds + Ly.gd);
@@ -294,7 +302,14 @@ struct Solver {
 #pragma unroll
         for (int k = 0; k < APT; ++k) {
             a[k] = tid + k * NT;
-            live[k] = a[k] < N;
+            // a grid point of a masked lattice without an antenna is no
+            // unknown: it has no pairs, gain 0 and a zero record (which the
+            // missing pairs of its neighbours read with weight 0)
+            live[k] = a[k] < N && (!pt || lv[a[k]]);
+            if (pt && a[k] < N && !live[k]) {
+                rec[a[k]] = make_float4(0.f, 0.f, 0.f, 0.f);
+                gd[a[k]] = make_double2(0.0, 0.0);
+            }
             m1[k] = m2[k] = 0u;
             gw[k] = 0.f;
             ax_[k] = a[k] % n;
@@ -304,17 +319,28 @@ struct Solver {
                 if (t >= K || !live[k]) continue;
                 const int dx = ty[t].dx, dy = ty[t].dy;
                 const int jx = ax_[k] - dx, jy = ay_[k] - dy, ix = ax_[k] + dx, iy = ay_[k] + dy;
-                if (jx >= 0 && jx < n && jy >= 0 && jy < n) m1[k] |= 1u << t;
-                if (ix >= 0 && ix < n && iy >= 0 && iy < n) m2[k] |= 1u << t;
+                if (jx >= 0 && jx < n && jy >= 0 && jy < n && (!pt || lv[jy * n + jx])) m1[k] |= 1u << t;
+                if (ix >= 0 && ix < n && iy >= 0 && iy < n && (!pt || lv[iy * n + ix])) m2[k] |= 1u << t;
             }
         }
     }
 
     __device__ __forceinline__ bool mine(int k) const { return k < APT ? live[k] : own_t; }
     __device__ __forceinline__ int dxy(int t) const { return ty[t].dxy; }
-    // pair (a, a - d_t) / (a + d_t, a) of own antenna k
-    __device__ __forceinline__ int b1(int t, int k) const { return ty[t].c1 + ay_[k] * ty[t].w + ax_[k]; }
-    __device__ __forceinline__ int b2(int t, int k) const { return ty[t].c2 + ay_[k] * ty[t].w + ax_[k]; }
+    // pair (a, a - d_t) / (a + d_t, a) of own antenna k: affine in (x, y)
+    // on a full grid, from the table on a masked lattice (MK)
+    template <bool MK>
+    __device__ __forceinline__ int b1v(int t, int k) const {
+        if constexpr (MK) return pt[(size_t)t * N + a[k]];
+        else return ty[t].c1 + ay_[k] * ty[t].w + ax_[k];
+    }
+    template <bool MK>
+    __device__ __forceinline__ int b2v(int t, int k) const {
+        if constexpr (MK) return pt[(size_t)t * N + a[k] + ty[t].dxy];
+        else return ty[t].c2 + ay_[k] * ty[t].w + ax_[k];
+    }
+    __device__ __forceinline__ int b1(int t, int k) const { return pt ? b1v<true>(t, k) : b1v<false>(t, k); }
+    __device__ __forceinline__ int b2(int t, int k) const { return pt ? b2v<true>(t, k) : b2v<false>(t, k); }
     __device__ __forceinline__ int ax(int k) const { return ax_[k]; }
     __device__ __forceinline__ int ay(int k) const { return ay_[k]; }
 
@@ -339,7 +365,7 @@ struct Solver {
     // bit 1: the LDS copy), for loops that must stay free of branches
     template <int VM>
     __device__ __forceinline__ double2 vr64v(int b) const {
-        if constexpr ((VM & 2) != 0) {
+        if constexpr ((VM & 2) != 0 && (VM & 4) == 0) {
             const uint2 q = vl[b];
             if constexpr ((VM & 1) != 0) return make_double2((double)(int)q.x, (double)(int)q.y);
             else return make_double2(__int_as_float((int)q.x), __int_as_float((int)q.y));
@@ -361,7 +387,9 @@ struct Solver {
     // of its antennas' pairs; type rows are block sums over the pairs (each
     // pair counted at its first antenna), up to kChunk types at a time.
     __device__ __forceinline__ double residuals() {
-        // one straight-line instance per V^reduced source
+        // one straight-line instance per V^reduced source (VM bit 2: the
+        // masked lattice's pair table)
+        if (pt) return ci4 ? residuals_v<5>() : residuals_v<4>();
         if constexpr (kVcache) {
             if (vl) return ci4 ? residuals_v<3>() : residuals_v<2>();
         }
@@ -396,7 +424,8 @@ struct Solver {
                     const bool ok = live[k] && (((e ? m2[k] : m1[k]) >> t) & 1u);
                     const int i = ok ? (e ? a[k] + dxy(t) : a[k]) : 0;
                     const int j = ok ? i - dxy(t) : 0;
-                    const int b = ok ? (e ? b2(t, k) : b1(t, k)) : 0;
+                    constexpr bool MK = (VM & 4) != 0;
+                    const int b = ok ? (e ? b2v<MK>(t, k) : b1v<MK>(t, k)) : 0;
                     const double2 mm = dmul(dmulc(gd[i], gd[j]), vt);
                     const double2 q = dmulc(dsub(vr64v<VM>(b), mm), mm);
                     const double wb = ok ? dabs2(mm) : 0.0;
@@ -823,7 +852,7 @@ struct Solver {
             else vmd[tid] = dmul(vmd[tid], f);
         }
         block_sum<NT, 1>(e2, red);
-        return sqrtf(e2[0] / (float)(N + K));
+        return sqrtf(e2[0] / (float)(n_live + K));
     }
 };
 
@@ -934,7 +963,7 @@ __device__ __forceinline__ void solve_unit(const SolveLaunch& L, Shared<NT / 64>
         block_sum<NT, 9>(v9, sh.red);
         if (tid == 0) {
             // [N  Sx  Sy ; Sx Sxx Sxy ; Sy Sxy Syy] c = [S, Sx, Sy] by Cramer's rule
-            const double a00 = N, a01 = v9[4], a02 = v9[5], a11 = v9[6], a12 = v9[7], a22 = v9[8];
+            const double a00 = S.n_live, a01 = v9[4], a02 = v9[5], a11 = v9[6], a12 = v9[7], a22 = v9[8];
             const double det = a00 * (a11 * a22 - a12 * a12) - a01 * (a01 * a22 - a12 * a02) +
                                a02 * (a01 * a12 - a11 * a02);
             const double b0 = v9[1], b1 = v9[2], b2 = v9[3];
@@ -944,25 +973,28 @@ __device__ __forceinline__ void solve_unit(const SolveLaunch& L, Shared<NT / 64>
                                a02 * (a01 * b2 - b1 * a02)) / det;
             const double c2 = (a00 * (a11 * b2 - b1 * a12) - a01 * (a01 * b2 - b1 * a02) +
                                b0 * (a01 * a12 - a11 * a02)) / det;
-            sh.bcast[0] = exp(v9[0] / N);
+            sh.bcast[0] = exp(v9[0] / S.n_live);
             sh.bcast[1] = c0;
             sh.bcast[2] = c1;
             sh.bcast[3] = c2;
         }
     } else {
-        // sum ln|g| = 0; antennas (0,0), (1,0) and (0,1) real
+        // sum ln|g| = 0; the first antenna and its +x and +y neighbours
+        // real ((0,0), (1,0) and (0,1) on a full grid)
         double v1[1] = {0.0};
 #pragma unroll
         for (int k = 0; k < APT; ++k)
             if (S.live[k]) v1[0] += 0.5 * log(dabs2(S.gd[S.a[k]]));
         block_sum<NT, 1>(v1, sh.red);
         if (tid == 0) {
-            const double2 g0 = S.gd[0], g1 = S.gd[1], gn = S.gd[s.n];
+            const int r0 = S.ref0;
+            const double2 g0 = S.gd[r0], g1 = S.gd[r0 + 1], gn = S.gd[r0 + s.n];
             const double2 qx = dmulc(g1, g0), qy = dmulc(gn, g0);
-            sh.bcast[0] = exp(v1[0] / N);
-            sh.bcast[1] = atan2(g0.y, g0.x);
+            sh.bcast[0] = exp(v1[0] / S.n_live);
+            // the plane c0 + kx x + ky y through the references
             sh.bcast[2] = atan2(qx.y, qx.x);
             sh.bcast[3] = atan2(qy.y, qy.x);
+            sh.bcast[1] = atan2(g0.y, g0.x) - sh.bcast[2] * (r0 % s.n) - sh.bcast[3] * (r0 / s.n);
         }
     }
     __syncthreads();
@@ -1003,8 +1035,10 @@ __device__ __forceinline__ void solve_unit(const SolveLaunch& L, Shared<NT / 64>
     }
     block_sum<NT, 1>(c1, sh.red);
 #pragma unroll
-    for (int k = 0; k < APT; ++k)
+    for (int k = 0; k < APT; ++k) {
         if (S.live[k]) L.gains_out[(size_t)unit * N + S.a[k]] = to_f(S.gd[S.a[k]]);
+        else if (S.a[k] < N) L.gains_out[(size_t)unit * N + S.a[k]] = make_float2(0.f, 0.f);
+    }
     if (S.own_t) L.vmodel[(size_t)unit * K + tid] = to_f(S.vmd[tid]);
     if (tid == 0) {
         const bool fin = c1[0] == c1[0] && !isinf(c1[0]);

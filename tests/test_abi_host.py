@@ -239,6 +239,11 @@ def test_masked_plan_info_and_refusals():
     hs = (ctypes.c_void_p * 1)(plan._h)
     b = ctypes.c_void_p()
     assert lib.rrc_batch_create(ctypes.byref(b), 1, hs, 0) == _lib.RRC_ENOTIMPL
+    # started from the caller's gains the whole path accepts a masked plan
+    # (these calls then fail only on the missing buffers)
+    pg = rrc.Plan(n, types, 3, 64, mask=m, init_mode="gains")
+    assert lib.rrc_run(pg._h, None, 0, ctypes.byref(_lib.RunIO())) == _lib.RRC_EINVAL
+    assert lib.rrc_solve(pg._h, None, one, one, None, one, one, one, one, one, None) == _lib.RRC_EINVAL
 
 
 def test_masked_plan_errors():

@@ -164,3 +164,107 @@ def test_masked_full_grid_equals_plain_plan(rrc):
     sb = b.omnical(vb, gains_in=gd, max_iter=300, tol=0.0)
     for k in ("gains", "vmodel", "chisq", "niter"):
         assert torch.equal(sa[k], sb[k]), k
+
+
+def _hex_solve_case(rrc, side, U, T, snr=10.0, **opts):
+    n, mask, pos, idx = _hex(rrc, side)
+    types, _ = rrc.select_subset_masked(n, mask, "hex")
+    pairs, tix = OG.group_pairs(pos, types)
+    plan = rrc.Plan(n, types, U, T, mask=mask, init_mode="gains", **opts)
+    v, g = make_units(n, U, T, snr=snr)
+    vr32 = np.empty((U, len(pairs)), dtype=np.complex64)
+    vr64 = np.empty((U, len(pairs)), dtype=np.complex128)
+    for u in range(U):
+        vr32[u], vr64[u] = as_c64(OC.xengine(OC.fx_correlate(v[u][:, idx].astype(np.complex128)), pairs))
+    return n, mask, pos, idx, types, pairs, tix, plan, v, g, vr32, vr64
+
+
+@pytest.mark.parametrize("side,U,T", [(3, 2, 512), (4, 2, 1024), (6, 2, 1024), (11, 1, 2048)])
+def test_hex_gauss_newton_matches_oracle(rrc, side, U, T):
+    # the adjoint-driven Gauss-Newton solve on a masked lattice, started from
+    # the true gains, against the oracle's FP64 solve of the same (rounded)
+    # V^reduced, both fixed against the first antenna and its neighbours
+    from tests.gpu_util import TOL_GAINS
+    n, mask, pos, idx, types, pairs, tix, plan, v, g, vr32, vr64 = _hex_solve_case(rrc, side, U, T)
+    gin = torch.from_numpy(g.astype(np.complex64)).to(DEV)
+    out = plan.solve(torch.from_numpy(vr32).to(DEV), gains_in=gin)
+    torch.cuda.synchronize()
+    gg = out["gains"].cpu().numpy()
+    dead = np.ones(n * n, dtype=bool)
+    dead[idx] = False
+    for u in range(U):
+        gl = g[u][idx]
+        ref = OR.calibrate(vr64[u], pos, types, pairs, tix,
+                           init=(gl, OR.group_mean(vr64[u], gl, pairs, tix, len(types))))
+        gerr = gain_err(gg[u][idx], ref["g"])
+        cerr = abs(float(out["chisq"][u]) - ref["chisq"]) / ref["chisq"]
+        print(f"hex side {side} unit {u}: Gauss-Newton gains {gerr:.2e} chi2 {cerr:.2e} "
+              f"steps {int(out['niter'][u])} dof {plan.dof} (oracle {ref['dof']})")
+        assert int(out["status"][u]) == 0
+        assert gerr <= TOL_GAINS
+        assert cerr <= 1e-5
+        assert plan.dof == ref["dof"]
+        assert np.all(gg[u][dead] == 0)
+
+
+def test_hex_gauss_newton_match_mode(rrc):
+    # MATCH: the mean log-amplitude and the phase plane of the reference
+    # gains (the paper's procedure), on the hexagon's antennas only
+    from tests.gpu_util import TOL_GAINS
+    side, U, T = 4, 2, 1024
+    n, mask, pos, idx, types, pairs, tix, plan, v, g, vr32, vr64 = _hex_solve_case(rrc, side, U, T,
+                                                                                     degen_mode="match")
+    gin = torch.from_numpy(g.astype(np.complex64)).to(DEV)
+    out = plan.solve(torch.from_numpy(vr32).to(DEV), gains_in=gin, gains_ref=gin)
+    torch.cuda.synchronize()
+    for u in range(U):
+        gl = g[u].astype(np.complex64).astype(np.complex128)[idx]
+        ref = OR.calibrate(vr64[u], pos, types, pairs, tix, fix="match", g_ref=gl,
+                           init=(gl, OR.group_mean(vr64[u], gl, pairs, tix, len(types))))
+        gerr = gain_err(out["gains"][u].cpu().numpy()[idx], ref["g"])
+        print(f"hex side {side} unit {u}: MATCH gains {gerr:.2e}")
+        assert gerr <= TOL_GAINS
+
+
+@pytest.mark.parametrize("mode", ["selfcal", "pipelined"])
+def test_hex_whole_path_run(rrc, mode):
+    # rrc_run on a hexagonal array: X-engine, Gauss-Newton from the given
+    # gains, FFT-correlator; against the oracle's whole FP64 chain
+    from tests.gpu_util import TOL_GAINS_E2E
+    side, U, T = 6, 2, 1024
+    n, mask, pos, idx, types, pairs, tix, plan, v, g, vr32, vr64 = _hex_solve_case(rrc, side, U, T)
+    gin = torch.from_numpy(g.astype(np.complex64)).to(DEV)
+    out = plan.run(torch.from_numpy(v).to(DEV), gains_in=gin, mode=mode)
+    torch.cuda.synchronize()
+    assert int((out["status"] != 0).sum()) == 0
+    lags = OC.canonical_lags(n)
+    for u in range(U):
+        vf = OC.fx_correlate(v[u][:, idx].astype(np.complex128))
+        assert np.max(np.abs(out["vred"][u].cpu().numpy() - OC.xengine(vf, pairs))) <= TOL_XENG * np.mean(
+            np.abs(v[u][:, idx]) ** 2)
+        gl = g[u][idx]
+        vr = OC.xengine(vf, pairs)
+        ref = OR.calibrate(vr, pos, types, pairs, tix, init=(gl, OR.group_mean(vr, gl, pairs, tix, len(types))))
+        gerr = gain_err(out["gains"][u].cpu().numpy()[idx], ref["g"])
+        # the FFT-correlator applied the solved gains (selfcal) or the given ones (pipelined)
+        gfft = ref["g"] if mode == "selfcal" else g[u].astype(np.complex64).astype(np.complex128)[idx]
+        vref = OC.redundant_average(vf, gfft, pos, lags)
+        verr = rel_l2(out["vunique"][u].cpu().numpy(), vref)
+        print(f"{mode} hex side {side} unit {u}: gains {gerr:.2e}, V^unique {verr:.2e}")
+        assert gerr <= TOL_GAINS_E2E
+        assert verr <= TOL_VUNIQUE
+
+
+def test_masked_full_grid_solve_equals_plain_plan(rrc):
+    # a full mask runs the same Gauss-Newton arithmetic as the plain plan
+    n, U, T = 8, 2, 256
+    types, _ = rrc.select_subset(n)
+    v, g = make_units(n, U, T)
+    vd, gd = torch.from_numpy(v).to(DEV), torch.from_numpy(g.astype(np.complex64)).to(DEV)
+    a = rrc.Plan(n, types, U, T, init_mode="gains")
+    b = rrc.Plan(n, types, U, T, mask=np.ones(n * n, dtype=np.uint8), init_mode="gains")
+    oa = a.run(vd, gains_in=gd, mode="selfcal")
+    ob = b.run(vd, gains_in=gd, mode="selfcal")
+    torch.cuda.synchronize()
+    for k in ("vred", "gains", "vmodel", "chisq", "niter", "status", "vunique", "vauto"):
+        assert torch.equal(oa[k], ob[k]), k
