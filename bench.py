@@ -15,7 +15,8 @@ before timing starts.  Prints one JSON line.
 
 The default workload is the 64x64-grid, 1024-channel, 4096-sample 4-bit one
 (the largest single-GPU configuration); the 32x32-grid, 256-channel
-complex64 one is measured beside it under "extra".
+complex64 one and the paper's 331-antenna hexagonal array (1024 channels,
+2048 samples) are measured beside it under "extra".
 """
 from __future__ import annotations
 
@@ -563,6 +564,47 @@ def measure(w, args, rrc, dev, with_oracle):
     return rec
 
 
+def measure_hex(side, n_chan, n_time, args, rrc, dev):
+    """A hexagonal array (Sec. 3, Fig. 2) on its lattice grid: the whole
+    path (rrc_run PIPELINED, the solve started from the given gains) over
+    every channel, and each stage alone.  The 11-antennas-per-side hexagon is
+    the paper's 331-antenna array (Sec. 6.4)."""
+    import torch
+    from synthdata import Workload
+    from synthdata.device import device_voltages
+    n, mask = rrc.hex_mask(side)
+    w = Workload(5, f"hex{side}_c{n_chan}_t{n_time}", (n,), n_chan, n_time, 10.0,
+                 note=f"hexagon of side {side} on its {n}x{n} grid")
+    volt, g = device_voltages(w, 0, dev)
+    types, npairs = rrc.select_subset_masked(n, mask, "hex")
+    plan = rrc.Plan(n, types, n_chan, n_time, mask=mask, init_mode="gains")
+    plan.workspace(dev)
+    gin = torch.from_numpy(g.astype(np.complex64)).to(dev)
+    out = plan.alloc_outputs(dev)
+    log(f"{w.name}: {args.warmup} warm-up + {args.steps} timed steps")
+    ms = time_fn(lambda: plan.run(volt, gains_in=gin, mode="pipelined", out=out), max(args.steps, 20))
+    st = {"xengine": time_fn(lambda: plan.xengine(volt), 10),
+          "fftcorr": time_fn(lambda: plan.fftcorr(volt, gin), 10)}
+    vred = plan.xengine(volt)
+    st["solve"] = time_fn(lambda: plan.solve(vred, gains_in=gin), 10)
+    torch.cuda.synchronize()
+    flops = fft_flops_per_sample(n) * n_time * n_chan
+    tf = flops / (st["fftcorr"] * 1e-3) / 1e12
+    vbytes = 8.0 * n * n * n_time * n_chan
+    status = int((out["status"] != 0).sum())
+    del volt
+    torch.cuda.empty_cache()
+    return {"value": n_chan / (ms * 1e-3), "ms_per_step": ms,
+            "config": {"workload": w.name, "layout": "hexagonal", "side": side, "grid": n,
+                       "antennas": int(mask.sum()), "channels": n_chan, "samples": n_time,
+                       "voltage_format": "complex64", "fft_size": pad_size(n), "types": len(types),
+                       "pairs": npairs, "mode": "pipelined, all channels per launch, solve from the given gains"},
+            "stages_ms": st, "status_nonzero": status,
+            "roofline": {"bound": "alu", "achieved": tf, "peak": VALU_FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": tf / VALU_FP32_PEAK_TFLOPS, "kernel": "FFT-correlator stage",
+                         "algorithmic_flops_per_launch": flops, "hbm_frac": vbytes / (st["fftcorr"] * 1e-3) / 1e9 / HBM_PEAK_GBS}}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -605,6 +647,8 @@ def main():
         rec["extra"] = {EXTRA_WORKLOAD: {k: x[k] for k in ("value", "ms_per_step", "config", "stages_ms",
                                                            "roofline", "roofline_other", "plain_per_channel",
                                                            "solver_comparison")}}
+        hx = measure_hex(11, 1024, 2048, a2, rrc, dev)
+        rec["extra"][hx["config"]["workload"]] = hx
     print(json.dumps(rec), flush=True)
 
 
