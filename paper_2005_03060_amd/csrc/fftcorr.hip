@@ -284,6 +284,24 @@ __global__ __launch_bounds__(kFftThreads) void k_fftcorr(const void* __restrict_
 
     __syncthreads();
 
+    // complex64 rows of even n (16-byte pairs, H / 2 of them per row) are
+    // loaded one step ahead at M = 64, so the loads are in flight during the
+    // column stage (193 VGPRs, still the two waves per SIMD the LDS allows;
+    // at M = 32 the extra registers would cost a wave per SIMD); a sample
+    // past the chunk end re-reads the last one and meets the zero row of the
+    // table, and columns k >= n re-read column n-2 and meet 1/g = 0
+    constexpr bool PF = W2 && M == 64;
+    float4 rq[PF ? H / 2 : 1];
+    auto load_row = [&](int t0) {
+        const int t = min(t0 + rs, te - 1);
+        const float2* vr = reinterpret_cast<const float2*>(volt) + ((size_t)unit * T + t) * N + (size_t)ry * n;
+#pragma unroll
+        for (int k = 0; k < H; k += 2) rq[k / 2] = *reinterpret_cast<const float4*>(vr + min(k, n - 2));
+    };
+    if constexpr (PF) {
+        if (row_active) load_row(tb);
+    }
+
     for (int t0 = tb; t0 < te; t0 += S) {
         if (row_active) {
             float2 x[H];
@@ -295,7 +313,14 @@ __global__ __launch_bounds__(kFftThreads) void k_fftcorr(const void* __restrict_
             const float2* hrow = hinv + (live ? ry : H) * (H + 1);
             {
                 // columns k >= n re-read column n-1 (finite) and meet 1/g = 0
-                if constexpr (W2) {
+                if constexpr (PF) {
+#pragma unroll
+                    for (int k = 0; k < H; k += 2) {
+                        const float4 q = rq[k / 2];
+                        x[k] = cmul(make_float2(q.x, q.y), hrow[k]);
+                        x[k + 1] = cmul(make_float2(q.z, q.w), hrow[k + 1]);
+                    }
+                } else if constexpr (W2) {
                     const float2* vr = reinterpret_cast<const float2*>(volt) + rowbase;
 #pragma unroll
                     for (int k = 0; k < H; k += 2) {
@@ -323,6 +348,9 @@ __global__ __launch_bounds__(kFftThreads) void k_fftcorr(const void* __restrict_
             }
         }
         __syncthreads();
+        if constexpr (PF) {
+            if (row_active && t0 + S < te) load_row(t0 + S);
+        }
 #pragma unroll
         for (int c = 0; c < CPT; ++c) {
             const int s = cs0 + c * G;
