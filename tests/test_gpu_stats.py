@@ -155,3 +155,36 @@ def test_whole_array_chisq_r_near_one(rrc):
     # the fit to the whole array stays close to one
     assert chir.mean() <= chit.mean()
     assert abs(chir.mean() - 1.0) <= 0.05
+
+
+@pytest.mark.parametrize("side,seed", [(4, 31), (6, 32)])
+def test_hex_gain_spread_matches_predicted_covariance(rrc, side, seed):
+    # Sec. 3 simulations on the paper's own layout, a hexagonal array: the
+    # spread of the masked Gauss-Newton solve's gains over 2048 realisations
+    # against eq. gaincov for the hexagon's antennas and pairs
+    U, snr = 2048, 100.0
+    n, mask = rrc.hex_mask(side)
+    _, _, pos = OG.hex_grid(side)
+    idx = pos[:, 1] * n + pos[:, 0]
+    types, _ = rrc.select_subset_masked(n, mask, "hex")
+    pairs, tix = OG.group_pairs(pos, types)
+    N, K = len(pos), len(types)
+    vred, g, _ = simulate_reduced_visibilities(seed, pairs, tix, N, K, U, snr)
+    plan = rrc.Plan(n, types, U, 256, mask=mask, init_mode="gains", degen_mode="match")
+    gfull = np.ones(n * n, dtype=np.complex128)
+    gfull[idx] = g
+    g32 = torch.from_numpy(np.broadcast_to(gfull.astype(np.complex64), (U, n * n)).copy()).to(DEV)
+    out = plan.solve(torch.from_numpy(vred.astype(np.complex64)).to(DEV), gains_in=g32, gains_ref=g32)
+    torch.cuda.synchronize()
+    assert int((out["status"] != 0).sum()) == 0
+    gg = out["gains"].cpu().numpy()[:, idx].astype(np.complex128)
+    emp = np.mean(np.abs(gg / g.astype(np.complex64).astype(np.complex128) - 1.0) ** 2, axis=0)
+    pred = OS.predicted_gain_variance(pos, pairs, tix, K, snr)
+    ratio = emp / pred
+    chir = OS.reduced_chisq(out["chisq"].cpu().numpy().astype(np.float64), 1.0 / snr ** 2, len(pairs), N, K)
+    dof = len(pairs) - N - K + 2
+    print(f"hex side {side} ({N} antennas): gain variance / predicted mean {ratio.mean():.4f}, range "
+          f"[{ratio.min():.3f}, {ratio.max():.3f}]; chi^2_r mean {chir.mean():.4f}")
+    assert abs(ratio.mean() - 1.0) <= 0.03
+    assert np.all(np.abs(ratio - 1.0) <= 0.12)
+    assert abs(chir.mean() - 1.0) <= 4.0 / np.sqrt(U * dof)
