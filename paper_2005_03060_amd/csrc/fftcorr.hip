@@ -393,18 +393,19 @@ __global__ __launch_bounds__(kFftThreads) void k_fftcorr(const void* __restrict_
 // wave (s, R) loads input group R (eight pairs j, j + 32) of every row of
 // sample s, divides by the gains and writes all four quarters' folded,
 // twiddled inputs into that row of the row buffer; after a barrier wave
-// (s, q) reads quarter q's 32 inputs back, transforms them, and after a
-// second barrier writes E(4m + q) over them.  So every voltage is unpacked
-// and divided by its gain once, not once per quarter.  Column stage: wave
-// (q, h) takes quarter q of columns 64h .. 64h + 63 of both samples, so
-// each work-item owns 32 grid points of |E|^2 outright and writes them with
-// no reduction.
+// (s, q) reads quarter q's 32 inputs back, transforms them and writes
+// E(4m + q) over them, at column 32 q + m.  So every voltage is unpacked
+// and divided by its gain once, not once per quarter, and a row's
+// transform rewrites only the block its own lane read.  Column stage: wave
+// (q, h) takes quarter q of the buffer's columns 64h .. 64h + 63 (natural
+// columns 4 (c mod 32) + c div 32) of both samples, so each work-item owns
+// 32 grid points of |E|^2 outright and writes them with no reduction.
 //
 // LDS: the two row buffers (128 KB) and the 1/g table (32 KB) fill the
 // 160 KB, so nothing is padded.  The table is stored transposed ([k][y]),
 // which makes the row stage's reads (lanes on rows) consecutive.  Row
-// buffer entry (y, k) sits at column k ^ (y mod 32): row-stage writes
-// (lanes on rows, one k) then spread over the banks, and column-stage
+// buffer entry (y, c) sits at column c ^ (y mod 32): row-stage writes
+// (lanes on rows, one c) then spread over the banks, and column-stage
 // reads (lanes on columns, one row) stay a permutation of consecutive
 // words.  The XOR acts below bit 10 of the byte address, so every access
 // is one XOR of a per-lane base with a constant plus an immediate offset.
@@ -518,21 +519,19 @@ __device__ __forceinline__ void row_fold(const RowRaw<CI4, W>& raw, const float2
 }
 
 // Row stage, second half: quarter Q of one row, the 32-point transform of
-// u_Q read back from the row; outputs E(4m + Q) stay in registers until
-// every wave has read its inputs.
+// u_Q read back from the row, its outputs E(4m + Q) written over u_Q: output
+// m goes to column 32 Q + m, the block u_Q occupied, so each lane rewrites
+// only what it has read and no other wave needs to have read first.
 template <int Q>
-__device__ __forceinline__ void row_fft(const float2* rbuf, uint32_t wbase, float2 (&u)[32]) {
+__device__ __forceinline__ void row_transform(float2* rbuf, uint32_t wbase) {
+    float2 u[32];
 #pragma unroll
     for (int j = 0; j < 32; ++j) u[j] = lds_at(rbuf, wbase ^ ((32 * Q + j) << 3));
     fft_dif<32>(u);
-}
-
-template <int Q>
-__device__ __forceinline__ void row_store(float2* rbuf, uint32_t wbase, const float2 (&u)[32]) {
     char* rb = reinterpret_cast<char*>(rbuf);
 #pragma unroll
     for (int r = 0; r < 32; ++r)
-        *reinterpret_cast<float2*>(rb + (wbase ^ ((4 * bitrev<32>(r) + Q) << 3))) = u[r];
+        *reinterpret_cast<float2*>(rb + (wbase ^ ((32 * Q + bitrev<32>(r)) << 3))) = u[r];
 }
 
 // Quarter Q of one column of one sample's row buffer; |E|^2 into acc.
@@ -562,7 +561,7 @@ __global__ __launch_bounds__(kQThreads) void k_fftcorr_q(const void* __restrict_
     static_assert(NT == 4 * 64 * S, "one row quarter per wave and sample");
     static_assert(M * 8 == 1024, "row stride of 1 KiB: the swizzle stays below bit 10");
     // (the launcher guarantees 33 <= n <= 64)
-    __shared__ float2 rbuf[S * H * M];   // [s][y][k ^ (y mod 32)]
+    __shared__ float2 rbuf[S * H * M];   // [s][y][c ^ (y mod 32)]
     __shared__ float2 hinv[H * H];       // [k][y], zero outside the grid
 
     const int tid = threadIdx.x;
@@ -622,22 +621,12 @@ __global__ __launch_bounds__(kQThreads) void k_fftcorr_q(const void* __restrict_
             }
         }
         __syncthreads();
-        float2 u[32];
         if (row_lane) {
             switch (rq) {
-                case 0: row_fft<0>(rbuf, wbase, u); break;
-                case 1: row_fft<1>(rbuf, wbase, u); break;
-                case 2: row_fft<2>(rbuf, wbase, u); break;
-                default: row_fft<3>(rbuf, wbase, u); break;
-            }
-        }
-        __syncthreads();   // every quarter has read its inputs: the row may be overwritten
-        if (row_lane) {
-            switch (rq) {
-                case 0: row_store<0>(rbuf, wbase, u); break;
-                case 1: row_store<1>(rbuf, wbase, u); break;
-                case 2: row_store<2>(rbuf, wbase, u); break;
-                default: row_store<3>(rbuf, wbase, u); break;
+                case 0: row_transform<0>(rbuf, wbase); break;
+                case 1: row_transform<1>(rbuf, wbase); break;
+                case 2: row_transform<2>(rbuf, wbase); break;
+                default: row_transform<3>(rbuf, wbase); break;
             }
         }
         __syncthreads();
@@ -657,10 +646,12 @@ __global__ __launch_bounds__(kQThreads) void k_fftcorr_q(const void* __restrict_
         __syncthreads();
     }
 
-    // grid point (ky, kx) = (4 bitrev(r) + cq, cu): lanes write consecutive kx
+    // grid point (ky, kx) = (4 bitrev(r) + cq, kx), where the row buffer's
+    // column cu = 32 q' + m holds kx = 4 m + q'
+    const int kx = 4 * (cu & 31) + (cu >> 5);
     float* dst = ppart + ((size_t)unit * nchunk + chunk) * (M * M);
 #pragma unroll
-    for (int r = 0; r < 32; ++r) dst[(4 * bitrev<32>(r) + cq) * M + cu] = acc[r];
+    for (int r = 0; r < 32; ++r) dst[(4 * bitrev<32>(r) + cq) * M + kx] = acc[r];
 }
 
 constexpr int kFinThreads = 256;
