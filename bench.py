@@ -54,7 +54,7 @@ def pad_size(n: int) -> int:
     return m
 
 
-def fft_flops_per_sample(n: int) -> float:
+def fft_flops_per_sample(n: int, m: int = 0) -> float:
     """Algorithmic FP32 flops of one sample's FFT-correlator work.
 
     The practical count of the hot-path scope: every row (n of them) and
@@ -63,10 +63,17 @@ def fft_flops_per_sample(n: int) -> float:
     |E|^2 accumulation 4 flops per grid point; gain application 6 flops per
     antenna.  M is the default padded size (the next power of two >= 2n):
     at n = 16, 32, 64 this gives 32.5 MF, 314 MF and 2.94 GF per unit of
-    1024, 2048 and 4096 samples.
+    1024, 2048 and 4096 samples.  `m` = 48 counts the mixed-radix transform
+    the plan can use instead of 64 when 2n - 1 <= 48.
     """
-    m = pad_size(n)
-    return (n + m) * 4.25 * m * (math.log2(m) - 1) + 4 * m * m + 6 * n * n
+    m = m or pad_size(n)
+    if m == 48:
+        # two 24-point halves, each a radix-3 step (8 butterflies of 30
+        # flops) and three 8-point radix-2^2 transforms
+        per = 2 * (8 * 30 + 3 * 4.25 * 8 * 3)
+    else:
+        per = 4.25 * m * (math.log2(m) - 1)
+    return (n + m) * per + 4 * m * m + 6 * n * n
 
 
 def parse():
@@ -578,6 +585,9 @@ def measure_hex(side, n_chan, n_time, args, rrc, dev):
     volt, g = device_voltages(w, 0, dev)
     types, npairs = rrc.select_subset_masked(n, mask, "hex")
     plan = rrc.Plan(n, types, n_chan, n_time, mask=mask, init_mode="gains")
+    if 2 * n - 1 <= 48 < pad_size(n):
+        plan.set_fft_size(48)         # the faster transform for grids up to 24 x 24
+    m = plan.info["fft_size"]
     plan.workspace(dev)
     gin = torch.from_numpy(g.astype(np.complex64)).to(dev)
     out = plan.alloc_outputs(dev)
@@ -588,7 +598,7 @@ def measure_hex(side, n_chan, n_time, args, rrc, dev):
     vred = plan.xengine(volt)
     st["solve"] = time_fn(lambda: plan.solve(vred, gains_in=gin), 10)
     torch.cuda.synchronize()
-    flops = fft_flops_per_sample(n) * n_time * n_chan
+    flops = fft_flops_per_sample(n, m) * n_time * n_chan
     tf = flops / (st["fftcorr"] * 1e-3) / 1e12
     vbytes = 8.0 * n * n * n_time * n_chan
     status = int((out["status"] != 0).sum())
@@ -597,7 +607,7 @@ def measure_hex(side, n_chan, n_time, args, rrc, dev):
     return {"value": n_chan / (ms * 1e-3), "ms_per_step": ms,
             "config": {"workload": w.name, "layout": "hexagonal", "side": side, "grid": n,
                        "antennas": int(mask.sum()), "channels": n_chan, "samples": n_time,
-                       "voltage_format": "complex64", "fft_size": pad_size(n), "types": len(types),
+                       "voltage_format": "complex64", "fft_size": m, "types": len(types),
                        "pairs": npairs, "mode": "pipelined, all channels per launch, solve from the given gains"},
             "stages_ms": st, "status_nonzero": status,
             "roofline": {"bound": "alu", "achieved": tf, "peak": VALU_FP32_PEAK_TFLOPS, "unit": "TFLOP/s",

@@ -211,8 +211,8 @@ int rrc_degeneracy_count_masked(int32_t n, const uint8_t* mask, const int32_t* t
  * exist.  Supported calls: rrc_fftcorr, rrc_xengine (dot-product kernel),
  * rrc_omnical, the info/workspace queries, and with RRC_INIT_GAINS (the
  * solve starts from the caller's gains, e.g. the previous integration's)
- * rrc_solve (its d_work is then required) and rrc_run; otherwise those two,
- * and rrc_run_static, rrc_chisq_*, rrc_plan_tune and batches, return
+ * rrc_solve (its d_work is then required), rrc_run and rrc_plan_tune;
+ * otherwise those, and rrc_run_static, rrc_chisq_* and batches, return
  * RRC_ENOTIMPL.  Device calls first rebuild the plan's mask, pair and lag
  * tables in d_work from the mask bits the plan passes by value (two small
  * kernels), so the plan still owns no device memory.  Limits as for
@@ -248,6 +248,14 @@ int rrc_plan_set_order(rrc_plan* plan, int32_t order);
  * RRC_XENG_MFMA: int8 matrix-core tiles over windows covering the selected
  *   diagonals (RRC_ENOTIMPL if the selection's cover fits none of its
  *   instantiations).  Both are exact; V^reduced is identical bit for bit. */
+/* Padded spatial FFT size M of the FFT-correlator (Sec. 1; any M >= 2n - 1
+ * gives the same lags): the default is the next power of two >= 2n; 48 =
+ * 3 x 16 (one radix-3 step in the register FFT) is accepted for grids with
+ * 2n - 1 <= 48 whose default is larger (17 <= n <= 24), (48/64)^2 of the
+ * grid points.  V^unique differs only by FP32 rounding.  RRC_EINVAL for
+ * another size. */
+int rrc_plan_set_fft_size(rrc_plan* plan, int32_t fft_size);
+
 #define RRC_XENG_AUTO 0
 #define RRC_XENG_DOT  1
 #define RRC_XENG_MFMA 2
@@ -438,7 +446,8 @@ int rrc_chisq_full(int32_t n, int32_t n_units, void* stream, const void* d_vfull
  * length, i.e. fewer workgroups each integrating more samples and fewer
  * partial grids for the finish), the branch order (rrc_plan_set_order) and,
  * for 4-bit plans whose cover fits, the X-engine kernel
- * (rrc_plan_set_xengine).  Each candidate runs the whole path (rrc_run,
+ * (rrc_plan_set_xengine), and the FFT size (rrc_plan_set_fft_size) where a
+ * second one fits.  Each candidate runs the whole path (rrc_run,
  * PIPELINED, on `io`, whose contents it overwrites) once to warm up and
  * three times under HIP events on `stream`; the fastest is applied to the
  * plan.  cache_path (may be NULL): a text file of past choices, one line
@@ -454,6 +463,7 @@ typedef struct {
     int32_t xengine;    /* RRC_XENG_*                               */
     float   ms_per_run; /* the chosen candidate's time per rrc_run */
     int32_t from_cache;
+    int32_t fft_size;   /* M (rrc_plan_set_fft_size)                */
 } rrc_tune;
 int rrc_plan_tune(rrc_plan* plan, void* stream, const rrc_io* io, const char* cache_path, rrc_tune* out);
 

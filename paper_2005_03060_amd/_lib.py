@@ -47,7 +47,8 @@ EXPORTS = ("rrc_default_opts", "rrc_select_subset", "rrc_degeneracy_count", "rrc
            "rrc_plan_set_order", "rrc_wall_clock_hz", "rrc_run_static", "rrc_plan_set_xengine",
            "rrc_gain_variance", "rrc_omnical", "rrc_lowcad_schedule", "rrc_lowcad_xengine",
            "rrc_lowcad_solve", "rrc_plan_tune", "rrc_hex_mask", "rrc_select_subset_masked",
-           "rrc_degeneracy_count_masked", "rrc_plan_create_masked", "rrc_chisq_full")
+           "rrc_degeneracy_count_masked", "rrc_plan_create_masked", "rrc_chisq_full",
+           "rrc_plan_set_fft_size")
 
 
 class SolverOpts(C.Structure):
@@ -74,7 +75,7 @@ class RunIO(C.Structure):
 
 class Tune(C.Structure):
     _fields_ = [("fft_chunk_factor", C.c_int32), ("order", C.c_int32), ("xengine", C.c_int32),
-                ("ms_per_run", C.c_float), ("from_cache", C.c_int32)]
+                ("ms_per_run", C.c_float), ("from_cache", C.c_int32), ("fft_size", C.c_int32)]
 
 
 class RRCError(RuntimeError):
@@ -124,6 +125,7 @@ def load_library() -> C.CDLL:
         "rrc_omnical": (C.c_int, [vp, vp, vp, vp, i32, C.c_float, i32, vp, vp, pf, vp, vp, pf, vp]),
         "rrc_hex_mask": (C.c_int, [i32, vp, i32, pi32, pi32]),
         "rrc_chisq_full": (C.c_int, [i32, i32, vp, vp, vp, vp, vp, vp]),
+        "rrc_plan_set_fft_size": (C.c_int, [vp, i32]),
         "rrc_select_subset_masked": (C.c_int, [i32, vp, i32, C.c_double, C.c_double, pi32, i32, pi32, pi32]),
         "rrc_degeneracy_count_masked": (C.c_int, [i32, vp, pi32, i32, pi32, pi32]),
         "rrc_plan_create_masked": (C.c_int, [C.POINTER(vp), i32, vp, pi32, i32, i32, i32, i32,

@@ -380,8 +380,8 @@ class Plan:
     def tune(self, volt: torch.Tensor, gains_in: torch.Tensor, out: Optional[Dict[str, torch.Tensor]] = None,
              cache_path: Optional[str] = None) -> Dict[str, float]:
         """rrc_plan_tune: pick the fastest launch parameters of the pipelined
-        run (FFT time chunk, branch order, 4-bit X-engine kernel); `out` is
-        overwritten.  Returns the choice."""
+        run (FFT time chunk, branch order, 4-bit X-engine kernel, FFT size);
+        `out` is overwritten.  Returns the choice."""
         if out is None:
             out = self.alloc_outputs(volt.device)
         io = self.run_io(volt, gains_in, None, out)
@@ -399,6 +399,14 @@ class Plan:
         """X-engine kernel of a 4-bit plan: "auto", "dot" or "mfma"."""
         code = {"auto": L.RRC_XENG_AUTO, "dot": L.RRC_XENG_DOT, "mfma": L.RRC_XENG_MFMA}[kind]
         L.check(self._lib.rrc_plan_set_xengine(self._h, code), "rrc_plan_set_xengine")
+
+    def set_fft_size(self, m: int) -> None:
+        """Padded FFT size of the FFT-correlator: the default power of two, or
+        48 for grids with 2n - 1 <= 48 whose default is larger."""
+        L.check(self._lib.rrc_plan_set_fft_size(self._h, int(m)), "rrc_plan_set_fft_size")
+        info = L.PlanInfo()
+        L.check(self._lib.rrc_plan_get_info(self._h, C.byref(info)), "rrc_plan_get_info")
+        self.info = {f: getattr(info, f) for f, _ in L.PlanInfo._fields_}
 
     def prepare(self) -> None:
         """Bind the plan to the current device and make its device resources."""

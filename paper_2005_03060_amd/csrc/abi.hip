@@ -27,6 +27,7 @@ struct rrc_plan {
     // FFT-correlator
     int fft_tchunk, fft_nchunk;
     int fft_tchunk0;                 // the default chunk (the workspace is sized for it)
+    int M_default = 0;               // the power of two the workspace is sized for
     // X-engine; 4-bit plans whose window cover an int8 matrix-core
     // instantiation holds use it (x_mf: its launch fields) unless the
     // caller selects the dot-product kernel
@@ -421,6 +422,7 @@ static int plan_create(rrc_plan** out, int32_t n, const int32_t* types_xy, int32
     int M = 16;                      // smallest transform the kernels instantiate
     while (M < 2 * n) M *= 2;
     p->M = M;
+    p->M_default = M;
     p->nlag = 2 * n * (n - 1);
     p->U = n_units;
     p->T = n_time;
@@ -638,6 +640,22 @@ void rrc_plan_destroy(rrc_plan* p) {
 int rrc_plan_set_order(rrc_plan* p, int32_t order) {
     if (!p || (order != RRC_ORDER_XENG_FIRST && order != RRC_ORDER_FFT_FIRST)) return RRC_EINVAL;
     p->order = order;
+    return RRC_OK;
+}
+
+// FFT sizes of a plan: the default power of two, or 48 = 3 x 16 when the
+// grid's lags fit it (2n - 1 <= 48) and it is smaller.
+static bool fft_size_ok(const rrc_plan* p, int M) {
+    if (M == p->M_default) return true;
+    return M == 48 && 2 * p->sel.n - 1 <= 48 && M < p->M_default;
+}
+
+int rrc_plan_set_fft_size(rrc_plan* p, int32_t M) {
+    if (!p || !fft_size_ok(p, M)) return RRC_EINVAL;
+    // both sizes step the same number of samples, so the default chunking
+    // (and the workspace sized for the default size) holds
+    if (rrc::fft_samples_per_step_for(M) != rrc::fft_samples_per_step_for(p->M_default)) return RRC_ENOTIMPL;
+    p->M = M;
     return RRC_OK;
 }
 
@@ -1005,12 +1023,22 @@ static std::string tune_key(const rrc_plan* p) {
     for (int t = 0; t < p->sel.K; ++t)
         key += std::to_string(p->sel.dx[t]) + ":" + std::to_string(p->sel.dy[t]) + (t + 1 < p->sel.K ? "," : "");
     key += " U=" + std::to_string(p->U) + " T=" + std::to_string(p->T) + " dtype=" + std::to_string(p->dtype);
+    if (p->masked) {   // FNV-1a of the mask bits
+        uint64_t h = 1469598103934665603ull;
+        for (int w = 0; w < rrc::kMaskWords; ++w) {
+            h ^= p->mask_bits[w];
+            h *= 1099511628211ull;
+        }
+        char buf[32];
+        std::snprintf(buf, sizeof(buf), " mask=%016llx", (unsigned long long)h);
+        key += buf;
+    }
     return key;
 }
 
 int rrc_plan_tune(rrc_plan* p, void* stream, const rrc_io* io, const char* cache_path, rrc_tune* out) {
     if (!p || !io || !out || !io->d_gains_in) return RRC_EINVAL;
-    if (p->masked) return RRC_ENOTIMPL;
+    if (p->masked && p->opts.init_mode != RRC_INIT_GAINS) return RRC_ENOTIMPL;   // as rrc_run
     int rc = prepare(p);
     if (rc != RRC_OK) return rc;
     const std::string key = tune_key(p);
@@ -1021,14 +1049,15 @@ int rrc_plan_tune(rrc_plan* p, void* stream, const rrc_io* io, const char* cache
         while (std::getline(f, line)) {
             const size_t bar = line.find(" | ");
             if (bar == std::string::npos || line.substr(0, bar) != key) continue;
-            int fa = 0, ord = 0, xk = 0;
+            int fa = 0, ord = 0, xk = 0, mf = 0;
             float ms = 0.f;
-            if (std::sscanf(line.c_str() + bar + 3, "chunk_factor=%d order=%d xengine=%d ms=%f", &fa, &ord, &xk,
-                            &ms) == 4 && fa >= 1) {
+            if (std::sscanf(line.c_str() + bar + 3, "chunk_factor=%d order=%d xengine=%d fft_size=%d ms=%f", &fa, &ord,
+                            &xk, &mf, &ms) == 5 && fa >= 1 && fft_size_ok(p, mf)) {
+                p->M = mf;
                 set_fft_chunk_factor(p, fa);
                 p->order = ord;
                 p->x_kind = xk;
-                *out = rrc_tune{fa, ord, xk, ms, 1};
+                *out = rrc_tune{fa, ord, xk, ms, 1, mf};
                 return RRC_OK;
             }
         }
@@ -1041,11 +1070,16 @@ int rrc_plan_tune(rrc_plan* p, void* stream, const rrc_io* io, const char* cache
     }
     const int xkinds[2] = {RRC_XENG_DOT, RRC_XENG_MFMA};
     const int nx = (p->dtype == RRC_CI4 && p->x_mf_ok) ? 2 : 1;
-    rrc_tune best{1, RRC_ORDER_XENG_FIRST, RRC_XENG_AUTO, 1e30f, 0};
+    const int msizes[2] = {p->M_default, 48};
+    const int nm = (fft_size_ok(p, 48) && p->M_default != 48 &&
+                    rrc::fft_samples_per_step_for(48) == rrc::fft_samples_per_step_for(p->M_default)) ? 2 : 1;
+    rrc_tune best{1, RRC_ORDER_XENG_FIRST, RRC_XENG_AUTO, 1e30f, 0, p->M_default};
+    for (int mi = 0; mi < nm && rc == RRC_OK; ++mi)
     for (int fa = 1; fa <= 4 && rc == RRC_OK; fa *= 2) {
         if (fa > 1 && p->fft_tchunk0 * (fa / 2) >= p->T) break;       // no fewer chunks left
         for (int ord = RRC_ORDER_XENG_FIRST; ord <= RRC_ORDER_FFT_FIRST && rc == RRC_OK; ++ord)
             for (int xi = 0; xi < nx && rc == RRC_OK; ++xi) {
+                p->M = msizes[mi];
                 set_fft_chunk_factor(p, fa);
                 p->order = ord;
                 p->x_kind = nx > 1 ? xkinds[xi] : RRC_XENG_AUTO;
@@ -1059,11 +1093,12 @@ int rrc_plan_tune(rrc_plan* p, void* stream, const rrc_io* io, const char* cache
                                      hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
                     rc = RRC_EDEVICE;
                 ms /= 3.f;
-                if (rc == RRC_OK && ms < best.ms_per_run) best = rrc_tune{fa, ord, p->x_kind, ms, 0};
+                if (rc == RRC_OK && ms < best.ms_per_run) best = rrc_tune{fa, ord, p->x_kind, ms, 0, p->M};
             }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    p->M = best.fft_size;
     set_fft_chunk_factor(p, best.fft_chunk_factor);
     p->order = best.order;
     p->x_kind = best.xengine;
@@ -1072,8 +1107,8 @@ int rrc_plan_tune(rrc_plan* p, void* stream, const rrc_io* io, const char* cache
     if (cache_path) {
         std::ofstream f(cache_path, std::ios::app);
         char buf[160];
-        std::snprintf(buf, sizeof(buf), " | chunk_factor=%d order=%d xengine=%d ms=%.4f", best.fft_chunk_factor,
-                      best.order, best.xengine, best.ms_per_run);
+        std::snprintf(buf, sizeof(buf), " | chunk_factor=%d order=%d xengine=%d fft_size=%d ms=%.4f",
+                      best.fft_chunk_factor, best.order, best.xengine, best.fft_size, best.ms_per_run);
         f << key << buf << "\n";
     }
     return RRC_OK;

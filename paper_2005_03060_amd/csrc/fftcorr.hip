@@ -29,12 +29,16 @@ namespace rrc {
 // S samples per step; BOTH: one work-item computes both halves of a row,
 // so the row is loaded and divided by the gains once
 template <int M> struct FftCfg;
-template <> struct FftCfg<16>  { static constexpr int S = 16; static constexpr bool BOTH = true; };
-template <> struct FftCfg<32>  { static constexpr int S = 8; static constexpr bool BOTH = true; };
-template <> struct FftCfg<64>  { static constexpr int S = 4; static constexpr bool BOTH = false; };
+// NT: work-items of the M <= 64 kernel, a multiple of 2M (each half of a
+// column transform spread over NT / (2M) work-items); M = 48 = 3 x 16 uses
+// the radix-3 register FFT.
+template <> struct FftCfg<16>  { static constexpr int S = 16; static constexpr bool BOTH = true; static constexpr int NT = 256; };
+template <> struct FftCfg<32>  { static constexpr int S = 8; static constexpr bool BOTH = true; static constexpr int NT = 256; };
+template <> struct FftCfg<48>  { static constexpr int S = 4; static constexpr bool BOTH = true; static constexpr int NT = 192; };
+template <> struct FftCfg<64>  { static constexpr int S = 4; static constexpr bool BOTH = false; static constexpr int NT = 256; };
 template <> struct FftCfg<128> { static constexpr int S = 2; };   // k_fftcorr_q
 
-constexpr int kFftThreads = 256;
+constexpr int kFftThreads = 256;   // the finish kernels
 
 template <int M>
 constexpr int fft_samples_per_step() { return FftCfg<M>::S; }
@@ -137,8 +141,8 @@ __device__ __forceinline__ void inverse_to_lags(float2* lds, const float* __rest
         fft_dif<H>(z);
 #pragma unroll
         for (int f = 0; f < H; ++f) {
-            const float2 zf = z[bitrev<H>(f)];
-            const float2 zc = cconj(z[bitrev<H>((H - f) & (H - 1))]);
+            const float2 zf = z[index_of<H>(f)];
+            const float2 zc = cconj(z[index_of<H>((H - f) % H)]);
             const float2 ev = make_float2(0.5f * (zf.x + zc.x), 0.5f * (zf.y + zc.y));
             const float2 od = make_float2(0.5f * (zf.y - zc.y), -0.5f * (zf.x - zc.x));
             const float2 wod = twmul<M>(od, f);
@@ -156,7 +160,7 @@ __device__ __forceinline__ void inverse_to_lags(float2* lds, const float* __rest
             for (int k = 0; k < H; ++k) x[k] = A[(2 * k + h) * RS + f];
             fft_dif<H>(x);
 #pragma unroll
-            for (int r = 0; r < H; ++r) eo[(h * M + f) * H + bitrev<H>(r)] = x[r];
+            for (int r = 0; r < H; ++r) eo[(h * M + f) * H + freq_of<H>(r)] = x[r];
         }
     }
     __syncthreads();
@@ -195,7 +199,7 @@ __device__ __forceinline__ void row_half(float2 (&x)[M / 2], float2* out) {
     }
     fft_dif<H>(x);
 #pragma unroll
-    for (int r = 0; r < H; ++r) out[2 * bitrev<H>(r) + ODD] = x[r];
+    for (int r = 0; r < H; ++r) out[2 * freq_of<H>(r) + ODD] = x[r];
 }
 
 // Column stage: add the powers of the half's outputs (in bit-reversed
@@ -216,14 +220,14 @@ __device__ __forceinline__ void col_half(float2 (&x)[M / 2], float (&acc)[M / 2]
 // instructions; each lane reads its own row, so every load touches as many
 // cache lines as there are lanes).
 template <int M, bool CI4, bool W2 = false>
-__global__ __launch_bounds__(kFftThreads) void k_fftcorr(const void* __restrict__ volt,
+__global__ __launch_bounds__(FftCfg<M>::NT) void k_fftcorr(const void* __restrict__ volt,
                                                          const float2* __restrict__ gains,
                                                          float* __restrict__ ppart, int n, int T,
                                                          int tchunk, int nchunk,
                                                          const uint8_t* __restrict__ live) {
     constexpr int H = M / 2;
     constexpr int S = FftCfg<M>::S;
-    constexpr int NT = kFftThreads;
+    constexpr int NT = FftCfg<M>::NT;
     constexpr int RS = M + 1;                     // padded LDS row stride (complex)
     constexpr bool BOTH = FftCfg<M>::BOTH;
     constexpr int CPT = 2 * M * S / NT;           // column tasks per thread (1 or 2)
@@ -372,7 +376,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fftcorr(const void* __restrict_
     for (int gidx = 0; gidx < G; ++gidx) {
         if (cs0 == gidx) {
 #pragma unroll
-            for (int r = 0; r < H; ++r) pl[(2 * bitrev<H>(r) + ch) * M + cu] += acc[r];
+            for (int r = 0; r < H; ++r) pl[(2 * freq_of<H>(r) + ch) * M + cu] += acc[r];
         }
         __syncthreads();
     }
@@ -755,10 +759,10 @@ static hipError_t launch_fft_m(const FftLaunch& L, hipStream_t st) {
     } else {
         dim3 grid1(L.nchunk, L.n_units);
         if (!CI4 && L.n % 2 == 0)
-            hipLaunchKernelGGL((k_fftcorr<M, CI4, !CI4>), grid1, dim3(kFftThreads), 0, st, L.volt, L.gains,
+            hipLaunchKernelGGL((k_fftcorr<M, CI4, !CI4>), grid1, dim3(FftCfg<M>::NT), 0, st, L.volt, L.gains,
                                L.ppart, L.n, L.T, L.tchunk, L.nchunk, L.mt.live);
         else
-            hipLaunchKernelGGL((k_fftcorr<M, CI4, false>), grid1, dim3(kFftThreads), 0, st, L.volt, L.gains,
+            hipLaunchKernelGGL((k_fftcorr<M, CI4, false>), grid1, dim3(FftCfg<M>::NT), 0, st, L.volt, L.gains,
                                L.ppart, L.n, L.T, L.tchunk, L.nchunk, L.mt.live);
     }
     hipError_t e = hipGetLastError();
@@ -777,6 +781,7 @@ int fft_samples_per_step_for(int M) {
     switch (M) {
         case 16: return fft_samples_per_step<16>();
         case 32: return fft_samples_per_step<32>();
+        case 48: return fft_samples_per_step<48>();
         case 64: return fft_samples_per_step<64>();
         case 128: return fft_samples_per_step<128>();
         default: return 0;
@@ -787,6 +792,7 @@ hipError_t launch_fftcorr(const FftLaunch& L, hipStream_t st) {
     switch (L.M) {
         case 16: return L.ci4 ? launch_fft_m<16, true>(L, st) : launch_fft_m<16, false>(L, st);
         case 32: return L.ci4 ? launch_fft_m<32, true>(L, st) : launch_fft_m<32, false>(L, st);
+        case 48: return L.ci4 ? launch_fft_m<48, true>(L, st) : launch_fft_m<48, false>(L, st);
         case 64: return L.ci4 ? launch_fft_m<64, true>(L, st) : launch_fft_m<64, false>(L, st);
         case 128: return L.ci4 ? launch_fft_m<128, true>(L, st) : launch_fft_m<128, false>(L, st);
         default: return hipErrorInvalidValue;

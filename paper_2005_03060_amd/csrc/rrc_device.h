@@ -124,8 +124,30 @@ RRC_HD float2 twmul(float2 d, int k) {
 // three general multiplies where two radix-2 stages take four.  Same
 // positions as the radix-2 form, so the same output order.  An odd number
 // of stages ends with one radix-2 stage (no twiddles).
+// A length with one factor 3 (L = 3 P, P a power of two: 12, 24, 48) takes
+// one radix-3 decimation-in-frequency step first: for j < P, with
+// w = e^{-2 pi i / 3}, y_r(j) = x_j + w^r x_{j+P} + w^2r x_{j+2P} times
+// w_L^{j r}, and X[3 m + r] is the P-point FFT of y_r; so element r P + p
+// holds frequency 3 bitrev_P(p) + r (freq_of).
 template <int L>
 RRC_HD void fft_dif(float2 (&a)[L]) {
+    if constexpr (L % 3 == 0) {
+        constexpr int P = L / 3;
+        constexpr float h3 = 0.86602540378443864676f;   // sqrt(3) / 2
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+            const float2 a0 = a[j], a1 = a[j + P], a2 = a[j + 2 * P];
+            const float2 sm = cadd(a1, a2), df = csub(a1, a2);
+            const float2 t = make_float2(fmaf(-0.5f, sm.x, a0.x), fmaf(-0.5f, sm.y, a0.y));
+            const float2 e = make_float2(h3 * df.y, -h3 * df.x);        // -i (sqrt3/2)(x_{j+P} - x_{j+2P})
+            a[j] = cadd(a0, sm);
+            a[j + P] = twmul<L>(cadd(t, e), j);
+            a[j + 2 * P] = twmul<L>(csub(t, e), 2 * j);
+        }
+#pragma unroll
+        for (int r = 0; r < 3; ++r) fft_dif<P>(*reinterpret_cast<float2(*)[P]>(&a[r * P]));
+        return;
+    }
 #pragma unroll
     for (int h = L / 2; h >= 2; h >>= 2) {
         const int q = h / 2;
@@ -161,6 +183,20 @@ constexpr int bitrev(int r) {
     for (int m = 1, k = L >> 1; m < L; m <<= 1, k >>= 1)
         if (r & m) out |= k;
     return out;
+}
+
+// Frequency held by element r of fft_dif<L>'s output, and the element that
+// holds frequency f (bit reversal for a power of two; for L = 3 P, element
+// r' P + p holds 3 bitrev_P(p) + r').
+template <int L>
+constexpr int freq_of(int r) {
+    if constexpr (L % 3 == 0) return 3 * bitrev<L / 3>(r % (L / 3)) + r / (L / 3);
+    else return bitrev<L>(r);
+}
+template <int L>
+constexpr int index_of(int f) {
+    if constexpr (L % 3 == 0) return (f % 3) * (L / 3) + bitrev<L / 3>(f / 3);
+    else return bitrev<L>(f);
 }
 
 constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v >> 1); }

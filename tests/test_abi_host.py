@@ -267,3 +267,22 @@ def test_masked_plan_errors():
     with pytest.raises(rrc.RRCError) as e:
         rrc.Plan(n, [(1, 0), (-1, 1), (0, 1)], 1, 16, dtype="ci4", mask=m)
     assert e.value.code == _lib.RRC_ENOTIMPL
+
+
+def test_fft_size_choices():
+    # M = 48 only where 2n - 1 <= 48 and the default power of two is larger
+    for n, ok in ((16, False), (17, True), (20, True), (24, True), (25, False), (32, False)):
+        types, _ = rrc.select_subset(n)
+        p = rrc.Plan(n, types, 1, 64)
+        default = p.info["fft_size"]
+        if ok:
+            p.set_fft_size(48)
+            assert p.info["fft_size"] == 48
+            p.set_fft_size(default)
+            assert p.info["fft_size"] == default
+        else:
+            with pytest.raises(rrc.RRCError) as e:
+                p.set_fft_size(48)
+            assert e.value.code == _lib.RRC_EINVAL
+        with pytest.raises(rrc.RRCError):
+            p.set_fft_size(96)

@@ -62,6 +62,30 @@ def test_hex_fftcorr_matches_oracle(rrc, side, U, T):
         assert abs(va[u] - aref) <= 1e-5 * aref
 
 
+@pytest.mark.parametrize("side,U,T", [(11, 2, 256), (9, 1, 100), (12, 1, 64)])
+def test_hex_fftcorr_m48_matches_oracle(rrc, side, U, T):
+    # hexagons with 2 side - 1 <= 24 grid rows fit the 48-point transform
+    n, mask, pos, idx = _hex(rrc, side)
+    types, _ = rrc.select_subset_masked(n, mask, "hex")
+    plan = rrc.Plan(n, types, U, T, mask=mask)
+    plan.set_fft_size(48)
+    v, g = make_units(n, U, T)
+    g64 = g.astype(np.complex64)
+    vu, va = plan.fftcorr(torch.from_numpy(v).to(DEV), torch.from_numpy(g64).to(DEV))
+    vu, va = vu.cpu().numpy(), va.cpu().numpy()
+    lags = OC.canonical_lags(n)
+    empty = np.array([len(OG.PositionIndex(pos).pairs_of(dx, dy)[0]) == 0 for dx, dy in lags])
+    for u in range(U):
+        vf = OC.fx_correlate(v[u][:, idx].astype(np.complex128))
+        gl = g64[u][idx].astype(np.complex128)
+        ref = OC.redundant_average(vf, gl, pos, lags)
+        err = rel_l2(vu[u], ref)
+        print(f"M=48 hex side {side} (n={n}) T={T} unit {u}: V^unique rel L2 {err:.2e}")
+        assert err <= TOL_VUNIQUE
+        assert np.all(vu[u][empty] == 0)
+        assert abs(va[u] - OC.calibrated_auto(vf, gl)) <= 1e-5 * OC.calibrated_auto(vf, gl)
+
+
 @pytest.mark.parametrize("side,U,T", [(3, 2, 300), (4, 2, 1024), (11, 1, 512)])
 def test_hex_xengine_float_matches_oracle(rrc, side, U, T):
     n, mask, pos, idx = _hex(rrc, side)

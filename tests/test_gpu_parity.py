@@ -59,6 +59,50 @@ def test_fftcorr_ci4_matches_oracle(rrc, n, U, T):
         assert abs(va[u] - aref) <= 1e-5 * aref
 
 
+@pytest.mark.parametrize("n,U,T,dtype", [(17, 2, 131, "c64"), (20, 1, 64, "c64"), (24, 2, 200, "c64"),
+                                         (23, 1, 1, "c64"), (20, 2, 77, "ci4"), (24, 1, 256, "ci4")])
+def test_fftcorr_m48_matches_oracle(rrc, n, U, T, dtype):
+    # the mixed-radix (3 x 16) padded transform: 2n - 1 <= 48 keeps the
+    # circular correlation free of wrap-around, as at the default 64
+    if dtype == "ci4":
+        b, re, im, g = make_ci4_units(n, U, T)
+        vd = torch.from_numpy(b).to(DEV)
+        v = re.astype(np.complex128) + 1j * im.astype(np.complex128)
+    else:
+        v, g = make_units(n, U, T)
+        vd = torch.from_numpy(v).to(DEV)
+    plan, _ = _plan(rrc, n, U, T, dtype=dtype)
+    assert plan.info["fft_size"] == 64
+    plan.set_fft_size(48)
+    assert plan.info["fft_size"] == 48
+    g64 = g.astype(np.complex64)
+    vu, va = plan.fftcorr(vd, torch.from_numpy(g64).to(DEV))
+    vu, va = vu.cpu().numpy(), va.cpu().numpy()
+    for u in range(U):
+        ref, aref = oracle_vunique(v[u], g64[u].astype(np.complex128), n)
+        err = rel_l2(vu[u], ref)
+        print(f"M=48 {dtype} n={n} T={T} unit {u}: V^unique rel L2 {err:.2e}")
+        assert err <= TOL_VUNIQUE
+        assert abs(va[u] - aref) <= 1e-5 * aref
+
+
+def test_fftcorr_m48_single_mode_closed_form(rrc):
+    # a sky mode on the 48-point frequency grid, unit gains, no noise:
+    # V(d) = <|s|^2> exp(-2 pi i k0.d / 48)
+    n, T, m = 24, 40, 48
+    rng = np.random.default_rng(48)
+    s = (rng.standard_normal(T) + 1j * rng.standard_normal(T))
+    k0 = np.array([5, 29])
+    pos = OG.square_positions(n)
+    v = (s[:, None] * np.exp(-2j * np.pi * (pos @ k0) / m)[None, :]).astype(np.complex64)[None]
+    plan, _ = _plan(rrc, n, 1, T)
+    plan.set_fft_size(48)
+    vu, _ = plan.fftcorr(torch.from_numpy(v).to(DEV), torch.ones((1, n * n), dtype=torch.complex64, device=DEV))
+    p = np.mean(np.abs(v[0, :, 0].astype(np.complex128)) ** 2)
+    ref = np.array([p * np.exp(-2j * np.pi * (k0 @ np.array(d)) / m) for d in OC.canonical_lags(n)])
+    assert rel_l2(vu.cpu().numpy()[0], ref) <= TOL_VUNIQUE
+
+
 def test_fftcorr_single_mode_closed_form(rrc):
     # one sky mode, no noise, unit gains: V(d) = <|s|^2> exp(-2 pi i k0.d / M)
     n, T, m = 16, 64, 32
@@ -616,6 +660,27 @@ def test_tuner_choice_cached_and_results_unchanged(rrc, dtype, tmp_path):
     plan2, _ = _plan(rrc, n, U, T, dtype=dtype)
     t2 = plan2.tune(vd, gin, cache_path=cache)
     assert t2["from_cache"] == 1
-    for k in ("fft_chunk_factor", "order", "xengine"):
+    for k in ("fft_chunk_factor", "order", "xengine", "fft_size"):
         assert t2[k] == t1[k], k
     print(f"{dtype}: tuned {t1}")
+
+
+def test_tuner_weighs_fft_sizes_and_keeps_results(rrc, tmp_path):
+    # a 24 x 24 grid: the tuner times the 48- and the 64-point transform
+    n, U, T = 24, 4, 1024
+    v, g = make_units(n, U, T)
+    vd = torch.from_numpy(v).to(DEV)
+    gin = torch.from_numpy(g.astype(np.complex64)).to(DEV)
+    plan, _ = _plan(rrc, n, U, T)
+    ref = plan.run(vd, gains_in=gin, mode="pipelined")
+    t1 = plan.tune(vd, gin, cache_path=str(tmp_path / "tune.txt"))
+    assert t1["fft_size"] in (48, 64)
+    got = plan.run(vd, gains_in=gin, mode="pipelined", out=plan.alloc_outputs(DEV))
+    torch.cuda.synchronize()
+    for key in ("vred", "gains", "vmodel", "chisq", "niter", "status"):
+        assert torch.equal(got[key], ref[key]), key
+    vu = got["vunique"].cpu().numpy()
+    for u in range(U):
+        want, _ = oracle_vunique(v[u], g[u].astype(np.complex64).astype(np.complex128), n)
+        assert rel_l2(vu[u], want) <= TOL_VUNIQUE
+    print(f"n=24: tuned {t1}")
