@@ -48,10 +48,9 @@ EXTRA_WORKLOAD = "g32_c256_t2048"
 
 
 def pad_size(n: int) -> int:
-    m = 1
-    while m < 2 * n:
-        m *= 2
-    return m
+    """The plan's default FFT size: the smallest of 16, 32, 48, 64, 96, 128
+    with M >= 2n - 1."""
+    return min(m for m in (16, 32, 48, 64, 96, 128) if m >= 2 * n - 1)
 
 
 def fft_flops_per_sample(n: int, m: int = 0) -> float:
@@ -61,16 +60,20 @@ def fft_flops_per_sample(n: int, m: int = 0) -> float:
     column (M) transform of the padded M-point FFT costs 4.25 M log2 M flops
     less its first (trivial, half-zero) stage, i.e. 4.25 M (log2 M - 1);
     |E|^2 accumulation 4 flops per grid point; gain application 6 flops per
-    antenna.  M is the default padded size (the next power of two >= 2n):
-    at n = 16, 32, 64 this gives 32.5 MF, 314 MF and 2.94 GF per unit of
-    1024, 2048 and 4096 samples.  `m` = 48 counts the mixed-radix transform
-    the plan can use instead of 64 when 2n - 1 <= 48.
+    antenna.  M is the plan's FFT size (by default the smallest with
+    M >= 2n - 1): at n = 16, 32, 64 this gives 32.5 MF, 314 MF and 2.94 GF
+    per unit of 1024, 2048 and 4096 samples.  The mixed-radix sizes count
+    the transforms the kernels run.
     """
     m = m or pad_size(n)
     if m == 48:
         # two 24-point halves, each a radix-3 step (8 butterflies of 30
         # flops) and three 8-point radix-2^2 transforms
         per = 2 * (8 * 30 + 3 * 4.25 * 8 * 3)
+    elif m == 96:
+        # three 32-point transforms and their folded inputs: a twiddle on
+        # each of the 96 inputs, a partner term on 16 per third
+        per = 3 * 4.25 * 32 * 5 + 3 * 32 * 6 + 3 * 16 * 8
     else:
         per = 4.25 * m * (math.log2(m) - 1)
     return (n + m) * per + 4 * m * m + 6 * n * n
@@ -494,7 +497,7 @@ def measure(w, args, rrc, dev, with_oracle):
     import torch
     serial_ms = time_fn(lambda: run_lane(S["lanes"][0]), args.steps)
     stages = stage_times(S, w, max(3, min(args.steps, 20)))
-    flops = sum(fft_flops_per_sample(a["n"]) * w.n_time * w.n_chan for a in S["arrays"])
+    flops = sum(fft_flops_per_sample(a["n"], a["plan"].info["fft_size"]) * w.n_time * w.n_chan for a in S["arrays"])
     vbytes = sum((1.0 if w.ci4 else 8.0) * a["n"] ** 2 * w.n_time * w.n_chan for a in S["arrays"])
     fft_s = stages["fftcorr"] * 1e-3
     x_s = stages["xengine"] * 1e-3
@@ -585,8 +588,6 @@ def measure_hex(side, n_chan, n_time, args, rrc, dev):
     volt, g = device_voltages(w, 0, dev)
     types, npairs = rrc.select_subset_masked(n, mask, "hex")
     plan = rrc.Plan(n, types, n_chan, n_time, mask=mask, init_mode="gains")
-    if 2 * n - 1 <= 48 < pad_size(n):
-        plan.set_fft_size(48)         # the faster transform for grids up to 24 x 24
     m = plan.info["fft_size"]
     plan.workspace(dev)
     gin = torch.from_numpy(g.astype(np.complex64)).to(dev)

@@ -92,7 +92,7 @@ extern "C" {
 
 /* Limits of this build. */
 #define RRC_MAX_TYPES 16     /* K, selected baseline-types                    */
-#define RRC_MAX_GRID  64     /* n; the padded FFT size is M = max(16, 2^ceil(log2 2n)) */
+#define RRC_MAX_GRID  64     /* n; the padded FFT size M <= 128 (rrc_plan_set_fft_size) */
 
 typedef struct rrc_plan rrc_plan;
 
@@ -249,11 +249,13 @@ int rrc_plan_set_order(rrc_plan* plan, int32_t order);
  *   diagonals (RRC_ENOTIMPL if the selection's cover fits none of its
  *   instantiations).  Both are exact; V^reduced is identical bit for bit. */
 /* Padded spatial FFT size M of the FFT-correlator (Sec. 1; any M >= 2n - 1
- * gives the same lags): the default is the next power of two >= 2n; 48 =
- * 3 x 16 (one radix-3 step in the register FFT) is accepted for grids with
- * 2n - 1 <= 48 whose default is larger (17 <= n <= 24), (48/64)^2 of the
- * grid points.  V^unique differs only by FP32 rounding.  RRC_EINVAL for
- * another size. */
+ * gives the same lags, since the padding only keeps the circular
+ * correlation from wrapping).  The default is the smallest of 16, 32, 48,
+ * 64, 96, 128 with M >= 2n - 1: 48 = 3 x 16 for 17 <= n <= 24 and
+ * 96 = 3 x 32 for 33 <= n <= 48 (mixed radix), a power of two otherwise.
+ * Where the default is mixed radix, the next power of two (64 or 128) is
+ * accepted too; the workspace holds either.  V^unique differs between the
+ * two only by FP32 rounding.  RRC_EINVAL for any other size. */
 int rrc_plan_set_fft_size(rrc_plan* plan, int32_t fft_size);
 
 #define RRC_XENG_AUTO 0

@@ -27,7 +27,8 @@ struct rrc_plan {
     // FFT-correlator
     int fft_tchunk, fft_nchunk;
     int fft_tchunk0;                 // the default chunk (the workspace is sized for it)
-    int M_default = 0;               // the power of two the workspace is sized for
+    int M_default = 0;               // the smallest size whose lags do not wrap (see plan_create)
+    int M_alt = 0;                   // the next power of two when it differs, else 0
     // X-engine; 4-bit plans whose window cover an int8 matrix-core
     // instantiation holds use it (x_mf: its launch fields) unless the
     // caller selects the dot-product kernel
@@ -40,6 +41,7 @@ struct rrc_plan {
     size_t solve_lds_bytes;
     // workspace layout
     size_t off_fft, off_x, off_gcopy, ws_bytes;
+    size_t off_hinv = 0;             // 1/g table of the M = 96 kernel
     // pipelined run: the FFT-correlator forked after the X-engine (default)
     // or before it (RRC_ORDER_FFT_FIRST)
     int32_t order = RRC_ORDER_XENG_FIRST;
@@ -419,10 +421,18 @@ static int plan_create(rrc_plan** out, int32_t n, const int32_t* types_xy, int32
     }
     p->n_live = n_live;
     p->ref0 = ref0;
-    int M = 16;                      // smallest transform the kernels instantiate
-    while (M < 2 * n) M *= 2;
+    // FFT size: the smallest the kernels instantiate (16, 32, 48, 64, 96,
+    // 128) with M >= 2n - 1, so the lags -(n-1) .. n-1 never wrap round;
+    // the next power of two, where it differs, is the alternative a caller
+    // or the tuner may choose.  The workspace holds either.
+    int Mp = 16;
+    while (Mp < 2 * n) Mp *= 2;
+    int M = Mp;
+    for (const int c : {48, 96})
+        if (c >= 2 * n - 1 && c < M) M = c;
     p->M = M;
     p->M_default = M;
+    p->M_alt = M != Mp ? Mp : 0;
     p->nlag = 2 * n * (n - 1);
     p->U = n_units;
     p->T = n_time;
@@ -475,7 +485,11 @@ static int plan_create(rrc_plan** out, int32_t n, const int32_t* types_xy, int32
 
     size_t off = 0;
     p->off_fft = off;
-    off = align256(off + (size_t)n_units * p->fft_nchunk * M * M * sizeof(float));
+    off = align256(off + (size_t)n_units * p->fft_nchunk * Mp * Mp * sizeof(float));
+    if (M == 96) {
+        p->off_hinv = off;
+        off = align256(off + (size_t)n_units * 48 * 48 * 8);
+    }
     p->off_x = off;
     off = align256(off + (p->x_nchunk > 1 ? (size_t)n_units * p->x_nchunk * s.P * 8 : 0));
     p->off_gcopy = off;                      // copy of gains_in when it aliases gains_out
@@ -643,18 +657,15 @@ int rrc_plan_set_order(rrc_plan* p, int32_t order) {
     return RRC_OK;
 }
 
-// FFT sizes of a plan: the default power of two, or 48 = 3 x 16 when the
-// grid's lags fit it (2n - 1 <= 48) and it is smaller.
+// FFT sizes of a plan: the default, or the power of two beside it.  The
+// default's samples per step are a multiple of the alternative's, so its
+// time chunks suit both, and the workspace holds the larger grid.
 static bool fft_size_ok(const rrc_plan* p, int M) {
-    if (M == p->M_default) return true;
-    return M == 48 && 2 * p->sel.n - 1 <= 48 && M < p->M_default;
+    return M == p->M_default || (p->M_alt != 0 && M == p->M_alt);
 }
 
 int rrc_plan_set_fft_size(rrc_plan* p, int32_t M) {
     if (!p || !fft_size_ok(p, M)) return RRC_EINVAL;
-    // both sizes step the same number of samples, so the default chunking
-    // (and the workspace sized for the default size) holds
-    if (rrc::fft_samples_per_step_for(M) != rrc::fft_samples_per_step_for(p->M_default)) return RRC_ENOTIMPL;
     p->M = M;
     return RRC_OK;
 }
@@ -734,6 +745,7 @@ static int fftcorr_impl(rrc_plan* p, void* stream, const void* d_volt, const voi
     L.volt = d_volt;
     L.gains = reinterpret_cast<const float2*>(d_gains);
     L.ppart = reinterpret_cast<float*>(static_cast<char*>(d_work) + p->off_fft);
+    L.hinv = p->off_hinv ? reinterpret_cast<float2*>(static_cast<char*>(d_work) + p->off_hinv) : nullptr;
     L.vunique = reinterpret_cast<float2*>(d_vunique);
     L.vauto = d_vauto;
     const int rc = mask_tables(p, stream, d_work, L.mt, build);
@@ -1070,9 +1082,8 @@ int rrc_plan_tune(rrc_plan* p, void* stream, const rrc_io* io, const char* cache
     }
     const int xkinds[2] = {RRC_XENG_DOT, RRC_XENG_MFMA};
     const int nx = (p->dtype == RRC_CI4 && p->x_mf_ok) ? 2 : 1;
-    const int msizes[2] = {p->M_default, 48};
-    const int nm = (fft_size_ok(p, 48) && p->M_default != 48 &&
-                    rrc::fft_samples_per_step_for(48) == rrc::fft_samples_per_step_for(p->M_default)) ? 2 : 1;
+    const int msizes[2] = {p->M_default, p->M_alt};
+    const int nm = p->M_alt ? 2 : 1;
     rrc_tune best{1, RRC_ORDER_XENG_FIRST, RRC_XENG_AUTO, 1e30f, 0, p->M_default};
     for (int mi = 0; mi < nm && rc == RRC_OK; ++mi)
     for (int fa = 1; fa <= 4 && rc == RRC_OK; fa *= 2) {

@@ -36,6 +36,7 @@ template <> struct FftCfg<16>  { static constexpr int S = 16; static constexpr b
 template <> struct FftCfg<32>  { static constexpr int S = 8; static constexpr bool BOTH = true; static constexpr int NT = 256; };
 template <> struct FftCfg<48>  { static constexpr int S = 4; static constexpr bool BOTH = true; static constexpr int NT = 192; };
 template <> struct FftCfg<64>  { static constexpr int S = 4; static constexpr bool BOTH = false; static constexpr int NT = 256; };
+template <> struct FftCfg<96>  { static constexpr int S = 4; };   // k_fftcorr_t
 template <> struct FftCfg<128> { static constexpr int S = 2; };   // k_fftcorr_q
 
 constexpr int kFftThreads = 256;   // the finish kernels
@@ -455,15 +456,16 @@ template <bool CI4, int W> struct RowRaw;
 template <int W> struct RowRaw<true, W> { uint32_t w[16 / W]; };
 template <int W> struct RowRaw<false, W> { float2 v[16]; };
 
-// Inputs 32 .. 63 may lie past the row (n >= 33 keeps 0 .. 31 inside):
-// their groups are clamped to the last one, and the table zeroes them.
+// Two runs of eight inputs, from ja and from jb.  Inputs 32 .. 63 may lie
+// past the row (n >= 33 keeps 0 .. 31 inside): their groups are clamped to
+// the last one, and the 1/g table zeroes them.
 template <bool CI4, int W>
-__device__ __forceinline__ void row_load(const void* __restrict__ volt, size_t rowbase, int R, int n,
+__device__ __forceinline__ void row_load(const void* __restrict__ volt, size_t rowbase, int ja, int jb, int n,
                                          RowRaw<CI4, W>& raw) {
     const int nw = n - W;
 #pragma unroll
     for (int e = 0; e < 8; e += W) {
-        const size_t ia = rowbase + 8 * R + e, ib = rowbase + min(8 * R + 32 + e, nw);
+        const size_t ia = rowbase + ja + e, ib = rowbase + min(jb + e, nw);
         if constexpr (CI4) {
             const uint8_t* b = reinterpret_cast<const uint8_t*>(volt);
             if constexpr (W == 4) {
@@ -606,7 +608,7 @@ __global__ __launch_bounds__(kQThreads) void k_fftcorr_q(const void* __restrict_
     constexpr bool PF = CI4;
     RowRaw<CI4, W> raw;
     auto rowbase_of = [&](int t) { return ((size_t)unit * T + t) * N + (size_t)y * n; };
-    if (PF && tb + rs < te && y < n) row_load<CI4, W>(volt, rowbase_of(tb + rs), rq, n, raw);
+    if (PF && tb + rs < te && y < n) row_load<CI4, W>(volt, rowbase_of(tb + rs), 8 * rq, 8 * rq + 32, n, raw);
     for (int t0 = tb; t0 < te; t0 += S) {
         const int t = t0 + rs;
         const bool row_lane = t < te && y < n;
@@ -616,7 +618,7 @@ __global__ __launch_bounds__(kQThreads) void k_fftcorr_q(const void* __restrict_
         uint32_t wbase = (uint32_t)((rs * H + y) * M * 8) | (uint32_t)((y & 31) << 3);
         asm volatile("" : "+v"(wbase));
         if (row_lane) {
-            if constexpr (!PF) row_load<CI4, W>(volt, rowbase_of(t), rq, n, raw);
+            if constexpr (!PF) row_load<CI4, W>(volt, rowbase_of(t), 8 * rq, 8 * rq + 32, n, raw);
             switch (rq) {
                 case 0: row_fold<0, CI4, W>(raw, hinv + y, rbuf, wbase); break;
                 case 1: row_fold<1, CI4, W>(raw, hinv + y, rbuf, wbase); break;
@@ -635,7 +637,7 @@ __global__ __launch_bounds__(kQThreads) void k_fftcorr_q(const void* __restrict_
         }
         __syncthreads();
         // the next step's inputs, in flight during the column stage
-        if (PF && t + S < te && y < n) row_load<CI4, W>(volt, rowbase_of(t + S), rq, n, raw);
+        if (PF && t + S < te && y < n) row_load<CI4, W>(volt, rowbase_of(t + S), 8 * rq, 8 * rq + 32, n, raw);
         const int ns = min(S, te - t0);
         for (int s = 0; s < ns; ++s) {
             uint32_t rbase = (uint32_t)(s * H * M * 8) | (uint32_t)(cu << 3);
@@ -656,6 +658,229 @@ __global__ __launch_bounds__(kQThreads) void k_fftcorr_q(const void* __restrict_
     float* dst = ppart + ((size_t)unit * nchunk + chunk) * (M * M);
 #pragma unroll
     for (int r = 0; r < 32; ++r) dst[(4 * bitrev<32>(r) + cq) * M + kx] = acc[r];
+}
+
+// ------------------------------------------------------------------ M = 96
+// Grids of 33 .. 48 points per side need 2n - 1 <= 95 points of padded
+// transform, so 96 serves where 128 would pad 1.78x more grid points.
+// With x_j = 0 for j >= 48, E(3m + q) = sum_j w_32^{mj} u_q(j) for
+// u_q(j) = w_96^{qj} [x_j + w_3^q x_{j+32}]: three 32-point transforms (the
+// thirds q) per row and per column, the 96-point analogue of the quarter
+// split above.  Nine waves, three per third, four samples per step.
+//  - Row stage: the 192 lanes of third q's waves take (sample, row) =
+//    (i / 48, i % 48); row group q holds inputs j in [8q, 8q + 8) with their
+//    partners j + 32 (q = 0, 1), or j in [16, 32) (q = 2).  Each input is
+//    divided by its gain once, every third's u(j) written to the row.
+//  - Column stage: lanes take (p, c) = (i / 96, i % 96), samples p and
+//    p + 2 of the step, column c; the two lanes of one (q, c) add their
+//    sums at the end.
+// Row buffer: rows r = 48 s + y of 96 complex (768 B); entry (r, c) sits at
+// column 32 (c / 32) + ((c mod 32) ^ (r mod 32)).  The four samples' rows
+// take 144 KiB of LDS, so the 1/g table comes from the workspace (18 KiB
+// per unit, L1-resident) instead of LDS.
+constexpr int kTThreads = 576;
+constexpr int kTFrame = 48;           // the 1/g table's frame: [k][y], k, y < 48
+
+// 1/g of every antenna, [U][k][y] on the 48 x 48 frame, zero outside the
+// grid and at dead grid points.
+__global__ __launch_bounds__(256) void k_hinv48(const float2* __restrict__ gains, float2* __restrict__ hinv,
+                                                int n, const uint8_t* __restrict__ live) {
+    constexpr int F = kTFrame;
+    const int unit = blockIdx.x;
+    const int N = n * n;
+    for (int x = threadIdx.x; x < F * F; x += 256) {
+        const int k = x / F, y = x % F;
+        float2 h = make_float2(0.0f, 0.0f);
+        if (y < n && k < n && (!live || live[y * n + k])) {
+            const float2 g = gains[(size_t)unit * N + y * n + k];
+            const float d = 1.0f / cabs2(g);
+            h = make_float2(g.x * d, -g.y * d);
+        }
+        hinv[(size_t)unit * (F * F) + x] = h;
+    }
+}
+
+// Row stage, first half, third kernel: row group R (see above); hrow =
+// the unit's 1/g table + y; wbase = byte offset of the row | (r mod 32) << 3.
+template <int R, bool CI4, int W>
+__device__ __forceinline__ void row_fold_t(const RowRaw<CI4, W>& raw, const float2* __restrict__ hrow,
+                                           float2* rbuf, uint32_t wbase) {
+    float2 a[8], b[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        if constexpr (CI4) {
+            const int wa = (int)((raw.w[e / W] >> (8 * (e % W))) & 0xFFu);
+            const int wb = (int)((raw.w[8 / W + e / W] >> (8 * (e % W))) & 0xFFu);
+            a[e] = make_float2((float)((wa << 24) >> 28), (float)((wa << 28) >> 28));
+            b[e] = make_float2((float)((wb << 24) >> 28), (float)((wb << 28) >> 28));
+        } else {
+            a[e] = raw.v[e];
+            b[e] = raw.v[8 + e];
+        }
+    }
+    char* rb = reinterpret_cast<char*>(rbuf);
+    if constexpr (R < 2) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int j = 8 * R + e;
+            const float2 xa = cmul(a[e], hrow[j * kTFrame]);
+            const float2 xb = cmul(b[e], hrow[(j + 32) * kTFrame]);
+#pragma unroll
+            for (int q = 0; q < 3; ++q)
+                *reinterpret_cast<float2*>(rb + (wbase ^ (j << 3)) + 256 * q) =
+                    twmul<96>(cadd(xa, twmul<96>(xb, 32 * q)), j * q);
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int j = 16 + e;
+            const float2 x = cmul(e < 8 ? a[e] : b[e - 8], hrow[j * kTFrame]);
+#pragma unroll
+            for (int q = 0; q < 3; ++q)
+                *reinterpret_cast<float2*>(rb + (wbase ^ (j << 3)) + 256 * q) = twmul<96>(x, j * q);
+        }
+    }
+}
+
+// Row stage, second half: third Q of one row, its outputs E(3m + Q) written
+// over its inputs (output m at column 32 Q + m).
+template <int Q>
+__device__ __forceinline__ void row_transform_t(float2* rbuf, uint32_t wbase) {
+    float2 u[32];
+#pragma unroll
+    for (int j = 0; j < 32; ++j) u[j] = lds_at(rbuf, (wbase ^ (j << 3)) + 256 * Q);
+    fft_dif<32>(u);
+    char* rb = reinterpret_cast<char*>(rbuf);
+#pragma unroll
+    for (int r = 0; r < 32; ++r)
+        *reinterpret_cast<float2*>(rb + (wbase ^ (bitrev<32>(r) << 3)) + 256 * Q) = u[r];
+}
+
+// Third Q of one column of one sample's rows; |E|^2 into acc.  rbase =
+// byte offset of the sample's rows + 256 (c / 32) | ((c mod 32) ^ 16 (s mod 2))
+// << 3: row j's entry is then (rbase ^ (j << 3)) + 768 j, and row j + 32
+// shares row j's swizzle.
+template <int Q>
+__device__ __forceinline__ void col_third(const float2* rbuf, uint32_t rbase, float (&acc)[32]) {
+    float2 v[32];
+#pragma unroll
+    for (int j = 0; j < 32; ++j) {
+        const uint32_t o = rbase ^ (j << 3);
+        const float2 a = lds_at(rbuf, o + j * 768);
+        if (j < 16) {
+            const float2 b = lds_at(rbuf, o + (j + 32) * 768);
+            v[j] = twmul<96>(cadd(a, twmul<96>(b, 32 * Q)), j * Q);
+        } else {
+            v[j] = twmul<96>(a, j * Q);
+        }
+    }
+    fft_dif<32>(v);
+#pragma unroll
+    for (int r = 0; r < 32; ++r) acc[r] = acc_power(acc[r], v[r]);
+}
+
+template <bool CI4, int W>
+__global__ __launch_bounds__(kTThreads) void k_fftcorr_t(const void* __restrict__ volt,
+                                                         const float2* __restrict__ hinv,
+                                                         float* __restrict__ ppart, int n, int T,
+                                                         int tchunk, int nchunk) {
+    constexpr int M = 96, H = 48, S = FftCfg<96>::S, NT = kTThreads;
+    constexpr int RB = H * M * 8;                 // bytes of one sample's rows
+    static_assert(NT == 9 * 64 && S * H == 3 * 64, "three waves per third: four samples of 48 rows");
+    static_assert(RB % 256 == 0, "the swizzle stays below bit 8");
+    // (the launcher guarantees 33 <= n <= 48)
+    __shared__ float2 rbuf[S * H * M];
+
+    const int tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int q = wave / 3;
+    const int i = (wave - 3 * q) * 64 + (tid & 63);
+    const int unit = blockIdx.y;
+    const int chunk = blockIdx.x;
+    const int N = n * n;
+    const int tb = chunk * tchunk;
+    const int te = min(T, tb + tchunk);
+
+    // rows n .. 47 of every sample stay zero
+    for (int x = tid; x < S * (H - n) * M; x += NT) {
+        const int s = x / ((H - n) * M), r = x % ((H - n) * M);
+        rbuf[(s * H + n) * M + r] = make_float2(0.0f, 0.0f);
+    }
+
+    float acc[32];
+#pragma unroll
+    for (int r = 0; r < 32; ++r) acc[r] = 0.0f;
+    const int rs = i / H, y = i - H * rs;          // row stage: sample, row (row i of the buffer)
+    const int cp = i / M, cc = i - M * cp;         // column stage: sample parity, column
+    const int ja = q < 2 ? 8 * q : 16, jb = q < 2 ? 8 * q + 32 : 24;
+    const float2* hunit = hinv + (size_t)unit * (kTFrame * kTFrame);
+    __syncthreads();
+
+    constexpr bool PF = CI4;
+    RowRaw<CI4, W> raw;
+    auto rowbase_of = [&](int t) { return ((size_t)unit * T + t) * N + (size_t)y * n; };
+    if (PF && tb + rs < te && y < n) row_load<CI4, W>(volt, rowbase_of(tb + rs), ja, jb, n, raw);
+    for (int t0 = tb; t0 < te; t0 += S) {
+        const int t = t0 + rs;
+        const bool row_lane = t < te && y < n;
+        uint32_t wbase = (uint32_t)(i * M * 8) | (uint32_t)((i & 31) << 3);
+        asm volatile("" : "+v"(wbase));
+        // the 16 1/g values are re-read each step (from L1), not held in
+        // registers across the loop
+        int hoff = y;
+        asm volatile("" : "+v"(hoff));
+        const float2* hrow = hunit + hoff;
+        if (row_lane) {
+            if constexpr (!PF) row_load<CI4, W>(volt, rowbase_of(t), ja, jb, n, raw);
+            switch (q) {
+                case 0: row_fold_t<0, CI4, W>(raw, hrow, rbuf, wbase); break;
+                case 1: row_fold_t<1, CI4, W>(raw, hrow, rbuf, wbase); break;
+                default: row_fold_t<2, CI4, W>(raw, hrow, rbuf, wbase); break;
+            }
+        }
+        __syncthreads();
+        if (row_lane) {
+            switch (q) {
+                case 0: row_transform_t<0>(rbuf, wbase); break;
+                case 1: row_transform_t<1>(rbuf, wbase); break;
+                default: row_transform_t<2>(rbuf, wbase); break;
+            }
+        }
+        __syncthreads();
+        // the next step's inputs, in flight during the column stage
+        if (PF && t + S < te && y < n) row_load<CI4, W>(volt, rowbase_of(t + S), ja, jb, n, raw);
+        const int ns = min(S, te - t0);
+        uint32_t rbase = (uint32_t)(cp * RB + 256 * (cc >> 5)) | (uint32_t)(((cc & 31) ^ (16 * cp)) << 3);
+        asm volatile("" : "+v"(rbase));
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            if (cp + 2 * k < ns) {
+                switch (q) {
+                    case 0: col_third<0>(rbuf, rbase + k * 2 * RB, acc); break;
+                    case 1: col_third<1>(rbuf, rbase + k * 2 * RB, acc); break;
+                    default: col_third<2>(rbuf, rbase + k * 2 * RB, acc); break;
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    // the lanes of odd samples hand their sums to the even ones' lanes
+    // through LDS ([q][r][c]), which add them in a fixed order; grid point
+    // (ky, kx) = (3 bitrev(r) + q, kx), where column cc = 32 q' + m holds
+    // kx = 3 m + q'
+    float* red = reinterpret_cast<float*>(rbuf);
+    if (cp == 1) {
+#pragma unroll
+        for (int r = 0; r < 32; ++r) red[(q * 32 + r) * M + cc] = acc[r];
+    }
+    __syncthreads();
+    if (cp == 0) {
+        const int kx = 3 * (cc & 31) + (cc >> 5);
+        float* dst = ppart + ((size_t)unit * nchunk + chunk) * (M * M);
+#pragma unroll
+        for (int r = 0; r < 32; ++r) dst[(3 * bitrev<32>(r) + q) * M + kx] = acc[r] + red[(q * 32 + r) * M + cc];
+    }
 }
 
 constexpr int kFinThreads = 256;
@@ -690,10 +915,14 @@ __global__ __launch_bounds__(kFinThreads) void k_fftfin(const float* __restrict_
             float2 a = make_float2(0.0f, 0.0f);
             if (dx <= n - 1) {
                 const float* prow = pw + uy * M;
+                const int step = dx < 0 ? dx + M : dx;     // ux dx mod M, stepped
+                int k = 0;
                 for (int ux = 0; ux < M; ++ux) {
-                    const float2 w = twp[(ux * dx) & (M - 1)];
+                    const float2 w = twp[k];
                     a.x += prow[ux] * w.x;
                     a.y += prow[ux] * w.y;
+                    k += step;
+                    if (k >= M) k -= M;
                 }
             }
             abuf[q] = a;
@@ -705,8 +934,11 @@ __global__ __launch_bounds__(kFinThreads) void k_fftfin(const float* __restrict_
             const int dx = dx0 + di;
             if (dx > n - 1 || (dy == 0 && dx < 0)) continue;
             float2 c = make_float2(0.0f, 0.0f);
+            int k = 0;
             for (int uy = 0; uy < M; ++uy) {
-                c = cadd(c, cmul(abuf[uy * DB + di], twp[(uy * dy) & (M - 1)]));
+                c = cadd(c, cmul(abuf[uy * DB + di], twp[k]));
+                k += dy;
+                if (k >= M) k -= M;
             }
             if (dx == 0 && dy == 0) {
                 vauto[unit] = c.x * norm / (float)n_live;
@@ -744,9 +976,27 @@ static void launch_q(const FftLaunch& L, hipStream_t st) {
                        L.gains, L.ppart, L.n, L.T, L.tchunk, L.nchunk, L.mt.live);
 }
 
+template <bool CI4, int W>
+static void launch_t(const FftLaunch& L, hipStream_t st) {
+    hipLaunchKernelGGL((k_fftcorr_t<CI4, W>), dim3(L.nchunk, L.n_units), dim3(kTThreads), 0, st, L.volt,
+                       L.hinv, L.ppart, L.n, L.T, L.tchunk, L.nchunk);
+}
+
 template <int M, bool CI4>
 static hipError_t launch_fft_m(const FftLaunch& L, hipStream_t st) {
-    if constexpr (M == 128) {
+    if constexpr (M == 96) {
+        if (L.n < 33 || L.n > 48 || (CI4 && (L.n & 1)) || !L.hinv) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_hinv48, dim3(L.n_units), dim3(256), 0, st, L.gains, L.hinv, L.n, L.mt.live);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        if constexpr (CI4) {
+            if (L.n % 4 == 0) launch_t<true, 4>(L, st);
+            else launch_t<true, 2>(L, st);
+        } else {
+            if (L.n % 2 == 0) launch_t<false, 2>(L, st);
+            else launch_t<false, 1>(L, st);
+        }
+    } else if constexpr (M == 128) {
         // widest load group that divides n (4-bit plans have n even)
         if (L.n < 33 || L.n > 64 || (CI4 && (L.n & 1))) return hipErrorInvalidValue;
         if constexpr (CI4) {
@@ -783,6 +1033,7 @@ int fft_samples_per_step_for(int M) {
         case 32: return fft_samples_per_step<32>();
         case 48: return fft_samples_per_step<48>();
         case 64: return fft_samples_per_step<64>();
+        case 96: return fft_samples_per_step<96>();
         case 128: return fft_samples_per_step<128>();
         default: return 0;
     }
@@ -794,6 +1045,7 @@ hipError_t launch_fftcorr(const FftLaunch& L, hipStream_t st) {
         case 32: return L.ci4 ? launch_fft_m<32, true>(L, st) : launch_fft_m<32, false>(L, st);
         case 48: return L.ci4 ? launch_fft_m<48, true>(L, st) : launch_fft_m<48, false>(L, st);
         case 64: return L.ci4 ? launch_fft_m<64, true>(L, st) : launch_fft_m<64, false>(L, st);
+        case 96: return L.ci4 ? launch_fft_m<96, true>(L, st) : launch_fft_m<96, false>(L, st);
         case 128: return L.ci4 ? launch_fft_m<128, true>(L, st) : launch_fft_m<128, false>(L, st);
         default: return hipErrorInvalidValue;
     }

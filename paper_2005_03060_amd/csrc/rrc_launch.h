@@ -40,6 +40,7 @@ struct FftLaunch {
     const void* volt;
     const float2* gains;
     float* ppart;          // workspace: [U][nchunk][M][M]
+    float2* hinv;          // workspace: [U][48][48] 1/g table of the M = 96 kernel (else unused)
     float2* vunique;
     float* vauto;
     unsigned long long* stamps;   // optional [1 + U] run stamps (see unit_done_stamp)

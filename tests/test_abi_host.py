@@ -270,19 +270,24 @@ def test_masked_plan_errors():
 
 
 def test_fft_size_choices():
-    # M = 48 only where 2n - 1 <= 48 and the default power of two is larger
-    for n, ok in ((16, False), (17, True), (20, True), (24, True), (25, False), (32, False)):
+    # default: the smallest of 16, 32, 48, 64, 96, 128 with M >= 2n - 1 (the
+    # lags never wrap round); the next power of two is the one alternative
+    for n, default, alt in ((3, 16, None), (8, 16, None), (16, 32, None), (17, 48, 64), (24, 48, 64),
+                            (25, 64, None), (32, 64, None), (33, 96, 128), (40, 96, 128), (48, 96, 128),
+                            (49, 128, None), (64, 128, None)):
         types, _ = rrc.select_subset(n)
         p = rrc.Plan(n, types, 1, 64)
-        default = p.info["fft_size"]
-        if ok:
-            p.set_fft_size(48)
-            assert p.info["fft_size"] == 48
+        assert p.info["fft_size"] == default, n
+        for m in (16, 32, 48, 64, 96, 128):
+            if m in (default, alt):
+                p.set_fft_size(m)
+                assert p.info["fft_size"] == m
+            else:
+                with pytest.raises(rrc.RRCError) as e:
+                    p.set_fft_size(m)
+                assert e.value.code == _lib.RRC_EINVAL
+        # the workspace holds the larger grid's partial sums
+        if alt:
+            ws = p.info["workspace_bytes"]
             p.set_fft_size(default)
-            assert p.info["fft_size"] == default
-        else:
-            with pytest.raises(rrc.RRCError) as e:
-                p.set_fft_size(48)
-            assert e.value.code == _lib.RRC_EINVAL
-        with pytest.raises(rrc.RRCError):
-            p.set_fft_size(96)
+            assert p.info["workspace_bytes"] == ws

@@ -37,7 +37,7 @@ def _embedded(side, n):
 
 
 @pytest.mark.parametrize("side,U,T", [(2, 2, 64), (3, 2, 200), (4, 2, 256), (6, 1, 333), (11, 2, 512),
-                                      (17, 1, 64), (4, 1, 1)])
+                                      (17, 1, 64), (4, 1, 1), (20, 2, 100), (24, 1, 1)])
 def test_hex_fftcorr_matches_oracle(rrc, side, U, T):
     n, mask, pos, idx = _hex(rrc, side)
     types, _ = rrc.select_subset_masked(n, mask, "hex")
@@ -62,13 +62,16 @@ def test_hex_fftcorr_matches_oracle(rrc, side, U, T):
         assert abs(va[u] - aref) <= 1e-5 * aref
 
 
-@pytest.mark.parametrize("side,U,T", [(11, 2, 256), (9, 1, 100), (12, 1, 64)])
-def test_hex_fftcorr_m48_matches_oracle(rrc, side, U, T):
-    # hexagons with 2 side - 1 <= 24 grid rows fit the 48-point transform
+@pytest.mark.parametrize("side,U,T,m", [(11, 2, 256, 64), (9, 1, 100, 64), (12, 1, 64, 64), (20, 1, 64, 128),
+                                        (24, 2, 33, 128)])
+def test_hex_fftcorr_power_of_two_size_matches_oracle(rrc, side, U, T, m):
+    # the default is the mixed-radix size (48 up to 12 antennas a side, 96 up
+    # to 24); the power of two beside it
     n, mask, pos, idx = _hex(rrc, side)
     types, _ = rrc.select_subset_masked(n, mask, "hex")
     plan = rrc.Plan(n, types, U, T, mask=mask)
-    plan.set_fft_size(48)
+    assert plan.info["fft_size"] == m * 3 // 4
+    plan.set_fft_size(m)
     v, g = make_units(n, U, T)
     g64 = g.astype(np.complex64)
     vu, va = plan.fftcorr(torch.from_numpy(v).to(DEV), torch.from_numpy(g64).to(DEV))
@@ -80,7 +83,7 @@ def test_hex_fftcorr_m48_matches_oracle(rrc, side, U, T):
         gl = g64[u][idx].astype(np.complex128)
         ref = OC.redundant_average(vf, gl, pos, lags)
         err = rel_l2(vu[u], ref)
-        print(f"M=48 hex side {side} (n={n}) T={T} unit {u}: V^unique rel L2 {err:.2e}")
+        print(f"M={m} hex side {side} (n={n}) T={T} unit {u}: V^unique rel L2 {err:.2e}")
         assert err <= TOL_VUNIQUE
         assert np.all(vu[u][empty] == 0)
         assert abs(va[u] - OC.calibrated_auto(vf, gl)) <= 1e-5 * OC.calibrated_auto(vf, gl)
@@ -292,3 +295,39 @@ def test_masked_full_grid_solve_equals_plain_plan(rrc):
     torch.cuda.synchronize()
     for k in ("vred", "gains", "vmodel", "chisq", "niter", "status", "vunique", "vauto"):
         assert torch.equal(oa[k], ob[k]), k
+
+
+def test_hex_tuner_keeps_results(rrc, tmp_path):
+    # the autotuner on the 331-antenna hexagon (21 x 21 grid: the 48-point
+    # transform is a candidate); the tuned run's V^reduced and solve are the
+    # untuned ones bit for bit, V^unique meets the oracle
+    side, U, T = 11, 4, 512
+    n, mask, pos, idx = _hex(rrc, side)
+    types, _ = rrc.select_subset_masked(n, mask, "hex")
+    plan = rrc.Plan(n, types, U, T, mask=mask, init_mode="gains")
+    v, g = make_units(n, U, T)
+    vd = torch.from_numpy(v).to(DEV)
+    gin = torch.from_numpy(g.astype(np.complex64)).to(DEV)
+    ref = plan.run(vd, gains_in=gin, mode="pipelined")
+    cache = str(tmp_path / "tune.txt")
+    t1 = plan.tune(vd, gin, cache_path=cache)
+    assert t1["from_cache"] == 0 and t1["fft_size"] in (48, 64)
+    got = plan.run(vd, gains_in=gin, mode="pipelined", out=plan.alloc_outputs(DEV))
+    torch.cuda.synchronize()
+    for key in ("vred", "gains", "vmodel", "chisq", "niter", "status"):
+        assert torch.equal(got[key], ref[key]), key
+    lags = OC.canonical_lags(n)
+    for u in range(U):
+        vf = OC.fx_correlate(v[u][:, idx].astype(np.complex128))
+        want = OC.redundant_average(vf, g[u].astype(np.complex64).astype(np.complex128)[idx], pos, lags)
+        assert rel_l2(got["vunique"][u].cpu().numpy(), want) <= TOL_VUNIQUE
+    # another mask on the same grid shape does not take this choice
+    other = mask.copy()
+    other[np.flatnonzero(other)[0]] = 0
+    types2, _ = rrc.select_subset_masked(n, other, "hex")
+    p2 = rrc.Plan(n, types2, U, T, mask=other, init_mode="gains")
+    assert p2.tune(vd, gin, cache_path=cache)["from_cache"] == 0
+    p3 = rrc.Plan(n, types, U, T, mask=mask, init_mode="gains")
+    t3 = p3.tune(vd, gin, cache_path=cache)
+    assert t3["from_cache"] == 1 and t3["fft_size"] == t1["fft_size"]
+    print(f"hex side {side}: tuned {t1}")

@@ -60,10 +60,14 @@ def test_fftcorr_ci4_matches_oracle(rrc, n, U, T):
 
 
 @pytest.mark.parametrize("n,U,T,dtype", [(17, 2, 131, "c64"), (20, 1, 64, "c64"), (24, 2, 200, "c64"),
-                                         (23, 1, 1, "c64"), (20, 2, 77, "ci4"), (24, 1, 256, "ci4")])
-def test_fftcorr_m48_matches_oracle(rrc, n, U, T, dtype):
-    # the mixed-radix (3 x 16) padded transform: 2n - 1 <= 48 keeps the
-    # circular correlation free of wrap-around, as at the default 64
+                                         (23, 1, 1, "c64"), (20, 2, 77, "ci4"), (24, 1, 256, "ci4"),
+                                         (33, 2, 70, "c64"), (40, 1, 129, "c64"), (45, 2, 37, "c64"),
+                                         (48, 2, 256, "c64"), (47, 1, 1, "c64"), (34, 1, 22, "ci4"),
+                                         (44, 2, 96, "ci4"), (48, 1, 301, "ci4")])
+def test_fftcorr_both_sizes_match_oracle(rrc, n, U, T, dtype):
+    # 17 <= n <= 24 and 33 <= n <= 48: the mixed-radix default (48 = 3 x 16,
+    # 96 = 3 x 32) and the power of two beside it; 2n - 1 <= M keeps the
+    # circular correlation free of wrap-around at either size
     if dtype == "ci4":
         b, re, im, g = make_ci4_units(n, U, T)
         vd = torch.from_numpy(b).to(DEV)
@@ -72,31 +76,35 @@ def test_fftcorr_m48_matches_oracle(rrc, n, U, T, dtype):
         v, g = make_units(n, U, T)
         vd = torch.from_numpy(v).to(DEV)
     plan, _ = _plan(rrc, n, U, T, dtype=dtype)
-    assert plan.info["fft_size"] == 64
-    plan.set_fft_size(48)
-    assert plan.info["fft_size"] == 48
+    mixed = 48 if n <= 24 else 96
+    assert plan.info["fft_size"] == mixed
     g64 = g.astype(np.complex64)
-    vu, va = plan.fftcorr(vd, torch.from_numpy(g64).to(DEV))
-    vu, va = vu.cpu().numpy(), va.cpu().numpy()
-    for u in range(U):
-        ref, aref = oracle_vunique(v[u], g64[u].astype(np.complex128), n)
-        err = rel_l2(vu[u], ref)
-        print(f"M=48 {dtype} n={n} T={T} unit {u}: V^unique rel L2 {err:.2e}")
-        assert err <= TOL_VUNIQUE
-        assert abs(va[u] - aref) <= 1e-5 * aref
+    refs = [oracle_vunique(v[u], g64[u].astype(np.complex128), n) for u in range(U)]
+    for m in (mixed, {48: 64, 96: 128}[mixed]):
+        plan.set_fft_size(m)
+        assert plan.info["fft_size"] == m
+        vu, va = plan.fftcorr(vd, torch.from_numpy(g64).to(DEV))
+        vu, va = vu.cpu().numpy(), va.cpu().numpy()
+        for u in range(U):
+            ref, aref = refs[u]
+            err = rel_l2(vu[u], ref)
+            print(f"M={m} {dtype} n={n} T={T} unit {u}: V^unique rel L2 {err:.2e}")
+            assert err <= TOL_VUNIQUE
+            assert abs(va[u] - aref) <= 1e-5 * aref
 
 
-def test_fftcorr_m48_single_mode_closed_form(rrc):
-    # a sky mode on the 48-point frequency grid, unit gains, no noise:
-    # V(d) = <|s|^2> exp(-2 pi i k0.d / 48)
-    n, T, m = 24, 40, 48
-    rng = np.random.default_rng(48)
+@pytest.mark.parametrize("n,m,k0", [(24, 48, (5, 29)), (48, 96, (7, 61))])
+def test_fftcorr_mixed_radix_single_mode_closed_form(rrc, n, m, k0):
+    # a sky mode on the M-point frequency grid, unit gains, no noise:
+    # V(d) = <|s|^2> exp(-2 pi i k0.d / M)
+    T = 40
+    rng = np.random.default_rng(m)
     s = (rng.standard_normal(T) + 1j * rng.standard_normal(T))
-    k0 = np.array([5, 29])
+    k0 = np.array(k0)
     pos = OG.square_positions(n)
     v = (s[:, None] * np.exp(-2j * np.pi * (pos @ k0) / m)[None, :]).astype(np.complex64)[None]
     plan, _ = _plan(rrc, n, 1, T)
-    plan.set_fft_size(48)
+    assert plan.info["fft_size"] == m
     vu, _ = plan.fftcorr(torch.from_numpy(v).to(DEV), torch.ones((1, n * n), dtype=torch.complex64, device=DEV))
     p = np.mean(np.abs(v[0, :, 0].astype(np.complex128)) ** 2)
     ref = np.array([p * np.exp(-2j * np.pi * (k0 @ np.array(d)) / m) for d in OC.canonical_lags(n)])
