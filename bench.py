@@ -94,9 +94,10 @@ def parse():
                     help="batches in flight: step i runs on lane i mod D, each lane with its own "
                          "stream, plans, input copy and outputs; 0 picks enough for the solves "
                          "(one workgroup per unit) of all lanes to cover the CUs, at most 4")
-    ap.add_argument("--order", default="auto", choices=["auto", "xeng_first", "fft_first"],
-                    help="pipelined branch order (auto: FFT first for 4-bit workloads, whose FFT stage "
-                         "is VALU-bound and dominates)")
+    ap.add_argument("--order", default="auto", choices=["auto", "xeng_first", "fft_first", "serial"],
+                    help="pipelined branch order (auto: serial for 4-bit workloads, whose VALU-bound "
+                         "FFT stage and solve each fill the device and slow each other down when they "
+                         "share it; X-engine first otherwise)")
     ap.add_argument("--latency-reps", type=int, default=50)
     ap.add_argument("--xengine", default="auto", choices=["auto", "dot", "mfma"],
                     help="X-engine kernel of 4-bit plans (auto: the dot-product kernel)")
@@ -163,7 +164,7 @@ def setup(w, dev, rrc, inflight, order, xengine="auto"):
     cus = torch.cuda.get_device_properties(dev).multi_processor_count
     D = inflight if inflight > 0 else max(1, min(4, -(-cus // (w.n_chan * len(arrays)))))
     if order == "auto":
-        order = "fft_first" if w.ci4 else "xeng_first"
+        order = "serial" if w.ci4 else "xeng_first"
     lanes = []
     for li in range(D):
         la = []

@@ -232,10 +232,14 @@ int rrc_plan_prepare(rrc_plan* plan);
  * RRC_ORDER_XENG_FIRST (default): X-engine, then the FFT-correlator forked
  *   beside the solve -- for FFT stages that are short or HBM-bound;
  * RRC_ORDER_FFT_FIRST: the FFT-correlator forked first, the X-engine and
- *   the solve beside it -- for a VALU-bound FFT stage that dominates.
- * Results are identical either way. */
+ *   the solve beside it -- for a VALU-bound FFT stage that dominates;
+ * RRC_ORDER_SERIAL: X-engine, FFT-correlator and solve one after another on
+ *   `stream` -- for stages that each fill the device, which slow each other
+ *   down more than they gain when they share its CUs.
+ * Results are identical in every order. */
 #define RRC_ORDER_XENG_FIRST 0
 #define RRC_ORDER_FFT_FIRST  1
+#define RRC_ORDER_SERIAL     2
 int rrc_plan_set_order(rrc_plan* plan, int32_t order);
 
 /* X-engine kernel of a 4-bit plan (complex64 plans have one):

@@ -28,6 +28,7 @@ RRC_RUN_PIPELINED = 1
 RRC_RUN_SELFCAL = 2
 RRC_ORDER_XENG_FIRST = 0
 RRC_ORDER_FFT_FIRST = 1
+RRC_ORDER_SERIAL = 2
 RRC_BATCH_GRAPH = 1
 RRC_XENG_AUTO = 0
 RRC_XENG_DOT = 1

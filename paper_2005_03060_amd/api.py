@@ -391,8 +391,9 @@ class Plan:
         return {f: getattr(t, f) for f, _ in L.Tune._fields_}
 
     def set_order(self, order: str) -> None:
-        """Branch order of the pipelined run: "xeng_first" or "fft_first"."""
-        code = {"xeng_first": L.RRC_ORDER_XENG_FIRST, "fft_first": L.RRC_ORDER_FFT_FIRST}[order]
+        """Branch order of the pipelined run: "xeng_first", "fft_first" or "serial"."""
+        code = {"xeng_first": L.RRC_ORDER_XENG_FIRST, "fft_first": L.RRC_ORDER_FFT_FIRST,
+                "serial": L.RRC_ORDER_SERIAL}[order]
         L.check(self._lib.rrc_plan_set_order(self._h, code), "rrc_plan_set_order")
 
     def set_xengine(self, kind: str) -> None:

@@ -652,7 +652,7 @@ void rrc_plan_destroy(rrc_plan* p) {
 }
 
 int rrc_plan_set_order(rrc_plan* p, int32_t order) {
-    if (!p || (order != RRC_ORDER_XENG_FIRST && order != RRC_ORDER_FFT_FIRST)) return RRC_EINVAL;
+    if (!p || order < RRC_ORDER_XENG_FIRST || order > RRC_ORDER_SERIAL) return RRC_EINVAL;
     p->order = order;
     return RRC_OK;
 }
@@ -964,6 +964,18 @@ int rrc_run(rrc_plan* p, void* stream, int32_t mode, const rrc_io* io) {
             gfft = copy;
         }
     }
+    if (p->order == RRC_ORDER_SERIAL) {
+        // the three stages one after another on `stream`
+        rc = xengine_impl(p, stream, io->d_volt, io->d_vred, io->d_work, false);
+        if (rc == RRC_OK)
+            rc = fftcorr_impl(p, stream, io->d_volt, gfft, io->d_vunique, io->d_vauto, io->d_work, io->d_stamps,
+                              false);
+        if (rc == RRC_OK)
+            rc = solve_impl(p, stream, io->d_vred, io->d_gains_in, io->d_gains_ref, io->d_gains_out,
+                            io->d_vmodel, io->d_chisq, io->d_niter, io->d_status, io->d_stamps, io->d_work,
+                            false);
+        return rc;
+    }
     auto fork_fft = [&]() -> int {
         if (hipEventRecord(p->ev_fork, st) != hipSuccess) return RRC_EDEVICE;
         if (hipStreamWaitEvent(p->aux, p->ev_fork, 0) != hipSuccess) return RRC_EDEVICE;
@@ -1088,7 +1100,7 @@ int rrc_plan_tune(rrc_plan* p, void* stream, const rrc_io* io, const char* cache
     for (int mi = 0; mi < nm && rc == RRC_OK; ++mi)
     for (int fa = 1; fa <= 4 && rc == RRC_OK; fa *= 2) {
         if (fa > 1 && p->fft_tchunk0 * (fa / 2) >= p->T) break;       // no fewer chunks left
-        for (int ord = RRC_ORDER_XENG_FIRST; ord <= RRC_ORDER_FFT_FIRST && rc == RRC_OK; ++ord)
+        for (int ord = RRC_ORDER_XENG_FIRST; ord <= RRC_ORDER_SERIAL && rc == RRC_OK; ++ord)
             for (int xi = 0; xi < nx && rc == RRC_OK; ++xi) {
                 p->M = msizes[mi];
                 set_fft_chunk_factor(p, fa);

@@ -915,14 +915,22 @@ __global__ __launch_bounds__(kFinThreads) void k_fftfin(const float* __restrict_
             float2 a = make_float2(0.0f, 0.0f);
             if (dx <= n - 1) {
                 const float* prow = pw + uy * M;
-                const int step = dx < 0 ? dx + M : dx;     // ux dx mod M, stepped
-                int k = 0;
-                for (int ux = 0; ux < M; ++ux) {
-                    const float2 w = twp[k];
-                    a.x += prow[ux] * w.x;
-                    a.y += prow[ux] * w.y;
-                    k += step;
-                    if (k >= M) k -= M;
+                if constexpr ((M & (M - 1)) == 0) {
+                    for (int ux = 0; ux < M; ++ux) {
+                        const float2 w = twp[(ux * dx) & (M - 1)];
+                        a.x += prow[ux] * w.x;
+                        a.y += prow[ux] * w.y;
+                    }
+                } else {
+                    const int step = dx < 0 ? dx + M : dx;     // ux dx mod M, stepped
+                    int k = 0;
+                    for (int ux = 0; ux < M; ++ux) {
+                        const float2 w = twp[k];
+                        a.x += prow[ux] * w.x;
+                        a.y += prow[ux] * w.y;
+                        k += step;
+                        if (k >= M) k -= M;
+                    }
                 }
             }
             abuf[q] = a;
@@ -934,11 +942,15 @@ __global__ __launch_bounds__(kFinThreads) void k_fftfin(const float* __restrict_
             const int dx = dx0 + di;
             if (dx > n - 1 || (dy == 0 && dx < 0)) continue;
             float2 c = make_float2(0.0f, 0.0f);
-            int k = 0;
-            for (int uy = 0; uy < M; ++uy) {
-                c = cadd(c, cmul(abuf[uy * DB + di], twp[k]));
-                k += dy;
-                if (k >= M) k -= M;
+            if constexpr ((M & (M - 1)) == 0) {
+                for (int uy = 0; uy < M; ++uy) c = cadd(c, cmul(abuf[uy * DB + di], twp[(uy * dy) & (M - 1)]));
+            } else {
+                int k = 0;
+                for (int uy = 0; uy < M; ++uy) {
+                    c = cadd(c, cmul(abuf[uy * DB + di], twp[k]));
+                    k += dy;
+                    if (k >= M) k -= M;
+                }
             }
             if (dx == 0 && dy == 0) {
                 vauto[unit] = c.x * norm / (float)n_live;

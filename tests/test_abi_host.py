@@ -291,3 +291,12 @@ def test_fft_size_choices():
             ws = p.info["workspace_bytes"]
             p.set_fft_size(default)
             assert p.info["workspace_bytes"] == ws
+
+def test_branch_orders_accepted():
+    types, _ = rrc.select_subset(8)
+    p = rrc.Plan(8, types, 1, 64)
+    for o in ("xeng_first", "fft_first", "serial"):
+        p.set_order(o)
+    lib = rrc.load_library()
+    assert lib.rrc_plan_set_order(p._h, 3) == _lib.RRC_EINVAL
+    assert lib.rrc_plan_set_order(p._h, -1) == _lib.RRC_EINVAL
