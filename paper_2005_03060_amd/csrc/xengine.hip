@@ -157,8 +157,10 @@ __global__ __launch_bounds__(kXThreads, 2) void k_xant(XengLaunch L) {
     // transposed and stored as one 16-byte LDS write: LDS word (g, a) holds
     // samples 4g .. 4g + 3 of antenna a.  Wave w takes groups w, w + 4, ...
     // (row addresses uniform over the wave) and lane l columns l and l + 64,
-    // so no word is loaded twice; rows past the chunk's end are zeroed, since
-    // they are summed in groups of four.
+    // so no word is loaded twice; rows past the chunk's end are zeroed when
+    // they go to LDS (not as they arrive, which would wait for each load),
+    // since they are summed in groups of four.  4-bit row offsets are
+    // 32-bit (at most S rows of N / 4 words).
     const RT* vol = reinterpret_cast<const RT*>(L.volt);
     const size_t rowstride = (size_t)N / W;
     constexpr int GW = S / 4 / (NT / 64);          // 4-bit groups per wave
@@ -167,8 +169,11 @@ __global__ __launch_bounds__(kXThreads, 2) void k_xant(XengLaunch L) {
     static_assert(!CI4 || (kXThreads + kXHaloMax + 6) / 4 <= 128, "two word columns per lane");
     RT r[RU][RK];
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6), ln = tid & 63;
+    const int rs32 = (int)rowstride;
+    int pend_last = S - 1;                         // last valid row of the staged step
     auto load = [&](int t0) {
         const int last = min(S, te - t0) - 1;
+        pend_last = last;
         const RT* base = vol + (((size_t)unit * T + t0) * N + lo) / W;
         if constexpr (CI4) {
 #pragma unroll
@@ -180,8 +185,8 @@ __global__ __launch_bounds__(kXThreads, 2) void k_xant(XengLaunch L) {
                     if (c >= upr) continue;
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
-                        const uint32_t w = base[(size_t)min(g4 + i, last) * rowstride + c];
-                        r[2 * gi + m][i] = g4 + i <= last ? w : 0u;
+                        const RT* row = base + min(g4 + i, last) * rs32;   // uniform over the wave
+                        r[2 * gi + m][i] = row[c];
                     }
                 }
             }
@@ -204,7 +209,9 @@ __global__ __launch_bounds__(kXThreads, 2) void k_xant(XengLaunch L) {
                 for (int m = 0; m < 2; ++m) {
                     const int c = ln + 64 * m;
                     if (c >= upr) continue;
-                    const uint32_t w[4] = {r[2 * gi + m][0], r[2 * gi + m][1], r[2 * gi + m][2], r[2 * gi + m][3]};
+                    uint32_t w[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) w[i] = 4 * g + i <= pend_last ? r[2 * gi + m][i] : 0u;
                     uint32_t o[4];
                     transpose4x4(w, o);
                     st[g * (kXRowW4 / 4) + c] = make_uint4(o[0], o[1], o[2], o[3]);
