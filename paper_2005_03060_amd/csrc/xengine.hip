@@ -89,7 +89,7 @@ struct XStage {
 };
 
 template <bool CI4, bool WIDE, int KMAX>
-__global__ __launch_bounds__(kXThreads, 2) void k_xant(XengLaunch L) {
+__global__ __launch_bounds__(kXThreads, KMAX <= 9 ? 4 : 2) void k_xant(XengLaunch L) {
     constexpr int NT = kXThreads;
     constexpr int S = xeng_samples<CI4>();
     using G = XStage<CI4, WIDE>;
