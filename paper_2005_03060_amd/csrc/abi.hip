@@ -447,14 +447,14 @@ static int plan_create(rrc_plan** out, int32_t n, const int32_t* types_xy, int32
     p->fft_nchunk = ceil_div(n_time, tch);
     p->fft_tchunk0 = tch;
 
-    // X-engine: blocks of 256 antennas, S samples staged per step, time
+    // X-engine: blocks of 512 (4-bit) or 256 antennas, S samples staged per step, time
     // chunks (whole steps) so that the launch has >= 2048 workgroups while
     // each still runs >= 4 steps and >= 64 samples (fewer chunk partials
     // for the finishing pass to add)
     {
         int halo = 0;
         for (int t = 0; t < s.K; ++t) halo = std::max(halo, s.dy[t] * s.n + s.dx[t]);
-        const int apb = rrc::xengine_antennas_per_block();
+        const int apb = rrc::xengine_antennas_per_block(dtype == RRC_CI4);
         // staging limits of the X-engine: partners within 248 antennas in
         // raster order, and whole 32-bit words of 4-bit samples
         if (halo > rrc::xengine_max_halo() || (dtype == RRC_CI4 && (s.N & 3))) {

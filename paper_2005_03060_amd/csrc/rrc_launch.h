@@ -143,7 +143,7 @@ int fft_samples_per_step_for(int M);
 hipError_t launch_fftcorr(const FftLaunch& L, hipStream_t st);
 hipError_t launch_xengine(const XengLaunch& L, hipStream_t st);
 size_t xengine_lds_bytes(int halo, bool ci4);
-int xengine_antennas_per_block();
+int xengine_antennas_per_block(bool ci4);
 int xengine_max_halo();
 int xengine_samples_per_step(bool ci4);
 bool xmfma_plan(const Sel& s, XengLaunch& X);

@@ -10,9 +10,10 @@
 // Work-item a owns antenna a and the (at most K) pairs with a first; it
 // reads v_a once per sample and its K partners, all from LDS, so a sample
 // costs K + 1 LDS reads for K pairs (a pair-centric layout costs 2K).  A
-// workgroup owns one unit, one block of 256 consecutive antennas and one
+// workgroup owns one unit, one block of B consecutive antennas (B = 512 for
+// 4-bit voltages, 256 for complex64) and one
 // chunk of samples; each step stages S samples of the antennas
-// [a0 - halo, a0 + 256) (halo = the largest d_t) with coalesced loads.
+// [a0 - halo, a0 + B) (halo = the largest d_t) with coalesced loads.
 // Pairs that do not exist are computed against the antenna itself and
 // never written, so the inner loop has no branches.  Partial sums per time
 // chunk go to the workspace and a second kernel adds them in a fixed
@@ -41,16 +42,21 @@
 
 namespace rrc {
 
-constexpr int kXThreads = 256;
+// Antennas (work-items) per workgroup: 4-bit blocks of 512 halve the share
+// of re-read halo antennas against 256 (1.25x the voltages at 64 x 64
+// instead of 1.49x; 7.1 -> 6.5 ms there); complex64 keeps 256, whose grids
+// then still give enough workgroups without more time chunks.
+template <bool CI4>
+constexpr int xthreads() { return CI4 ? 512 : 256; }
 constexpr int kXHaloMax = 248;   // largest raster offset d_t the staging covers
 // LDS row stride of a staged complex64 sample (float2 units), fixed at the
 // largest halo: a compile-time stride turns the sample offset of every LDS
 // read into an immediate, so the products need no address arithmetic
-constexpr int kXRowF = kXThreads + kXHaloMax + 2;
+constexpr int kXRowF = xthreads<false>() + kXHaloMax + 2;
 // LDS stride of a staged group of four 4-bit samples (words, one per
 // antenna), fixed for the same reason: a group's offset is an immediate
-constexpr int kXRowW4 = 512;
-static_assert(kXRowW4 >= kXThreads + kXHaloMax + 6, "a 4-bit group row holds every staged antenna");
+constexpr int kXRowW4 = 1024;
+static_assert(kXRowW4 >= xthreads<true>() + kXHaloMax + 6, "a 4-bit group row holds every staged antenna");
 
 // Transpose a 4 x 4 block of bytes: out[k] byte q = in[q] byte k.
 __device__ __forceinline__ void transpose4x4(const uint32_t (&w)[4], uint32_t (&o)[4]) {
@@ -89,8 +95,8 @@ struct XStage {
 };
 
 template <bool CI4, bool WIDE, int KMAX>
-__global__ __launch_bounds__(kXThreads, KMAX <= 9 ? 4 : 2) void k_xant(XengLaunch L) {
-    constexpr int NT = kXThreads;
+__global__ __launch_bounds__(xthreads<CI4>(), KMAX <= 9 ? 4 : 2) void k_xant(XengLaunch L) {
+    constexpr int NT = xthreads<CI4>();
     constexpr int S = xeng_samples<CI4>();
     using G = XStage<CI4, WIDE>;
     using RT = typename G::RT;
@@ -163,10 +169,12 @@ __global__ __launch_bounds__(kXThreads, KMAX <= 9 ? 4 : 2) void k_xant(XengLaunc
     // 32-bit (at most S rows of N / 4 words).
     const RT* vol = reinterpret_cast<const RT*>(L.volt);
     const size_t rowstride = (size_t)N / W;
-    constexpr int GW = S / 4 / (NT / 64);          // 4-bit groups per wave
-    constexpr int RU = CI4 ? 2 * GW : S;           // register rows of staged data
+    constexpr int NW = NT / 64;
+    constexpr int GW = S / 4 / NW;                 // 4-bit groups per wave
+    constexpr int CM = ((NT + kXHaloMax + 6) / 4 + 63) / 64;   // word columns per lane
+    constexpr int RU = CI4 ? CM * GW : S;          // register rows of staged data
     constexpr int RK = CI4 ? 4 : KPT;
-    static_assert(!CI4 || (kXThreads + kXHaloMax + 6) / 4 <= 128, "two word columns per lane");
+    static_assert(!CI4 || S / 4 % NW == 0, "whole groups per wave");
     RT r[RU][RK];
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6), ln = tid & 63;
     const int rs32 = (int)rowstride;
@@ -178,15 +186,15 @@ __global__ __launch_bounds__(kXThreads, KMAX <= 9 ? 4 : 2) void k_xant(XengLaunc
         if constexpr (CI4) {
 #pragma unroll
             for (int gi = 0; gi < GW; ++gi) {
-                const int g4 = 4 * (wv + 4 * gi);
+                const int g4 = 4 * (wv + NW * gi);
 #pragma unroll
-                for (int m = 0; m < 2; ++m) {
+                for (int m = 0; m < CM; ++m) {
                     const int c = ln + 64 * m;
                     if (c >= upr) continue;
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
                         const RT* row = base + min(g4 + i, last) * rs32;   // uniform over the wave
-                        r[2 * gi + m][i] = row[c];
+                        r[CM * gi + m][i] = row[c];
                     }
                 }
             }
@@ -204,14 +212,14 @@ __global__ __launch_bounds__(kXThreads, KMAX <= 9 ? 4 : 2) void k_xant(XengLaunc
             uint4* st = reinterpret_cast<uint4*>(xsm);
 #pragma unroll
             for (int gi = 0; gi < GW; ++gi) {
-                const int g = wv + 4 * gi;
+                const int g = wv + NW * gi;
 #pragma unroll
-                for (int m = 0; m < 2; ++m) {
+                for (int m = 0; m < CM; ++m) {
                     const int c = ln + 64 * m;
                     if (c >= upr) continue;
                     uint32_t w[4];
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) w[i] = 4 * g + i <= pend_last ? r[2 * gi + m][i] : 0u;
+                    for (int i = 0; i < 4; ++i) w[i] = 4 * g + i <= pend_last ? r[CM * gi + m][i] : 0u;
                     uint32_t o[4];
                     transpose4x4(w, o);
                     st[g * (kXRowW4 / 4) + c] = make_uint4(o[0], o[1], o[2], o[3]);
@@ -322,14 +330,14 @@ __global__ __launch_bounds__(kXThreads, KMAX <= 9 ? 4 : 2) void k_xant(XengLaunc
 }
 
 // LDS of one workgroup: complex64, S staged rows of kXRowF values; 4-bit,
-// S/4 group rows of kXRowW4 words (up to 256 + halo + 6 antennas, whole
+// S/4 group rows of kXRowW4 words (up to 512 + halo + 6 antennas, whole
 // words, four samples each).
 size_t xengine_lds_bytes(int halo, bool ci4) {
     return ci4 ? (size_t)xeng_samples<true>() / 4 * kXRowW4 * 4
                : (size_t)xeng_samples<false>() * kXRowF * 8;
 }
 
-int xengine_antennas_per_block() { return kXThreads; }
+int xengine_antennas_per_block(bool ci4) { return ci4 ? xthreads<true>() : xthreads<false>(); }
 int xengine_max_halo() { return kXHaloMax; }
 int xengine_samples_per_step(bool ci4) { return ci4 ? xeng_samples<true>() : xeng_samples<false>(); }
 
@@ -365,7 +373,7 @@ static hipError_t launch_x(const XengLaunch& L, hipStream_t st) {
     } else {
         const size_t lds = xengine_lds_bytes(L.halo, CI4);
         dim3 grid(L.nablk, L.nchunk, L.n_units);
-        hipLaunchKernelGGL((k_xant<CI4, WIDE, KMAX>), grid, dim3(kXThreads), lds, st, L);
+        hipLaunchKernelGGL((k_xant<CI4, WIDE, KMAX>), grid, dim3(xthreads<CI4>()), lds, st, L);
         e = hipGetLastError();
     }
     if (e != hipSuccess || L.nchunk == 1) return e;
