@@ -40,7 +40,7 @@ def log(msg: str) -> None:
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz; the 157.3 TFLOP/s
-# vector figure counts packed (two-wide) FP32, which this build does not use
+# vector figure counts packed (two-wide) FP32, which these kernels do not use
 VALU_FP32_PEAK_TFLOPS = 78.6
 METRIC = "calibrated channel-integrations/sec (batched+adjoint vs plain) at stated gain error"
 DEFAULT_WORKLOAD = "g64_c1024_t4096_ci4"

@@ -71,7 +71,7 @@ extern "C" {
 #define RRC_EINVAL   -1   /* bad argument (NULL pointer, size, type, mode)   */
 #define RRC_EDEGEN   -2   /* selection has more than the four degeneracies  */
 #define RRC_EDEVICE  -3   /* a HIP runtime call failed                       */
-#define RRC_ENOTIMPL -4   /* combination not supported by this build         */
+#define RRC_ENOTIMPL -4   /* combination not supported by this library       */
 #define RRC_ERANGE   -5   /* size beyond a documented limit                  */
 
 /* ---- voltage formats ---------------------------------------------------- */
@@ -90,7 +90,7 @@ extern "C" {
 #define RRC_UNIT_MAXITER   1
 #define RRC_UNIT_NONFINITE 2
 
-/* Limits of this build. */
+/* Limits of this library. */
 #define RRC_MAX_TYPES 16     /* K, selected baseline-types                    */
 #define RRC_MAX_GRID  64     /* n; the padded FFT size M <= 128 (rrc_plan_set_fft_size) */
 
@@ -479,7 +479,7 @@ int rrc_plan_tune(rrc_plan* plan, void* stream, const rrc_io* io, const char* ca
  * every array).  The plans must be distinct and outlive the batch.  Host
  * only; owns streams and events.
  * flags: 0.  RRC_BATCH_GRAPH (replaying the whole batch as one captured
- * graph launch) returns RRC_ENOTIMPL in this build: capturing the batch's
+ * graph launch) returns RRC_ENOTIMPL in this library: capturing the batch's
  * fork/join ended the process with a host-side fault in the runtime. */
 #define RRC_BATCH_GRAPH 1u
 typedef struct rrc_batch rrc_batch;

@@ -14,7 +14,7 @@ Solvers
 * `logcal_amplitude`: the real part of eq. logcal, solved by linear least
   squares (a starting point only: it is noise-biased, Sec. 2).
 * `firstcal`: logcal amplitudes plus phases propagated along the (1,0) and
-  (0,1) redundant groups (a definition of this build; the paper does not
+  (0,1) redundant groups (a definition of this library; the paper does not
   say how its solver was started).
 * `lincal`: Gauss-Newton on the Taylor-expanded model (the "Taylor
   expansion" linearisation of Sec. 2): FP64 normal equations of the
