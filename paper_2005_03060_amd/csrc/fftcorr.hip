@@ -884,7 +884,11 @@ __global__ __launch_bounds__(kTThreads) void k_fftcorr_t(const void* __restrict_
 }
 
 constexpr int kFinThreads = 256;
-constexpr int kFinDxBlock = 32;
+// lags dx per pass of the direct finish: at M = 128 a block of 8 keeps the
+// workgroup's LDS (the M x M power grid plus M x DB partial sums) under
+// half a CU, so two units share one
+template <int M>
+constexpr int fin_dx_block() { return M == 128 ? 8 : 32; }
 
 template <int M>
 __global__ __launch_bounds__(kFinThreads) void k_fftfin(const float* __restrict__ ppart, int nchunk,
@@ -893,7 +897,7 @@ __global__ __launch_bounds__(kFinThreads) void k_fftfin(const float* __restrict_
                                                         unsigned long long* __restrict__ stamps,
                                                         const float* __restrict__ ndt, int n_live) {
     constexpr int NT = kFinThreads;
-    constexpr int DB = kFinDxBlock;
+    constexpr int DB = fin_dx_block<M>();
     __shared__ float pw[M * M];
     __shared__ float2 twp[M];              // e^{+2 pi i k / M}
     __shared__ float2 abuf[M * DB];
