@@ -479,8 +479,8 @@ static int plan_create(rrc_plan** out, int32_t n, const int32_t* types_xy, int32
     // solver
     // the solver's state always fits in LDS (131 KB at 4096 antennas);
     // V^reduced joins it when there is room, on one-antenna-per-work-item
-    // shapes (up to 1024 antennas)
-    p->solve_vcache = s.N <= 1024 && rrc::solve_lds_bytes(s, true) <= 150 * 1024;
+    // shapes (up to 512 antennas)
+    p->solve_vcache = s.N <= 512 && rrc::solve_lds_bytes(s, true) <= 150 * 1024;
     p->solve_lds_bytes = rrc::solve_lds_bytes(s, p->solve_vcache);
 
     size_t off = 0;

@@ -77,9 +77,9 @@ __host__ __device__ inline SolveLayout solve_layout(const Sel& s, bool vcache) {
 
 size_t solve_lds_bytes(const Sel& s, bool vcache) { return solve_layout(s, vcache).bytes; }
 
-// Workgroup shape: one antenna per work-item up to 1024 antennas, then
-// 512 work-items with 4, 5 or 8 antennas each.
-inline int solve_threads_for(int N) { return N <= 256 ? 256 : (N <= 512 || N > 1024 ? 512 : 1024); }
+// Workgroup shape: one antenna per work-item up to 512 antennas, then
+// 512 work-items with 2, 4, 5 or 8 antennas each.
+inline int solve_threads_for(int N) { return N <= 256 ? 256 : 512; }
 
 // Per-type constants of the selection, in LDS: the raster offset d_t of
 // the type and the pair indices as affine functions of an antenna's
@@ -1097,10 +1097,12 @@ static hipError_t solve_dispatch(const SolveLaunch& L, hipStream_t st, bool prep
     if (L.sel.K < 1 || L.sel.K > kMaxTypes || L.sel.K > solve_threads_for(N)) return hipErrorInvalidValue;
     if (N <= 256) return launch_solve_shape<256, 1>(L, st, prep);
     if (N <= 512) return launch_solve_shape<512, 1>(L, st, prep);
-    if (N <= 1024) return launch_solve_shape<1024, 1>(L, st, prep);
     // larger grids: 512 work-items (256 VGPRs each) rather than 1024 (128),
     // with as few antennas per work-item as cover the grid (at 48 x 48, five
-    // instead of eight take the solve from 3.5 to 1.2 ms: no spills)
+    // instead of eight take the solve from 3.5 to 1.2 ms: no spills; at
+    // 32 x 32, two per work-item instead of 1024 work-items of one, which
+    // spilled, 0.455 -> 0.413 ms)
+    if (N <= 1024) return launch_solve_shape<512, 2>(L, st, prep);
     if (N <= 2048) return launch_solve_shape<512, 4>(L, st, prep);
     if (N <= 2560) return launch_solve_shape<512, 5>(L, st, prep);
     if (N <= 4096) return launch_solve_shape<512, 8>(L, st, prep);

@@ -206,7 +206,7 @@ def _hex_solve_case(rrc, side, U, T, snr=10.0, **opts):
     return n, mask, pos, idx, types, pairs, tix, plan, v, g, vr32, vr64
 
 
-@pytest.mark.parametrize("side,U,T", [(3, 2, 512), (4, 2, 1024), (6, 2, 1024), (11, 1, 2048)])
+@pytest.mark.parametrize("side,U,T", [(3, 2, 512), (4, 2, 1024), (6, 2, 1024), (11, 1, 2048), (14, 1, 1024)])
 def test_hex_gauss_newton_matches_oracle(rrc, side, U, T):
     # the adjoint-driven Gauss-Newton solve on a masked lattice, started from
     # the true gains, against the oracle's FP64 solve of the same (rounded)
